@@ -1,0 +1,136 @@
+/*
+ * oracle.h -- plain, slow, single-threaded FP64 CPU implementation of the
+ * particle advance of the non-hybrid joint velocity-frequency-scalar PDF
+ * method (Bakosi, Franzese & Boybeyi, arXiv:1006.0549).
+ *
+ * THIS IS TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it. It shares no source with the
+ * GPU library; both implement the same written contract from the paper:
+ *
+ *   position SDE            Eq.(2)
+ *   GLM velocity SDE        Eq.(4)   (same Wiener increment as Eq.(2), Sec. II)
+ *   frequency SDE           Eq.(5) with the source Eq.(6)
+ *   IECM micromixing        Eq.(9)
+ *   forward Euler, grid statistics, pressure projection   Sec. II, last paragraph
+ *   grid roles (i) statistics, (ii) Eulerian solves, (iii) tracking   Sec. I
+ *
+ * Every point the paper leaves open is fixed by a numbered reading (R-nn),
+ * listed in the design notes of the repository and restated where used.
+ *
+ * Ownership: every pointer argument is borrowed for the duration of the call.
+ * Errors: functions return 0 on success and a positive code otherwise; the
+ * message is available from orc_last_error(). Nothing aborts.
+ */
+#ifndef PDFMC_ORACLE_H
+#define PDFMC_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_E_INVALID = 1, ORC_E_MESH = 2, ORC_E_STATE = 5 };
+enum { ORC_BC_WALL = 0, ORC_BC_PERIODIC = 1 };
+/* modes: 0 = every Eulerian field frozen at the uploaded values,
+ *        1 = simplified Langevin model (G from <omega>), frozen pressure gradient,
+ *        2 = elliptic relaxation for G_ij + pressure projection (R-19, R-27) */
+enum { ORC_MODE_FROZEN = 0, ORC_MODE_SLM = 1, ORC_MODE_ER = 2 };
+
+#define ORC_NF 22      /* Eulerian fields per node (R-06 field list) */
+#define ORC_MAXS 4     /* scalars per case */
+#define ORC_NCOUNT 12
+
+typedef struct {
+    int32_t type;        /* ORC_BC_WALL or ORC_BC_PERIODIC */
+    double u_wall[3];    /* wall velocity (wall only) */
+    double shift[2];     /* translation to the partner edge (periodic only) */
+} orc_bc;
+
+typedef struct {
+    int32_t n_nodes; const double* xy;     /* [2*n_nodes] interleaved */
+    int32_t n_elems; const int32_t* tri;   /* [3*n_elems], counter-clockwise */
+    const int32_t* edge_tag;               /* [3*n_elems]; edge k is opposite vertex k;
+                                              -1 interior, else index into bc[] */
+    int32_t n_bc; const orc_bc* bc;
+} orc_mesh_desc;
+
+typedef struct {
+    int32_t mode;
+    double dt, nu;
+    double C0, C3, C4, Cw1, Cw2, Cphi;            /* R-20, R-22, R-24 */
+    double C1, C2, gamma5, Cv, CL, Ceta;          /* R-19 */
+    double dpdx[2];      /* frozen (mode 1) or driving (mode 2) mean pressure gradient */
+    int32_t n_scalars, n_bins, n_min;             /* R-23 */
+    double src[ORC_MAXS][4];   /* per scalar: cx, cy, r, value; r <= 0 = no source (R-26) */
+    double k_floor, eps_floor;                    /* R-18 */
+    double cg_rtol; int32_t cg_maxit;             /* R-28 */
+    uint64_t seed; uint32_t stream;               /* R-09 key and counter word 2 */
+} orc_params;
+
+typedef struct {
+    int64_t n;
+    double *x, *y, *u, *v, *w, *omega, *weight;
+    double* psi;          /* [n_scalars*n], scalar-major */
+    int32_t* elem;        /* case-local element index */
+    uint32_t* id;         /* RNG identity (R-32) */
+    uint8_t* bin;         /* IECM velocity bin (R-23) */
+} orc_particles;
+
+typedef struct orc_ctx orc_ctx;
+
+orc_ctx*    orc_create(void);
+void        orc_destroy(orc_ctx* c);
+const char* orc_last_error(const orc_ctx* c);
+
+int orc_add_case(orc_ctx* c, const orc_mesh_desc* m, const orc_params* p, int32_t* case_id);
+int orc_mesh_info(orc_ctx* c, int32_t cs, int32_t* n_stat_nodes, int32_t* stat_node /*[n_nodes]*/,
+                  int32_t* nbr /*[3*ne] or NULL*/, double* rec /*[8*ne] or NULL*/,
+                  double* vol /*[n_nodes] or NULL*/);
+int orc_particles_upload(orc_ctx* c, int32_t cs, const orc_particles* p);
+int orc_particles_download(orc_ctx* c, int32_t cs, orc_particles* p);
+/* F: [n_nodes*ORC_NF], node-major, per raw node (periodic images must agree) */
+int orc_fields_upload(orc_ctx* c, int32_t cs, const double* F);
+int orc_fields_download(orc_ctx* c, int32_t cs, double* F);
+int orc_pressure_download(orc_ctx* c, int32_t cs, double* P /*[n_nodes]*/);
+/* initialisation pass: statistics of the uploaded state, Eulerian fields
+ * (except in mode 0), velocity bins and cell means */
+int orc_init(orc_ctx* c);
+/* only the bins + cell means of the current state against the current fields */
+int orc_rebin(orc_ctx* c);
+int orc_step(orc_ctx* c, int32_t n_steps);
+int orc_set_step_index(orc_ctx* c, uint32_t n);
+/* statistics per raw node: [n_nodes*(12+2*n_s)]:
+ * W, rho, <U1..3>, <u1u1>,<u2u2>,<u3u3>,<u1u2>,<u1u3>,<u2u3>, <omega>, <psi_a>.., <psi_a'^2>.. */
+int orc_stats(orc_ctx* c, int32_t cs, double* out);
+/* raw node sums sum_p w N_n(X_p) Q_p per raw node: [n_nodes*(11+2n_s)]:
+ * 1, U1..3, U1U1,U2U2,U3U3,U1U2,U1U3,U2U3, omega, psi_a.., psi_a^2.. */
+int orc_node_sums(orc_ctx* c, int32_t cs, double* out);
+/* cell means [n_elems*8*n_s] and cell counts [n_elems*8] */
+int orc_cell_means(orc_ctx* c, int32_t cs, double* mean, int32_t* count);
+int orc_counters(orc_ctx* c, int32_t cs, int64_t* out /*[ORC_NCOUNT]*/);
+
+/* ---- individual steps, exported so that tests can pin them ---- */
+void   orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_ln(double u);
+void   orc_sincos2pi(double u, double* s, double* c);
+void   orc_gauss6(uint64_t seed, uint32_t id, uint32_t step, uint32_t stream, double xi[6]);
+void   orc_uniform6(uint64_t seed, uint32_t id, uint32_t step, uint32_t stream, double u[6]);
+/* barycentric coordinates of (x,y) in element e of a case (R-05) */
+int orc_bary(orc_ctx* c, int32_t cs, int32_t e, double x, double y, double lam[3]);
+/* brute-force location (R-13): lowest-index element with min(lam) >= 0, else -1 */
+int32_t orc_locate_brute(orc_ctx* c, int32_t cs, double x, double y);
+/* the walk of R-12..R-15 from element e0; updates x,y,u (3 comps); returns element */
+int32_t orc_walk(orc_ctx* c, int32_t cs, int32_t e0, double* x, double* y, double* u3);
+/* recovered nodal gradient and Laplacian of a nodal field f (per raw node), R-16 */
+int orc_recover(orc_ctx* c, int32_t cs, const double* f, double* gx, double* gy, double* lap);
+/* Galerkin P1 solve of (M + K_L) s = M r with nodal L^2 and nodal r (per raw
+ * node); Dirichlet values dval where dmask != 0. tol: relative residual. */
+int orc_fem_helmholtz(orc_ctx* c, int32_t cs, const double* L2, const double* r,
+                      const int32_t* dmask, const double* dval, double tol, double* s);
+/* P1 projection solve: int grad N . grad phi = (1/dt) int grad N . U, zero mean */
+int orc_fem_projection(orc_ctx* c, int32_t cs, const double* U1, const double* U2,
+                       double dt, double tol, double* phi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
