@@ -1,0 +1,181 @@
+/*
+ * pdfmc.h -- C ABI of the MI355X particle-advance library for the non-hybrid
+ * joint velocity-frequency-scalar PDF method of Bakosi, Franzese & Boybeyi
+ * (arXiv:1006.0549).
+ *
+ * What a time step computes (Sec. II, last paragraph: forward Euler; Eulerian
+ * statistics estimated on the grid and evaluated at the particles; the mean
+ * pressure from a projection on the grid):
+ *   - particle tracking on the unstructured grid (Sec. I, grid role (iii)) with
+ *     no-slip imposed on particles at walls and periodic edges,
+ *   - the position SDE, Eq.(2), and the generalized Langevin velocity SDE,
+ *     Eq.(4), driven by the same Wiener increment dW_i,
+ *   - the turbulent-frequency SDE, Eq.(5), with the source S_omega of Eq.(6),
+ *   - IECM micromixing of the scalars, Eq.(9), plus concentrated sources,
+ *   - the shape-weighted statistics at gridpoints (Sec. I, grid role (i)),
+ *   - the Eulerian fields: recovered gradients, the elliptic-relaxation G_ij
+ *     (Sec. II, after Eq.(4)) and the pressure projection (grid role (ii)).
+ * The points the paper leaves open are fixed by numbered readings (R-nn)
+ * that this library and its test oracle implement alike.
+ *
+ * Conventions for every call:
+ *  - Returns PDFMC_OK or an error code; pdfmc_last_error() gives the message.
+ *    Nothing aborts or throws across this boundary.
+ *  - Host pointers are borrowed for the duration of the call only.
+ *  - Device memory: the library never allocates. pdfmc_workspace_query()
+ *    returns the size of one device buffer that the caller allocates and
+ *    binds with pdfmc_workspace_bind(); it stays owned by the caller and must
+ *    outlive the context (or the next bind).
+ *  - All device work is enqueued on the caller's HIP stream given at
+ *    pdfmc_create(); calls that return host data synchronise that stream.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef PDFMC_H
+#define PDFMC_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdfmc_ctx pdfmc_ctx;
+
+typedef enum {
+    PDFMC_OK = 0,
+    PDFMC_E_INVALID = 1,      /* bad argument */
+    PDFMC_E_MESH = 2,         /* mesh rejected (orientation, manifoldness, periodic matching) */
+    PDFMC_E_NOMEM = 3,        /* bound workspace too small */
+    PDFMC_E_HIP = 4,          /* a HIP call failed */
+    PDFMC_E_STATE = 5,        /* call out of order (e.g. step before bind/init) */
+    PDFMC_E_UNSUPPORTED = 6
+} pdfmc_status;
+
+typedef enum { PDFMC_FP64 = 0, PDFMC_FP32 = 1 } pdfmc_precision;
+typedef enum { PDFMC_BC_WALL = 0, PDFMC_BC_PERIODIC = 1 } pdfmc_bc_type;
+/* 0: Eulerian fields frozen at the uploaded values;
+ * 1: simplified Langevin model, G_ij = -(1/2 + 3/4 C0)<omega> delta_ij, frozen
+ *    mean pressure gradient (R-20);
+ * 2: elliptic relaxation for G_ij and pressure projection (R-19, R-27). */
+typedef enum { PDFMC_MODE_FROZEN = 0, PDFMC_MODE_SLM = 1, PDFMC_MODE_ER = 2 } pdfmc_mode;
+
+#define PDFMC_NF 22        /* Eulerian field slots per node (R-06)          */
+#define PDFMC_MAX_SCALARS 4
+#define PDFMC_N_COUNTERS 12
+
+typedef struct {
+    int32_t type;          /* pdfmc_bc_type                                  */
+    double u_wall[3];      /* wall velocity (walls)                          */
+    double shift[2];       /* translation onto the partner edge (periodic)   */
+} pdfmc_bc;
+
+typedef struct {
+    int32_t n_nodes;  const double* xy;        /* [2*n_nodes] interleaved x,y      */
+    int32_t n_elems;  const int32_t* tri;      /* [3*n_elems] counter-clockwise    */
+    const int32_t* edge_tag;  /* [3*n_elems]; edge k is opposite vertex k;
+                                 -1 interior, else an index into bc[]           */
+    int32_t n_bc;     const pdfmc_bc* bc;
+} pdfmc_mesh_desc;
+
+typedef struct {
+    int32_t mode;                                  /* pdfmc_mode                 */
+    double dt, nu;                                 /* time step, viscosity (rho=1) */
+    double C0, C3, C4, Cw1, Cw2, Cphi;             /* Eq.(4),(5),(6); R-24        */
+    double C1, C2, gamma5, Cv, CL, Ceta;           /* elliptic relaxation, R-19   */
+    double dpdx[2];        /* mode 1: frozen d<P>/dx_j; mode 2: driving gradient */
+    int32_t n_scalars;     /* 0..PDFMC_MAX_SCALARS                              */
+    int32_t n_bins;        /* 1 (IEM limit) or 8 velocity octants, R-23          */
+    int32_t n_min;         /* smaller cells pool into a residual cell, R-23      */
+    double src[PDFMC_MAX_SCALARS][4];  /* cx, cy, r, value; r <= 0: none, R-26   */
+    double k_floor, eps_floor;                     /* R-18                        */
+    double cg_rtol; int32_t cg_maxit;              /* R-28                        */
+    uint64_t seed; uint32_t stream;                /* RNG key and stream, R-09    */
+} pdfmc_case_params;
+
+/* Particle ensemble on the host, structure of arrays, always FP64 here (the
+ * FP32 context converts on upload/download). psi is [n_scalars*n],
+ * scalar-major. elem is the case-local element holding (x, y); id is the
+ * RNG identity (R-32); bin may be NULL on upload. */
+typedef struct {
+    int64_t n;
+    double *x, *y, *u, *v, *w, *omega, *weight, *psi;
+    int32_t* elem;
+    uint32_t* id;
+    uint8_t* bin;
+} pdfmc_particles_host;
+
+/* Context on the caller's stream (a hipStream_t, NULL = default stream). */
+pdfmc_status pdfmc_create(pdfmc_ctx** out, int32_t precision, void* hip_stream);
+void         pdfmc_destroy(pdfmc_ctx* ctx);
+const char*  pdfmc_last_error(const pdfmc_ctx* ctx);   /* valid until the next call */
+
+/* Mesh upload (Sec. I: the unstructured grid) and case settings. The mesh is
+ * validated and its tables derived on the host (neighbours, periodic
+ * partners, merged periodic nodes, element records of R-05). capacity is the
+ * largest particle count the case will hold. Must precede workspace_query. */
+pdfmc_status pdfmc_add_case(pdfmc_ctx* ctx, const pdfmc_mesh_desc* mesh, const pdfmc_case_params* params,
+                            int64_t capacity, int32_t* case_id);
+/* Statistics nodes of a case (periodic images merged, R-33): count and the
+ * map raw node -> statistics node (may be NULL). */
+pdfmc_status pdfmc_case_info(pdfmc_ctx* ctx, int32_t case_id, int32_t* n_stat_nodes, int32_t* stat_node);
+
+/* Device workspace: size in bytes (alignment 256) for all cases added so far;
+ * bind uploads the mesh tables into it (asynchronously on the stream). */
+pdfmc_status pdfmc_workspace_query(pdfmc_ctx* ctx, uint64_t* bytes);
+pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* ctx, void* dev_ptr, uint64_t bytes);
+
+/* Particle init: upload an ensemble (n <= capacity). Rejects an element id
+ * outside the case. Particles keep their id across sorts. */
+pdfmc_status pdfmc_particles_upload(pdfmc_ctx* ctx, int32_t case_id, const pdfmc_particles_host* p);
+pdfmc_status pdfmc_particles_download(pdfmc_ctx* ctx, int32_t case_id, pdfmc_particles_host* p);
+
+/* Eulerian fields per raw node, [n_nodes*PDFMC_NF] node-major, slots:
+ * 0-2 <U_i>; 3-4 d<P>/dx_j; 5-10 d<U_i>/dx_j (i-major); 11-13 lap <U_i>;
+ * 14-18 G11,G12,G21,G22,G33; 19 <omega>; 20 C0 eps; 21 S_omega. */
+pdfmc_status pdfmc_fields_upload(pdfmc_ctx* ctx, int32_t case_id, const double* F);
+pdfmc_status pdfmc_fields_download(pdfmc_ctx* ctx, int32_t case_id, double* F);
+pdfmc_status pdfmc_pressure_download(pdfmc_ctx* ctx, int32_t case_id, double* P);
+
+/* Initialisation pass over every case: statistics of the uploaded state,
+ * the Eulerian fields (not in mode 0), velocity bins and cell means. */
+pdfmc_status pdfmc_init(pdfmc_ctx* ctx);
+/* Only recompute bins and cell means against the current fields. */
+pdfmc_status pdfmc_rebin(pdfmc_ctx* ctx);
+/* Advance every case by n_steps time steps (asynchronous). */
+pdfmc_status pdfmc_step(pdfmc_ctx* ctx, int32_t n_steps);
+/* Time-step index that enters the RNG counter (R-09); for restarts. */
+pdfmc_status pdfmc_set_step_index(pdfmc_ctx* ctx, uint32_t n);
+
+/* Statistics readback per raw node: [n_nodes*(12+2*n_scalars)]:
+ * W, rho, <U_1..3>, <u1u1>,<u2u2>,<u3u3>,<u1u2>,<u1u3>,<u2u3>, <omega>,
+ * <psi_a> (n_scalars), <psi_a'^2> (n_scalars). Synchronises the stream. */
+pdfmc_status pdfmc_stats_readback(pdfmc_ctx* ctx, int32_t case_id, double* out);
+/* Raw weighted node sums of the last statistics pass, [n_nodes*(11+2*n_s)]:
+ * sum_p w N_n(X_p) Q_p for Q = 1, U_1..3, U1U1,U2U2,U3U3,U1U2,U1U3,U2U3,
+ * omega, psi_a, psi_a^2. */
+pdfmc_status pdfmc_node_sums(pdfmc_ctx* ctx, int32_t case_id, double* out);
+/* Cell means of the IECM conditional mean, [n_elems*8*n_s], and cell
+ * particle counts [n_elems*8] (either pointer may be NULL). */
+pdfmc_status pdfmc_cell_means(pdfmc_ctx* ctx, int32_t case_id, double* mean, int32_t* count);
+/* Counters since upload, [PDFMC_N_COUNTERS]: walk fallbacks, reflections,
+ * periodic crossings, omega sign flips, empty nodes, non-finite particles,
+ * walk steps, ER CG iterations, projection CG iterations, CG failures,
+ * k floor hits, eps floor hits. */
+pdfmc_status pdfmc_counters(pdfmc_ctx* ctx, int32_t case_id, int64_t* out);
+
+/* Execution options: re-sort the particles by element every sort_interval
+ * steps (0 = never), particle-kernel block size (64..1024, multiple of 64),
+ * capture the step sequence into a HIP graph (0/1). */
+pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t block_size, int32_t use_graph);
+/* Sort the particles of every case by element now (stable counting sort). */
+pdfmc_status pdfmc_sort(pdfmc_ctx* ctx);
+pdfmc_status pdfmc_synchronize(pdfmc_ctx* ctx);
+
+/* Device-side draws of the Wiener increments for n particles (test hook of
+ * R-09/R-10): ids, out are DEVICE pointers; out is [6*n] (FP64 context:
+ * doubles; FP32 context: floats), increment j of particle i at out[6*i+j]. */
+pdfmc_status pdfmc_draw_gaussians(pdfmc_ctx* ctx, uint64_t seed, uint32_t step, uint32_t stream,
+                                  const uint32_t* ids, int64_t n, void* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

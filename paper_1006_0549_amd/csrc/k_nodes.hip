@@ -1,0 +1,466 @@
+// Node- and element-level kernels of a time step, all in FP64 (the Eulerian
+// side of the method: Sec. I grid roles (i) statistics and (ii) Eulerian
+// solves). Each kernel covers every case of the context in one launch:
+// threads map to global statistics nodes or elements and look up their case.
+//
+//   k_node_stats   node sums -> weighted means, central moments, density (R-11)
+//   k_cell_means   cell sums -> IECM cell means with the residual rule (R-23)
+//   k_fields_grad  <U>, <omega>, recovered gradients of <U> (R-16)
+//   k_fields_derived  Laplacians (R-16), k, eps, production, S_omega
+//                  (Eq.(6), R-17, R-18), simplified Langevin G_ij (R-20) or
+//                  the elliptic-relaxation sources, length scale and wall values (R-19)
+//   k_er_assemble  Galerkin (M + K_L) matrix, M r right-hand sides, Dirichlet rows
+//   k_cg           Jacobi-preconditioned conjugate gradients, one workgroup
+//                  per linear system, warm-started (R-28)
+//   k_er_finish    G_ij and C0 eps from the relaxed tensor (R-19)
+//   k_proj_rhs / k_proj_finish  pressure projection (R-27)
+//   k_mirror_f32   FP32 copy of the fields for the FP32 particle kernel
+#include "pdfmc_dev.h"
+#include "pdfmc_nodes.h"
+
+namespace pdfmc {
+
+__global__ void k_fill_f64(double* __restrict__ a, int64_t n, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
+}
+
+__global__ void k_step_increment(uint32_t* step) { if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += 1u; }
+
+__global__ void k_node_stats(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const int c = A.node_case[s];
+    const CaseDev& C = A.cases[c];
+    const int ns = C.ns;
+    const double* r = A.nsum + (int64_t)s * NQ;
+    double* st = A.stats + (int64_t)s * NST;
+    const double W = r[0];
+    if (W > 0.0) {
+        st[0] = W;
+        st[1] = W / A.vol[s];
+        const double m1 = r[1] / W, m2 = r[2] / W, m3 = r[3] / W;
+        st[2] = m1; st[3] = m2; st[4] = m3;
+        st[5] = r[4] / W - m1 * m1;
+        st[6] = r[5] / W - m2 * m2;
+        st[7] = r[6] / W - m3 * m3;
+        st[8] = r[7] / W - m1 * m2;
+        st[9] = r[8] / W - m1 * m3;
+        st[10] = r[9] / W - m2 * m3;
+        st[11] = r[10] / W;
+        for (int a = 0; a < ns; ++a) {
+            double m = r[11 + a] / W;
+            st[12 + a] = m;
+            st[12 + ns + a] = r[11 + ns + a] / W - m * m;
+        }
+    } else {
+        st[0] = 0.0; st[1] = 0.0;     // empty node: keep the previous moments
+        atomicAdd(A.counters + (int64_t)c * NCNT + C_EMPTY_NODE, 1ull);
+    }
+}
+
+template <typename R>
+__global__ void k_cell_means(NodeArgs A, R* __restrict__ cmean)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.ne) return;
+    const int c = A.elem_case[e];
+    const CaseDev& C = A.cases[c];
+    const int ns = C.ns;
+    if (ns == 0) return;
+    const int el = e - C.eoff;
+    const int32_t* cnt = A.ccnt + (int64_t)e * 8;
+    const double* cs = A.csum + C.csoff + (int64_t)el * 8 * (1 + ns);
+    double rw = 0.0, rp[MAXS] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 8; ++b)
+        if (cnt[b] > 0 && cnt[b] < C.nmin) {
+            rw += cs[b * (1 + ns)];
+            for (int a = 0; a < ns; ++a) rp[a] += cs[b * (1 + ns) + 1 + a];
+        }
+    R* out = cmean + C.cmoff + (int64_t)el * 8 * ns;
+    for (int b = 0; b < 8; ++b)
+        for (int a = 0; a < ns; ++a) {
+            double m = 0.0;
+            if (cnt[b] >= C.nmin) m = cs[b * (1 + ns) + 1 + a] / cs[b * (1 + ns)];
+            else if (rw > 0.0) m = rp[a] / rw;
+            out[b * ns + a] = (R)m;
+        }
+}
+template __global__ void k_cell_means<double>(NodeArgs, double*);
+template __global__ void k_cell_means<float>(NodeArgs, float*);
+
+// R-16: area-weighted average of the element gradients of a P1 field
+__device__ inline void recover_grad(const NodeArgs& A, const double* f, int fstride, int s, double& gx, double& gy)
+{
+    double Asum = 0.0, sx = 0.0, sy = 0.0;
+    for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
+        const int e = A.inc[j] / 3;
+        const double* r = A.rec + 8 * (int64_t)e;
+        const int4 t = A.tri_s[e];
+        const double f0 = f[(int64_t)t.x * fstride], f1 = f[(int64_t)t.y * fstride], f2 = f[(int64_t)t.z * fstride];
+        const double ex = (f0 * r[2] + f1 * r[3]) + f2 * r[4];
+        const double ey = (f0 * r[5] + f1 * r[6]) + f2 * r[7];
+        const double ae = A.area[e];
+        sx += ae * ex; sy += ae * ey; Asum += ae;
+    }
+    gx = sx / Asum; gy = sy / Asum;
+}
+
+__global__ void k_fields_grad(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const CaseDev& C = A.cases[A.node_case[s]];
+    if (C.mode == 0) return;
+    double* F = A.F + (int64_t)s * NF;
+    const double* st = A.stats + (int64_t)s * NST;
+    F[F_U1] = st[2]; F[F_U2] = st[3]; F[F_U3] = st[4];
+    F[F_OMEGA] = st[11];
+    for (int i = 0; i < 3; ++i) {
+        double gx, gy;
+        recover_grad(A, A.stats + 2 + i, NST, s, gx, gy);
+        F[F_DU1X + 2 * i] = gx;
+        F[F_DU1X + 2 * i + 1] = gy;
+    }
+}
+
+__device__ inline double det3(const double R[3][3])
+{
+    return R[0][0] * (R[1][1] * R[2][2] - R[1][2] * R[2][1])
+         - R[0][1] * (R[1][0] * R[2][2] - R[1][2] * R[2][0])
+         + R[0][2] * (R[1][0] * R[2][1] - R[1][1] * R[2][0]);
+}
+
+__global__ void k_fields_derived(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const int c = A.node_case[s];
+    const CaseDev& C = A.cases[c];
+    if (C.mode == 0) return;
+    double* F = A.F + (int64_t)s * NF;
+    const double* st = A.stats + (int64_t)s * NST;
+    // Laplacian: area-weighted element divergence of the recovered gradient (R-16)
+    for (int i = 0; i < 3; ++i) {
+        double Asum = 0.0, sd = 0.0;
+        for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
+            const int e = A.inc[j] / 3;
+            const double* r = A.rec + 8 * (int64_t)e;
+            const int4 t = A.tri_s[e];
+            const int tt[3] = {t.x, t.y, t.z};
+            double div = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double* Fk = A.F + (int64_t)tt[k] * NF;
+                div += r[2 + k] * Fk[F_DU1X + 2 * i] + r[5 + k] * Fk[F_DU1X + 2 * i + 1];
+            }
+            sd += A.area[e] * div; Asum += A.area[e];
+        }
+        F[F_LAP1 + i] = sd / Asum;
+    }
+    const double k = 0.5 * ((st[5] + st[6]) + st[7]);
+    const double om = st[11];
+    const double eps = k * om;
+    double kf = k, ef = eps;
+    unsigned long long* cnt = A.counters + (int64_t)c * NCNT;
+    if (kf < C.k_floor) { kf = C.k_floor; atomicAdd(cnt + C_K_FLOOR, 1ull); }
+    if (ef < C.eps_floor) { ef = C.eps_floor; atomicAdd(cnt + C_EPS_FLOOR, 1ull); }
+    A.kf[s] = kf; A.ef[s] = ef;
+    const double u11 = st[5], u22 = st[6], u33 = st[7], u12 = st[8], u13 = st[9], u23 = st[10];
+    const double prod = -(((u11 * F[F_DU1X] + u12 * F[F_DU1Y]) + (u12 * F[F_DU2X] + u22 * F[F_DU2Y]))
+                          + (u13 * F[F_DU3X] + u23 * F[F_DU3Y]));
+    F[F_SOMEGA] = C.Cw2 - C.Cw1 * prod / ef;
+    if (C.mode == 1) {
+        const double g = -(0.5 + 0.75 * C.C0) * om;
+        F[F_G11] = g; F[F_G22] = g; F[F_G33] = g; F[F_G12] = 0.0; F[F_G21] = 0.0;
+        F[F_C0EPS] = C.C0 * eps;
+        F[F_DPX] = C.dpdx[0]; F[F_DPY] = C.dpdx[1];
+        return;
+    }
+    // mode 2: sources of the elliptic-relaxation equation (R-19)
+    const double Rm[3][3] = {{u11, u12, u13}, {u12, u22, u23}, {u13, u23, u33}};
+    const double dU[3][3] = {{F[F_DU1X], F[F_DU1Y], 0.0}, {F[F_DU2X], F[F_DU2Y], 0.0}, {F[F_DU3X], F[F_DU3Y], 0.0}};
+    double b[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) b[i][j] = Rm[i][j] / (2.0 * kf) - (i == j ? 1.0 / 3.0 : 0.0);
+    const double k23 = (2.0 / 3.0) * kf;
+    double Av = C.Cv * det3(Rm) / (k23 * k23 * k23);
+    if (Av > 1.0) Av = 1.0;
+    const double cA = C.C2 * Av + C.gamma5 / 3.0;
+    const int ci[NER] = {0, 0, 1, 1, 2}, cj[NER] = {0, 1, 0, 1, 2};
+    const double nvec[3] = {A.wnx[s], A.wny[s], 0.0};
+    for (int q = 0; q < NER; ++q) {
+        const int i = ci[q], j = cj[q];
+        double h = cA * dU[i][j] - (C.gamma5 / 3.0) * dU[j][i];
+        for (int kk = 0; kk < 3; ++kk) h += C.gamma5 * b[i][kk] * dU[kk][j];
+        for (int l = 0; l < 3; ++l) h -= C.gamma5 * b[i][l] * dU[j][l];
+        double val = kf * h;
+        if (i == j) val += 0.5 * (1.0 - C.C1) * ef;
+        A.er_r[(int64_t)q * A.nn + s] = val;
+        A.er_dval[(int64_t)q * A.nn + s] = -4.5 * ef * nvec[i] * nvec[j];
+    }
+    const double lt = kf * __builtin_sqrt(kf) / ef;
+    const double lk = C.Ceta * C.nu34 / __builtin_sqrt(__builtin_sqrt(ef));
+    const double L = C.CL * (lt > lk ? lt : lk);
+    A.L2[s] = L * L;
+}
+
+// Galerkin matrix (M + K_L) with L^2 per element = mean of the nodal values,
+// right-hand sides M r for the five components, Dirichlet rows at walls.
+// One thread per row; the row's entries are accumulated in incidence order.
+__global__ void k_er_assemble(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const CaseDev& C = A.cases[A.node_case[s]];
+    if (C.mode != 2) return;
+    const int r0 = A.csr_ptr[s], r1 = A.csr_ptr[s + 1];
+    for (int j = r0; j < r1; ++j) A.er_val[j] = 0.0;
+    double rhs[NER] = {0, 0, 0, 0, 0};
+    for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
+        const int ent = A.inc[j];
+        const int e = ent / 3, a = ent % 3;
+        const double* rc = A.rec + 8 * (int64_t)e;
+        const int4 t4 = A.tri_s[e];
+        const int t[3] = {t4.x, t4.y, t4.z};
+        const double Ae = A.area[e];
+        const double L2e = ((A.L2[t[0]] + A.L2[t[1]]) + A.L2[t[2]]) / 3.0;
+        for (int cc = 0; cc < 3; ++cc) {
+            const double Mab = Ae / 12.0 * (a == cc ? 2.0 : 1.0);
+            const double Kab = Ae * (rc[2 + a] * rc[2 + cc] + rc[5 + a] * rc[5 + cc]);
+            A.er_val[A.incpos[3 * (int64_t)j + cc]] += Mab + L2e * Kab;
+            for (int q = 0; q < NER; ++q) rhs[q] += Mab * A.er_r[(int64_t)q * A.nn + t[cc]];
+        }
+    }
+    if (A.is_wall[s]) {
+        for (int j = r0; j < r1; ++j) A.er_val[j] = (A.csr_col[j] == s) ? 1.0 : 0.0;
+        for (int q = 0; q < NER; ++q) A.er_b[(int64_t)q * A.nn + s] = A.er_dval[(int64_t)q * A.nn + s];
+        return;
+    }
+    for (int j = r0; j < r1; ++j) {
+        const int col = A.csr_col[j];
+        if (A.is_wall[col]) {
+            for (int q = 0; q < NER; ++q) rhs[q] -= A.er_val[j] * A.er_dval[(int64_t)q * A.nn + col];
+            A.er_val[j] = 0.0;
+        }
+    }
+    for (int q = 0; q < NER; ++q) A.er_b[(int64_t)q * A.nn + s] = rhs[q];
+}
+
+// Stiffness matrix of the projection (constant; assembled once).
+__global__ void k_stiffness_assemble(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    for (int j = A.csr_ptr[s]; j < A.csr_ptr[s + 1]; ++j) A.pk_val[j] = 0.0;
+    for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
+        const int ent = A.inc[j];
+        const int e = ent / 3, a = ent % 3;
+        const double* rc = A.rec + 8 * (int64_t)e;
+        const double Ae = A.area[e];
+        for (int cc = 0; cc < 3; ++cc)
+            A.pk_val[A.incpos[3 * (int64_t)j + cc]] += Ae * (rc[2 + a] * rc[2 + cc] + rc[5 + a] * rc[5 + cc]);
+    }
+}
+
+__global__ void k_er_finish(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const CaseDev& C = A.cases[A.node_case[s]];
+    if (C.mode != 2) return;
+    double* F = A.F + (int64_t)s * NF;
+    const double* st = A.stats + (int64_t)s * NST;
+    const double K = A.kf[s], E = A.ef[s];
+    const int64_t n = A.nn;
+    const double w11 = A.er_x[s], w12 = A.er_x[n + s], w21 = A.er_x[2 * n + s], w22 = A.er_x[3 * n + s],
+                 w33 = A.er_x[4 * n + s];
+    F[F_G11] = (w11 - 0.5 * E) / K;
+    F[F_G12] = w12 / K;
+    F[F_G21] = w21 / K;
+    F[F_G22] = (w22 - 0.5 * E) / K;
+    F[F_G33] = (w33 - 0.5 * E) / K;
+    const double tr = (st[5] * w11 + st[8] * w12) + (st[8] * w21 + st[6] * w22) + st[7] * w33;
+    const double c0e = -(2.0 / 3.0) * tr / K;
+    F[F_C0EPS] = c0e > 0.0 ? c0e : 0.0;
+}
+
+// right-hand side of the projection: (1/dt) sum_e A_e grad N_a . <U>_e
+__global__ void k_proj_rhs(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const CaseDev& C = A.cases[A.node_case[s]];
+    if (C.mode != 2) return;
+    double b = 0.0;
+    for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
+        const int ent = A.inc[j];
+        const int e = ent / 3, a = ent % 3;
+        const double* rc = A.rec + 8 * (int64_t)e;
+        const int4 t = A.tri_s[e];
+        const double* S0 = A.stats + (int64_t)t.x * NST;
+        const double* S1 = A.stats + (int64_t)t.y * NST;
+        const double* S2 = A.stats + (int64_t)t.z * NST;
+        const double ue = ((S0[2] + S1[2]) + S2[2]) / 3.0;
+        const double ve = ((S0[3] + S1[3]) + S2[3]) / 3.0;
+        b += A.area[e] * (rc[2 + a] * ue + rc[5 + a] * ve) / C.dt;
+    }
+    A.pb[s] = b;
+}
+
+// <P> += phi, then d<P>/dx_j = driving gradient + recovered gradient of <P>
+__global__ void k_proj_update(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const CaseDev& C = A.cases[A.node_case[s]];
+    if (C.mode != 2) return;
+    A.P[s] += A.phi[s];
+}
+
+__global__ void k_proj_grad(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const CaseDev& C = A.cases[A.node_case[s]];
+    if (C.mode != 2) return;
+    double gx, gy;
+    recover_grad(A, A.P, 1, s, gx, gy);
+    A.F[(int64_t)s * NF + F_DPX] = C.dpdx[0] + gx;
+    A.F[(int64_t)s * NF + F_DPY] = C.dpdx[1] + gy;
+}
+
+__global__ void k_mirror_f32(const double* __restrict__ F, float* __restrict__ F32, int nn)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nn * NF32) return;
+    const int64_t s = i / NF32;
+    const int q = (int)(i % NF32);
+    F32[i] = q < NF ? (float)F[s * NF + q] : 0.0f;
+}
+
+// ---------------------------------------------------------------- CG
+
+__device__ inline void block_sum(double* v, int nv, double* sh)
+{
+    // sh: [32 * 4] doubles of LDS; nv <= 4
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int k = 0; k < nv; ++k) {
+        double x = v[k];
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+        if (lane == 0) sh[wid * 4 + k] = x;
+    }
+    __syncthreads();
+    for (int k = 0; k < nv; ++k) {
+        double x = 0.0;
+        for (int w = 0; w < nw; ++w) x += sh[w * 4 + k];
+        v[k] = x;
+    }
+    __syncthreads();
+}
+
+// One workgroup per system: rows [r0, r0+n) of a global CSR matrix.
+__global__ void __launch_bounds__(1024) k_cg(const CgJob* __restrict__ jobs)
+{
+    const CgJob J = jobs[blockIdx.x];
+    if (J.n <= 0) return;
+    __shared__ double sh[16 * 4];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int n = J.n, r0 = J.r0;
+    double v[4];
+    if (J.mean_free) {
+        v[0] = 0.0;
+        for (int i = tid; i < n; i += nt) v[0] += J.b[r0 + i];
+        block_sum(v, 1, sh);
+        const double mb = v[0] / n;
+        for (int i = tid; i < n; i += nt) J.b[r0 + i] -= mb;
+        __syncthreads();
+    }
+    // r = b - A x, z = D^-1 r, p = z
+    v[0] = 0.0; v[1] = 0.0; v[2] = 0.0;
+    for (int i = tid; i < n; i += nt) {
+        const int row = r0 + i;
+        double ax = 0.0, d = 1.0;
+        for (int j = J.ptr[row]; j < J.ptr[row + 1]; ++j) {
+            const int col = J.col[j];
+            ax += J.val[j] * J.x[col];
+            if (col == row) d = J.val[j];
+        }
+        const double rr = J.b[row] - ax;
+        const double di = 1.0 / d;
+        J.dinv[row] = di;
+        J.r[row] = rr;
+        const double z = di * rr;
+        J.p[row] = z;
+        v[0] += rr * z; v[1] += rr * rr; v[2] += J.b[row] * J.b[row];
+    }
+    block_sum(v, 3, sh);
+    double rz = v[0], rr = v[1];
+    const double bb = v[2];
+    const double tol2 = J.tol * J.tol * bb;
+    int it = 0;
+    bool ok = (rr <= tol2);
+    while (!ok && it < J.maxit) {
+        // q = A p ; pq
+        v[0] = 0.0;
+        for (int i = tid; i < n; i += nt) {
+            const int row = r0 + i;
+            double q = 0.0;
+            for (int j = J.ptr[row]; j < J.ptr[row + 1]; ++j) q += J.val[j] * J.p[J.col[j]];
+            J.q[row] = q;
+            v[0] += J.p[row] * q;
+        }
+        block_sum(v, 1, sh);
+        const double alpha = rz / v[0];
+        v[0] = 0.0;
+        for (int i = tid; i < n; i += nt) {
+            const int row = r0 + i;
+            J.x[row] += alpha * J.p[row];
+            const double rn = J.r[row] - alpha * J.q[row];
+            J.r[row] = rn;
+            v[0] += rn;
+        }
+        double mr = 0.0;
+        if (J.mean_free) {
+            block_sum(v, 1, sh);
+            mr = v[0] / n;
+        }
+        v[0] = 0.0; v[1] = 0.0;
+        for (int i = tid; i < n; i += nt) {
+            const int row = r0 + i;
+            const double rn = J.r[row] - mr;
+            J.r[row] = rn;
+            const double z = J.dinv[row] * rn;
+            J.q[row] = z;                 // q now holds z
+            v[0] += rn * z; v[1] += rn * rn;
+        }
+        block_sum(v, 2, sh);
+        const double beta = v[0] / rz;
+        rz = v[0]; rr = v[1];
+        for (int i = tid; i < n; i += nt) {
+            const int row = r0 + i;
+            J.p[row] = J.q[row] + beta * J.p[row];
+        }
+        __syncthreads();
+        ++it;
+        ok = (rr <= tol2);
+    }
+    if (J.mean_free) {
+        v[0] = 0.0;
+        for (int i = tid; i < n; i += nt) v[0] += J.x[r0 + i];
+        block_sum(v, 1, sh);
+        const double mx = v[0] / n;
+        for (int i = tid; i < n; i += nt) J.x[r0 + i] -= mx;
+    }
+    if (tid == 0) {
+        atomicAdd(J.iters, (unsigned long long)it);
+        if (!ok) atomicAdd(J.fails, 1ull);
+    }
+}
+
+}  // namespace pdfmc

@@ -1,0 +1,360 @@
+// Particle kernel: one forward-Euler step of every particle of every case in
+// one launch, fused with the grid statistics of the new state.
+//
+// Per particle (order of reading R-08):
+//   barycentric coordinates in its element (R-05) -> P1 interpolation of the
+//   Eulerian fields (R-06) -> Wiener increments (R-09, R-10) -> IECM mixing,
+//   Eq.(9) (R-23, R-24) -> velocity increment, Eq.(4) -> position increment,
+//   Eq.(2), with the same dW_i -> frequency increment, Eq.(5) (R-21) ->
+//   neighbour walk with wall reflection and periodic shift (R-12..R-15) ->
+//   concentrated sources (R-26) -> velocity bin against the fields of this
+//   step (R-23) -> shape-weighted sums of the new state at the element's
+//   three statistics nodes (R-11) and cell sums for the next mixing step.
+//
+// Layout: structure of arrays, one lane per particle, tiles of 256 particles
+// that never straddle two cases. The scatter first reduces runs of equal
+// element inside each wavefront (segmented shuffle reduction; particles are
+// kept sorted by element so runs are long) and only the run head issues the
+// FP64 atomic adds, so a node sees a few atomics per wavefront instead of one
+// per particle. Arithmetic of the FP64 instantiation follows the operation
+// order of the readings exactly (no contraction; explicit fma only where the
+// readings put one), so that it reproduces the CPU oracle bit for bit.
+#include "pdfmc_dev.h"
+#include "pdfmc_math.h"
+
+namespace pdfmc {
+
+template <typename R> __device__ inline R rfma(R a, R b, R c);
+template <> __device__ inline double rfma<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <> __device__ inline float rfma<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <typename R> __device__ inline R rsqrt_cr(R a);
+template <> __device__ inline double rsqrt_cr<double>(double a) { return __builtin_sqrt(a); }
+template <> __device__ inline float rsqrt_cr<float>(float a) { return __builtin_sqrtf(a); }
+
+__device__ inline int pick(const int4& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+// R-05: lambda_k = fma(c_k, dy, fma(b_k, dx, delta_k1)), dx = x - x1, dy = y - y1
+template <typename R>
+__device__ inline void bary(const R* __restrict__ rec, int e, R x, R y, R lam[3])
+{
+    const R* r = rec + 8 * (int64_t)e;
+    R dx = x - r[0], dy = y - r[1];
+    lam[0] = rfma<R>(r[5], dy, rfma<R>(r[2], dx, R(1)));
+    lam[1] = rfma<R>(r[6], dy, rfma<R>(r[3], dx, R(0)));
+    lam[2] = rfma<R>(r[7], dy, rfma<R>(r[4], dx, R(0)));
+}
+
+struct WalkCount { int refl, per, steps, fallback; };
+
+// R-12..R-15 walk; returns the element holding (x, y) and its lambda.
+template <typename R>
+__device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R u3[3], R lam[3], WalkCount& wc)
+{
+    int nrefl = 0;
+    for (int it = 0; it < 1024; ++it) {
+        bary<R>(M.rec, e, x, y, lam);
+        int k = 0;
+        if (lam[1] < lam[k]) k = 1;
+        if (lam[2] < lam[k]) k = 2;
+        if (lam[k] >= R(0)) return e;
+        wc.steps++;
+        int nb = pick(M.nbr[e], k);
+        if (nb >= 0) { e = nb; continue; }
+        const BcDev& bc = M.bc[-1 - nb];
+        if (bc.type == 1) {
+            if constexpr (sizeof(R) == 8) { x = x + bc.shift[0]; y = y + bc.shift[1]; }
+            else { x = x + bc.shiftf[0]; y = y + bc.shiftf[1]; }
+            e = pick(M.partner[e], k);
+            wc.per++;
+            continue;
+        }
+        if (nrefl == 8) break;
+        const R* v = M.exy + 6 * (int64_t)e;
+        int ka = (k + 1) % 3, kb = (k + 2) % 3;
+        R xa = v[2 * ka], ya = v[2 * ka + 1];
+        R ex = v[2 * kb] - xa, ey = v[2 * kb + 1] - ya;
+        R L = rsqrt_cr<R>(ex * ex + ey * ey);
+        R nx = ey / L, ny = -ex / L;
+        R d = (x - xa) * nx + (y - ya) * ny;
+        x = x - (R(2) * d) * nx;
+        y = y - (R(2) * d) * ny;
+        for (int i = 0; i < 3; ++i) {
+            R uw;
+            if constexpr (sizeof(R) == 8) uw = bc.uw[i]; else uw = bc.uwf[i];
+            u3[i] = R(2) * uw - u3[i];
+        }
+        nrefl++;
+        wc.refl++;
+    }
+    // R-13 fallback: lowest-index containing element, else the one maximising min lambda
+    wc.fallback++;
+    int best = -1;
+    R bestv = R(0);
+    for (int q = C.eoff; q < C.eoff + C.ne; ++q) {
+        R l[3];
+        bary<R>(M.rec, q, x, y, l);
+        R mn = l[0];
+        if (l[1] < mn) mn = l[1];
+        if (l[2] < mn) mn = l[2];
+        if (mn >= R(0)) { best = q; break; }
+        if (best < 0 || mn > bestv) { best = q; bestv = mn; }
+    }
+    bary<R>(M.rec, best, x, y, lam);
+    return best;
+}
+
+// ---------------------------------------------------------------- wave helpers
+
+struct Runs {
+    bool head;
+    unsigned long long same;   // bit j set: lane + 2^j is in the same run
+};
+
+__device__ inline Runs make_runs(int key)
+{
+    const int lane = __lane_id();
+    int prev = __shfl_up(key, 1);
+    bool head = (lane == 0) || (prev != key);
+    unsigned long long hm = __ballot(head);
+    int rid = __popcll(hm & (~0ull >> (63 - lane)));
+    Runs r;
+    r.head = head;
+    r.same = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        int d = 1 << j;
+        int o = __shfl_down(rid, d);
+        if (lane + d < 64 && o == rid) r.same |= (1ull << j);
+    }
+    return r;
+}
+
+// sum over the lane's run, valid in the run head
+__device__ inline double run_sum(double v, const Runs& r)
+{
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double t = __shfl_down(v, 1 << j);
+        if (r.same & (1ull << j)) v += t;
+    }
+    return v;
+}
+
+__device__ inline int wave_sum_int(int v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+// ---------------------------------------------------------------- the kernel
+
+template <typename R>
+__device__ inline void load_field_row(const R* __restrict__ F, int stride, int s, R* out)
+{
+    const R* row = F + (int64_t)s * stride;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) out[q] = row[q];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int tile = (int)(gid / TILE);
+    if (tile >= A.ntiles) return;                      // whole wavefronts exit together
+    const int c = A.tile_case[tile];
+    const CaseDev& C = A.cases[c];
+    const int64_t i = gid - C.poff;
+    const bool valid = (i >= 0) && (i < C.np);
+    const int64_t p = gid;
+    const int ns = C.ns;
+    const uint32_t step = *A.step;
+
+    int e = -1;
+    R x = R(0), y = R(0), wt = R(0), om = R(0);
+    R u3[3] = {R(0), R(0), R(0)};
+    R psi[MAXS] = {R(0), R(0), R(0), R(0)};
+    R lam[3] = {R(0), R(0), R(0)};
+    int4 sn = make_int4(0, 0, 0, 0);
+    int bin = 0;
+    WalkCount wc = {0, 0, 0, 0};
+    int flips = 0, nans = 0;
+
+    if (valid) {
+        e = A.P.elem[p];
+        x = A.P.x[p]; y = A.P.y[p];
+        u3[0] = A.P.u[p]; u3[1] = A.P.v[p]; u3[2] = A.P.w[p];
+        om = A.P.om[p]; wt = A.P.wt[p];
+        for (int a = 0; a < ns; ++a) psi[a] = A.P.psi[C.psioff + (int64_t)a * C.cap + i];
+        bary<R>(A.M.rec, e, x, y, lam);
+        sn = A.M.tri_s[e];
+        if (A.advance) {
+            R f[NF];
+            {
+                R F0[NF], F1[NF], F2[NF];
+                load_field_row<R>(A.F, A.fstride, sn.x, F0);
+                load_field_row<R>(A.F, A.fstride, sn.y, F1);
+                load_field_row<R>(A.F, A.fstride, sn.z, F2);
+#pragma unroll
+                for (int q = 0; q < NF; ++q) f[q] = rfma<R>(lam[2], F2[q], rfma<R>(lam[1], F1[q], lam[0] * F0[q]));
+                // Eq.(9) IECM with the cell means of this state (R-23, R-24)
+                if (ns > 0) {
+                    R om_e = ((F0[F_OMEGA] + F1[F_OMEGA]) + F2[F_OMEGA]) / R(3);
+                    R hphi, dt;
+                    if constexpr (sizeof(R) == 8) { hphi = C.hphi; dt = C.dt; } else { hphi = C.fhphi; dt = C.fdt; }
+                    R fm = dt * (hphi * om_e);
+                    if (fm > R(1)) fm = R(1);
+                    const int b = A.P.bin[p];
+                    const R* cm = A.cmean + C.cmoff + ((int64_t)(e - C.eoff) * 8 + b) * ns;
+                    for (int a = 0; a < ns; ++a) psi[a] = psi[a] - fm * (psi[a] - cm[a]);
+                }
+            }
+            R xi[6];
+            if constexpr (sizeof(R) == 8) gauss6_f64(C.seed_lo, C.seed_hi, A.P.id[p], step, C.stream, xi);
+            else gauss6_f32(C.seed_lo, C.seed_hi, A.P.id[p], step, C.stream, xi);
+            R dt, tnu, sq_nu, C3, c34;
+            if constexpr (sizeof(R) == 8) { dt = C.dt; tnu = C.tnu; sq_nu = C.sq_nu; C3 = C.C3; c34 = C.c34; }
+            else { dt = C.fdt; tnu = C.ftnu; sq_nu = C.fsq_nu; C3 = C.fC3; c34 = C.fc34; }
+            // Eq.(4), generalized Langevin model; same dW_j as Eq.(2) (R-01)
+            const R u = u3[0], v = u3[1], w = u3[2];
+            const R d1 = u - f[F_U1], d2 = v - f[F_U2], d3 = w - f[F_U3];
+            const R c0e = f[F_C0EPS] > R(0) ? f[F_C0EPS] : R(0);
+            const R sq_c0 = rsqrt_cr<R>(c0e * dt);
+            R du = dt * ((-f[F_DPX] + tnu * f[F_LAP1]) + (f[F_G11] * d1 + f[F_G12] * d2))
+                 + sq_nu * (f[F_DU1X] * xi[0] + f[F_DU1Y] * xi[1]) + sq_c0 * xi[2];
+            R dv = dt * ((-f[F_DPY] + tnu * f[F_LAP2]) + (f[F_G21] * d1 + f[F_G22] * d2))
+                 + sq_nu * (f[F_DU2X] * xi[0] + f[F_DU2Y] * xi[1]) + sq_c0 * xi[3];
+            R dw = dt * (tnu * f[F_LAP3] + f[F_G33] * d3)
+                 + sq_nu * (f[F_DU3X] * xi[0] + f[F_DU3Y] * xi[1]) + sq_c0 * xi[4];
+            // Eq.(2): X^{n+1} = X^n + U^n dt + (2 nu)^{1/2} dW
+            x = (x + u * dt) + sq_nu * xi[0];
+            y = (y + v * dt) + sq_nu * xi[1];
+            u3[0] = u + du; u3[1] = v + dv; u3[2] = w + dw;
+            // Eq.(5) with S_omega of Eq.(6) (R-17, R-21)
+            const R W = f[F_OMEGA], S = f[F_SOMEGA];
+            const R drift = ((-C3 * W) * (om - W)) - ((S * W) * om);
+            const R omp = om > R(0) ? om : R(0);
+            const R diff = rsqrt_cr<R>(((c34 * (W * W)) * omp) * dt);
+            R omn = (om + dt * drift) + diff * xi[5];
+            if (omn < R(0)) { omn = -omn; flips = 1; }
+            om = omn;
+            // tracking (R-12..R-15)
+            if (__builtin_isfinite(x) && __builtin_isfinite(y)) {
+                e = walk<R>(A.M, C, e, x, y, u3, lam, wc);
+            } else {
+                nans = 1;
+            }
+            // concentrated sources (R-26)
+            for (int a = 0; a < ns; ++a) {
+                R r, cx, cy, val;
+                if constexpr (sizeof(R) == 8) { r = C.src[a][2]; cx = C.src[a][0]; cy = C.src[a][1]; val = C.src[a][3]; }
+                else { r = C.srcf[a][2]; cx = C.srcf[a][0]; cy = C.srcf[a][1]; val = C.srcf[a][3]; }
+                if (r > R(0)) {
+                    R dx = x - cx, dy = y - cy;
+                    if (dx * dx + dy * dy < r * r) psi[a] = val;
+                }
+            }
+            A.P.x[p] = x; A.P.y[p] = y;
+            A.P.u[p] = u3[0]; A.P.v[p] = u3[1]; A.P.w[p] = u3[2];
+            A.P.om[p] = om; A.P.elem[p] = e;
+            for (int a = 0; a < ns; ++a) A.P.psi[C.psioff + (int64_t)a * C.cap + i] = psi[a];
+            sn = A.M.tri_s[e];
+        }
+        // R-23 bin: octant of U - <U>(X) with <U> from the fields of this step
+        if (A.do_bins && C.nbins == 8) {
+            const R* F0 = A.F + (int64_t)sn.x * A.fstride;
+            const R* F1 = A.F + (int64_t)sn.y * A.fstride;
+            const R* F2 = A.F + (int64_t)sn.z * A.fstride;
+            for (int q = 0; q < 3; ++q) {
+                R m = rfma<R>(lam[2], F2[q], rfma<R>(lam[1], F1[q], lam[0] * F0[q]));
+                if (u3[q] - m >= R(0)) bin += (1 << q);
+            }
+        }
+        if (A.do_bins) A.P.bin[p] = (uint8_t)bin;
+    }
+
+    // ---- shape-weighted node sums of the (new) state (R-11), FP64
+    {
+        const int key = valid ? e : -1;
+        const Runs r = make_runs(key);
+        const double w = (double)wt;
+        const double Q[3] = {(double)u3[0], (double)u3[1], (double)u3[2]};
+        const double dom = (double)om;
+        const int s3[3] = {sn.x, sn.y, sn.z};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double wn = valid ? w * (double)lam[k] : 0.0;
+            double* dst = A.nsum + (int64_t)s3[k] * NQ;
+            double val[11];
+            val[0] = wn;
+            val[1] = wn * Q[0]; val[2] = wn * Q[1]; val[3] = wn * Q[2];
+            val[4] = wn * Q[0] * Q[0]; val[5] = wn * Q[1] * Q[1]; val[6] = wn * Q[2] * Q[2];
+            val[7] = wn * Q[0] * Q[1]; val[8] = wn * Q[0] * Q[2]; val[9] = wn * Q[1] * Q[2];
+            val[10] = wn * dom;
+#pragma unroll
+            for (int q = 0; q < 11; ++q) {
+                double s = run_sum(val[q], r);
+                if (r.head && key >= 0) unsafeAtomicAdd(dst + q, s);
+            }
+            for (int a = 0; a < ns; ++a) {
+                double ps = (double)psi[a];
+                double s1 = run_sum(wn * ps, r);
+                double s2 = run_sum(wn * ps * ps, r);
+                if (r.head && key >= 0) {
+                    unsafeAtomicAdd(dst + 11 + a, s1);
+                    unsafeAtomicAdd(dst + 11 + ns + a, s2);
+                }
+            }
+        }
+    }
+    // ---- cell sums for the next mixing step (R-23)
+    if (A.do_bins && ns > 0) {
+        const int key = valid ? e * 8 + bin : -1;
+        const Runs r = make_runs(key);
+        double cnt = run_sum(valid ? 1.0 : 0.0, r);
+        double sw = run_sum(valid ? (double)wt : 0.0, r);
+        double swp[MAXS];
+        for (int a = 0; a < ns; ++a) swp[a] = run_sum(valid ? (double)wt * (double)psi[a] : 0.0, r);
+        if (r.head && key >= 0) {
+            atomicAdd(A.ccnt + key, (int)cnt);
+            double* dst = A.csum + C.csoff + ((int64_t)(e - C.eoff) * 8 + bin) * (1 + ns);
+            unsafeAtomicAdd(dst, sw);
+            for (int a = 0; a < ns; ++a) unsafeAtomicAdd(dst + 1 + a, swp[a]);
+        }
+    }
+    // ---- counters, one atomic per wavefront
+    {
+        int v0 = wave_sum_int(wc.fallback), v1 = wave_sum_int(wc.refl), v2 = wave_sum_int(wc.per);
+        int v3 = wave_sum_int(flips), v5 = wave_sum_int(nans), v6 = wave_sum_int(wc.steps);
+        if (__lane_id() == 0) {
+            unsigned long long* cc = A.counters + (int64_t)c * NCNT;
+            if (v0) atomicAdd(cc + C_WALK_FALLBACK, (unsigned long long)v0);
+            if (v1) atomicAdd(cc + C_REFLECT, (unsigned long long)v1);
+            if (v2) atomicAdd(cc + C_PERIODIC, (unsigned long long)v2);
+            if (v3) atomicAdd(cc + C_OMEGA_FLIP, (unsigned long long)v3);
+            if (v5) atomicAdd(cc + C_NAN, (unsigned long long)v5);
+            if (v6) atomicAdd(cc + C_WALK_STEPS, (unsigned long long)v6);
+        }
+    }
+}
+
+template __global__ void k_particle_step<double>(StepArgs<double>);
+template __global__ void k_particle_step<float>(StepArgs<float>);
+
+// Device draws of the Wiener increments (test hook of R-09/R-10).
+template <typename R>
+__global__ void k_draw_gaussians(uint32_t slo, uint32_t shi, uint32_t step, uint32_t stream,
+                                 const uint32_t* __restrict__ ids, int64_t n, R* __restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    R xi[6];
+    if constexpr (sizeof(R) == 8) gauss6_f64(slo, shi, ids[i], step, stream, xi);
+    else gauss6_f32(slo, shi, ids[i], step, stream, xi);
+    for (int j = 0; j < 6; ++j) out[6 * i + j] = xi[j];
+}
+template __global__ void k_draw_gaussians<double>(uint32_t, uint32_t, uint32_t, uint32_t, const uint32_t*, int64_t, double*);
+template __global__ void k_draw_gaussians<float>(uint32_t, uint32_t, uint32_t, uint32_t, const uint32_t*, int64_t, float*);
+
+}  // namespace pdfmc

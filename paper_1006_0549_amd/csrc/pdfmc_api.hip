@@ -1,0 +1,968 @@
+// C ABI of the particle-advance library: contexts, cases, the caller-owned
+// device workspace, uploads/readbacks and the step sequence.
+//
+// One step (reading R-08), every case in each launch:
+//   clear accumulators -> particle kernel (advance + statistics + cell sums)
+//   -> node statistics -> cell means -> recovered gradients -> derived fields
+//   -> [elliptic relaxation: assemble, 5 CG solves, G_ij/C0 eps]
+//   -> [projection: right-hand side, CG, <P> update, recovered grad <P>]
+//   -> FP32 mirror of the fields -> step index + 1.
+// The sequence can be captured once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pdfmc.h"
+#include "pdfmc_kernels.h"
+#include "pdfmc_mesh.h"
+
+using namespace pdfmc;
+
+namespace {
+
+struct Case {
+    pdfmc_case_params p{};
+    MeshHost m;
+    int64_t cap = 0, np = 0;
+    int64_t poff = 0, psioff = 0, cmoff = 0, csoff = 0, nnz_off = 0, inc_off = 0;
+    int eoff = 0, noff = 0, bcoff = 0;
+};
+
+struct PartBufs {
+    char *x, *y, *u, *v, *w, *om, *wt, *psi;   // Real arrays (FP64 or FP32)
+    int32_t* elem;
+    uint32_t* id;
+    uint8_t* bin;
+};
+
+}  // namespace
+
+struct pdfmc_ctx {
+    int prec = PDFMC_FP64;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<Case> cases;
+    // totals
+    int64_t NP = 0, PSI = 0, CM = 0, CS = 0;
+    int NE = 0, NN = 0, NBC = 0, NNZ = 0, ntiles = 0;
+    // workspace
+    bool bound = false, initialised = false;
+    char* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    // device arrays
+    CaseDev* d_cases = nullptr;
+    int32_t *d_tile_case = nullptr, *d_node_case = nullptr, *d_elem_case = nullptr;
+    char* d_rec = nullptr;          // Real records for the particle kernel
+    double* d_rec64 = nullptr;      // FP64 records for the node kernels
+    char* d_exy = nullptr;
+    int4 *d_tri_s = nullptr, *d_nbr = nullptr, *d_partner = nullptr;
+    BcDev* d_bc = nullptr;
+    double *d_area = nullptr, *d_vol = nullptr, *d_wnx = nullptr, *d_wny = nullptr;
+    int32_t *d_inc_ptr = nullptr, *d_inc = nullptr, *d_incpos = nullptr, *d_csr_ptr = nullptr, *d_csr_col = nullptr,
+            *d_is_wall = nullptr;
+    PartBufs part[2]{};
+    int cur = 0;
+    double *d_F = nullptr, *d_nsum = nullptr, *d_stats = nullptr, *d_csum = nullptr;
+    float* d_F32 = nullptr;
+    char* d_cmean = nullptr;
+    int32_t* d_ccnt = nullptr;
+    double *d_kf = nullptr, *d_ef = nullptr, *d_L2 = nullptr, *d_er_r = nullptr, *d_er_dval = nullptr, *d_er_b = nullptr,
+           *d_er_x = nullptr, *d_er_val = nullptr, *d_pk_val = nullptr, *d_pb = nullptr, *d_phi = nullptr, *d_P = nullptr;
+    double* d_cg = nullptr;         // CG scratch: (5 + 1) systems x 4 vectors x NN
+    CgJob* d_jobs_er = nullptr;
+    CgJob* d_jobs_p = nullptr;
+    int n_jobs_er = 0, n_jobs_p = 0;
+    unsigned long long* d_counters = nullptr;
+    uint32_t* d_step = nullptr;
+    int32_t* d_sort_count = nullptr;
+    int64_t *d_sort_scan = nullptr, *d_sort_cursor = nullptr;
+    // options
+    int sort_interval = 0, block = 256, use_graph = 0;
+    int steps_since_sort = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool any_er = false, any_eul = false, any_scalars = false;
+};
+
+namespace {
+
+pdfmc_status fail(pdfmc_ctx* c, pdfmc_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(ctx, PDFMC_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+#define LAUNCHCHK(ctx)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = hipGetLastError();                                                     \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(ctx, PDFMC_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t rsz(const pdfmc_ctx* c) { return c->prec == PDFMC_FP32 ? 4 : 8; }
+
+struct Carver {
+    char* base;
+    uint64_t off = 0;
+    bool assign;
+    template <typename T>
+    void take(T*& ptr, size_t count, size_t elsize = sizeof(T))
+    {
+        off = (off + 255) & ~uint64_t(255);
+        if (assign) ptr = reinterpret_cast<T*>(base + off);
+        off += std::max<size_t>(count, 1) * elsize;
+    }
+};
+
+void carve(pdfmc_ctx* c, Carver& k)
+{
+    const size_t R = rsz(c);
+    const int64_t NP = c->NP;
+    k.take(c->d_cases, c->cases.size());
+    k.take(c->d_tile_case, c->ntiles);
+    k.take(c->d_node_case, c->NN);
+    k.take(c->d_elem_case, c->NE);
+    k.take(c->d_rec, 8 * (size_t)c->NE, R);
+    k.take(c->d_rec64, 8 * (size_t)c->NE);
+    k.take(c->d_exy, 6 * (size_t)c->NE, R);
+    k.take(c->d_tri_s, c->NE);
+    k.take(c->d_nbr, c->NE);
+    k.take(c->d_partner, c->NE);
+    k.take(c->d_bc, c->NBC);
+    k.take(c->d_area, c->NE);
+    k.take(c->d_vol, c->NN);
+    k.take(c->d_wnx, c->NN);
+    k.take(c->d_wny, c->NN);
+    k.take(c->d_inc_ptr, c->NN + 1);
+    k.take(c->d_inc, 3 * (size_t)c->NE);
+    k.take(c->d_incpos, 9 * (size_t)c->NE);
+    k.take(c->d_csr_ptr, c->NN + 1);
+    k.take(c->d_csr_col, c->NNZ);
+    k.take(c->d_is_wall, c->NN);
+    for (int b = 0; b < 2; ++b) {
+        PartBufs& P = c->part[b];
+        k.take(P.x, NP, R); k.take(P.y, NP, R); k.take(P.u, NP, R); k.take(P.v, NP, R);
+        k.take(P.w, NP, R); k.take(P.om, NP, R); k.take(P.wt, NP, R);
+        k.take(P.psi, c->PSI, R);
+        k.take(P.elem, NP); k.take(P.id, NP); k.take(P.bin, NP);
+    }
+    k.take(c->d_F, (size_t)c->NN * NF);
+    if (c->prec == PDFMC_FP32) k.take(c->d_F32, (size_t)c->NN * NF32);
+    k.take(c->d_nsum, (size_t)c->NN * NQ);
+    k.take(c->d_stats, (size_t)c->NN * NST);
+    k.take(c->d_csum, c->CS);
+    k.take(c->d_cmean, c->CM, R);
+    k.take(c->d_ccnt, 8 * (size_t)c->NE);
+    k.take(c->d_kf, c->NN); k.take(c->d_ef, c->NN); k.take(c->d_L2, c->NN);
+    k.take(c->d_er_r, (size_t)NER * c->NN); k.take(c->d_er_dval, (size_t)NER * c->NN);
+    k.take(c->d_er_b, (size_t)NER * c->NN); k.take(c->d_er_x, (size_t)NER * c->NN);
+    k.take(c->d_er_val, c->NNZ); k.take(c->d_pk_val, c->NNZ);
+    k.take(c->d_pb, c->NN); k.take(c->d_phi, c->NN); k.take(c->d_P, c->NN);
+    k.take(c->d_cg, (size_t)(NER + 1) * 4 * c->NN);
+    k.take(c->d_jobs_er, NER * c->cases.size());
+    k.take(c->d_jobs_p, c->cases.size());
+    k.take(c->d_counters, NCNT * c->cases.size());
+    k.take(c->d_step, 1);
+    k.take(c->d_sort_count, c->NE);
+    k.take(c->d_sort_scan, c->NE);
+    k.take(c->d_sort_cursor, c->NE);
+}
+
+void compute_offsets(pdfmc_ctx* c)
+{
+    int64_t NP = 0, PSI = 0, CM = 0, CS = 0, NNZ = 0;
+    int NE = 0, NN = 0, NBC = 0;
+    for (auto& cs : c->cases) {
+        cs.poff = NP;
+        NP += (cs.cap + TILE - 1) / TILE * TILE;
+        cs.psioff = PSI; PSI += (int64_t)cs.p.n_scalars * cs.cap;
+        cs.cmoff = CM; CM += (int64_t)cs.m.ne * 8 * cs.p.n_scalars;
+        cs.csoff = CS; CS += (int64_t)cs.m.ne * 8 * (1 + cs.p.n_scalars);
+        cs.eoff = NE; NE += cs.m.ne;
+        cs.noff = NN; NN += cs.m.nsn;
+        cs.bcoff = NBC; NBC += (int)cs.m.bc.size();
+        cs.nnz_off = NNZ; NNZ += (int64_t)cs.m.csr_col.size();
+        cs.inc_off = 3 * (int64_t)cs.eoff;
+    }
+    c->NP = NP; c->PSI = PSI; c->CM = CM; c->CS = CS; c->NE = NE; c->NN = NN; c->NBC = NBC; c->NNZ = (int)NNZ;
+    c->ntiles = (int)(NP / TILE);
+}
+
+CaseDev make_case_dev(const pdfmc_ctx* c, const Case& cs)
+{
+    CaseDev d{};
+    const pdfmc_case_params& p = cs.p;
+    d.poff = cs.poff; d.np = cs.np; d.psioff = cs.psioff; d.cap = cs.cap; d.cmoff = cs.cmoff; d.csoff = cs.csoff;
+    d.eoff = cs.eoff; d.ne = cs.m.ne; d.noff = cs.noff; d.nsn = cs.m.nsn; d.bcoff = cs.bcoff; d.nbc = (int)cs.m.bc.size();
+    d.ns = p.n_scalars; d.nbins = p.n_bins; d.nmin = p.n_min; d.mode = p.mode;
+    d.seed_lo = (uint32_t)p.seed; d.seed_hi = (uint32_t)(p.seed >> 32); d.stream = p.stream;
+    d.csr_row0 = cs.noff; d.nnz_off = cs.nnz_off; d.nnz = (int64_t)cs.m.csr_col.size(); d.inc_off = cs.inc_off;
+    // the same expressions as the step contract: 2 nu, sqrt(2 nu dt), 2 C3 C4, Cphi/2
+    d.dt = p.dt; d.tnu = 2.0 * p.nu; d.sq_nu = std::sqrt(d.tnu * p.dt); d.C3 = p.C3;
+    d.c34 = 2.0 * p.C3 * p.C4; d.hphi = 0.5 * p.Cphi;
+    d.fdt = (float)d.dt; d.ftnu = (float)d.tnu; d.fsq_nu = (float)d.sq_nu; d.fC3 = (float)d.C3;
+    d.fc34 = (float)d.c34; d.fhphi = (float)d.hphi;
+    for (int a = 0; a < MAXS; ++a)
+        for (int j = 0; j < 4; ++j) { d.src[a][j] = p.src[a][j]; d.srcf[a][j] = (float)p.src[a][j]; }
+    d.nu = p.nu; d.C0 = p.C0; d.Cw1 = p.Cw1; d.Cw2 = p.Cw2; d.C1 = p.C1; d.C2 = p.C2; d.gamma5 = p.gamma5;
+    d.Cv = p.Cv; d.CL = p.CL; d.Ceta = p.Ceta; d.nu34 = std::sqrt(p.nu * std::sqrt(p.nu));
+    d.k_floor = p.k_floor; d.eps_floor = p.eps_floor; d.dpdx[0] = p.dpdx[0]; d.dpdx[1] = p.dpdx[1];
+    d.cg_rtol = p.cg_rtol; d.cg_maxit = p.cg_maxit;
+    (void)c;
+    return d;
+}
+
+template <typename T>
+pdfmc_status h2d(pdfmc_ctx* c, T* dst, const std::vector<T>& src)
+{
+    if (src.empty()) return PDFMC_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return PDFMC_OK;
+}
+
+#define TRY(x) do { pdfmc_status s_ = (x); if (s_ != PDFMC_OK) return s_; } while (0)
+
+NodeArgs node_args(pdfmc_ctx* c)
+{
+    NodeArgs A{};
+    A.nn = c->NN; A.ne = c->NE; A.cases = c->d_cases; A.node_case = c->d_node_case; A.elem_case = c->d_elem_case;
+    A.rec = c->d_rec64; A.area = c->d_area; A.vol = c->d_vol; A.tri_s = c->d_tri_s;
+    A.inc_ptr = c->d_inc_ptr; A.inc = c->d_inc; A.incpos = c->d_incpos; A.csr_ptr = c->d_csr_ptr; A.csr_col = c->d_csr_col;
+    A.is_wall = c->d_is_wall; A.wnx = c->d_wnx; A.wny = c->d_wny;
+    A.nsum = c->d_nsum; A.stats = c->d_stats; A.F = c->d_F; A.csum = c->d_csum; A.ccnt = c->d_ccnt;
+    A.kf = c->d_kf; A.ef = c->d_ef; A.L2 = c->d_L2; A.er_r = c->d_er_r; A.er_dval = c->d_er_dval; A.er_b = c->d_er_b;
+    A.er_x = c->d_er_x; A.er_val = c->d_er_val; A.pk_val = c->d_pk_val; A.pb = c->d_pb; A.phi = c->d_phi; A.P = c->d_P;
+    A.counters = c->d_counters;
+    return A;
+}
+
+template <typename R>
+StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins)
+{
+    StepArgs<R> A{};
+    PartBufs& B = c->part[c->cur];
+    A.P = Particles<R>{(R*)B.x, (R*)B.y, (R*)B.u, (R*)B.v, (R*)B.w, (R*)B.om, (R*)B.wt, (R*)B.psi, B.elem, B.id, B.bin};
+    A.M = MeshDev<R>{(const R*)c->d_rec, c->d_tri_s, c->d_nbr, c->d_partner, (const R*)c->d_exy, c->d_bc};
+    A.cases = c->d_cases;
+    A.tile_case = c->d_tile_case;
+    if constexpr (sizeof(R) == 8) { A.F = (const R*)c->d_F; A.fstride = NF; }
+    else { A.F = (const R*)c->d_F32; A.fstride = NF32; }
+    A.cmean = (const R*)c->d_cmean;
+    A.nsum = c->d_nsum; A.csum = c->d_csum; A.ccnt = c->d_ccnt; A.counters = c->d_counters; A.step = c->d_step;
+    A.ntiles = c->ntiles; A.advance = advance; A.do_bins = do_bins;
+    return A;
+}
+
+unsigned nblk(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+pdfmc_status enqueue_fill(pdfmc_ctx* c, double* p, int64_t n)
+{
+    if (n <= 0) return PDFMC_OK;
+    hipLaunchKernelGGL(k_fill_f64, dim3(std::min<int64_t>(nblk(n, 256), 4096)), dim3(256), 0, c->stream, p, n, 0.0);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
+pdfmc_status enqueue_fill_i(pdfmc_ctx* c, int32_t* p, int64_t n)
+{
+    if (n <= 0) return PDFMC_OK;
+    hipLaunchKernelGGL(k_fill_i32, dim3(std::min<int64_t>(nblk(n, 256), 4096)), dim3(256), 0, c->stream, p, n, 0);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
+pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins)
+{
+    if (c->ntiles == 0) return PDFMC_OK;
+    const int64_t threads = (int64_t)c->ntiles * TILE;
+    const int b = c->block;
+    if (c->prec == PDFMC_FP64)
+        hipLaunchKernelGGL(k_particle_step<double>, dim3(nblk(threads, b)), dim3(b), 0, c->stream,
+                           step_args<double>(c, advance, do_bins));
+    else
+        hipLaunchKernelGGL(k_particle_step<float>, dim3(nblk(threads, b)), dim3(b), 0, c->stream,
+                           step_args<float>(c, advance, do_bins));
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
+pdfmc_status enqueue_accum_clear(pdfmc_ctx* c, bool cells)
+{
+    TRY(enqueue_fill(c, c->d_nsum, (int64_t)c->NN * NQ));
+    if (cells && c->any_scalars) {
+        TRY(enqueue_fill(c, c->d_csum, c->CS));
+        TRY(enqueue_fill_i(c, c->d_ccnt, 8 * (int64_t)c->NE));
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status enqueue_cell_means(pdfmc_ctx* c)
+{
+    if (!c->any_scalars) return PDFMC_OK;
+    NodeArgs A = node_args(c);
+    if (c->prec == PDFMC_FP64)
+        hipLaunchKernelGGL(k_cell_means<double>, dim3(nblk(c->NE, 256)), dim3(256), 0, c->stream, A, (double*)c->d_cmean);
+    else
+        hipLaunchKernelGGL(k_cell_means<float>, dim3(nblk(c->NE, 256)), dim3(256), 0, c->stream, A, (float*)c->d_cmean);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
+pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
+{
+    NodeArgs A = node_args(c);
+    const dim3 g(nblk(c->NN, 256)), b(256);
+    if (c->any_eul) {
+        hipLaunchKernelGGL(k_fields_grad, g, b, 0, c->stream, A);
+        hipLaunchKernelGGL(k_fields_derived, g, b, 0, c->stream, A);
+        LAUNCHCHK(c);
+    }
+    if (c->any_er) {
+        hipLaunchKernelGGL(k_er_assemble, g, b, 0, c->stream, A);
+        hipLaunchKernelGGL(k_cg, dim3(c->n_jobs_er), dim3(1024), 0, c->stream, c->d_jobs_er);
+        hipLaunchKernelGGL(k_er_finish, g, b, 0, c->stream, A);
+        LAUNCHCHK(c);
+        if (project) {
+            hipLaunchKernelGGL(k_proj_rhs, g, b, 0, c->stream, A);
+            hipLaunchKernelGGL(k_cg, dim3(c->n_jobs_p), dim3(1024), 0, c->stream, c->d_jobs_p);
+            hipLaunchKernelGGL(k_proj_update, g, b, 0, c->stream, A);
+            LAUNCHCHK(c);
+        }
+        hipLaunchKernelGGL(k_proj_grad, g, b, 0, c->stream, A);
+        LAUNCHCHK(c);
+    }
+    if (c->prec == PDFMC_FP32) {
+        hipLaunchKernelGGL(k_mirror_f32, dim3(nblk((int64_t)c->NN * NF32, 256)), dim3(256), 0, c->stream,
+                           (const double*)c->d_F, c->d_F32, c->NN);
+        LAUNCHCHK(c);
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status enqueue_step_body(pdfmc_ctx* c)
+{
+    TRY(enqueue_accum_clear(c, true));
+    TRY(enqueue_particles(c, 1, 1));
+    hipLaunchKernelGGL(k_node_stats, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, node_args(c));
+    LAUNCHCHK(c);
+    TRY(enqueue_cell_means(c));
+    TRY(enqueue_fields(c, true));
+    hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, c->stream, c->d_step);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
+pdfmc_status enqueue_sort(pdfmc_ctx* c)
+{
+    if (c->ntiles == 0) return PDFMC_OK;
+    SortArgs S{};
+    S.cases = c->d_cases; S.tile_case = c->d_tile_case; S.elem_case = c->d_elem_case;
+    S.ntiles = c->ntiles; S.ne = c->NE; S.elem = c->part[c->cur].elem;
+    S.count = c->d_sort_count; S.scan = c->d_sort_scan; S.cursor = c->d_sort_cursor;
+    TRY(enqueue_fill_i(c, c->d_sort_count, c->NE));
+    const int64_t threads = (int64_t)c->ntiles * TILE;
+    hipLaunchKernelGGL(k_sort_hist, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, c->stream, S);
+    LAUNCHCHK(c);
+    PartBufs& A = c->part[c->cur];
+    PartBufs& B = c->part[1 - c->cur];
+    if (c->prec == PDFMC_FP64) {
+        Particles<double> src{(double*)A.x, (double*)A.y, (double*)A.u, (double*)A.v, (double*)A.w, (double*)A.om,
+                              (double*)A.wt, (double*)A.psi, A.elem, A.id, A.bin};
+        Particles<double> dst{(double*)B.x, (double*)B.y, (double*)B.u, (double*)B.v, (double*)B.w, (double*)B.om,
+                              (double*)B.wt, (double*)B.psi, B.elem, B.id, B.bin};
+        hipLaunchKernelGGL(k_sort_scatter<double>, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S, src, dst);
+    } else {
+        Particles<float> src{(float*)A.x, (float*)A.y, (float*)A.u, (float*)A.v, (float*)A.w, (float*)A.om,
+                             (float*)A.wt, (float*)A.psi, A.elem, A.id, A.bin};
+        Particles<float> dst{(float*)B.x, (float*)B.y, (float*)B.u, (float*)B.v, (float*)B.w, (float*)B.om,
+                             (float*)B.wt, (float*)B.psi, B.elem, B.id, B.bin};
+        hipLaunchKernelGGL(k_sort_scatter<float>, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S, src, dst);
+    }
+    LAUNCHCHK(c);
+    c->cur = 1 - c->cur;
+    c->steps_since_sort = 0;
+    return PDFMC_OK;
+}
+
+pdfmc_status check_case(pdfmc_ctx* c, int32_t cs)
+{
+    if (!c) return PDFMC_E_INVALID;
+    if (cs < 0 || cs >= (int32_t)c->cases.size()) return fail(c, PDFMC_E_INVALID, "bad case id");
+    return PDFMC_OK;
+}
+
+pdfmc_status check_bound(pdfmc_ctx* c)
+{
+    if (!c->bound) return fail(c, PDFMC_E_STATE, "bind a workspace first");
+    return PDFMC_OK;
+}
+
+void drop_graphs(pdfmc_ctx* c)
+{
+    for (auto& g : c->graph)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
+}  // namespace
+
+// ============================================================== ABI
+
+extern "C" {
+
+pdfmc_status pdfmc_create(pdfmc_ctx** out, int32_t precision, void* hip_stream)
+{
+    if (!out) return PDFMC_E_INVALID;
+    *out = nullptr;
+    if (precision != PDFMC_FP64 && precision != PDFMC_FP32) return PDFMC_E_INVALID;
+    pdfmc_ctx* c = new (std::nothrow) pdfmc_ctx();
+    if (!c) return PDFMC_E_NOMEM;
+    c->prec = precision;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return PDFMC_OK;
+}
+
+void pdfmc_destroy(pdfmc_ctx* c)
+{
+    if (!c) return;
+    if (c->bound) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    delete c;
+}
+
+const char* pdfmc_last_error(const pdfmc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+pdfmc_status pdfmc_add_case(pdfmc_ctx* c, const pdfmc_mesh_desc* mesh, const pdfmc_case_params* p, int64_t capacity,
+                            int32_t* case_id)
+{
+    if (!c) return PDFMC_E_INVALID;
+    if (!mesh || !p || !case_id) return fail(c, PDFMC_E_INVALID, "add_case: null argument");
+    if (c->bound) return fail(c, PDFMC_E_STATE, "add_case: cases must be added before the workspace is bound");
+    if (p->n_scalars < 0 || p->n_scalars > PDFMC_MAX_SCALARS) return fail(c, PDFMC_E_INVALID, "add_case: n_scalars must be 0..4");
+    if (p->n_bins != 1 && p->n_bins != 8) return fail(c, PDFMC_E_INVALID, "add_case: n_bins must be 1 or 8");
+    if (p->mode < 0 || p->mode > 2) return fail(c, PDFMC_E_INVALID, "add_case: mode must be 0, 1 or 2");
+    if (!(p->dt > 0.0) || !(p->nu >= 0.0)) return fail(c, PDFMC_E_INVALID, "add_case: need dt > 0 and nu >= 0");
+    if (capacity < 0 || capacity > ((int64_t)1 << 31)) return fail(c, PDFMC_E_INVALID, "add_case: bad capacity");
+    Case cs;
+    cs.p = *p;
+    cs.cap = capacity;
+    std::string err;
+    int rc = derive_mesh(*mesh, cs.m, err);
+    if (rc != PDFMC_OK) return fail(c, (pdfmc_status)rc, err);
+    c->cases.push_back(std::move(cs));
+    *case_id = (int32_t)c->cases.size() - 1;
+    compute_offsets(c);
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_case_info(pdfmc_ctx* c, int32_t cs, int32_t* n_stat_nodes, int32_t* stat_node)
+{
+    TRY(check_case(c, cs));
+    const Case& k = c->cases[cs];
+    if (n_stat_nodes) *n_stat_nodes = k.m.nsn;
+    if (stat_node) std::copy(k.m.snode.begin(), k.m.snode.end(), stat_node);
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_workspace_query(pdfmc_ctx* c, uint64_t* bytes)
+{
+    if (!c || !bytes) return PDFMC_E_INVALID;
+    Carver k{nullptr, 0, false};
+    carve(c, k);
+    *bytes = k.off + 256;
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
+{
+    if (!c) return PDFMC_E_INVALID;
+    if (!dev) return fail(c, PDFMC_E_INVALID, "workspace_bind: null pointer");
+    if (c->cases.empty()) return fail(c, PDFMC_E_STATE, "workspace_bind: add a case first");
+    uint64_t need = 0;
+    TRY(pdfmc_workspace_query(c, &need));
+    if (bytes < need) return fail(c, PDFMC_E_NOMEM, "workspace_bind: need " + std::to_string(need) + " bytes");
+    char* base = (char*)(((uintptr_t)dev + 255) & ~(uintptr_t)255);
+    Carver k{base, 0, true};
+    carve(c, k);
+    drop_graphs(c);
+    c->ws = (char*)dev; c->ws_bytes = bytes; c->cur = 0;
+    c->any_er = c->any_eul = c->any_scalars = false;
+    for (auto& cs : c->cases) {
+        c->any_er |= cs.p.mode == 2;
+        c->any_eul |= cs.p.mode >= 1;
+        c->any_scalars |= cs.p.n_scalars > 0;
+    }
+    // ---- host staging of the global tables
+    const int NE = c->NE, NN = c->NN;
+    std::vector<CaseDev> cd;
+    std::vector<int32_t> tile_case(c->ntiles), node_case(NN), elem_case(NE);
+    std::vector<double> rec64(8 * (size_t)NE), exy64(6 * (size_t)NE), area(NE), vol(NN), wnx(NN), wny(NN);
+    std::vector<int4> tri_s(NE), nbr(NE), partner(NE);
+    std::vector<BcDev> bc(std::max(c->NBC, 1));
+    std::vector<int32_t> inc_ptr(NN + 1), inc(3 * (size_t)NE), incpos(9 * (size_t)NE), csr_ptr(NN + 1),
+        csr_col(std::max(c->NNZ, 1)), is_wall(NN);
+    int ci = 0;
+    for (auto& cs : c->cases) {
+        const MeshHost& m = cs.m;
+        cd.push_back(make_case_dev(c, cs));
+        for (int64_t t = cs.poff / TILE; t < (cs.poff + (cs.cap + TILE - 1) / TILE * TILE) / TILE; ++t) tile_case[t] = ci;
+        for (int s = 0; s < m.nsn; ++s) {
+            const int g = cs.noff + s;
+            node_case[g] = ci;
+            vol[g] = m.vol[s];
+            wnx[g] = m.wnx[s]; wny[g] = m.wny[s];
+            is_wall[g] = m.is_wall[s];
+            inc_ptr[g] = 3 * cs.eoff + m.inc_ptr[s];
+            csr_ptr[g] = (int32_t)cs.nnz_off + m.csr_ptr[s];
+        }
+        for (int e = 0; e < m.ne; ++e) {
+            const int g = cs.eoff + e;
+            elem_case[g] = ci;
+            std::copy(&m.rec[8 * (size_t)e], &m.rec[8 * (size_t)e + 8], &rec64[8 * (size_t)g]);
+            for (int k = 0; k < 3; ++k) {
+                exy64[6 * (size_t)g + 2 * k] = m.x[m.tri[3 * e + k]];
+                exy64[6 * (size_t)g + 2 * k + 1] = m.y[m.tri[3 * e + k]];
+            }
+            area[g] = m.area[e];
+            tri_s[g] = make_int4(cs.noff + m.tri_s[3 * e], cs.noff + m.tri_s[3 * e + 1], cs.noff + m.tri_s[3 * e + 2], ci);
+            int nb[3], pt[3];
+            for (int k = 0; k < 3; ++k) {
+                const int n = m.nbr[3 * e + k];
+                nb[k] = n >= 0 ? cs.eoff + n : -1 - (cs.bcoff + m.tag[3 * e + k]);
+                pt[k] = m.partner[3 * e + k] >= 0 ? cs.eoff + m.partner[3 * e + k] : -1;
+            }
+            nbr[g] = make_int4(nb[0], nb[1], nb[2], 0);
+            partner[g] = make_int4(pt[0], pt[1], pt[2], 0);
+        }
+        for (size_t j = 0; j < m.inc.size(); ++j) {
+            const int ent = m.inc[j];
+            inc[3 * (size_t)cs.eoff + j] = 3 * (cs.eoff + ent / 3) + ent % 3;
+            for (int k = 0; k < 3; ++k) incpos[3 * (3 * (size_t)cs.eoff + j) + k] = (int32_t)cs.nnz_off + m.incpos[3 * j + k];
+        }
+        for (size_t j = 0; j < m.csr_col.size(); ++j) csr_col[cs.nnz_off + j] = cs.noff + m.csr_col[j];
+        for (size_t b = 0; b < m.bc.size(); ++b) {
+            BcDev& d = bc[cs.bcoff + b];
+            d.type = m.bc[b].type;
+            for (int i = 0; i < 3; ++i) { d.uw[i] = m.bc[b].u_wall[i]; d.uwf[i] = (float)m.bc[b].u_wall[i]; }
+            for (int i = 0; i < 2; ++i) { d.shift[i] = m.bc[b].shift[i]; d.shiftf[i] = (float)m.bc[b].shift[i]; }
+        }
+        ++ci;
+    }
+    inc_ptr[NN] = 3 * NE;
+    csr_ptr[NN] = c->NNZ;
+    TRY(h2d(c, c->d_cases, cd));
+    TRY(h2d(c, c->d_tile_case, tile_case));
+    TRY(h2d(c, c->d_node_case, node_case));
+    TRY(h2d(c, c->d_elem_case, elem_case));
+    TRY(h2d(c, c->d_rec64, rec64));
+    TRY(h2d(c, c->d_tri_s, tri_s));
+    TRY(h2d(c, c->d_nbr, nbr));
+    TRY(h2d(c, c->d_partner, partner));
+    TRY(h2d(c, c->d_bc, bc));
+    TRY(h2d(c, c->d_area, area));
+    TRY(h2d(c, c->d_vol, vol));
+    TRY(h2d(c, c->d_wnx, wnx));
+    TRY(h2d(c, c->d_wny, wny));
+    TRY(h2d(c, c->d_inc_ptr, inc_ptr));
+    TRY(h2d(c, c->d_inc, inc));
+    TRY(h2d(c, c->d_incpos, incpos));
+    TRY(h2d(c, c->d_csr_ptr, csr_ptr));
+    TRY(h2d(c, c->d_csr_col, csr_col));
+    TRY(h2d(c, c->d_is_wall, is_wall));
+    std::vector<float> rec32, exy32;
+    if (c->prec == PDFMC_FP64) {
+        TRY(h2d(c, (double*)c->d_rec, rec64));
+        TRY(h2d(c, (double*)c->d_exy, exy64));
+    } else {
+        rec32.assign(rec64.begin(), rec64.end());
+        exy32.assign(exy64.begin(), exy64.end());
+        TRY(h2d(c, (float*)c->d_rec, rec32));
+        TRY(h2d(c, (float*)c->d_exy, exy32));
+    }
+    // CG jobs: 5 relaxation systems per mode-2 case and one projection system
+    std::vector<CgJob> jer, jp;
+    double* cg = c->d_cg;
+    const int64_t n = NN;
+    for (auto& cs : c->cases) {
+        if (cs.p.mode != 2) continue;
+        for (int q = 0; q < NER; ++q) {
+            CgJob J{};
+            J.r0 = cs.noff; J.n = cs.m.nsn; J.ptr = c->d_csr_ptr; J.col = c->d_csr_col; J.val = c->d_er_val;
+            J.b = c->d_er_b + q * n; J.x = c->d_er_x + q * n;
+            J.r = cg + (4 * q + 0) * n; J.p = cg + (4 * q + 1) * n; J.q = cg + (4 * q + 2) * n; J.dinv = cg + (4 * q + 3) * n;
+            J.tol = cs.p.cg_rtol; J.maxit = cs.p.cg_maxit; J.mean_free = 0;
+            const int cidx = (int)(&cs - &c->cases[0]);
+            J.iters = c->d_counters + (int64_t)cidx * NCNT + C_CG_ER;
+            J.fails = c->d_counters + (int64_t)cidx * NCNT + C_CG_FAIL;
+            jer.push_back(J);
+        }
+        CgJob J{};
+        J.r0 = cs.noff; J.n = cs.m.nsn; J.ptr = c->d_csr_ptr; J.col = c->d_csr_col; J.val = c->d_pk_val;
+        J.b = c->d_pb; J.x = c->d_phi;
+        J.r = cg + (4 * NER + 0) * n; J.p = cg + (4 * NER + 1) * n; J.q = cg + (4 * NER + 2) * n; J.dinv = cg + (4 * NER + 3) * n;
+        J.tol = cs.p.cg_rtol; J.maxit = cs.p.cg_maxit; J.mean_free = 1;
+        const int cidx = (int)(&cs - &c->cases[0]);
+        J.iters = c->d_counters + (int64_t)cidx * NCNT + C_CG_P;
+        J.fails = c->d_counters + (int64_t)cidx * NCNT + C_CG_FAIL;
+        jp.push_back(J);
+    }
+    c->n_jobs_er = (int)jer.size();
+    c->n_jobs_p = (int)jp.size();
+    TRY(h2d(c, c->d_jobs_er, jer));
+    TRY(h2d(c, c->d_jobs_p, jp));
+    // state that starts at zero
+    TRY(enqueue_fill(c, c->d_F, (int64_t)NN * NF));
+    TRY(enqueue_fill(c, c->d_stats, (int64_t)NN * NST));
+    TRY(enqueue_fill(c, c->d_er_x, (int64_t)NER * NN));
+    TRY(enqueue_fill(c, c->d_phi, NN));
+    TRY(enqueue_fill(c, c->d_P, NN));
+    TRY(enqueue_fill(c, c->d_pb, NN));
+    TRY(enqueue_fill(c, c->d_cg, (int64_t)(NER + 1) * 4 * NN));
+    TRY(enqueue_fill(c, (double*)c->d_counters, (int64_t)NCNT * c->cases.size()));
+    TRY(enqueue_fill_i(c, (int32_t*)c->d_step, 1));
+    if (c->any_er) {
+        hipLaunchKernelGGL(k_stiffness_assemble, dim3(nblk(NN, 256)), dim3(256), 0, c->stream, node_args(c));
+        LAUNCHCHK(c);
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->bound = true;
+    c->initialised = false;
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_particles_upload(pdfmc_ctx* c, int32_t ci, const pdfmc_particles_host* p)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    Case& cs = c->cases[ci];
+    if (!p || p->n < 0 || p->n > cs.cap) return fail(c, PDFMC_E_INVALID, "particles_upload: n must be 0..capacity");
+    if (!p->x || !p->y || !p->u || !p->v || !p->w || !p->omega || !p->weight || !p->elem || !p->id ||
+        (cs.p.n_scalars > 0 && !p->psi))
+        return fail(c, PDFMC_E_INVALID, "particles_upload: null array");
+    const int64_t n = p->n;
+    for (int64_t i = 0; i < n; ++i)
+        if (p->elem[i] < 0 || p->elem[i] >= cs.m.ne)
+            return fail(c, PDFMC_E_INVALID, "particles_upload: particle " + std::to_string(i) + " has element " +
+                                                std::to_string(p->elem[i]) + " outside the case");
+    if (p->bin)
+        for (int64_t i = 0; i < n; ++i)
+            if (p->bin[i] >= (cs.p.n_bins == 8 ? 8 : 1))
+                return fail(c, PDFMC_E_INVALID, "particles_upload: particle " + std::to_string(i) + " has bin " +
+                                                    std::to_string(p->bin[i]));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    PartBufs& B = c->part[c->cur];
+    const size_t R = rsz(c);
+    auto put = [&](char* dbase, int64_t off, const double* src, int64_t cnt) -> pdfmc_status {
+        if (cnt == 0) return PDFMC_OK;
+        char* dst = (char*)dbase + off * R;
+        if (R == 8) {
+            HIPCHK(c, hipMemcpy(dst, src, cnt * 8, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> tmp(src, src + cnt);
+            HIPCHK(c, hipMemcpy(dst, tmp.data(), cnt * 4, hipMemcpyHostToDevice));
+        }
+        return PDFMC_OK;
+    };
+    TRY(put(B.x, cs.poff, p->x, n)); TRY(put(B.y, cs.poff, p->y, n));
+    TRY(put(B.u, cs.poff, p->u, n)); TRY(put(B.v, cs.poff, p->v, n)); TRY(put(B.w, cs.poff, p->w, n));
+    TRY(put(B.om, cs.poff, p->omega, n)); TRY(put(B.wt, cs.poff, p->weight, n));
+    for (int a = 0; a < cs.p.n_scalars; ++a) TRY(put(B.psi, cs.psioff + a * cs.cap, p->psi + a * n, n));
+    std::vector<int32_t> el(n);
+    for (int64_t i = 0; i < n; ++i) el[i] = p->elem[i] + cs.eoff;
+    std::vector<uint8_t> bins(n, 0);
+    if (p->bin) std::copy(p->bin, p->bin + n, bins.begin());
+    if (n) {
+        HIPCHK(c, hipMemcpy(B.elem + cs.poff, el.data(), n * 4, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(B.id + cs.poff, p->id, n * 4, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(B.bin + cs.poff, bins.data(), n, hipMemcpyHostToDevice));
+    }
+    cs.np = n;
+    CaseDev d = make_case_dev(c, cs);
+    HIPCHK(c, hipMemcpy(c->d_cases + ci, &d, sizeof d, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(c->d_counters + (int64_t)ci * NCNT, 0, NCNT * sizeof(unsigned long long)));
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_particles_download(pdfmc_ctx* c, int32_t ci, pdfmc_particles_host* p)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    Case& cs = c->cases[ci];
+    if (!p || p->n != cs.np) return fail(c, PDFMC_E_INVALID, "particles_download: n must equal the uploaded count");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    PartBufs& B = c->part[c->cur];
+    const size_t R = rsz(c);
+    const int64_t n = cs.np;
+    auto get = [&](const char* dbase, int64_t off, double* dst, int64_t cnt) -> pdfmc_status {
+        if (!dst || cnt == 0) return PDFMC_OK;
+        const char* src = (const char*)dbase + off * R;
+        if (R == 8) {
+            HIPCHK(c, hipMemcpy(dst, src, cnt * 8, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> tmp(cnt);
+            HIPCHK(c, hipMemcpy(tmp.data(), src, cnt * 4, hipMemcpyDeviceToHost));
+            std::copy(tmp.begin(), tmp.end(), dst);
+        }
+        return PDFMC_OK;
+    };
+    TRY(get(B.x, cs.poff, p->x, n)); TRY(get(B.y, cs.poff, p->y, n));
+    TRY(get(B.u, cs.poff, p->u, n)); TRY(get(B.v, cs.poff, p->v, n)); TRY(get(B.w, cs.poff, p->w, n));
+    TRY(get(B.om, cs.poff, p->omega, n)); TRY(get(B.wt, cs.poff, p->weight, n));
+    if (p->psi)
+        for (int a = 0; a < cs.p.n_scalars; ++a) TRY(get(B.psi, cs.psioff + a * cs.cap, p->psi + a * n, n));
+    if (n) {
+        if (p->elem) {
+            HIPCHK(c, hipMemcpy(p->elem, B.elem + cs.poff, n * 4, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) p->elem[i] -= cs.eoff;
+        }
+        if (p->id) HIPCHK(c, hipMemcpy(p->id, B.id + cs.poff, n * 4, hipMemcpyDeviceToHost));
+        if (p->bin) HIPCHK(c, hipMemcpy(p->bin, B.bin + cs.poff, n, hipMemcpyDeviceToHost));
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_fields_upload(pdfmc_ctx* c, int32_t ci, const double* F)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    if (!F) return fail(c, PDFMC_E_INVALID, "fields_upload: null");
+    const Case& cs = c->cases[ci];
+    std::vector<double> tmp((size_t)cs.m.nsn * NF);
+    for (int s = 0; s < cs.m.nsn; ++s) std::copy(F + (size_t)cs.m.rep[s] * NF, F + (size_t)cs.m.rep[s] * NF + NF, &tmp[(size_t)s * NF]);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->d_F + (size_t)cs.noff * NF, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
+    if (c->prec == PDFMC_FP32) {
+        hipLaunchKernelGGL(k_mirror_f32, dim3(nblk((int64_t)c->NN * NF32, 256)), dim3(256), 0, c->stream,
+                           (const double*)c->d_F, c->d_F32, c->NN);
+        LAUNCHCHK(c);
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_fields_download(pdfmc_ctx* c, int32_t ci, double* F)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    if (!F) return fail(c, PDFMC_E_INVALID, "fields_download: null");
+    const Case& cs = c->cases[ci];
+    std::vector<double> tmp((size_t)cs.m.nsn * NF);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(tmp.data(), c->d_F + (size_t)cs.noff * NF, tmp.size() * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < cs.m.nn; ++i)
+        std::copy(&tmp[(size_t)cs.m.snode[i] * NF], &tmp[(size_t)cs.m.snode[i] * NF] + NF, F + (size_t)i * NF);
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_pressure_download(pdfmc_ctx* c, int32_t ci, double* P)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    if (!P) return fail(c, PDFMC_E_INVALID, "pressure_download: null");
+    const Case& cs = c->cases[ci];
+    std::vector<double> tmp(std::max(cs.m.nsn, 1));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(tmp.data(), c->d_P + cs.noff, cs.m.nsn * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < cs.m.nn; ++i) P[i] = tmp[cs.m.snode[i]];
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_init(pdfmc_ctx* c)
+{
+    if (!c) return PDFMC_E_INVALID;
+    TRY(check_bound(c));
+    // statistics of the uploaded state
+    TRY(enqueue_accum_clear(c, true));
+    TRY(enqueue_particles(c, 0, 0));
+    hipLaunchKernelGGL(k_node_stats, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, node_args(c));
+    LAUNCHCHK(c);
+    // Eulerian fields (no projection at initialisation: <P> starts at 0)
+    TRY(enqueue_fields(c, false));
+    // bins and cell means against those fields
+    TRY(enqueue_accum_clear(c, true));
+    TRY(enqueue_particles(c, 0, 1));
+    TRY(enqueue_cell_means(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->initialised = true;
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_rebin(pdfmc_ctx* c)
+{
+    if (!c) return PDFMC_E_INVALID;
+    TRY(check_bound(c));
+    if (c->prec == PDFMC_FP32) {
+        hipLaunchKernelGGL(k_mirror_f32, dim3(nblk((int64_t)c->NN * NF32, 256)), dim3(256), 0, c->stream,
+                           (const double*)c->d_F, c->d_F32, c->NN);
+        LAUNCHCHK(c);
+    }
+    TRY(enqueue_accum_clear(c, true));
+    TRY(enqueue_particles(c, 0, 1));
+    TRY(enqueue_cell_means(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->initialised = true;
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps)
+{
+    if (!c) return PDFMC_E_INVALID;
+    TRY(check_bound(c));
+    if (!c->initialised) return fail(c, PDFMC_E_STATE, "step: call pdfmc_init (or pdfmc_rebin) first");
+    if (n_steps < 0) return fail(c, PDFMC_E_INVALID, "step: n_steps < 0");
+    for (int s = 0; s < n_steps; ++s) {
+        if (c->sort_interval > 0 && c->steps_since_sort >= c->sort_interval) TRY(enqueue_sort(c));
+        if (c->use_graph) {
+            hipGraphExec_t& g = c->graph[c->cur];
+            if (!g) {
+                hipGraph_t graph = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                pdfmc_status st = enqueue_step_body(c);
+                hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+                if (st != PDFMC_OK) { if (graph) (void)hipGraphDestroy(graph); return st; }
+                if (e2 != hipSuccess) return fail(c, PDFMC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e2));
+                hipError_t e3 = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (e3 != hipSuccess) { g = nullptr; return fail(c, PDFMC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e3)); }
+            }
+            HIPCHK(c, hipGraphLaunch(g, c->stream));
+        } else {
+            TRY(enqueue_step_body(c));
+        }
+        c->steps_since_sort++;
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_set_step_index(pdfmc_ctx* c, uint32_t n)
+{
+    if (!c) return PDFMC_E_INVALID;
+    TRY(check_bound(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->d_step, &n, 4, hipMemcpyHostToDevice));
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_stats_readback(pdfmc_ctx* c, int32_t ci, double* out)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    if (!out) return fail(c, PDFMC_E_INVALID, "stats_readback: null");
+    const Case& cs = c->cases[ci];
+    const int ns = cs.p.n_scalars, nst = 12 + 2 * ns;
+    std::vector<double> tmp((size_t)std::max(cs.m.nsn, 1) * NST);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(tmp.data(), c->d_stats + (size_t)cs.noff * NST, (size_t)cs.m.nsn * NST * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < cs.m.nn; ++i) {
+        const double* s = &tmp[(size_t)cs.m.snode[i] * NST];
+        std::copy(s, s + nst, out + (size_t)i * nst);
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_node_sums(pdfmc_ctx* c, int32_t ci, double* out)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    if (!out) return fail(c, PDFMC_E_INVALID, "node_sums: null");
+    const Case& cs = c->cases[ci];
+    const int ns = cs.p.n_scalars, nq = 11 + 2 * ns;
+    std::vector<double> tmp((size_t)std::max(cs.m.nsn, 1) * NQ);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(tmp.data(), c->d_nsum + (size_t)cs.noff * NQ, (size_t)cs.m.nsn * NQ * 8, hipMemcpyDeviceToHost));
+    for (int i = 0; i < cs.m.nn; ++i) {
+        const double* s = &tmp[(size_t)cs.m.snode[i] * NQ];
+        std::copy(s, s + nq, out + (size_t)i * nq);
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_cell_means(pdfmc_ctx* c, int32_t ci, double* mean, int32_t* count)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    const Case& cs = c->cases[ci];
+    const int ns = cs.p.n_scalars;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (mean && ns > 0) {
+        const size_t cnt = (size_t)cs.m.ne * 8 * ns;
+        if (c->prec == PDFMC_FP64) {
+            HIPCHK(c, hipMemcpy(mean, (double*)c->d_cmean + cs.cmoff, cnt * 8, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> tmp(cnt);
+            HIPCHK(c, hipMemcpy(tmp.data(), (float*)c->d_cmean + cs.cmoff, cnt * 4, hipMemcpyDeviceToHost));
+            std::copy(tmp.begin(), tmp.end(), mean);
+        }
+    }
+    if (count) HIPCHK(c, hipMemcpy(count, c->d_ccnt + 8 * (size_t)cs.eoff, 8 * (size_t)cs.m.ne * 4, hipMemcpyDeviceToHost));
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_counters(pdfmc_ctx* c, int32_t ci, int64_t* out)
+{
+    TRY(check_case(c, ci));
+    TRY(check_bound(c));
+    if (!out) return fail(c, PDFMC_E_INVALID, "counters: null");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(out, c->d_counters + (int64_t)ci * NCNT, NCNT * 8, hipMemcpyDeviceToHost));
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_set_options(pdfmc_ctx* c, int32_t sort_interval, int32_t block_size, int32_t use_graph)
+{
+    if (!c) return PDFMC_E_INVALID;
+    if (sort_interval < 0) return fail(c, PDFMC_E_INVALID, "set_options: sort_interval < 0");
+    if (block_size < 64 || block_size > 256 || block_size % 64) return fail(c, PDFMC_E_INVALID, "set_options: block size must be 64, 128, 192 or 256");
+    if (block_size != c->block) drop_graphs(c);
+    c->sort_interval = sort_interval;
+    c->block = block_size;
+    c->use_graph = use_graph ? 1 : 0;
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_sort(pdfmc_ctx* c)
+{
+    if (!c) return PDFMC_E_INVALID;
+    TRY(check_bound(c));
+    TRY(enqueue_sort(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_synchronize(pdfmc_ctx* c)
+{
+    if (!c) return PDFMC_E_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_draw_gaussians(pdfmc_ctx* c, uint64_t seed, uint32_t step, uint32_t stream, const uint32_t* ids,
+                                  int64_t n, void* out)
+{
+    if (!c) return PDFMC_E_INVALID;
+    if (n < 0 || (n > 0 && (!ids || !out))) return fail(c, PDFMC_E_INVALID, "draw_gaussians: bad arguments");
+    if (n == 0) return PDFMC_OK;
+    if (c->prec == PDFMC_FP64)
+        hipLaunchKernelGGL(k_draw_gaussians<double>, dim3(nblk(n, 256)), dim3(256), 0, c->stream, (uint32_t)seed,
+                           (uint32_t)(seed >> 32), step, stream, ids, n, (double*)out);
+    else
+        hipLaunchKernelGGL(k_draw_gaussians<float>, dim3(nblk(n, 256)), dim3(256), 0, c->stream, (uint32_t)seed,
+                           (uint32_t)(seed >> 32), step, stream, ids, n, (float*)out);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDFMC_OK;
+}
+
+}  // extern "C"

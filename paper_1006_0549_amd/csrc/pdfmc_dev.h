@@ -1,0 +1,107 @@
+// Internal layout shared by the library's host and kernel sources.
+//
+// Device data of a context are concatenations over its cases: particles,
+// elements, statistics nodes (periodic images merged) and boundary records
+// each carry a per-case offset. Element and node ids stored on the device are
+// global (offset included); the host converts to case-local ids at the API.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdfmc {
+
+constexpr int NF = 22;         // Eulerian field slots per node
+constexpr int NF32 = 24;       // padded FP32 mirror stride
+constexpr int MAXS = 4;        // scalars per case
+constexpr int NQ = 19;         // node-sum stride: 11 + 2*MAXS
+constexpr int NST = 20;        // statistics stride: 12 + 2*MAXS
+constexpr int NCNT = 12;       // counters per case
+constexpr int TILE = 256;      // particle ranges of cases are padded to this
+constexpr int NER = 5;         // elliptic-relaxation components 11,12,21,22,33
+
+enum Field {
+    F_U1 = 0, F_U2, F_U3, F_DPX, F_DPY,
+    F_DU1X, F_DU1Y, F_DU2X, F_DU2Y, F_DU3X, F_DU3Y,
+    F_LAP1, F_LAP2, F_LAP3,
+    F_G11, F_G12, F_G21, F_G22, F_G33,
+    F_OMEGA, F_C0EPS, F_SOMEGA
+};
+
+enum Counter {
+    C_WALK_FALLBACK = 0, C_REFLECT, C_PERIODIC, C_OMEGA_FLIP, C_EMPTY_NODE, C_NAN,
+    C_WALK_STEPS, C_CG_ER, C_CG_P, C_CG_FAIL, C_K_FLOOR, C_EPS_FLOOR
+};
+
+struct BcDev {
+    int32_t type;        // 0 wall, 1 periodic
+    int32_t pad;
+    double uw[3];
+    double shift[2];
+    float uwf[3];
+    float shiftf[2];
+};
+
+struct CaseDev {
+    int64_t poff, np;          // particle range [poff, poff+np)
+    int64_t psioff;            // scalar block: psi[psioff + a*cap + i]
+    int64_t cap;               // capacity (stride of the scalar block)
+    int64_t cmoff;             // cell means [ne][8][ns] at cmean + cmoff
+    int64_t csoff;             // cell sums  [ne][8][1+ns] at csum + csoff
+    int32_t eoff, ne, noff, nsn, bcoff, nbc;
+    int32_t ns, nbins, nmin, mode;
+    uint32_t seed_lo, seed_hi, stream, pad0;
+    int32_t csr_row0, pad1;    // first CSR row (= noff) and nnz offset
+    int64_t nnz_off, nnz;
+    int64_t inc_off;           // incidence list offset (entries 3*e+k, global e)
+    // particle-step constants, computed on the host in FP64 (and rounded for FP32)
+    double dt, tnu, sq_nu, C3, c34, hphi;
+    float fdt, ftnu, fsq_nu, fC3, fc34, fhphi;
+    double src[MAXS][4];
+    float srcf[MAXS][4];
+    // Eulerian constants
+    double nu, C0, Cw1, Cw2, C1, C2, gamma5, Cv, CL, Ceta, nu34, k_floor, eps_floor;
+    double dpdx[2];
+    double cg_rtol;
+    int32_t cg_maxit, pad2;
+};
+
+template <typename R>
+struct Particles {
+    R *x, *y, *u, *v, *w, *om, *wt, *psi;
+    int32_t* elem;
+    uint32_t* id;
+    uint8_t* bin;
+};
+
+template <typename R>
+struct MeshDev {
+    const R* rec;          // [8*NE]: x1, y1, b0, b1, b2, c0, c1, c2   (R-05)
+    const int4* tri_s;     // statistics node per vertex (global), .w unused
+    const int4* nbr;       // neighbour element (global) or -1 - global bc index
+    const int4* partner;   // partner element across a periodic edge (global) or -1
+    const R* exy;          // [6*NE]: vertex coordinates, for reflections
+    const BcDev* bc;
+};
+
+// Everything a particle kernel needs, passed by value.
+template <typename R>
+struct StepArgs {
+    Particles<R> P;
+    MeshDev<R> M;
+    const CaseDev* cases;
+    const int32_t* tile_case;     // particle tile -> case
+    const R* F;                   // fields: FP64 [NN][22] or FP32 mirror [NN][24]
+    int32_t fstride;
+    const R* cmean;               // cell means (Real)
+    double* nsum;                 // [NN][NQ] node sums (FP64)
+    double* csum;                 // cell sums (FP64)
+    int32_t* ccnt;                // [NE][8] cell counts
+    unsigned long long* counters; // [ncase][NCNT]
+    const uint32_t* step;         // device step index
+    int32_t ntiles;
+    int32_t advance;              // 1: advance then statistics; 0: statistics only
+    int32_t do_bins;              // 1: bins + cell sums
+    int32_t pad;
+};
+
+}  // namespace pdfmc

@@ -1,0 +1,31 @@
+// Declarations of the kernels launched by the host library.
+#pragma once
+#include "pdfmc_dev.h"
+#include "pdfmc_nodes.h"
+#include "pdfmc_sort.h"
+
+namespace pdfmc {
+
+template <typename R> __global__ void k_particle_step(StepArgs<R> A);
+template <typename R> __global__ void k_draw_gaussians(uint32_t slo, uint32_t shi, uint32_t step, uint32_t stream,
+                                                       const uint32_t* ids, int64_t n, R* out);
+__global__ void k_fill_f64(double* a, int64_t n, double v);
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v);
+__global__ void k_step_increment(uint32_t* step);
+__global__ void k_node_stats(NodeArgs A);
+template <typename R> __global__ void k_cell_means(NodeArgs A, R* cmean);
+__global__ void k_fields_grad(NodeArgs A);
+__global__ void k_fields_derived(NodeArgs A);
+__global__ void k_er_assemble(NodeArgs A);
+__global__ void k_stiffness_assemble(NodeArgs A);
+__global__ void k_er_finish(NodeArgs A);
+__global__ void k_proj_rhs(NodeArgs A);
+__global__ void k_proj_update(NodeArgs A);
+__global__ void k_proj_grad(NodeArgs A);
+__global__ void k_mirror_f32(const double* F, float* F32, int nn);
+__global__ void k_cg(const CgJob* jobs);
+__global__ void k_sort_hist(SortArgs A);
+__global__ void k_sort_scan(SortArgs A);
+template <typename R> __global__ void k_sort_scatter(SortArgs A, Particles<R> src, Particles<R> dst);
+
+}  // namespace pdfmc

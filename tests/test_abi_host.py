@@ -1,0 +1,98 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/pdfmc.h declares, validates meshes and arguments
+before any device work, and derives the same statistics-node map (periodic
+images merged) as the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_1006_0549_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        from paper_1006_0549_amd import build
+        build.build()
+    return P
+
+
+def test_exports_every_declared_symbol(pkg):
+    hdr = open(os.path.join(ROOT, "include", "pdfmc.h")).read()
+    declared = set(re.findall(r"\b(pdfmc_[a-z_0-9]+)\s*\(", hdr))
+    assert "pdfmc_step" in declared and len(declared) >= 20
+    L = pkg.lib()
+    missing = [f for f in sorted(declared) if not hasattr(L, f)]
+    assert not missing, missing
+    assert declared == set(pkg.EXPORTS)
+
+
+def _sim(pkg):
+    return pkg.Sim("fp64", host_only=True)
+
+
+def test_mesh_rejections(pkg):
+    mesh = W.unit_square(6, 0.0, periodic_x=True)
+    s = _sim(pkg)
+    bad = W.Mesh("cw", mesh.xy, mesh.tri[:, [0, 2, 1]].copy(), mesh.edge_tag, mesh.bcs)
+    with pytest.raises(pkg.PdfmcError, match="MESH.*counter-clockwise"):
+        s.add_case(bad, W.default_params(), 10)
+    bcs = [dict(b) for b in mesh.bcs]
+    bcs[2] = dict(type=W.BC_PERIODIC, shift=(0.5, 0.0))
+    with pytest.raises(pkg.PdfmcError, match="MESH.*partner"):
+        s.add_case(W.Mesh("p", mesh.xy, mesh.tri, mesh.edge_tag, bcs), W.default_params(), 10)
+    tag = mesh.edge_tag.copy()
+    e, k = next((e, k) for e in range(mesh.n_elems) for k in range(3) if tag[e, k] < 0)
+    tag[e, k] = 0
+    with pytest.raises(pkg.PdfmcError, match="MESH"):
+        s.add_case(W.Mesh("t", mesh.xy, mesh.tri, tag, mesh.bcs), W.default_params(), 10)
+    tri = mesh.tri.copy()
+    tri[0, 0] = mesh.n_nodes + 3
+    with pytest.raises(pkg.PdfmcError, match="MESH.*references node"):
+        s.add_case(W.Mesh("r", mesh.xy, tri, mesh.edge_tag, mesh.bcs), W.default_params(), 10)
+
+
+def test_argument_rejections(pkg):
+    mesh = W.unit_square(6, 0.0, periodic_x=True)
+    s = _sim(pkg)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*n_bins"):
+        s.add_case(mesh, W.default_params(n_bins=3), 10)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*n_scalars"):
+        s.add_case(mesh, W.default_params(n_scalars=5), 10)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*dt"):
+        s.add_case(mesh, W.default_params(dt=0.0), 10)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*capacity"):
+        s.add_case(mesh, W.default_params(), -1)
+    with pytest.raises(pkg.PdfmcError, match="STATE"):
+        s.init()
+    with pytest.raises(pkg.PdfmcError, match="STATE"):
+        s.step(1)
+    with pytest.raises(pkg.PdfmcError, match="INVALID"):
+        s.set_options(0, 100, False)
+
+
+@pytest.mark.parametrize("which", ["square", "channel"])
+def test_stat_node_map_matches_oracle(pkg, oracle_mod, which):
+    mesh = W.unit_square(12, 0.2, periodic_x=True) if which == "square" else W.channel(n_half=10, nx=30)
+    s = _sim(pkg)
+    cs = s.add_case(mesh, W.default_params(), 100)
+    nsn, sn = s.case_info(cs)
+    o = oracle_mod.Oracle()
+    oc = o.add_case(mesh, W.default_params())
+    info = o.mesh_info(oc)
+    assert nsn == info["n_stat_nodes"]
+    np.testing.assert_array_equal(sn, info["stat_node"])
+
+
+def test_workspace_grows_with_capacity(pkg):
+    mesh = W.unit_square(8, 0.2)
+    a = _sim(pkg)
+    a.add_case(mesh, W.default_params(), 1000)
+    b = _sim(pkg)
+    b.add_case(mesh, W.default_params(), 100000)
+    assert b.workspace_bytes() > a.workspace_bytes() + 2 * 99000 * 8 * 7

@@ -1,0 +1,165 @@
+"""GPU parity of the HIP particle advance against the FP64 CPU oracle, through
+the C ABI (include/pdfmc.h).
+
+Bar (FP64 path): element ids, velocity bins and the full particle state are
+bit-identical after a step from identical state; node sums agree to 1e-13 of
+sum |w N Q| (summation order differs: FP64 atomics on the GPU); statistics to
+1e-12 relative to their scale for one step and 1e-9 over a 100-step run with
+live fields. Cases span several tiles and a ragged last tile, walls, periodic
+edges, sources, 1 and 2 scalars, 8 velocity bins.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1006_0549_amd as P
+    return P
+
+
+def _pair(P, oracle_mod, mesh, params, parts, precision="fp64", fields=None, options=None):
+    n = len(parts["x"])
+    sim = P.Sim(precision, "cuda:0")
+    cs = sim.add_case(mesh, params, n)
+    sim.bind()
+    if options:
+        sim.set_options(**options)
+    if fields is not None:
+        sim.fields_upload(cs, fields)
+    sim.upload(cs, parts)
+    o = oracle_mod.Oracle()
+    oc = o.add_case(mesh, params)
+    if fields is not None:
+        o.fields_upload(oc, fields)
+    o.upload(oc, parts)
+    return sim, cs, o, oc
+
+
+def _stat_rows(sim, cs):
+    _, sn = sim.case_info(cs)
+    return np.unique(sn, return_index=True)[1]
+
+
+def _scale(st, ns):
+    """scale of each statistic: |mean| for means, sqrt(<QQ><Q'Q'>) for covariances"""
+    sc = np.abs(st).copy()
+    var = st[:, 5:8]
+    cov_idx = {8: (0, 1), 9: (0, 2), 10: (1, 2)}
+    for c, (i, j) in cov_idx.items():
+        sc[:, c] = np.sqrt(np.abs(var[:, i] * var[:, j]))
+    for c in range(5, 8):
+        sc[:, c] = np.abs(st[:, c])
+    return np.maximum(sc, 1e-300)
+
+
+def _assert_state_equal(g, r, keys=("x", "y", "u", "v", "w", "omega")):
+    assert np.array_equal(g["elem"], r["elem"]), np.nonzero(g["elem"] != r["elem"])[0][:10]
+    for k in keys:
+        bad = np.nonzero(g[k] != r[k])[0]
+        assert bad.size == 0, (k, bad[:5], g[k][bad[:5]], r[k][bad[:5]])
+    if r["psi"].size:
+        assert np.array_equal(g["psi"], r["psi"])
+
+
+def test_gaussians_bitwise_fp64(P, oracle_mod):
+    sim = P.Sim("fp64", "cuda:0")
+    ids = np.arange(0, 20000, dtype=np.uint32) * 7919
+    g = sim.draw_gaussians(10060549, 17, 3, ids)
+    r = np.array([oracle_mod.gauss6(10060549, int(i), 17, 3) for i in ids])
+    assert np.array_equal(g, r), np.max(np.abs(g - r))
+
+
+def test_gaussians_fp32_follow_fp64(P, oracle_mod):
+    sim = P.Sim("fp32", "cuda:0")
+    ids = np.arange(50000, dtype=np.uint32)
+    g = sim.draw_gaussians(10060549, 5, 1, ids).astype(np.float64)
+    for j in range(6):
+        assert abs(g[:, j].mean()) < 4.5 / np.sqrt(len(ids))
+        assert abs(g[:, j].var() - 1.0) < 4.5 * np.sqrt(2.0 / len(ids))
+    r = np.array([oracle_mod.gauss6(10060549, int(i), 5, 1) for i in ids[:3000]])
+    d = np.abs(g[:3000] - r)
+    assert np.median(d) < 1e-5 and np.quantile(d, 0.99) < 1e-3
+
+
+def _frozen_case(ns=1, nb=8, n=16, ppe=33, seed=5):
+    mesh = W.unit_square(n, 0.2, periodic_x=True, periodic_y=False, lid=(0.5, 0.0, 0.0), seed_key=(5, 0, 0))
+    rng = np.random.default_rng(seed)
+    F = W.frozen_fields(mesh, C0=2.1, omega=1.3, k=0.02, dpdx=(-1.0, 0.2))
+    F[:, 0:3] = rng.normal(0, 0.05, (mesh.n_nodes, 3))
+    F[:, 5:11] = rng.normal(0, 0.5, (mesh.n_nodes, 6))
+    F[:, 11:14] = rng.normal(0, 1.0, (mesh.n_nodes, 3))
+    F[:, 15:17] = rng.normal(0, 0.3, (mesh.n_nodes, 2))
+    F[:, 21] = rng.normal(0.7, 0.1, mesh.n_nodes)
+    # periodic images must carry equal fields: copy left column onto the right
+    right = np.nonzero(mesh.xy[:, 0] == 1.0)[0]
+    for r_ in right:
+        l_ = np.nonzero((mesh.xy[:, 0] == 0.0) & (mesh.xy[:, 1] == mesh.xy[r_, 1]))[0][0]
+        F[r_] = F[l_]
+    params = W.default_params(mode=0, dt=2e-3, nu=2e-3, n_scalars=ns, n_bins=nb,
+                              src=[(0.3, 0.7, 0.08, 1.0), (0.6, 0.2, 0.1, 0.5)][:ns])
+    parts = W.init_particles(mesh, ppe, ns, rng, u_std=0.4, psi_disks=[(0.5, 0.5, 0.25, 1.0), (0.2, 0.8, 0.3, 2.0)][:ns])
+    return mesh, params, parts, F
+
+
+@pytest.mark.parametrize("ns,nb", [(1, 8), (2, 8), (0, 1), (1, 1)])
+def test_one_step_frozen_bitwise(P, oracle_mod, ns, nb):
+    mesh, params, parts, F = _frozen_case(ns, nb)
+    n = len(parts["x"])
+    _flush(f"[one_step_frozen] ns={ns} nb={nb} particles={n} tiles={(n + 255) // 256}")
+    sim, cs, o, oc = _pair(P, oracle_mod, mesh, params, parts, fields=F)
+    sim.init(); o.init()
+    # bins and cell means of the initial state
+    assert np.array_equal(sim.download(cs, n)["bin"], o.download(oc, n)["bin"])
+    gm, gc = sim.cell_means(cs)
+    rm, rc = o.cell_means(oc)
+    assert np.array_equal(gc, rc)
+    np.testing.assert_allclose(gm, rm, rtol=1e-13, atol=1e-15)
+    for step in range(3):
+        sim.step(1); o.step(1)
+        g, r = sim.download(cs, n), o.download(oc, n)
+        _assert_state_equal(g, r)
+        assert np.array_equal(g["bin"], r["bin"])
+        gs, rs = sim.node_sums(cs), o.node_sums(oc)
+        # |delta| <= 1e-13 sum |w N Q|: bound with the sums of |Q| (partition of unity)
+        absq = np.abs(np.stack([np.ones(n), g["u"], g["v"], g["w"]]))
+        tol = 1e-13 * np.abs(rs).max(0) + 1e-300
+        assert np.all(np.abs(gs - rs) <= np.maximum(tol, 1e-13 * np.abs(rs))), np.max(np.abs(gs - rs))
+        gst, rst = sim.stats(cs), o.stats(oc)
+        rows = _stat_rows(sim, cs)
+        d = np.abs(gst - rst)[rows] / _scale(rst, ns)[rows]
+        assert d.max() <= 1e-12, (step, d.max(), np.unravel_index(np.argmax(d), d.shape))
+    gc_, rc_ = sim.counters(cs), o.counters(oc)
+    for k in ("walk_fallback", "reflect", "periodic", "omega_flip", "nan", "walk_steps"):
+        assert gc_[k] == rc_[k], (k, gc_[k], rc_[k])
+    assert rc_["reflect"] > 0 and rc_["periodic"] > 0
+
+
+def test_small_config_100_steps(P, oracle_mod):
+    cfg = W.config_small()
+    parts = cfg["particles"]
+    n = len(parts["x"])
+    _flush(f"[small_config] {cfg['name']} particles={n} steps=100")
+    sim, cs, o, oc = _pair(P, oracle_mod, cfg["mesh"], cfg["params"], parts)
+    sim.init(); o.init()
+    sim.step(100); o.step(100)
+    g, r = sim.download(cs, n), o.download(oc, n)
+    same = g["elem"] == r["elem"]
+    assert same.mean() > 0.999, same.mean()
+    gst, rst = sim.stats(cs), o.stats(oc)
+    rows = _stat_rows(sim, cs)
+    d = (np.abs(gst - rst)[rows] / _scale(rst, 1)[rows])
+    assert d.max() <= 1e-9, (d.max(), np.unravel_index(np.argmax(d), d.shape))
+    gF, rF = sim.fields(cs), o.fields(oc)
+    dF = np.abs(gF - rF)[rows] / np.maximum(np.abs(rF[rows]), 1e-6)
+    assert dF.max() <= 1e-8, dF.max()
