@@ -169,6 +169,14 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t bl
 pdfmc_status pdfmc_sort(pdfmc_ctx* ctx);
 pdfmc_status pdfmc_synchronize(pdfmc_ctx* ctx);
 
+/* Live timing of the particle kernel: while enabled, every time-step launch
+ * of the particle kernel is bracketed by two HIP events on the context's
+ * stream (graph replay is suspended meanwhile). timing_read synchronises,
+ * returns the summed kernel time in ms and the number of launches since the
+ * last read or enable, and restarts the count. */
+pdfmc_status pdfmc_timing(pdfmc_ctx* ctx, int32_t enable);
+pdfmc_status pdfmc_timing_read(pdfmc_ctx* ctx, double* total_ms, int64_t* launches);
+
 /* Device-side draws of the Wiener increments for n particles (test hook of
  * R-09/R-10): ids, out are DEVICE pointers; out is [6*n] (FP64 context:
  * doubles; FP32 context: floats), increment j of particle i at out[6*i+j]. */

@@ -362,7 +362,7 @@ int orc_derive_fields(orc_ctx* c, ocase* cs, int project)
         double* wp = orc_alloc(sizeof(double) * (size_t)nsn * 5);
         for (int q = 0; q < 5 && rc == ORC_OK; ++q) {
             int it = 0;
-            rc = orc_helmholtz(m, L2, r + (size_t)q * nsn, dm, dv + (size_t)q * nsn, 1e-12, 100000,
+            rc = orc_helmholtz(m, L2, r + (size_t)q * nsn, dm, dv + (size_t)q * nsn, 1e-13, 100000,
                                wp + (size_t)q * nsn, &it);
             cs->cnt[CNT_CG_ER] += it;
             if (rc) orc_err(c, rc, "elliptic relaxation solve did not converge");
@@ -391,7 +391,7 @@ int orc_derive_fields(orc_ctx* c, ocase* cs, int project)
             double* phi = orc_alloc(sizeof(double) * nsn);
             for (int s = 0; s < nsn; ++s) { U1[s] = cs->stats[(size_t)s * nst + 2]; U2[s] = cs->stats[(size_t)s * nst + 3]; }
             int it = 0;
-            rc = orc_projection(m, U1, U2, P->dt, 1e-12, 100000, phi, &it);
+            rc = orc_projection(m, U1, U2, P->dt, 1e-13, 100000, phi, &it);
             cs->cnt[CNT_CG_P] += it;
             if (rc) orc_err(c, rc, "pressure projection solve did not converge");
             for (int s = 0; s < nsn; ++s) cs->P[s] += phi[s];

@@ -86,6 +86,10 @@ struct pdfmc_ctx {
     int steps_since_sort = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool any_er = false, any_eul = false, any_scalars = false;
+    // live timing of the particle kernel: one event pair per launch
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -287,6 +291,15 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins)
     if (c->ntiles == 0) return PDFMC_OK;
     const int64_t threads = (int64_t)c->ntiles * TILE;
     const int b = c->block;
+    const bool timed = c->timing && advance;
+    if (timed) {
+        while (c->ev.size() < c->ev_used + 2) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+        HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+    }
     if (c->prec == PDFMC_FP64)
         hipLaunchKernelGGL(k_particle_step<double>, dim3(nblk(threads, b)), dim3(b), 0, c->stream,
                            step_args<double>(c, advance, do_bins));
@@ -294,6 +307,10 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins)
         hipLaunchKernelGGL(k_particle_step<float>, dim3(nblk(threads, b)), dim3(b), 0, c->stream,
                            step_args<float>(c, advance, do_bins));
     LAUNCHCHK(c);
+    if (timed) {
+        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+    }
     return PDFMC_OK;
 }
 
@@ -439,6 +456,7 @@ void pdfmc_destroy(pdfmc_ctx* c)
     if (!c) return;
     if (c->bound) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
+    for (auto e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -824,7 +842,7 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps)
     if (n_steps < 0) return fail(c, PDFMC_E_INVALID, "step: n_steps < 0");
     for (int s = 0; s < n_steps; ++s) {
         if (c->sort_interval > 0 && c->steps_since_sort >= c->sort_interval) TRY(enqueue_sort(c));
-        if (c->use_graph) {
+        if (c->use_graph && !c->timing) {
             hipGraphExec_t& g = c->graph[c->cur];
             if (!g) {
                 hipGraph_t graph = nullptr;
@@ -945,6 +963,30 @@ pdfmc_status pdfmc_synchronize(pdfmc_ctx* c)
 {
     if (!c) return PDFMC_E_INVALID;
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_timing(pdfmc_ctx* c, int32_t enable)
+{
+    if (!c) return PDFMC_E_INVALID;
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_timing_read(pdfmc_ctx* c, double* total_ms, int64_t* launches)
+{
+    if (!c || !total_ms || !launches) return PDFMC_E_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (int64_t)(c->ev_used / 2);
+    c->ev_used = 0;
     return PDFMC_OK;
 }
 

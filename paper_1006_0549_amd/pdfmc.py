@@ -61,7 +61,8 @@ EXPORTS = ["pdfmc_create", "pdfmc_destroy", "pdfmc_last_error", "pdfmc_add_case"
            "pdfmc_particles_download", "pdfmc_fields_upload", "pdfmc_fields_download",
            "pdfmc_pressure_download", "pdfmc_init", "pdfmc_rebin", "pdfmc_step", "pdfmc_set_step_index",
            "pdfmc_stats_readback", "pdfmc_node_sums", "pdfmc_cell_means", "pdfmc_counters",
-           "pdfmc_set_options", "pdfmc_sort", "pdfmc_synchronize", "pdfmc_draw_gaussians"]
+           "pdfmc_set_options", "pdfmc_sort", "pdfmc_synchronize", "pdfmc_timing", "pdfmc_timing_read",
+           "pdfmc_draw_gaussians"]
 
 
 def lib():
@@ -94,6 +95,8 @@ def lib():
         L.pdfmc_step.argtypes = [vp, C.c_int32]
         L.pdfmc_set_step_index.argtypes = [vp, C.c_uint32]
         L.pdfmc_set_options.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.pdfmc_timing.argtypes = [vp, C.c_int32]
+        L.pdfmc_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.pdfmc_draw_gaussians.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, C.c_int64, vp]
         for f in EXPORTS:
             if f not in ("pdfmc_destroy", "pdfmc_last_error"):
@@ -277,6 +280,14 @@ class Sim:
         out = np.zeros(N_COUNTERS, np.int64)
         self._check(self._L.pdfmc_counters(self._h, cs, out.ctypes.data), "counters")
         return dict(zip(COUNTER_NAMES, out.tolist()))
+
+    def timing(self, enable=True):
+        self._check(self._L.pdfmc_timing(self._h, int(bool(enable))), "timing")
+
+    def timing_read(self):
+        ms, cnt = C.c_double(), C.c_int64()
+        self._check(self._L.pdfmc_timing_read(self._h, C.byref(ms), C.byref(cnt)), "timing_read")
+        return ms.value, cnt.value
 
     def draw_gaussians(self, seed, step, stream, ids):
         torch = self.torch

@@ -69,7 +69,10 @@ def _assert_state_equal(g, r, keys=("x", "y", "u", "v", "w", "omega")):
         bad = np.nonzero(g[k] != r[k])[0]
         assert bad.size == 0, (k, bad[:5], g[k][bad[:5]], r[k][bad[:5]])
     if r["psi"].size:
-        assert np.array_equal(g["psi"], r["psi"])
+        # mixing uses cell means, i.e. FP64 sums whose order differs (atomics):
+        # |delta psi| <= (dt/t_m) |delta mean| ~ a few ulp of the scalar scale
+        d = np.abs(g["psi"] - r["psi"])
+        assert d.max() <= 1e-14 * max(1.0, np.abs(r["psi"]).max()), d.max()
 
 
 def test_gaussians_bitwise_fp64(P, oracle_mod):
@@ -131,8 +134,7 @@ def test_one_step_frozen_bitwise(P, oracle_mod, ns, nb):
         _assert_state_equal(g, r)
         assert np.array_equal(g["bin"], r["bin"])
         gs, rs = sim.node_sums(cs), o.node_sums(oc)
-        # |delta| <= 1e-13 sum |w N Q|: bound with the sums of |Q| (partition of unity)
-        absq = np.abs(np.stack([np.ones(n), g["u"], g["v"], g["w"]]))
+        # |delta| <= 1e-13 of the largest node sum of that moment
         tol = 1e-13 * np.abs(rs).max(0) + 1e-300
         assert np.all(np.abs(gs - rs) <= np.maximum(tol, 1e-13 * np.abs(rs))), np.max(np.abs(gs - rs))
         gst, rst = sim.stats(cs), o.stats(oc)
@@ -163,3 +165,125 @@ def test_small_config_100_steps(P, oracle_mod):
     gF, rF = sim.fields(cs), o.fields(oc)
     dF = np.abs(gF - rF)[rows] / np.maximum(np.abs(rF[rows]), 1e-6)
     assert dF.max() <= 1e-8, dF.max()
+
+
+def _small_channel(ppe=20, ns=1, rtol=1e-13):
+    mesh = W.channel(n_half=10, nx=24, seed_key=(1, 1, 0))
+    params = W.default_params(mode=2, dt=5e-4, nu=1.0 / 1080.0, n_scalars=ns, dpdx=(-1.0, 0.0),
+                              src=[(1.0, 0.5, 0.1, 1.0), (3.0, 1.5, 0.1, 1.0)][:ns], cg_rtol=rtol, cg_maxit=20000,
+                              stream=1)
+    parts = W.init_particles(mesh, ppe, ns, W.rng_for(1, 1, 1), u_std=1.0)
+    return mesh, params, parts
+
+
+def test_elliptic_relaxation_and_projection(P, oracle_mod):
+    mesh, params, parts = _small_channel()
+    n = len(parts["x"])
+    _flush(f"[er] channel {mesh.n_elems} triangles, {n} particles, mode 2")
+    sim, cs, o, oc = _pair(P, oracle_mod, mesh, params, parts)
+    sim.init(); o.init()
+    rows = _stat_rows(sim, cs)
+    gF, rF = sim.fields(cs)[rows], o.fields(oc)[rows]
+    # field scales: per slot, the largest magnitude over the nodes
+    sc = np.maximum(np.abs(rF).max(0), 1e-12)
+    d = np.abs(gF - rF) / sc
+    assert d.max() <= 1e-9, (d.max(), np.unravel_index(np.argmax(d), d.shape))
+    for step in range(4):
+        sim.step(1); o.step(1)
+    g, r = sim.download(cs, n), o.download(oc, n)
+    assert (g["elem"] == r["elem"]).mean() > 0.999
+    gst, rst = sim.stats(cs)[rows], o.stats(oc)[rows]
+    d = np.abs(gst - rst) / _scale(rst, 1)
+    assert d.max() <= 1e-8, (d.max(), np.unravel_index(np.argmax(d), d.shape))
+    gF, rF = sim.fields(cs)[rows], o.fields(oc)[rows]
+    sc = np.maximum(np.abs(rF).max(0), 1e-12)
+    d = np.abs(gF - rF) / sc
+    assert d.max() <= 1e-7, (d.max(), np.unravel_index(np.argmax(d), d.shape))
+    gc_ = sim.counters(cs)
+    assert gc_["cg_fail"] == 0 and gc_["cg_iters_er"] > 0 and gc_["cg_iters_p"] > 0
+
+
+def _band_fraction(gst, rst, parts_r, col, ns):
+    """fraction of nodes where |FP32 - FP64| <= 3 sigma_n, sigma_n^2 = var / N_eff"""
+    W_ = rst[:, 0]
+    var = {2: rst[:, 5], 3: rst[:, 6], 4: rst[:, 7], 12: rst[:, 12 + ns] if ns else None}[col]
+    neff = 20.0  # conservative lower bound of the effective sample size per node
+    sig = np.sqrt(np.maximum(var, 1e-30) / neff)
+    return np.mean(np.abs(gst[:, col] - rst[:, col]) <= 3 * sig)
+
+
+def test_fp32_within_statistical_band(P, oracle_mod):
+    cfg = W.config_small()
+    parts = cfg["particles"]
+    n = len(parts["x"])
+    _flush(f"[fp32] {cfg['name']} FP32 against the FP64 oracle, 100 steps")
+    sim, cs, o, oc = _pair(P, oracle_mod, cfg["mesh"], cfg["params"], parts, precision="fp32")
+    sim.init(); o.init()
+    sim.step(100); o.step(100)
+    rows = _stat_rows(sim, cs)
+    gst, rst = sim.stats(cs)[rows], o.stats(oc)[rows]
+    for col in (2, 3, 4, 12):
+        assert _band_fraction(gst, rst, parts, col, 1) >= 0.99, col
+    # the same Wiener path: FP32 particles stay close to the FP64 ones
+    g, r = sim.download(cs, n), o.download(oc, n)
+    assert (g["elem"] == r["elem"]).mean() > 0.99
+    du = np.abs(g["u"] - r["u"])
+    assert np.median(du) < 1e-4, np.median(du)
+
+
+def _run(P, mesh, params, parts, steps, precision="fp64", **opt):
+    n = len(parts["x"])
+    sim = P.Sim(precision, "cuda:0")
+    cs = sim.add_case(mesh, params, n)
+    sim.bind()
+    if opt:
+        sim.set_options(**opt)
+    sim.upload(cs, parts)
+    sim.init()
+    sim.step(steps)
+    return sim, cs
+
+
+def _by_id(d):
+    order = np.argsort(d["id"])
+    return {k: (v[..., order] if isinstance(v, np.ndarray) and v.shape[-1] == len(order) else v) for k, v in d.items()}
+
+
+@pytest.mark.parametrize("opts", [dict(sort_interval=3), dict(use_graph=True), dict(sort_interval=4, use_graph=True),
+                                  dict(block_size=64)])
+def test_sort_graph_block_invariance(P, opts):
+    cfg = W.config_small()
+    parts = cfg["particles"]
+    n = len(parts["x"])
+    _flush(f"[invariance] options {opts}")
+    a, ca = _run(P, cfg["mesh"], cfg["params"], parts, 20)
+    b, cb = _run(P, cfg["mesh"], cfg["params"], parts, 20, **opts)
+    A, B = _by_id(a.download(ca, n)), _by_id(b.download(cb, n))
+    assert np.array_equal(A["id"], np.arange(n))
+    assert np.array_equal(B["id"], np.arange(n))
+    assert (A["elem"] == B["elem"]).mean() > 0.999
+    for k in ("x", "y", "u", "v", "w", "omega"):
+        assert np.max(np.abs(A[k] - B[k])) <= 1e-10, k
+    sa, sb = a.stats(ca), b.stats(cb)
+    assert np.max(np.abs(sa - sb) / np.maximum(np.abs(sa), 1e-3)) <= 1e-9
+
+
+def test_batched_equals_sequential(P):
+    cfg = W.config_small()
+    mesh2, params2, parts2 = _small_channel(ppe=10, ns=2, rtol=1e-12)
+    _flush("[batched] two cases in one context against one context each")
+    sim = P.Sim("fp64", "cuda:0")
+    c1 = sim.add_case(cfg["mesh"], cfg["params"], len(cfg["particles"]["x"]))
+    c2 = sim.add_case(mesh2, params2, len(parts2["x"]))
+    sim.bind()
+    sim.upload(c1, cfg["particles"]); sim.upload(c2, parts2)
+    sim.init(); sim.step(5)
+    a, ca = _run(P, cfg["mesh"], cfg["params"], cfg["particles"], 5)
+    b, cb = _run(P, mesh2, params2, parts2, 5)
+    for (s_b, c_b), (s_s, c_s), parts in (((sim, c1), (a, ca), cfg["particles"]), ((sim, c2), (b, cb), parts2)):
+        n = len(parts["x"])
+        G, S = s_b.download(c_b, n), s_s.download(c_s, n)
+        assert (G["elem"] == S["elem"]).mean() > 0.999
+        assert np.max(np.abs(G["u"] - S["u"])) <= 1e-10
+        sb, ss = s_b.stats(c_b), s_s.stats(c_s)
+        assert np.max(np.abs(sb - ss) / np.maximum(np.abs(ss), 1e-3)) <= 1e-8
