@@ -77,9 +77,9 @@ def run_gpu(cfg, prec, steps, warmup, opts):
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
+    start.record(sim.stream)
     sim.step(steps)
-    stop.record()
+    stop.record(sim.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)

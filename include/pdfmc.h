@@ -162,8 +162,9 @@ pdfmc_status pdfmc_cell_means(pdfmc_ctx* ctx, int32_t case_id, double* mean, int
 pdfmc_status pdfmc_counters(pdfmc_ctx* ctx, int32_t case_id, int64_t* out);
 
 /* Execution options: re-sort the particles by element every sort_interval
- * steps (0 = never), particle-kernel block size (64..1024, multiple of 64),
- * capture the step sequence into a HIP graph (0/1). */
+ * steps (0 = never), particle-kernel block size (64, 128, 192 or 256),
+ * capture the step sequence into a HIP graph (0/1; needs a non-NULL stream,
+ * else PDFMC_E_INVALID). */
 pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t block_size, int32_t use_graph);
 /* Sort the particles of every case by element now (stable counting sort). */
 pdfmc_status pdfmc_sort(pdfmc_ctx* ctx);

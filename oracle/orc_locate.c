@@ -3,7 +3,9 @@
  *
  *  R-12 walk: in element e compute lambda (R-05); if min lambda >= 0 stop;
  *       otherwise cross the edge k* = argmin lambda (ties -> smallest k);
- *       at most 1024 walk iterations.
+ *       at most 1024 walk iterations. A step straight back into the element
+ *       just left (possible only through rounding on their shared edge) ends
+ *       the walk in whichever of the two has the larger min lambda.
  *  R-14 wall (no-slip imposed on particles only, Sec. I): mirror X across the
  *       wall edge line, U <- 2 U_wall - U for all three components, stay in
  *       the element; at most 8 reflections per step.
@@ -43,6 +45,8 @@ int orc_walk_case(ocase* cs, int e0, double* px, double* py, double u3[3])
         return e0;
     }
     int e = e0, nrefl = 0;
+    int prev = -1;                       /* element left by the last crossing */
+    double prev_min = 0.0, prev_x = 0.0, prev_y = 0.0;
     for (int it = 0; it < WALK_CAP; ++it) {
         double l[3];
         omesh_bary(m, e, x, y, l);
@@ -50,17 +54,27 @@ int orc_walk_case(ocase* cs, int e0, double* px, double* py, double u3[3])
         if (l[1] < l[k]) k = 1;
         if (l[2] < l[k]) k = 2;
         if (l[k] >= 0.0) { *px = x; *py = y; return e; }
-        cs->cnt[CNT_WALK_STEPS]++;
         int nb = m->nbr[3 * e + k];
-        if (nb >= 0) { e = nb; continue; }
-        const orc_bc* bc = &m->bc[m->tag[3 * e + k]];
+        const orc_bc* bc = nb >= 0 ? NULL : &m->bc[m->tag[3 * e + k]];
+        int next = nb >= 0 ? nb : (bc->type == ORC_BC_PERIODIC ? m->partner[3 * e + k] : e);
+        if (next == prev && next != e) {
+            /* two-cycle across one edge: only rounding on that edge can cause
+             * it; keep the element with the larger min lambda (R-12) */
+            if (prev_min > l[k]) { *px = prev_x; *py = prev_y; return prev; }
+            *px = x; *py = y;
+            return e;
+        }
+        cs->cnt[CNT_WALK_STEPS]++;
+        if (nb >= 0) { prev = e; prev_min = l[k]; prev_x = x; prev_y = y; e = nb; continue; }
         if (bc->type == ORC_BC_PERIODIC) {
+            prev = e; prev_min = l[k]; prev_x = x; prev_y = y;
             x = x + bc->shift[0];
             y = y + bc->shift[1];
             e = m->partner[3 * e + k];
             cs->cnt[CNT_PERIODIC]++;
             continue;
         }
+        prev = -1;
         /* wall */
         if (nrefl == REFLECT_CAP) break;
         int a = m->tri[3 * e + (k + 1) % 3], b = m->tri[3 * e + (k + 2) % 3];

@@ -27,9 +27,10 @@ namespace pdfmc {
 template <typename R> __device__ inline R rfma(R a, R b, R c);
 template <> __device__ inline double rfma<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <> __device__ inline float rfma<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-template <typename R> __device__ inline R rsqrt_cr(R a);
-template <> __device__ inline double rsqrt_cr<double>(double a) { return __builtin_sqrt(a); }
-template <> __device__ inline float rsqrt_cr<float>(float a) { return __builtin_sqrtf(a); }
+// square root: correctly rounded in FP64 (required for bit parity), hardware in FP32
+template <typename R> __device__ inline R r_sqrt(R a);
+template <> __device__ inline double r_sqrt<double>(double a) { return __builtin_sqrt(a); }
+template <> __device__ inline float r_sqrt<float>(float a) { return __builtin_sqrtf(a); }
 
 __device__ inline int pick(const int4& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 
@@ -47,48 +48,76 @@ __device__ inline void bary(const R* __restrict__ rec, int e, R x, R y, R lam[3]
 struct WalkCount { int refl, per, steps, fallback; };
 
 // R-12..R-15 walk; returns the element holding (x, y) and its lambda.
+// A step straight back into the element just left (rounding on their shared
+// edge) ends the walk in whichever of the two has the larger min lambda.
+// Fallback (cap reached): FP64 follows R-13 (brute force over the case);
+// FP32, whose rounding near thin wall cells can make every element look
+// slightly outside, keeps the visited element with the largest min lambda.
 template <typename R>
 __device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R u3[3], R lam[3], WalkCount& wc)
 {
     int nrefl = 0;
+    int prev = -1;
+    R prev_min = R(0), prev_x = R(0), prev_y = R(0);
+    int best = e;
+    R best_min = R(-1e30), best_x = x, best_y = y;
     for (int it = 0; it < 1024; ++it) {
         bary<R>(M.rec, e, x, y, lam);
         int k = 0;
         if (lam[1] < lam[k]) k = 1;
         if (lam[2] < lam[k]) k = 2;
         if (lam[k] >= R(0)) return e;
+        if constexpr (sizeof(R) == 4) {
+            if (lam[k] > best_min) { best = e; best_min = lam[k]; best_x = x; best_y = y; }
+        }
+        const int nb = pick(M.nbr[e], k);
+        const BcDev* bc = nb >= 0 ? nullptr : &M.bc[-1 - nb];
+        const int next = nb >= 0 ? nb : (bc->type == 1 ? pick(M.partner[e], k) : e);
+        if (next == prev && next != e) {
+            if (prev_min > lam[k]) {
+                x = prev_x; y = prev_y;
+                bary<R>(M.rec, prev, x, y, lam);
+                return prev;
+            }
+            return e;
+        }
         wc.steps++;
-        int nb = pick(M.nbr[e], k);
-        if (nb >= 0) { e = nb; continue; }
-        const BcDev& bc = M.bc[-1 - nb];
-        if (bc.type == 1) {
-            if constexpr (sizeof(R) == 8) { x = x + bc.shift[0]; y = y + bc.shift[1]; }
-            else { x = x + bc.shiftf[0]; y = y + bc.shiftf[1]; }
-            e = pick(M.partner[e], k);
+        if (nb >= 0) { prev = e; prev_min = lam[k]; prev_x = x; prev_y = y; e = nb; continue; }
+        if (bc->type == 1) {
+            prev = e; prev_min = lam[k]; prev_x = x; prev_y = y;
+            if constexpr (sizeof(R) == 8) { x = x + bc->shift[0]; y = y + bc->shift[1]; }
+            else { x = x + bc->shiftf[0]; y = y + bc->shiftf[1]; }
+            e = next;
             wc.per++;
             continue;
         }
+        prev = -1;
         if (nrefl == 8) break;
         const R* v = M.exy + 6 * (int64_t)e;
         int ka = (k + 1) % 3, kb = (k + 2) % 3;
         R xa = v[2 * ka], ya = v[2 * ka + 1];
         R ex = v[2 * kb] - xa, ey = v[2 * kb + 1] - ya;
-        R L = rsqrt_cr<R>(ex * ex + ey * ey);
+        R L = r_sqrt<R>(ex * ex + ey * ey);
         R nx = ey / L, ny = -ex / L;
         R d = (x - xa) * nx + (y - ya) * ny;
         x = x - (R(2) * d) * nx;
         y = y - (R(2) * d) * ny;
         for (int i = 0; i < 3; ++i) {
             R uw;
-            if constexpr (sizeof(R) == 8) uw = bc.uw[i]; else uw = bc.uwf[i];
+            if constexpr (sizeof(R) == 8) uw = bc->uw[i]; else uw = bc->uwf[i];
             u3[i] = R(2) * uw - u3[i];
         }
         nrefl++;
         wc.refl++;
     }
-    // R-13 fallback: lowest-index containing element, else the one maximising min lambda
     wc.fallback++;
-    int best = -1;
+    if constexpr (sizeof(R) == 4) {
+        x = best_x; y = best_y;
+        bary<R>(M.rec, best, x, y, lam);
+        return best;
+    }
+    // R-13: lowest-index containing element, else the one maximising min lambda
+    int bf = -1;
     R bestv = R(0);
     for (int q = C.eoff; q < C.eoff + C.ne; ++q) {
         R l[3];
@@ -96,11 +125,11 @@ __device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R 
         R mn = l[0];
         if (l[1] < mn) mn = l[1];
         if (l[2] < mn) mn = l[2];
-        if (mn >= R(0)) { best = q; break; }
-        if (best < 0 || mn > bestv) { best = q; bestv = mn; }
+        if (mn >= R(0)) { bf = q; break; }
+        if (bf < 0 || mn > bestv) { bf = q; bestv = mn; }
     }
-    bary<R>(M.rec, best, x, y, lam);
-    return best;
+    bary<R>(M.rec, bf, x, y, lam);
+    return bf;
 }
 
 // ---------------------------------------------------------------- wave helpers
@@ -220,7 +249,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             const R u = u3[0], v = u3[1], w = u3[2];
             const R d1 = u - f[F_U1], d2 = v - f[F_U2], d3 = w - f[F_U3];
             const R c0e = f[F_C0EPS] > R(0) ? f[F_C0EPS] : R(0);
-            const R sq_c0 = rsqrt_cr<R>(c0e * dt);
+            const R sq_c0 = r_sqrt<R>(c0e * dt);
             R du = dt * ((-f[F_DPX] + tnu * f[F_LAP1]) + (f[F_G11] * d1 + f[F_G12] * d2))
                  + sq_nu * (f[F_DU1X] * xi[0] + f[F_DU1Y] * xi[1]) + sq_c0 * xi[2];
             R dv = dt * ((-f[F_DPY] + tnu * f[F_LAP2]) + (f[F_G21] * d1 + f[F_G22] * d2))
@@ -235,7 +264,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             const R W = f[F_OMEGA], S = f[F_SOMEGA];
             const R drift = ((-C3 * W) * (om - W)) - ((S * W) * om);
             const R omp = om > R(0) ? om : R(0);
-            const R diff = rsqrt_cr<R>(((c34 * (W * W)) * omp) * dt);
+            const R diff = r_sqrt<R>(((c34 * (W * W)) * omp) * dt);
             R omn = (om + dt * drift) + diff * xi[5];
             if (omn < R(0)) { omn = -omn; flips = 1; }
             om = omn;

@@ -943,6 +943,8 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* c, int32_t sort_interval, int32_t bloc
     if (!c) return PDFMC_E_INVALID;
     if (sort_interval < 0) return fail(c, PDFMC_E_INVALID, "set_options: sort_interval < 0");
     if (block_size < 64 || block_size > 256 || block_size % 64) return fail(c, PDFMC_E_INVALID, "set_options: block size must be 64, 128, 192 or 256");
+    if (use_graph && c->stream == nullptr)
+        return fail(c, PDFMC_E_INVALID, "set_options: graph capture needs a stream other than the default (NULL) stream");
     if (block_size != c->block) drop_graphs(c);
     c->sort_interval = sort_interval;
     c->block = block_size;

@@ -125,7 +125,9 @@ class Sim:
             if not torch.cuda.is_available():
                 raise RuntimeError("no GPU visible: the pdfmc library runs on the GPU only")
             self.device = torch.device(device)
-            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            # a stream of our own (default priority): graph capture needs a
+            # stream other than the legacy default stream
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
             handle = self.stream.cuda_stream
         self._L = lib()
         h = C.c_void_p()
@@ -190,7 +192,8 @@ class Sim:
         if self.host_only:
             raise RuntimeError("a host-only context cannot bind a device workspace")
         nbytes = self.workspace_bytes()
-        self._ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        with self.torch.cuda.stream(self.stream):
+            self._ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
         self._check(self._L.pdfmc_workspace_bind(self._h, C.c_void_p(self._ws.data_ptr()), nbytes), "workspace_bind")
         return nbytes
 
