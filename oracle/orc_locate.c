@@ -3,7 +3,7 @@
  *
  *  R-12 walk: in element e compute lambda (R-05); if min lambda >= 0 stop;
  *       otherwise cross the edge k* = argmin lambda (ties -> smallest k);
- *       at most 1024 walk iterations. A step straight back into the element
+ *       at most 64 walk iterations. A step straight back into the element
  *       just left (possible only through rounding on their shared edge) ends
  *       the walk in whichever of the two has the larger min lambda.
  *  R-14 wall (no-slip imposed on particles only, Sec. I): mirror X across the
@@ -16,7 +16,7 @@
 #include "orc_internal.h"
 #include <math.h>
 
-#define WALK_CAP 1024
+#define WALK_CAP 64
 #define REFLECT_CAP 8
 
 static double min3(const double l[3]) { double m = l[0]; if (l[1] < m) m = l[1]; if (l[2] < m) m = l[2]; return m; }

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdfmc.so")
 HIP_SOURCES = ["pdfmc_api.hip", "k_particle.hip", "k_nodes.hip", "k_sort.hip"]
-CXX_SOURCES = ["pdfmc_mesh.cpp"]
+CXX_SOURCES = ["pdfmc_mesh.cpp", "pdfmc_amg.cpp"]
 ARCH = os.environ.get("PDFMC_ARCH", "gfx950")
 
 

@@ -348,7 +348,7 @@ __global__ void k_mirror_f32(const double* __restrict__ F, float* __restrict__ F
 
 __device__ inline void block_sum(double* v, int nv, double* sh)
 {
-    // sh: [32 * 4] doubles of LDS; nv <= 4
+    // sh: [16 * 4] doubles of LDS; nv <= 4
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int k = 0; k < nv; ++k) {
         double x = v[k];
@@ -364,14 +364,158 @@ __device__ inline void block_sum(double* v, int nv, double* sh)
     __syncthreads();
 }
 
-// One workgroup per system: rows [r0, r0+n) of a global CSR matrix.
+__global__ void k_galerkin(const GalJob* __restrict__ jobs)
+{
+    const GalJob J = jobs[blockIdx.y];
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < J.nnz; k += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = J.gptr[k]; j < J.gptr[k + 1]; ++j) s += J.gcoef[j] * J.src[J.gidx[j]];
+        J.dst[k] = s;
+    }
+}
+
+// Level views used by the V-cycle inside one workgroup.
+struct Lvl {
+    int n, coff;                    // rows; column offset (r0 on level 0, else 0)
+    const int32_t* Ap; const int32_t* Ac; const double* Av;
+    double *dinv, *x, *b, *t;
+};
+
+__device__ inline Lvl level(const AmgDev& H, double* work, int l, double* b0, double* x0)
+{
+    Lvl L;
+    L.n = H.n[l];
+    L.coff = l == 0 ? H.r0 : 0;
+    L.Ap = H.Aptr[l]; L.Ac = H.Acol[l]; L.Av = H.Aval[l];
+    int64_t off = 0;
+    for (int q = 0; q < l; ++q) off += 4 * (int64_t)H.n[q];
+    L.dinv = work + off;
+    L.x = l == 0 ? x0 : work + off + H.n[l];
+    L.b = l == 0 ? b0 : work + off + 2 * (int64_t)H.n[l];
+    L.t = work + off + 3 * (int64_t)H.n[l];
+    return L;
+}
+
+// t = b - A x on one level
+__device__ inline void lvl_residual(const Lvl& L)
+{
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+        double s = 0.0;
+        for (int j = L.Ap[i]; j < L.Ap[i + 1]; ++j) s += L.Av[j] * L.x[L.Ac[j] - L.coff];
+        L.t[i] = L.b[i] - s;
+    }
+    __syncthreads();
+}
+
+__device__ inline void lvl_jacobi(const Lvl& L, double w)
+{
+    lvl_residual(L);
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.x[i] += w * L.dinv[i] * L.t[i];
+    __syncthreads();
+}
+
+// z = V(r): one symmetric V-cycle (two Jacobi sweeps before and after the
+// coarse correction, dense solve on the coarsest level).
+__device__ void vcycle(const AmgDev& H, double* work, const double* ainv, double* r, double* z)
+{
+    const int nl = H.nlev;
+    for (int l = 0; l < nl - 1; ++l) {
+        Lvl L = level(H, work, l, r, z);
+        // first sweep from x = 0
+        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.x[i] = H.omega[l] * L.dinv[i] * L.b[i];
+        __syncthreads();
+        lvl_jacobi(L, H.omega[l]);
+        lvl_residual(L);
+        // restrict: b_{l+1} = R t
+        Lvl C = level(H, work, l + 1, r, z);
+        for (int i = threadIdx.x; i < C.n; i += blockDim.x) {
+            double s = 0.0;
+            for (int j = H.Rptr[l][i]; j < H.Rptr[l][i + 1]; ++j) s += H.Rval[l][j] * L.t[H.Rcol[l][j]];
+            C.b[i] = s;
+        }
+        __syncthreads();
+    }
+    {
+        Lvl C = level(H, work, nl - 1, r, z);
+        for (int i = threadIdx.x; i < C.n; i += blockDim.x) {
+            double s = 0.0;
+            for (int j = 0; j < C.n; ++j) s += ainv[i * AMG_MAXC + j] * C.b[j];
+            C.x[i] = s;
+        }
+        __syncthreads();
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+        Lvl L = level(H, work, l, r, z);
+        Lvl C = level(H, work, l + 1, r, z);
+        for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+            double s = 0.0;
+            for (int j = H.Pptr[l][i]; j < H.Pptr[l][i + 1]; ++j) s += H.Pval[l][j] * C.x[H.Pcol[l][j]];
+            L.x[i] += s;
+        }
+        __syncthreads();
+        lvl_jacobi(L, H.omega[l]);
+        lvl_jacobi(L, H.omega[l]);
+    }
+}
+
+// Prologue of a multigrid-preconditioned solve: Jacobi diagonals on every
+// level and the inverse of the (slightly shifted) coarsest matrix, by
+// Gauss-Jordan elimination in LDS (the matrix is symmetric positive).
+__device__ void amg_prepare(const AmgDev& H, double* work, double* ainv, double* r, double* z)
+{
+    for (int l = 0; l < H.nlev; ++l) {
+        Lvl L = level(H, work, l, r, z);
+        for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
+            double d = 1.0;
+            for (int j = L.Ap[i]; j < L.Ap[i + 1]; ++j)
+                if (L.Ac[j] - L.coff == i) d = L.Av[j];
+            L.dinv[i] = 1.0 / d;
+        }
+    }
+    const int nc = H.n[H.nlev - 1];
+    const int lc = H.nlev - 1;
+    const int coff = lc == 0 ? H.r0 : 0;
+    for (int q = threadIdx.x; q < AMG_MAXC * AMG_MAXC; q += blockDim.x) ainv[q] = 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nc; i += blockDim.x)
+        for (int j = H.Aptr[lc][i]; j < H.Aptr[lc][i + 1]; ++j) ainv[i * AMG_MAXC + (H.Acol[lc][j] - coff)] = H.Aval[lc][j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) ainv[i * AMG_MAXC + i] *= (1.0 + H.coarse_shift);
+    __syncthreads();
+    // in-place Gauss-Jordan inversion without pivoting
+    __shared__ double piv_row[AMG_MAXC], piv_col[AMG_MAXC];
+    for (int k = 0; k < nc; ++k) {
+        const double p = ainv[k * AMG_MAXC + k];
+        for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+            piv_row[j] = ainv[k * AMG_MAXC + j];
+            piv_col[j] = ainv[j * AMG_MAXC + k];
+        }
+        __syncthreads();
+        const double ip = 1.0 / p;
+        for (int q = threadIdx.x; q < nc * nc; q += blockDim.x) {
+            const int i = q / nc, j = q % nc;
+            double v;
+            if (i == k && j == k) v = ip;
+            else if (i == k) v = piv_row[j] * ip;
+            else if (j == k) v = -piv_col[i] * ip;
+            else v = ainv[i * AMG_MAXC + j] - piv_col[i] * piv_row[j] * ip;
+            ainv[i * AMG_MAXC + j] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per system: rows [r0, r0+n) of a global CSR matrix;
+// Jacobi or multigrid (one V-cycle) preconditioning.
 __global__ void __launch_bounds__(1024) k_cg(const CgJob* __restrict__ jobs)
 {
     const CgJob J = jobs[blockIdx.x];
     if (J.n <= 0) return;
     __shared__ double sh[16 * 4];
+    __shared__ double ainv[AMG_MAXC * AMG_MAXC];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int n = J.n, r0 = J.r0;
+    const bool mg = J.amg != nullptr;
     double v[4];
     if (J.mean_free) {
         v[0] = 0.0;
@@ -381,8 +525,9 @@ __global__ void __launch_bounds__(1024) k_cg(const CgJob* __restrict__ jobs)
         for (int i = tid; i < n; i += nt) J.b[r0 + i] -= mb;
         __syncthreads();
     }
-    // r = b - A x, z = D^-1 r, p = z
-    v[0] = 0.0; v[1] = 0.0; v[2] = 0.0;
+    if (mg) amg_prepare(*J.amg, J.amg_work, ainv, J.r + r0, J.q + r0);
+    // r = b - A x
+    v[0] = 0.0;
     for (int i = tid; i < n; i += nt) {
         const int row = r0 + i;
         double ax = 0.0, d = 1.0;
@@ -391,18 +536,40 @@ __global__ void __launch_bounds__(1024) k_cg(const CgJob* __restrict__ jobs)
             ax += J.val[j] * J.x[col];
             if (col == row) d = J.val[j];
         }
-        const double rr = J.b[row] - ax;
-        const double di = 1.0 / d;
-        J.dinv[row] = di;
-        J.r[row] = rr;
-        const double z = di * rr;
-        J.p[row] = z;
-        v[0] += rr * z; v[1] += rr * rr; v[2] += J.b[row] * J.b[row];
+        J.dinv[row] = 1.0 / d;
+        J.r[row] = J.b[row] - ax;
+        v[0] += J.b[row] * J.b[row];
     }
-    block_sum(v, 3, sh);
-    double rz = v[0], rr = v[1];
-    const double bb = v[2];
+    block_sum(v, 1, sh);
+    const double bb = v[0];
     const double tol2 = J.tol * J.tol * bb;
+    // z = M^-1 r (q holds z), p = z
+    auto precondition = [&](double* out) {
+        if (mg) {
+            vcycle(*J.amg, J.amg_work, ainv, J.r + r0, J.q + r0);
+            if (J.mean_free) {
+                double m[1] = {0.0};
+                for (int i = tid; i < n; i += nt) m[0] += J.q[r0 + i];
+                block_sum(m, 1, sh);
+                const double mz = m[0] / n;
+                for (int i = tid; i < n; i += nt) J.q[r0 + i] -= mz;
+            }
+        } else {
+            for (int i = tid; i < n; i += nt) J.q[r0 + i] = J.dinv[r0 + i] * J.r[r0 + i];
+        }
+        __syncthreads();
+        out[0] = 0.0; out[1] = 0.0;
+        for (int i = tid; i < n; i += nt) {
+            const int row = r0 + i;
+            out[0] += J.r[row] * J.q[row];
+            out[1] += J.r[row] * J.r[row];
+        }
+        block_sum(out, 2, sh);
+    };
+    precondition(v);
+    double rz = v[0], rr = v[1];
+    for (int i = tid; i < n; i += nt) J.p[r0 + i] = J.q[r0 + i];
+    __syncthreads();
     int it = 0;
     bool ok = (rr <= tol2);
     while (!ok && it < J.maxit) {
@@ -425,21 +592,13 @@ __global__ void __launch_bounds__(1024) k_cg(const CgJob* __restrict__ jobs)
             J.r[row] = rn;
             v[0] += rn;
         }
-        double mr = 0.0;
+        block_sum(v, 1, sh);
         if (J.mean_free) {
-            block_sum(v, 1, sh);
-            mr = v[0] / n;
+            const double mr = v[0] / n;
+            for (int i = tid; i < n; i += nt) J.r[r0 + i] -= mr;
+            __syncthreads();
         }
-        v[0] = 0.0; v[1] = 0.0;
-        for (int i = tid; i < n; i += nt) {
-            const int row = r0 + i;
-            const double rn = J.r[row] - mr;
-            J.r[row] = rn;
-            const double z = J.dinv[row] * rn;
-            J.q[row] = z;                 // q now holds z
-            v[0] += rn * z; v[1] += rn * rn;
-        }
-        block_sum(v, 2, sh);
+        precondition(v);
         const double beta = v[0] / rz;
         rz = v[0]; rr = v[1];
         for (int i = tid; i < n; i += nt) {

@@ -61,7 +61,8 @@ __device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R 
     R prev_min = R(0), prev_x = R(0), prev_y = R(0);
     int best = e;
     R best_min = R(-1e30), best_x = x, best_y = y;
-    for (int it = 0; it < 1024; ++it) {
+    int ring[4] = {-1, -1, -1, -1};   // FP32: recently left elements
+    for (int it = 0; it < 64; ++it) {
         bary<R>(M.rec, e, x, y, lam);
         int k = 0;
         if (lam[1] < lam[k]) k = 1;
@@ -73,6 +74,12 @@ __device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R 
         const int nb = pick(M.nbr[e], k);
         const BcDev* bc = nb >= 0 ? nullptr : &M.bc[-1 - nb];
         const int next = nb >= 0 ? nb : (bc->type == 1 ? pick(M.partner[e], k) : e);
+        if constexpr (sizeof(R) == 4) {
+            // a longer cycle (rounding around a vertex): stop in the best element seen
+            if (next != e && next != prev && (next == ring[0] || next == ring[1] || next == ring[2] || next == ring[3]))
+                break;
+            ring[it & 3] = e;
+        }
         if (next == prev && next != e) {
             if (prev_min > lam[k]) {
                 x = prev_x; y = prev_y;

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/pdfmc.h"
+#include "pdfmc_amg.h"
 #include "pdfmc_kernels.h"
 #include "pdfmc_mesh.h"
 
@@ -25,13 +26,101 @@ using namespace pdfmc;
 
 namespace {
 
+// Offsets of one multigrid hierarchy's arrays inside the flat int/double
+// regions of the workspace (levels >= 1 for A; P, R and the Galerkin lists
+// for every level but the coarsest).
+struct HierOff {
+    int64_t Aptr[AMG_MAXL], Acol[AMG_MAXL], Aval[AMG_MAXL];
+    int64_t Pptr[AMG_MAXL], Pcol[AMG_MAXL], Pval[AMG_MAXL];
+    int64_t Rptr[AMG_MAXL], Rcol[AMG_MAXL], Rval[AMG_MAXL];
+    int64_t Gptr[AMG_MAXL], Gidx[AMG_MAXL], Gcoef[AMG_MAXL];
+};
+
 struct Case {
     pdfmc_case_params p{};
     MeshHost m;
     int64_t cap = 0, np = 0;
     int64_t poff = 0, psioff = 0, cmoff = 0, csoff = 0, nnz_off = 0, inc_off = 0;
     int eoff = 0, noff = 0, bcoff = 0;
+    // multigrid hierarchies of the two Eulerian solves (mode 2): 0 elliptic
+    // relaxation (wall rows isolated), 1 projection
+    bool has_amg = false;
+    AmgH amg[2];
+    double omega[2][AMG_MAXL] = {};
+    HierOff hoff[2];
+    int amg_index = -1;           // position among the cases with hierarchies
+    int64_t work_off = 0;         // per-job multigrid vectors
 };
+
+// serialise (or only size) one hierarchy into the flat regions
+void pack_hier(const AmgH& H, HierOff& o, std::vector<int32_t>* ai, std::vector<double>* ad, int64_t& ni, int64_t& nd)
+{
+    auto puti = [&](const std::vector<int>& v) {
+        int64_t at = ni;
+        if (ai) ai->insert(ai->end(), v.begin(), v.end());
+        ni += (int64_t)v.size();
+        return at;
+    };
+    auto putd = [&](const std::vector<double>& v) {
+        int64_t at = nd;
+        if (ad) ad->insert(ad->end(), v.begin(), v.end());
+        nd += (int64_t)v.size();
+        return at;
+    };
+    const int L = (int)H.lv.size();
+    for (int l = 0; l < L; ++l) {
+        const AmgLevelH& Lv = H.lv[l];
+        if (l >= 1) { o.Aptr[l] = puti(Lv.A.ptr); o.Acol[l] = puti(Lv.A.col); o.Aval[l] = putd(Lv.A.val); }
+        if (l + 1 < L) {
+            o.Pptr[l] = puti(Lv.P.ptr); o.Pcol[l] = puti(Lv.P.col); o.Pval[l] = putd(Lv.P.val);
+            o.Rptr[l] = puti(Lv.R.ptr); o.Rcol[l] = puti(Lv.R.col); o.Rval[l] = putd(Lv.R.val);
+            o.Gptr[l] = puti(Lv.gptr); o.Gidx[l] = puti(Lv.gidx); o.Gcoef[l] = putd(Lv.gcoef);
+        }
+    }
+}
+
+// spectral radius of D^-1 A (power iteration) -> Jacobi weight 4/(3 rho)
+double jacobi_weight(const CsrH& A)
+{
+    std::vector<double> d(A.n, 1.0), v(A.n), w(A.n);
+    for (int i = 0; i < A.n; ++i)
+        for (int j = A.ptr[i]; j < A.ptr[i + 1]; ++j)
+            if (A.col[j] == i && A.val[j] != 0.0) d[i] = A.val[j];
+    for (int i = 0; i < A.n; ++i) v[i] = 1.0 + 0.5 * std::sin(0.7 * i + 0.3);
+    double rho = 1.0;
+    for (int it = 0; it < 30; ++it) {
+        double nw = 0.0, nv = 0.0;
+        for (int i = 0; i < A.n; ++i) {
+            double s = 0.0;
+            for (int j = A.ptr[i]; j < A.ptr[i + 1]; ++j) s += A.val[j] * v[A.col[j]];
+            w[i] = s / d[i];
+            nw += w[i] * w[i]; nv += v[i] * v[i];
+        }
+        rho = std::sqrt(nw / std::max(nv, 1e-300));
+        const double sc = 1.0 / std::sqrt(std::max(nw, 1e-300));
+        for (int i = 0; i < A.n; ++i) v[i] = w[i] * sc;
+    }
+    return std::min(1.0, std::max(0.2, 4.0 / (3.0 * rho)));
+}
+
+// Stiffness matrix of the case on its own Galerkin pattern (host copy used
+// only to build the hierarchies).
+CsrH host_stiffness(const MeshHost& m)
+{
+    CsrH K;
+    K.n = K.m = m.nsn;
+    K.ptr = m.csr_ptr;
+    K.col = m.csr_col;
+    K.val.assign(m.csr_col.size(), 0.0);
+    for (int s = 0; s < m.nsn; ++s)
+        for (int j = m.inc_ptr[s]; j < m.inc_ptr[s + 1]; ++j) {
+            const int e = m.inc[j] / 3, a = m.inc[j] % 3;
+            const double* rc = &m.rec[8 * (size_t)e];
+            for (int cc = 0; cc < 3; ++cc)
+                K.val[m.incpos[3 * (size_t)j + cc]] += m.area[e] * (rc[2 + a] * rc[2 + cc] + rc[5 + a] * rc[5 + cc]);
+        }
+    return K;
+}
 
 struct PartBufs {
     char *x, *y, *u, *v, *w, *om, *wt, *psi;   // Real arrays (FP64 or FP32)
@@ -86,6 +175,18 @@ struct pdfmc_ctx {
     int steps_since_sort = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool any_er = false, any_eul = false, any_scalars = false;
+    // multigrid data: flat int/double regions, hierarchy descriptors,
+    // Galerkin jobs of the relaxation hierarchies per level, per-job vectors
+    int64_t AMG_I = 0, AMG_D = 0, AMG_W = 0;
+    int n_amg = 0, amg_levels = 0;
+    int32_t* d_amg_i = nullptr;
+    double* d_amg_d = nullptr;
+    double* d_amg_work = nullptr;
+    AmgDev* d_amg = nullptr;
+    GalJob* d_gal = nullptr;           // [AMG_MAXL][n_amg]: relaxation, then projection at [AMG_MAXL*n_amg + ...]
+    int n_gal[AMG_MAXL] = {};
+    int n_gal_p[AMG_MAXL] = {};
+    int64_t gal_max[AMG_MAXL] = {}, gal_max_p[AMG_MAXL] = {};
     // live timing of the particle kernel: one event pair per launch
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -181,6 +282,11 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_sort_count, c->NE);
     k.take(c->d_sort_scan, c->NE);
     k.take(c->d_sort_cursor, c->NE);
+    k.take(c->d_amg_i, c->AMG_I);
+    k.take(c->d_amg_d, c->AMG_D);
+    k.take(c->d_amg_work, c->AMG_W);
+    k.take(c->d_amg, 2 * (size_t)std::max(c->n_amg, 1));
+    k.take(c->d_gal, 2 * (size_t)AMG_MAXL * std::max(c->n_amg, 1));
 }
 
 void compute_offsets(pdfmc_ctx* c)
@@ -199,6 +305,25 @@ void compute_offsets(pdfmc_ctx* c)
         cs.nnz_off = NNZ; NNZ += (int64_t)cs.m.csr_col.size();
         cs.inc_off = 3 * (int64_t)cs.eoff;
     }
+    int64_t ni = 0, nd = 0, nw = 0;
+    int na = 0, maxlev = 0;
+    for (auto& cs : c->cases) {
+        if (!cs.has_amg) { cs.amg_index = -1; continue; }
+        cs.amg_index = na++;
+        for (int h = 0; h < 2; ++h) {
+            pack_hier(cs.amg[h], cs.hoff[h], nullptr, nullptr, ni, nd);
+            maxlev = std::max(maxlev, (int)cs.amg[h].lv.size());
+        }
+        cs.work_off = nw;
+        int64_t per = 0;
+        for (int h = 0; h < 2; ++h) {
+            int64_t w = 0;
+            for (auto& lv : cs.amg[h].lv) w += 4 * (int64_t)lv.A.n;
+            per += (h == 0 ? NER : 1) * w;
+        }
+        nw += per;
+    }
+    c->AMG_I = ni; c->AMG_D = nd; c->AMG_W = nw; c->n_amg = na; c->amg_levels = maxlev;
     c->NP = NP; c->PSI = PSI; c->CM = CM; c->CS = CS; c->NE = NE; c->NN = NN; c->NBC = NBC; c->NNZ = (int)NNZ;
     c->ntiles = (int)(NP / TILE);
 }
@@ -347,6 +472,11 @@ pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
     }
     if (c->any_er) {
         hipLaunchKernelGGL(k_er_assemble, g, b, 0, c->stream, A);
+        for (int l = 0; l < AMG_MAXL; ++l) {
+            if (c->n_gal[l] == 0) continue;
+            hipLaunchKernelGGL(k_galerkin, dim3(std::min<int64_t>(nblk(c->gal_max[l], 256), 1024), c->n_gal[l]), dim3(256), 0,
+                               c->stream, (const GalJob*)(c->d_gal + (size_t)l * c->n_amg));
+        }
         hipLaunchKernelGGL(k_cg, dim3(c->n_jobs_er), dim3(1024), 0, c->stream, c->d_jobs_er);
         hipLaunchKernelGGL(k_er_finish, g, b, 0, c->stream, A);
         LAUNCHCHK(c);
@@ -479,6 +609,14 @@ pdfmc_status pdfmc_add_case(pdfmc_ctx* c, const pdfmc_mesh_desc* mesh, const pdf
     std::string err;
     int rc = derive_mesh(*mesh, cs.m, err);
     if (rc != PDFMC_OK) return fail(c, (pdfmc_status)rc, err);
+    if (p->mode == 2) {
+        const CsrH K = host_stiffness(cs.m);
+        amg_setup(K, cs.m.is_wall, cs.amg[0], AMG_MAXC, AMG_MAXL);
+        amg_setup(K, std::vector<int>(), cs.amg[1], AMG_MAXC, AMG_MAXL);
+        cs.has_amg = cs.amg[0].lv.back().A.n <= AMG_MAXC && cs.amg[1].lv.back().A.n <= AMG_MAXC;
+        for (int h = 0; h < 2 && cs.has_amg; ++h)
+            for (size_t l = 0; l < cs.amg[h].lv.size(); ++l) cs.omega[h][l] = jacobi_weight(cs.amg[h].lv[l].A);
+    }
     c->cases.push_back(std::move(cs));
     *case_id = (int32_t)c->cases.size() - 1;
     compute_offsets(c);
@@ -609,6 +747,72 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         TRY(h2d(c, (float*)c->d_rec, rec32));
         TRY(h2d(c, (float*)c->d_exy, exy32));
     }
+    // multigrid hierarchies: flat arrays, descriptors, Galerkin jobs
+    std::vector<AmgDev> amgdev(2 * (size_t)std::max(c->n_amg, 1));
+    std::vector<GalJob> gal(2 * (size_t)AMG_MAXL * std::max(c->n_amg, 1));
+    for (int l = 0; l < AMG_MAXL; ++l) { c->n_gal[l] = 0; c->n_gal_p[l] = 0; c->gal_max[l] = 0; c->gal_max_p[l] = 0; }
+    if (c->n_amg > 0) {
+        std::vector<int32_t> ai;
+        std::vector<double> ad;
+        ai.reserve(c->AMG_I);
+        ad.reserve(c->AMG_D);
+        int64_t ni = 0, nd = 0;
+        for (auto& cs : c->cases) {
+            if (!cs.has_amg) continue;
+            for (int h = 0; h < 2; ++h) pack_hier(cs.amg[h], cs.hoff[h], &ai, &ad, ni, nd);
+        }
+        TRY(h2d(c, c->d_amg_i, ai));
+        TRY(h2d(c, c->d_amg_d, ad));
+        for (auto& cs : c->cases) {
+            if (!cs.has_amg) continue;
+            const int a = cs.amg_index;
+            for (int h = 0; h < 2; ++h) {
+                const AmgH& H = cs.amg[h];
+                const HierOff& o = cs.hoff[h];
+                AmgDev& D = amgdev[2 * a + h];
+                D = AmgDev{};
+                D.nlev = (int)H.lv.size();
+                D.r0 = cs.noff;
+                D.coarse_shift = h == 0 ? 1e-12 : 1e-6;
+                for (int l = 0; l < D.nlev; ++l) {
+                    D.n[l] = H.lv[l].A.n;
+                    D.omega[l] = cs.omega[h][l];
+                    if (l == 0) {
+                        D.Aptr[0] = c->d_csr_ptr + cs.noff;
+                        D.Acol[0] = c->d_csr_col;
+                        D.Aval[0] = h == 0 ? c->d_er_val : c->d_pk_val;
+                    } else {
+                        D.Aptr[l] = c->d_amg_i + o.Aptr[l];
+                        D.Acol[l] = c->d_amg_i + o.Acol[l];
+                        D.Aval[l] = c->d_amg_d + o.Aval[l];
+                    }
+                    if (l + 1 < D.nlev) {
+                        D.Pptr[l] = c->d_amg_i + o.Pptr[l]; D.Pcol[l] = c->d_amg_i + o.Pcol[l]; D.Pval[l] = c->d_amg_d + o.Pval[l];
+                        D.Rptr[l] = c->d_amg_i + o.Rptr[l]; D.Rcol[l] = c->d_amg_i + o.Rcol[l]; D.Rval[l] = c->d_amg_d + o.Rval[l];
+                    }
+                }
+                // Galerkin jobs: level l -> l+1
+                for (int l = 0; l + 1 < D.nlev; ++l) {
+                    GalJob G{};
+                    G.nnz = (int32_t)H.lv[l + 1].A.col.size();
+                    G.gptr = c->d_amg_i + o.Gptr[l];
+                    G.gidx = c->d_amg_i + o.Gidx[l];
+                    G.gcoef = c->d_amg_d + o.Gcoef[l];
+                    G.src = l == 0 ? (h == 0 ? c->d_er_val : c->d_pk_val) + cs.nnz_off : D.Aval[l];
+                    G.dst = D.Aval[l + 1];
+                    if (h == 0) {
+                        gal[(size_t)l * c->n_amg + c->n_gal[l]++] = G;
+                        c->gal_max[l] = std::max<int64_t>(c->gal_max[l], G.nnz);
+                    } else {
+                        gal[(size_t)(AMG_MAXL + l) * c->n_amg + c->n_gal_p[l]++] = G;
+                        c->gal_max_p[l] = std::max<int64_t>(c->gal_max_p[l], G.nnz);
+                    }
+                }
+            }
+        }
+        TRY(h2d(c, c->d_amg, amgdev));
+        TRY(h2d(c, c->d_gal, gal));
+    }
     // CG jobs: 5 relaxation systems per mode-2 case and one projection system
     std::vector<CgJob> jer, jp;
     double* cg = c->d_cg;
@@ -624,6 +828,12 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
             const int cidx = (int)(&cs - &c->cases[0]);
             J.iters = c->d_counters + (int64_t)cidx * NCNT + C_CG_ER;
             J.fails = c->d_counters + (int64_t)cidx * NCNT + C_CG_FAIL;
+            if (cs.has_amg) {
+                int64_t w = 0;
+                for (auto& lv : cs.amg[0].lv) w += 4 * (int64_t)lv.A.n;
+                J.amg = c->d_amg + 2 * cs.amg_index;
+                J.amg_work = c->d_amg_work + cs.work_off + q * w;
+            }
             jer.push_back(J);
         }
         CgJob J{};
@@ -634,6 +844,12 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         const int cidx = (int)(&cs - &c->cases[0]);
         J.iters = c->d_counters + (int64_t)cidx * NCNT + C_CG_P;
         J.fails = c->d_counters + (int64_t)cidx * NCNT + C_CG_FAIL;
+        if (cs.has_amg) {
+            int64_t w0 = 0;
+            for (auto& lv : cs.amg[0].lv) w0 += 4 * (int64_t)lv.A.n;
+            J.amg = c->d_amg + 2 * cs.amg_index + 1;
+            J.amg_work = c->d_amg_work + cs.work_off + NER * w0;
+        }
         jp.push_back(J);
     }
     c->n_jobs_er = (int)jer.size();
@@ -653,6 +869,12 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     if (c->any_er) {
         hipLaunchKernelGGL(k_stiffness_assemble, dim3(nblk(NN, 256)), dim3(256), 0, c->stream, node_args(c));
         LAUNCHCHK(c);
+        for (int l = 0; l < AMG_MAXL; ++l) {
+            if (c->n_gal_p[l] == 0) continue;
+            hipLaunchKernelGGL(k_galerkin, dim3(std::min<int64_t>(nblk(c->gal_max_p[l], 256), 1024), c->n_gal_p[l]), dim3(256), 0,
+                               c->stream, (const GalJob*)(c->d_gal + (size_t)(AMG_MAXL + l) * c->n_amg));
+            LAUNCHCHK(c);
+        }
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->bound = true;

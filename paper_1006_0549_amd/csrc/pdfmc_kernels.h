@@ -24,6 +24,7 @@ __global__ void k_proj_update(NodeArgs A);
 __global__ void k_proj_grad(NodeArgs A);
 __global__ void k_mirror_f32(const double* F, float* F32, int nn);
 __global__ void k_cg(const CgJob* jobs);
+__global__ void k_galerkin(const GalJob* jobs);
 __global__ void k_sort_hist(SortArgs A);
 __global__ void k_sort_scan(SortArgs A);
 template <typename R> __global__ void k_sort_scatter(SortArgs A, Particles<R> src, Particles<R> dst);

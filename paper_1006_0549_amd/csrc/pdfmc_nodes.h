@@ -41,6 +41,38 @@ struct NodeArgs {
     unsigned long long* counters;    // [ncase][NCNT]
 };
 
+constexpr int AMG_MAXL = 8;        // multigrid levels
+constexpr int AMG_MAXC = 64;       // largest coarsest level (dense inverse in LDS)
+
+// One multigrid hierarchy. Level 0 is the fine system: its rows are the
+// case's statistics nodes, A0 is a slice of the global CSR (row offset r0,
+// global columns); coarser levels use local indices.
+struct AmgDev {
+    int32_t nlev, r0;
+    int32_t n[AMG_MAXL];
+    const int32_t* Aptr[AMG_MAXL];
+    const int32_t* Acol[AMG_MAXL];
+    double* Aval[AMG_MAXL];
+    const int32_t* Pptr[AMG_MAXL];
+    const int32_t* Pcol[AMG_MAXL];
+    const double* Pval[AMG_MAXL];
+    const int32_t* Rptr[AMG_MAXL];
+    const int32_t* Rcol[AMG_MAXL];
+    const double* Rval[AMG_MAXL];
+    double omega[AMG_MAXL];        // Jacobi smoothing weight per level
+    double coarse_shift;           // relative diagonal shift of the coarsest inverse
+};
+
+// Galerkin update of one level of one hierarchy: dst[k] = sum coef src[idx]
+struct GalJob {
+    int32_t nnz;
+    const int32_t* gptr;
+    const int32_t* gidx;           // positions relative to src
+    const double* gcoef;
+    const double* src;
+    double* dst;
+};
+
 struct CgJob {
     int32_t r0, n;                   // global row range
     const int32_t* ptr;
@@ -56,6 +88,8 @@ struct CgJob {
     int32_t maxit, mean_free;
     unsigned long long* iters;
     unsigned long long* fails;
+    const AmgDev* amg;             // multigrid preconditioner, or null for Jacobi
+    double* amg_work;              // per-job vectors: dinv, x, b, t on every level
 };
 
 }  // namespace pdfmc
