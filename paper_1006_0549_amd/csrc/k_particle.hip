@@ -99,6 +99,7 @@ __device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R 
             continue;
         }
         prev = -1;
+        if constexpr (sizeof(R) == 4) { ring[0] = ring[1] = ring[2] = ring[3] = -1; }  // a reflection turns the walk back
         if (nrefl == 8) break;
         const R* v = M.exy + 6 * (int64_t)e;
         int ka = (k + 1) % 3, kb = (k + 2) % 3;
@@ -183,6 +184,31 @@ __device__ inline int wave_sum_int(int v)
     return v;
 }
 
+// ---------------------------------------------------------------- LDS table
+
+constexpr int HS = 32;                           // element slots per workgroup
+constexpr int NV = 3 * NQ + 8 * (2 + MAXS);      // node sums of 3 vertices + 8 cells
+
+__device__ inline void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// slot of element e in the table (claimed on first use), or -1 when full
+__device__ inline int lds_slot(int* keys, int e)
+{
+    int h = (int)(((unsigned)e * 2654435761u) >> 27) & (HS - 1);
+    for (int probe = 0; probe < HS; ++probe) {
+        const int old = atomicCAS(&keys[h], -1, e);
+        if (old == -1 || old == e) return h;
+        h = (h + 1) & (HS - 1);
+    }
+    return -1;
+}
+
+__device__ inline void put(double* vals, int slot, int v, double* global, double x)
+{
+    if (slot >= 0) lds_add(&vals[slot * NV + v], x);
+    else unsafeAtomicAdd(global, x);
+}
+
 // ---------------------------------------------------------------- the kernel
 
 template <typename R>
@@ -196,13 +222,17 @@ __device__ inline void load_field_row(const R* __restrict__ F, int stride, int s
 template <typename R>
 __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
 {
+    __shared__ int s_key[HS];
+    __shared__ double s_val[HS * NV];
+    for (int i = threadIdx.x; i < HS; i += blockDim.x) s_key[i] = -1;
+    for (int i = threadIdx.x; i < HS * NV; i += blockDim.x) s_val[i] = 0.0;
+    __syncthreads();
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int tile = (int)(gid / TILE);
-    if (tile >= A.ntiles) return;                      // whole wavefronts exit together
-    const int c = A.tile_case[tile];
+    const int c = A.tile_case[tile < A.ntiles ? tile : A.ntiles - 1];
     const CaseDev& C = A.cases[c];
     const int64_t i = gid - C.poff;
-    const bool valid = (i >= 0) && (i < C.np);
+    const bool valid = tile < A.ntiles && (i >= 0) && (i < C.np);
     const int64_t p = gid;
     const int ns = C.ns;
     const uint32_t step = *A.step;
@@ -310,10 +340,17 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         if (A.do_bins) A.P.bin[p] = (uint8_t)bin;
     }
 
-    // ---- shape-weighted node sums of the (new) state (R-11), FP64
+    // ---- shape-weighted node sums of the new state (R-11) and cell sums
+    // (R-23), FP64. Runs of equal element inside a wavefront are summed with
+    // shuffles; the run heads add the run sums into a per-workgroup LDS table
+    // keyed by element; after the barrier the table is flushed with one FP64
+    // atomic per (element, value). A table overflow falls back to direct atomics.
+    const int nq = 11 + 2 * ns;
     {
         const int key = valid ? e : -1;
         const Runs r = make_runs(key);
+        int slot = -1;
+        if (r.head && key >= 0) slot = lds_slot(s_key, key);
         const double w = (double)wt;
         const double Q[3] = {(double)u3[0], (double)u3[1], (double)u3[2]};
         const double dom = (double)om;
@@ -321,7 +358,6 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const double wn = valid ? w * (double)lam[k] : 0.0;
-            double* dst = A.nsum + (int64_t)s3[k] * NQ;
             double val[11];
             val[0] = wn;
             val[1] = wn * Q[0]; val[2] = wn * Q[1]; val[3] = wn * Q[2];
@@ -330,33 +366,68 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             val[10] = wn * dom;
 #pragma unroll
             for (int q = 0; q < 11; ++q) {
-                double s = run_sum(val[q], r);
-                if (r.head && key >= 0) unsafeAtomicAdd(dst + q, s);
+                const double sum = run_sum(val[q], r);
+                if (r.head && key >= 0) put(s_val, slot, k * nq + q, A.nsum + (int64_t)s3[k] * NQ + q, sum);
             }
             for (int a = 0; a < ns; ++a) {
-                double ps = (double)psi[a];
-                double s1 = run_sum(wn * ps, r);
-                double s2 = run_sum(wn * ps * ps, r);
+                const double ps = (double)psi[a];
+                const double s1 = run_sum(wn * ps, r);
+                const double s2 = run_sum(wn * ps * ps, r);
                 if (r.head && key >= 0) {
-                    unsafeAtomicAdd(dst + 11 + a, s1);
-                    unsafeAtomicAdd(dst + 11 + ns + a, s2);
+                    put(s_val, slot, k * nq + 11 + a, A.nsum + (int64_t)s3[k] * NQ + 11 + a, s1);
+                    put(s_val, slot, k * nq + 11 + ns + a, A.nsum + (int64_t)s3[k] * NQ + 11 + ns + a, s2);
                 }
             }
         }
     }
-    // ---- cell sums for the next mixing step (R-23)
     if (A.do_bins && ns > 0) {
         const int key = valid ? e * 8 + bin : -1;
         const Runs r = make_runs(key);
-        double cnt = run_sum(valid ? 1.0 : 0.0, r);
-        double sw = run_sum(valid ? (double)wt : 0.0, r);
+        int slot = -1;
+        if (r.head && key >= 0) slot = lds_slot(s_key, e);
+        const double cnt = run_sum(valid ? 1.0 : 0.0, r);
+        const double sw = run_sum(valid ? (double)wt : 0.0, r);
         double swp[MAXS];
         for (int a = 0; a < ns; ++a) swp[a] = run_sum(valid ? (double)wt * (double)psi[a] : 0.0, r);
         if (r.head && key >= 0) {
-            atomicAdd(A.ccnt + key, (int)cnt);
+            const int base = 3 * nq + bin * (2 + ns);
             double* dst = A.csum + C.csoff + ((int64_t)(e - C.eoff) * 8 + bin) * (1 + ns);
-            unsafeAtomicAdd(dst, sw);
-            for (int a = 0; a < ns; ++a) unsafeAtomicAdd(dst + 1 + a, swp[a]);
+            if (slot >= 0) {
+                lds_add(&s_val[slot * NV + base], cnt);
+                lds_add(&s_val[slot * NV + base + 1], sw);
+                for (int a = 0; a < ns; ++a) lds_add(&s_val[slot * NV + base + 2 + a], swp[a]);
+            } else {
+                atomicAdd(A.ccnt + key, (int)cnt);
+                unsafeAtomicAdd(dst, sw);
+                for (int a = 0; a < ns; ++a) unsafeAtomicAdd(dst + 1 + a, swp[a]);
+            }
+        }
+    }
+    __syncthreads();
+    // flush the table
+    {
+        const int per = 3 * nq + ((A.do_bins && ns > 0) ? 8 * (2 + ns) : 0);
+        for (int idx = threadIdx.x; idx < HS * per; idx += blockDim.x) {
+            const int slot = idx / per, v = idx % per;
+            const int el = s_key[slot];
+            if (el < 0) continue;
+            const double x = s_val[slot * NV + v];
+            if (x == 0.0) continue;
+            if (v < 3 * nq) {
+                const int4 t = A.M.tri_s[el];
+                const int k = v / nq, q = v % nq;
+                const int node = k == 0 ? t.x : (k == 1 ? t.y : t.z);
+                unsafeAtomicAdd(A.nsum + (int64_t)node * NQ + q, x);
+            } else {
+                const int w8 = v - 3 * nq;
+                const int b = w8 / (2 + ns), j = w8 % (2 + ns);
+                if (j == 0) {
+                    atomicAdd(A.ccnt + (int64_t)el * 8 + b, (int)x);
+                } else {
+                    double* dst = A.csum + C.csoff + ((int64_t)(el - C.eoff) * 8 + b) * (1 + ns);
+                    unsafeAtomicAdd(dst + (j - 1), x);
+                }
+            }
         }
     }
     // ---- counters, one atomic per wavefront
