@@ -213,14 +213,17 @@ __global__ void k_fields_derived(NodeArgs A)
 // Galerkin matrix (M + K_L) with L^2 per element = mean of the nodal values,
 // right-hand sides M r for the five components, Dirichlet rows at walls.
 // One thread per row; the row's entries are accumulated in incidence order.
+// The matrix is stored per case in ELL form (column-major, local columns).
 __global__ void k_er_assemble(NodeArgs A)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;
-    const int r0 = A.csr_ptr[s], r1 = A.csr_ptr[s + 1];
-    for (int j = r0; j < r1; ++j) A.er_val[j] = 0.0;
+    const int n = C.nsn, i = s - C.noff, len = A.ell_len[s];
+    double* val = A.er_val + C.ell_off;
+    const int32_t* col = A.ell_col + C.ell_off;
+    for (int k = 0; k < C.ell_w; ++k) val[(int64_t)k * n + i] = 0.0;
     double rhs[NER] = {0, 0, 0, 0, 0};
     for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
         const int ent = A.inc[j];
@@ -238,15 +241,16 @@ __global__ void k_er_assemble(NodeArgs A)
         }
     }
     if (A.is_wall[s]) {
-        for (int j = r0; j < r1; ++j) A.er_val[j] = (A.csr_col[j] == s) ? 1.0 : 0.0;
+        for (int k = 0; k < len; ++k) val[(int64_t)k * n + i] = (col[(int64_t)k * n + i] == i) ? 1.0 : 0.0;
         for (int q = 0; q < NER; ++q) A.er_b[(int64_t)q * A.nn + s] = A.er_dval[(int64_t)q * A.nn + s];
         return;
     }
-    for (int j = r0; j < r1; ++j) {
-        const int col = A.csr_col[j];
-        if (A.is_wall[col]) {
-            for (int q = 0; q < NER; ++q) rhs[q] -= A.er_val[j] * A.er_dval[(int64_t)q * A.nn + col];
-            A.er_val[j] = 0.0;
+    for (int k = 0; k < len; ++k) {
+        const int64_t at = (int64_t)k * n + i;
+        const int g = C.noff + col[at];
+        if (A.is_wall[g]) {
+            for (int q = 0; q < NER; ++q) rhs[q] -= val[at] * A.er_dval[(int64_t)q * A.nn + g];
+            val[at] = 0.0;
         }
     }
     for (int q = 0; q < NER; ++q) A.er_b[(int64_t)q * A.nn + s] = rhs[q];
@@ -257,7 +261,10 @@ __global__ void k_stiffness_assemble(NodeArgs A)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
-    for (int j = A.csr_ptr[s]; j < A.csr_ptr[s + 1]; ++j) A.pk_val[j] = 0.0;
+    const CaseDev& C = A.cases[A.node_case[s]];
+    if (C.mode != 2) return;
+    const int n = C.nsn, i = s - C.noff;
+    for (int k = 0; k < C.ell_w; ++k) A.pk_val[C.ell_off + (int64_t)k * n + i] = 0.0;
     for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
         const int ent = A.inc[j];
         const int e = ent / 3, a = ent % 3;
@@ -370,91 +377,98 @@ __global__ void k_galerkin(const GalJob* __restrict__ jobs)
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < J.nnz; k += gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int j = J.gptr[k]; j < J.gptr[k + 1]; ++j) s += J.gcoef[j] * J.src[J.gidx[j]];
-        J.dst[k] = s;
+        J.dst[J.gdst[k]] = s;
     }
 }
 
-// Level views used by the V-cycle inside one workgroup.
+// y_i = sum_k A(k, i) x(col(k, i)) for one row of an ELL matrix
+__device__ inline double ell_row(const EllDev& A, const double* __restrict__ x, int i)
+{
+    double s0 = 0.0, s1 = 0.0;
+    int k = 0;
+    for (; k + 1 < A.w; k += 2) {
+        const int64_t a0 = (int64_t)k * A.n + i, a1 = a0 + A.n;
+        const int c0 = A.col[a0], c1 = A.col[a1];
+        s0 += A.val[a0] * x[c0];
+        s1 += A.val[a1] * x[c1];
+    }
+    if (k < A.w) {
+        const int64_t a0 = (int64_t)k * A.n + i;
+        s0 += A.val[a0] * x[A.col[a0]];
+    }
+    return s0 + s1;
+}
+
+__device__ inline double ell_diag(const EllDev& A, int i)
+{
+    for (int k = 0; k < A.w; ++k) {
+        const int64_t a = (int64_t)k * A.n + i;
+        if (A.col[a] == i) return A.val[a];
+    }
+    return 1.0;
+}
+
+// Vectors of one level inside the V-cycle: the level's solution is y.
 struct Lvl {
-    int n, coff;                    // rows; column offset (r0 on level 0, else 0)
-    const int32_t* Ap; const int32_t* Ac; const double* Av;
-    double *dinv, *x, *b, *t;
+    int n;
+    double *dinv, *x, *y, *b, *t;
 };
 
-__device__ inline Lvl level(const AmgDev& H, double* work, int l, double* b0, double* x0)
+__device__ inline Lvl level(const AmgDev& H, double* work, int l, double* b0, double* y0)
 {
     Lvl L;
     L.n = H.n[l];
-    L.coff = l == 0 ? H.r0 : 0;
-    L.Ap = H.Aptr[l]; L.Ac = H.Acol[l]; L.Av = H.Aval[l];
     int64_t off = 0;
-    for (int q = 0; q < l; ++q) off += 4 * (int64_t)H.n[q];
+    for (int q = 0; q < l; ++q) off += 5 * (int64_t)H.n[q];
     L.dinv = work + off;
-    L.x = l == 0 ? x0 : work + off + H.n[l];
-    L.b = l == 0 ? b0 : work + off + 2 * (int64_t)H.n[l];
-    L.t = work + off + 3 * (int64_t)H.n[l];
+    L.x = work + off + L.n;
+    L.y = l == 0 ? y0 : work + off + 2 * (int64_t)L.n;
+    L.b = l == 0 ? b0 : work + off + 3 * (int64_t)L.n;
+    L.t = work + off + 4 * (int64_t)L.n;
     return L;
 }
 
-// t = b - A x on one level
-__device__ inline void lvl_residual(const Lvl& L)
+// out = in + w D^-1 (b - A in), one phase
+__device__ inline void jacobi(const EllDev& A, const Lvl& L, double w, const double* in, double* out)
 {
-    for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
-        double s = 0.0;
-        for (int j = L.Ap[i]; j < L.Ap[i + 1]; ++j) s += L.Av[j] * L.x[L.Ac[j] - L.coff];
-        L.t[i] = L.b[i] - s;
-    }
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) out[i] = in[i] + w * L.dinv[i] * (L.b[i] - ell_row(A, in, i));
     __syncthreads();
 }
 
-__device__ inline void lvl_jacobi(const Lvl& L, double w)
-{
-    lvl_residual(L);
-    for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.x[i] += w * L.dinv[i] * L.t[i];
-    __syncthreads();
-}
-
-// z = V(r): one symmetric V-cycle (two Jacobi sweeps before and after the
-// coarse correction, dense solve on the coarsest level).
+// z = V(r): symmetric V-cycle, two Jacobi sweeps before and after the
+// coarse correction (ping-pong buffers, one barrier per sweep), dense
+// solve on the coarsest level.
 __device__ void vcycle(const AmgDev& H, double* work, const double* ainv, double* r, double* z)
 {
     const int nl = H.nlev;
     for (int l = 0; l < nl - 1; ++l) {
-        Lvl L = level(H, work, l, r, z);
-        // first sweep from x = 0
-        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.x[i] = H.omega[l] * L.dinv[i] * L.b[i];
+        const Lvl L = level(H, work, l, r, z);
+        const double w = H.omega[l];
+        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.x[i] = w * L.dinv[i] * L.b[i];
         __syncthreads();
-        lvl_jacobi(L, H.omega[l]);
-        lvl_residual(L);
-        // restrict: b_{l+1} = R t
-        Lvl C = level(H, work, l + 1, r, z);
-        for (int i = threadIdx.x; i < C.n; i += blockDim.x) {
-            double s = 0.0;
-            for (int j = H.Rptr[l][i]; j < H.Rptr[l][i + 1]; ++j) s += H.Rval[l][j] * L.t[H.Rcol[l][j]];
-            C.b[i] = s;
-        }
+        jacobi(H.A[l], L, w, L.x, L.y);
+        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.t[i] = L.b[i] - ell_row(H.A[l], L.y, i);
+        __syncthreads();
+        const Lvl Cl = level(H, work, l + 1, r, z);
+        for (int i = threadIdx.x; i < Cl.n; i += blockDim.x) Cl.b[i] = ell_row(H.R[l], L.t, i);
         __syncthreads();
     }
     {
-        Lvl C = level(H, work, nl - 1, r, z);
-        for (int i = threadIdx.x; i < C.n; i += blockDim.x) {
+        const Lvl Cl = level(H, work, nl - 1, r, z);
+        for (int i = threadIdx.x; i < Cl.n; i += blockDim.x) {
             double s = 0.0;
-            for (int j = 0; j < C.n; ++j) s += ainv[i * AMG_MAXC + j] * C.b[j];
-            C.x[i] = s;
+            for (int j = 0; j < Cl.n; ++j) s += ainv[i * AMG_MAXC + j] * Cl.b[j];
+            Cl.y[i] = s;
         }
         __syncthreads();
     }
     for (int l = nl - 2; l >= 0; --l) {
-        Lvl L = level(H, work, l, r, z);
-        Lvl C = level(H, work, l + 1, r, z);
-        for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
-            double s = 0.0;
-            for (int j = H.Pptr[l][i]; j < H.Pptr[l][i + 1]; ++j) s += H.Pval[l][j] * C.x[H.Pcol[l][j]];
-            L.x[i] += s;
-        }
+        const Lvl L = level(H, work, l, r, z);
+        const Lvl Cl = level(H, work, l + 1, r, z);
+        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.y[i] += ell_row(H.P[l], Cl.y, i);
         __syncthreads();
-        lvl_jacobi(L, H.omega[l]);
-        lvl_jacobi(L, H.omega[l]);
+        jacobi(H.A[l], L, H.omega[l], L.y, L.x);
+        jacobi(H.A[l], L, H.omega[l], L.x, L.y);
     }
 }
 
@@ -464,25 +478,21 @@ __device__ void vcycle(const AmgDev& H, double* work, const double* ainv, double
 __device__ void amg_prepare(const AmgDev& H, double* work, double* ainv, double* r, double* z)
 {
     for (int l = 0; l < H.nlev; ++l) {
-        Lvl L = level(H, work, l, r, z);
-        for (int i = threadIdx.x; i < L.n; i += blockDim.x) {
-            double d = 1.0;
-            for (int j = L.Ap[i]; j < L.Ap[i + 1]; ++j)
-                if (L.Ac[j] - L.coff == i) d = L.Av[j];
-            L.dinv[i] = 1.0 / d;
-        }
+        const Lvl L = level(H, work, l, r, z);
+        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.dinv[i] = 1.0 / ell_diag(H.A[l], i);
     }
-    const int nc = H.n[H.nlev - 1];
-    const int lc = H.nlev - 1;
-    const int coff = lc == 0 ? H.r0 : 0;
+    const EllDev& Ac = H.A[H.nlev - 1];
+    const int nc = Ac.n;
     for (int q = threadIdx.x; q < AMG_MAXC * AMG_MAXC; q += blockDim.x) ainv[q] = 0.0;
     __syncthreads();
     for (int i = threadIdx.x; i < nc; i += blockDim.x)
-        for (int j = H.Aptr[lc][i]; j < H.Aptr[lc][i + 1]; ++j) ainv[i * AMG_MAXC + (H.Acol[lc][j] - coff)] = H.Aval[lc][j];
+        for (int k = 0; k < Ac.w; ++k) {
+            const int64_t a = (int64_t)k * nc + i;
+            ainv[i * AMG_MAXC + Ac.col[a]] += Ac.val[a];
+        }
     __syncthreads();
     for (int i = threadIdx.x; i < nc; i += blockDim.x) ainv[i * AMG_MAXC + i] *= (1.0 + H.coarse_shift);
     __syncthreads();
-    // in-place Gauss-Jordan inversion without pivoting
     __shared__ double piv_row[AMG_MAXC], piv_col[AMG_MAXC];
     for (int k = 0; k < nc; ++k) {
         const double p = ainv[k * AMG_MAXC + k];
@@ -505,116 +515,101 @@ __device__ void amg_prepare(const AmgDev& H, double* work, double* ainv, double*
     }
 }
 
-// One workgroup per system: rows [r0, r0+n) of a global CSR matrix;
-// Jacobi or multigrid (one V-cycle) preconditioning.
+// One workgroup per system (local rows 0..n); Jacobi or one multigrid
+// V-cycle as preconditioner; warm start from the current x.
 __global__ void __launch_bounds__(1024) k_cg(const CgJob* __restrict__ jobs)
 {
     const CgJob J = jobs[blockIdx.x];
-    if (J.n <= 0) return;
+    const int n = J.A.n;
+    if (n <= 0) return;
     __shared__ double sh[16 * 4];
     __shared__ double ainv[AMG_MAXC * AMG_MAXC];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int n = J.n, r0 = J.r0;
     const bool mg = J.amg != nullptr;
     double v[4];
     if (J.mean_free) {
         v[0] = 0.0;
-        for (int i = tid; i < n; i += nt) v[0] += J.b[r0 + i];
+        for (int i = tid; i < n; i += nt) v[0] += J.b[i];
         block_sum(v, 1, sh);
         const double mb = v[0] / n;
-        for (int i = tid; i < n; i += nt) J.b[r0 + i] -= mb;
+        for (int i = tid; i < n; i += nt) J.b[i] -= mb;
         __syncthreads();
     }
-    if (mg) amg_prepare(*J.amg, J.amg_work, ainv, J.r + r0, J.q + r0);
+    if (mg) amg_prepare(*J.amg, J.amg_work, ainv, J.r, J.q);
     // r = b - A x
     v[0] = 0.0;
     for (int i = tid; i < n; i += nt) {
-        const int row = r0 + i;
-        double ax = 0.0, d = 1.0;
-        for (int j = J.ptr[row]; j < J.ptr[row + 1]; ++j) {
-            const int col = J.col[j];
-            ax += J.val[j] * J.x[col];
-            if (col == row) d = J.val[j];
-        }
-        J.dinv[row] = 1.0 / d;
-        J.r[row] = J.b[row] - ax;
-        v[0] += J.b[row] * J.b[row];
+        J.dinv[i] = 1.0 / ell_diag(J.A, i);
+        J.r[i] = J.b[i] - ell_row(J.A, J.x, i);
+        v[0] += J.b[i] * J.b[i];
     }
     block_sum(v, 1, sh);
     const double bb = v[0];
     const double tol2 = J.tol * J.tol * bb;
-    // z = M^-1 r (q holds z), p = z
+    // z = M^-1 r into q; returns (r.z, r.r)
     auto precondition = [&](double* out) {
         if (mg) {
-            vcycle(*J.amg, J.amg_work, ainv, J.r + r0, J.q + r0);
+            vcycle(*J.amg, J.amg_work, ainv, J.r, J.q);
             if (J.mean_free) {
                 double m[1] = {0.0};
-                for (int i = tid; i < n; i += nt) m[0] += J.q[r0 + i];
+                for (int i = tid; i < n; i += nt) m[0] += J.q[i];
                 block_sum(m, 1, sh);
                 const double mz = m[0] / n;
-                for (int i = tid; i < n; i += nt) J.q[r0 + i] -= mz;
+                for (int i = tid; i < n; i += nt) J.q[i] -= mz;
             }
         } else {
-            for (int i = tid; i < n; i += nt) J.q[r0 + i] = J.dinv[r0 + i] * J.r[r0 + i];
+            for (int i = tid; i < n; i += nt) J.q[i] = J.dinv[i] * J.r[i];
         }
         __syncthreads();
         out[0] = 0.0; out[1] = 0.0;
         for (int i = tid; i < n; i += nt) {
-            const int row = r0 + i;
-            out[0] += J.r[row] * J.q[row];
-            out[1] += J.r[row] * J.r[row];
+            out[0] += J.r[i] * J.q[i];
+            out[1] += J.r[i] * J.r[i];
         }
         block_sum(out, 2, sh);
     };
     precondition(v);
     double rz = v[0], rr = v[1];
-    for (int i = tid; i < n; i += nt) J.p[r0 + i] = J.q[r0 + i];
+    for (int i = tid; i < n; i += nt) J.p[i] = J.q[i];
     __syncthreads();
     int it = 0;
     bool ok = (rr <= tol2);
     while (!ok && it < J.maxit) {
-        // q = A p ; pq
         v[0] = 0.0;
         for (int i = tid; i < n; i += nt) {
-            const int row = r0 + i;
-            double q = 0.0;
-            for (int j = J.ptr[row]; j < J.ptr[row + 1]; ++j) q += J.val[j] * J.p[J.col[j]];
-            J.q[row] = q;
-            v[0] += J.p[row] * q;
+            const double q = ell_row(J.A, J.p, i);
+            J.q[i] = q;
+            v[0] += J.p[i] * q;
         }
         block_sum(v, 1, sh);
         const double alpha = rz / v[0];
         v[0] = 0.0;
         for (int i = tid; i < n; i += nt) {
-            const int row = r0 + i;
-            J.x[row] += alpha * J.p[row];
-            const double rn = J.r[row] - alpha * J.q[row];
-            J.r[row] = rn;
+            J.x[i] += alpha * J.p[i];
+            const double rn = J.r[i] - alpha * J.q[i];
+            J.r[i] = rn;
             v[0] += rn;
         }
         block_sum(v, 1, sh);
         if (J.mean_free) {
             const double mr = v[0] / n;
-            for (int i = tid; i < n; i += nt) J.r[r0 + i] -= mr;
+            for (int i = tid; i < n; i += nt) J.r[i] -= mr;
             __syncthreads();
         }
         precondition(v);
         const double beta = v[0] / rz;
         rz = v[0]; rr = v[1];
-        for (int i = tid; i < n; i += nt) {
-            const int row = r0 + i;
-            J.p[row] = J.q[row] + beta * J.p[row];
-        }
+        for (int i = tid; i < n; i += nt) J.p[i] = J.q[i] + beta * J.p[i];
         __syncthreads();
         ++it;
         ok = (rr <= tol2);
     }
     if (J.mean_free) {
         v[0] = 0.0;
-        for (int i = tid; i < n; i += nt) v[0] += J.x[r0 + i];
+        for (int i = tid; i < n; i += nt) v[0] += J.x[i];
         block_sum(v, 1, sh);
         const double mx = v[0] / n;
-        for (int i = tid; i < n; i += nt) J.x[r0 + i] -= mx;
+        for (int i = tid; i < n; i += nt) J.x[i] -= mx;
     }
     if (tid == 0) {
         atomicAdd(J.iters, (unsigned long long)it);

@@ -229,4 +229,30 @@ void amg_setup(const CsrH& A0, const std::vector<int>& isolated, AmgH& H, int ma
     }
 }
 
+void to_ell(const CsrH& A, bool pad_self, EllH& E)
+{
+    E.n = A.n;
+    E.w = 0;
+    for (int i = 0; i < A.n; ++i) E.w = std::max(E.w, A.ptr[i + 1] - A.ptr[i]);
+    E.w = std::max(E.w, 1);
+    E.col.assign((size_t)E.w * A.n, 0);
+    E.val.assign((size_t)E.w * A.n, 0.0);
+    E.len.assign(A.n, 0);
+    E.map.assign(A.col.size(), 0);
+    for (int i = 0; i < A.n; ++i) {
+        E.len[i] = A.ptr[i + 1] - A.ptr[i];
+        for (int k = 0; k < E.w; ++k) {
+            const size_t at = (size_t)k * A.n + i;
+            const int j = A.ptr[i] + k;
+            if (j < A.ptr[i + 1]) {
+                E.col[at] = A.col[j];
+                E.val[at] = A.val[j];
+                E.map[j] = (int)at;
+            } else {
+                E.col[at] = pad_self ? i : 0;
+            }
+        }
+    }
+}
+
 }  // namespace pdfmc

@@ -27,6 +27,18 @@ struct AmgH {
     std::vector<AmgLevelH> lv;          // lv.back() is the coarsest (no P/R)
 };
 
+// ELL form of a CSR matrix, column-major: entry k of row i at k * n + i.
+// Rows shorter than the width are padded with value 0 and column i itself
+// (pad_self) or column 0.
+struct EllH {
+    int n = 0, w = 0;
+    std::vector<int> col, len;
+    std::vector<double> val;
+    std::vector<int> map;               // CSR position -> ELL position
+};
+
+void to_ell(const CsrH& A, bool pad_self, EllH& E);
+
 // Build the hierarchy of the symmetric matrix A0 (values used for strength,
 // aggregation and prolongator smoothing). Rows flagged in `isolated` keep no
 // strong connections (Dirichlet rows). Coarsening stops at <= max_coarse

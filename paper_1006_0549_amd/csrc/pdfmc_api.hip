@@ -26,34 +26,62 @@ using namespace pdfmc;
 
 namespace {
 
-// Offsets of one multigrid hierarchy's arrays inside the flat int/double
-// regions of the workspace (levels >= 1 for A; P, R and the Galerkin lists
-// for every level but the coarsest).
+// ELL forms of one hierarchy: A on levels >= 1, P and R on every level but
+// the coarsest, and the Galerkin lists with ELL source/destination positions.
+struct HierEll {
+    std::vector<EllH> A, P, R;
+    std::vector<std::vector<int>> gptr, gidx, gdst;
+    std::vector<std::vector<double>> gcoef;
+};
+
+// Offsets of one hierarchy's arrays inside the flat int/double regions.
 struct HierOff {
-    int64_t Aptr[AMG_MAXL], Acol[AMG_MAXL], Aval[AMG_MAXL];
-    int64_t Pptr[AMG_MAXL], Pcol[AMG_MAXL], Pval[AMG_MAXL];
-    int64_t Rptr[AMG_MAXL], Rcol[AMG_MAXL], Rval[AMG_MAXL];
-    int64_t Gptr[AMG_MAXL], Gidx[AMG_MAXL], Gcoef[AMG_MAXL];
+    int64_t Acol[AMG_MAXL], Aval[AMG_MAXL], Pcol[AMG_MAXL], Pval[AMG_MAXL], Rcol[AMG_MAXL], Rval[AMG_MAXL];
+    int64_t Gptr[AMG_MAXL], Gidx[AMG_MAXL], Gdst[AMG_MAXL], Gcoef[AMG_MAXL];
 };
 
 struct Case {
     pdfmc_case_params p{};
     MeshHost m;
     int64_t cap = 0, np = 0;
-    int64_t poff = 0, psioff = 0, cmoff = 0, csoff = 0, nnz_off = 0, inc_off = 0;
+    int64_t poff = 0, psioff = 0, cmoff = 0, csoff = 0, inc_off = 0;
     int eoff = 0, noff = 0, bcoff = 0;
+    // Galerkin matrix pattern of the case in ELL form (mode 2)
+    EllH ell0;
+    int64_t ell_off = 0;
     // multigrid hierarchies of the two Eulerian solves (mode 2): 0 elliptic
     // relaxation (wall rows isolated), 1 projection
     bool has_amg = false;
     AmgH amg[2];
+    HierEll he[2];
     double omega[2][AMG_MAXL] = {};
     HierOff hoff[2];
     int amg_index = -1;           // position among the cases with hierarchies
     int64_t work_off = 0;         // per-job multigrid vectors
 };
 
+void build_hier_ell(const AmgH& H, const EllH& ell0, HierEll& E)
+{
+    const int L = (int)H.lv.size();
+    E.A.assign(L, EllH());
+    E.P.assign(L, EllH());
+    E.R.assign(L, EllH());
+    E.gptr.assign(L, {}); E.gidx.assign(L, {}); E.gdst.assign(L, {}); E.gcoef.assign(L, {});
+    for (int l = 1; l < L; ++l) to_ell(H.lv[l].A, true, E.A[l]);
+    for (int l = 0; l + 1 < L; ++l) {
+        to_ell(H.lv[l].P, false, E.P[l]);
+        to_ell(H.lv[l].R, false, E.R[l]);
+        const std::vector<int>& src_map = l == 0 ? ell0.map : E.A[l].map;
+        E.gptr[l] = H.lv[l].gptr;
+        E.gcoef[l] = H.lv[l].gcoef;
+        E.gidx[l].resize(H.lv[l].gidx.size());
+        for (size_t j = 0; j < H.lv[l].gidx.size(); ++j) E.gidx[l][j] = src_map[H.lv[l].gidx[j]];
+        E.gdst[l] = E.A[l + 1].map;
+    }
+}
+
 // serialise (or only size) one hierarchy into the flat regions
-void pack_hier(const AmgH& H, HierOff& o, std::vector<int32_t>* ai, std::vector<double>* ad, int64_t& ni, int64_t& nd)
+void pack_hier(const HierEll& E, HierOff& o, std::vector<int32_t>* ai, std::vector<double>* ad, int64_t& ni, int64_t& nd)
 {
     auto puti = [&](const std::vector<int>& v) {
         int64_t at = ni;
@@ -67,14 +95,14 @@ void pack_hier(const AmgH& H, HierOff& o, std::vector<int32_t>* ai, std::vector<
         nd += (int64_t)v.size();
         return at;
     };
-    const int L = (int)H.lv.size();
+    const int L = (int)E.A.size();
     for (int l = 0; l < L; ++l) {
-        const AmgLevelH& Lv = H.lv[l];
-        if (l >= 1) { o.Aptr[l] = puti(Lv.A.ptr); o.Acol[l] = puti(Lv.A.col); o.Aval[l] = putd(Lv.A.val); }
+        if (l >= 1) { o.Acol[l] = puti(E.A[l].col); o.Aval[l] = putd(E.A[l].val); }
         if (l + 1 < L) {
-            o.Pptr[l] = puti(Lv.P.ptr); o.Pcol[l] = puti(Lv.P.col); o.Pval[l] = putd(Lv.P.val);
-            o.Rptr[l] = puti(Lv.R.ptr); o.Rcol[l] = puti(Lv.R.col); o.Rval[l] = putd(Lv.R.val);
-            o.Gptr[l] = puti(Lv.gptr); o.Gidx[l] = puti(Lv.gidx); o.Gcoef[l] = putd(Lv.gcoef);
+            o.Pcol[l] = puti(E.P[l].col); o.Pval[l] = putd(E.P[l].val);
+            o.Rcol[l] = puti(E.R[l].col); o.Rval[l] = putd(E.R[l].val);
+            o.Gptr[l] = puti(E.gptr[l]); o.Gidx[l] = puti(E.gidx[l]); o.Gdst[l] = puti(E.gdst[l]);
+            o.Gcoef[l] = putd(E.gcoef[l]);
         }
     }
 }
@@ -138,7 +166,8 @@ struct pdfmc_ctx {
     std::vector<Case> cases;
     // totals
     int64_t NP = 0, PSI = 0, CM = 0, CS = 0;
-    int NE = 0, NN = 0, NBC = 0, NNZ = 0, ntiles = 0;
+    int NE = 0, NN = 0, NBC = 0, ntiles = 0;
+    int64_t NELL = 0;
     // workspace
     bool bound = false, initialised = false;
     char* ws = nullptr;
@@ -152,7 +181,7 @@ struct pdfmc_ctx {
     int4 *d_tri_s = nullptr, *d_nbr = nullptr, *d_partner = nullptr;
     BcDev* d_bc = nullptr;
     double *d_area = nullptr, *d_vol = nullptr, *d_wnx = nullptr, *d_wny = nullptr;
-    int32_t *d_inc_ptr = nullptr, *d_inc = nullptr, *d_incpos = nullptr, *d_csr_ptr = nullptr, *d_csr_col = nullptr,
+    int32_t *d_inc_ptr = nullptr, *d_inc = nullptr, *d_incpos = nullptr, *d_ell_col = nullptr, *d_ell_len = nullptr,
             *d_is_wall = nullptr;
     PartBufs part[2]{};
     int cur = 0;
@@ -164,7 +193,6 @@ struct pdfmc_ctx {
            *d_er_x = nullptr, *d_er_val = nullptr, *d_pk_val = nullptr, *d_pb = nullptr, *d_phi = nullptr, *d_P = nullptr;
     double* d_cg = nullptr;         // CG scratch: (5 + 1) systems x 4 vectors x NN
     CgJob* d_jobs_er = nullptr;
-    CgJob* d_jobs_p = nullptr;
     int n_jobs_er = 0, n_jobs_p = 0;
     unsigned long long* d_counters = nullptr;
     uint32_t* d_step = nullptr;
@@ -252,8 +280,8 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_inc_ptr, c->NN + 1);
     k.take(c->d_inc, 3 * (size_t)c->NE);
     k.take(c->d_incpos, 9 * (size_t)c->NE);
-    k.take(c->d_csr_ptr, c->NN + 1);
-    k.take(c->d_csr_col, c->NNZ);
+    k.take(c->d_ell_col, c->NELL);
+    k.take(c->d_ell_len, c->NN);
     k.take(c->d_is_wall, c->NN);
     for (int b = 0; b < 2; ++b) {
         PartBufs& P = c->part[b];
@@ -272,11 +300,10 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_kf, c->NN); k.take(c->d_ef, c->NN); k.take(c->d_L2, c->NN);
     k.take(c->d_er_r, (size_t)NER * c->NN); k.take(c->d_er_dval, (size_t)NER * c->NN);
     k.take(c->d_er_b, (size_t)NER * c->NN); k.take(c->d_er_x, (size_t)NER * c->NN);
-    k.take(c->d_er_val, c->NNZ); k.take(c->d_pk_val, c->NNZ);
+    k.take(c->d_er_val, c->NELL); k.take(c->d_pk_val, c->NELL);
     k.take(c->d_pb, c->NN); k.take(c->d_phi, c->NN); k.take(c->d_P, c->NN);
     k.take(c->d_cg, (size_t)(NER + 1) * 4 * c->NN);
-    k.take(c->d_jobs_er, NER * c->cases.size());
-    k.take(c->d_jobs_p, c->cases.size());
+    k.take(c->d_jobs_er, (NER + 1) * c->cases.size());
     k.take(c->d_counters, NCNT * c->cases.size());
     k.take(c->d_step, 1);
     k.take(c->d_sort_count, c->NE);
@@ -291,7 +318,7 @@ void carve(pdfmc_ctx* c, Carver& k)
 
 void compute_offsets(pdfmc_ctx* c)
 {
-    int64_t NP = 0, PSI = 0, CM = 0, CS = 0, NNZ = 0;
+    int64_t NP = 0, PSI = 0, CM = 0, CS = 0, NELL = 0;
     int NE = 0, NN = 0, NBC = 0;
     for (auto& cs : c->cases) {
         cs.poff = NP;
@@ -302,7 +329,7 @@ void compute_offsets(pdfmc_ctx* c)
         cs.eoff = NE; NE += cs.m.ne;
         cs.noff = NN; NN += cs.m.nsn;
         cs.bcoff = NBC; NBC += (int)cs.m.bc.size();
-        cs.nnz_off = NNZ; NNZ += (int64_t)cs.m.csr_col.size();
+        cs.ell_off = NELL; NELL += cs.p.mode == 2 ? (int64_t)cs.ell0.w * cs.m.nsn : 0;
         cs.inc_off = 3 * (int64_t)cs.eoff;
     }
     int64_t ni = 0, nd = 0, nw = 0;
@@ -311,20 +338,20 @@ void compute_offsets(pdfmc_ctx* c)
         if (!cs.has_amg) { cs.amg_index = -1; continue; }
         cs.amg_index = na++;
         for (int h = 0; h < 2; ++h) {
-            pack_hier(cs.amg[h], cs.hoff[h], nullptr, nullptr, ni, nd);
+            pack_hier(cs.he[h], cs.hoff[h], nullptr, nullptr, ni, nd);
             maxlev = std::max(maxlev, (int)cs.amg[h].lv.size());
         }
         cs.work_off = nw;
         int64_t per = 0;
         for (int h = 0; h < 2; ++h) {
             int64_t w = 0;
-            for (auto& lv : cs.amg[h].lv) w += 4 * (int64_t)lv.A.n;
+            for (auto& lv : cs.amg[h].lv) w += 5 * (int64_t)lv.A.n;
             per += (h == 0 ? NER : 1) * w;
         }
         nw += per;
     }
     c->AMG_I = ni; c->AMG_D = nd; c->AMG_W = nw; c->n_amg = na; c->amg_levels = maxlev;
-    c->NP = NP; c->PSI = PSI; c->CM = CM; c->CS = CS; c->NE = NE; c->NN = NN; c->NBC = NBC; c->NNZ = (int)NNZ;
+    c->NP = NP; c->PSI = PSI; c->CM = CM; c->CS = CS; c->NE = NE; c->NN = NN; c->NBC = NBC; c->NELL = NELL;
     c->ntiles = (int)(NP / TILE);
 }
 
@@ -336,7 +363,7 @@ CaseDev make_case_dev(const pdfmc_ctx* c, const Case& cs)
     d.eoff = cs.eoff; d.ne = cs.m.ne; d.noff = cs.noff; d.nsn = cs.m.nsn; d.bcoff = cs.bcoff; d.nbc = (int)cs.m.bc.size();
     d.ns = p.n_scalars; d.nbins = p.n_bins; d.nmin = p.n_min; d.mode = p.mode;
     d.seed_lo = (uint32_t)p.seed; d.seed_hi = (uint32_t)(p.seed >> 32); d.stream = p.stream;
-    d.csr_row0 = cs.noff; d.nnz_off = cs.nnz_off; d.nnz = (int64_t)cs.m.csr_col.size(); d.inc_off = cs.inc_off;
+    d.ell_w = cs.p.mode == 2 ? cs.ell0.w : 0; d.ell_off = cs.ell_off; d.inc_off = cs.inc_off;
     // the same expressions as the step contract: 2 nu, sqrt(2 nu dt), 2 C3 C4, Cphi/2
     d.dt = p.dt; d.tnu = 2.0 * p.nu; d.sq_nu = std::sqrt(d.tnu * p.dt); d.C3 = p.C3;
     d.c34 = 2.0 * p.C3 * p.C4; d.hphi = 0.5 * p.Cphi;
@@ -367,7 +394,7 @@ NodeArgs node_args(pdfmc_ctx* c)
     NodeArgs A{};
     A.nn = c->NN; A.ne = c->NE; A.cases = c->d_cases; A.node_case = c->d_node_case; A.elem_case = c->d_elem_case;
     A.rec = c->d_rec64; A.area = c->d_area; A.vol = c->d_vol; A.tri_s = c->d_tri_s;
-    A.inc_ptr = c->d_inc_ptr; A.inc = c->d_inc; A.incpos = c->d_incpos; A.csr_ptr = c->d_csr_ptr; A.csr_col = c->d_csr_col;
+    A.inc_ptr = c->d_inc_ptr; A.inc = c->d_inc; A.incpos = c->d_incpos; A.ell_col = c->d_ell_col; A.ell_len = c->d_ell_len;
     A.is_wall = c->d_is_wall; A.wnx = c->d_wnx; A.wny = c->d_wny;
     A.nsum = c->d_nsum; A.stats = c->d_stats; A.F = c->d_F; A.csum = c->d_csum; A.ccnt = c->d_ccnt;
     A.kf = c->d_kf; A.ef = c->d_ef; A.L2 = c->d_L2; A.er_r = c->d_er_r; A.er_dval = c->d_er_dval; A.er_b = c->d_er_b;
@@ -472,17 +499,17 @@ pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
     }
     if (c->any_er) {
         hipLaunchKernelGGL(k_er_assemble, g, b, 0, c->stream, A);
+        if (project) hipLaunchKernelGGL(k_proj_rhs, g, b, 0, c->stream, A);
         for (int l = 0; l < AMG_MAXL; ++l) {
             if (c->n_gal[l] == 0) continue;
             hipLaunchKernelGGL(k_galerkin, dim3(std::min<int64_t>(nblk(c->gal_max[l], 256), 1024), c->n_gal[l]), dim3(256), 0,
                                c->stream, (const GalJob*)(c->d_gal + (size_t)l * c->n_amg));
         }
-        hipLaunchKernelGGL(k_cg, dim3(c->n_jobs_er), dim3(1024), 0, c->stream, c->d_jobs_er);
+        // relaxation and projection systems of every case in one launch
+        hipLaunchKernelGGL(k_cg, dim3(c->n_jobs_er + (project ? c->n_jobs_p : 0)), dim3(1024), 0, c->stream, c->d_jobs_er);
         hipLaunchKernelGGL(k_er_finish, g, b, 0, c->stream, A);
         LAUNCHCHK(c);
         if (project) {
-            hipLaunchKernelGGL(k_proj_rhs, g, b, 0, c->stream, A);
-            hipLaunchKernelGGL(k_cg, dim3(c->n_jobs_p), dim3(1024), 0, c->stream, c->d_jobs_p);
             hipLaunchKernelGGL(k_proj_update, g, b, 0, c->stream, A);
             LAUNCHCHK(c);
         }
@@ -611,11 +638,14 @@ pdfmc_status pdfmc_add_case(pdfmc_ctx* c, const pdfmc_mesh_desc* mesh, const pdf
     if (rc != PDFMC_OK) return fail(c, (pdfmc_status)rc, err);
     if (p->mode == 2) {
         const CsrH K = host_stiffness(cs.m);
+        to_ell(K, true, cs.ell0);
         amg_setup(K, cs.m.is_wall, cs.amg[0], AMG_MAXC, AMG_MAXL);
         amg_setup(K, std::vector<int>(), cs.amg[1], AMG_MAXC, AMG_MAXL);
         cs.has_amg = cs.amg[0].lv.back().A.n <= AMG_MAXC && cs.amg[1].lv.back().A.n <= AMG_MAXC;
-        for (int h = 0; h < 2 && cs.has_amg; ++h)
+        for (int h = 0; h < 2 && cs.has_amg; ++h) {
             for (size_t l = 0; l < cs.amg[h].lv.size(); ++l) cs.omega[h][l] = jacobi_weight(cs.amg[h].lv[l].A);
+            build_hier_ell(cs.amg[h], cs.ell0, cs.he[h]);
+        }
     }
     c->cases.push_back(std::move(cs));
     *case_id = (int32_t)c->cases.size() - 1;
@@ -667,8 +697,8 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     std::vector<double> rec64(8 * (size_t)NE), exy64(6 * (size_t)NE), area(NE), vol(NN), wnx(NN), wny(NN);
     std::vector<int4> tri_s(NE), nbr(NE), partner(NE);
     std::vector<BcDev> bc(std::max(c->NBC, 1));
-    std::vector<int32_t> inc_ptr(NN + 1), inc(3 * (size_t)NE), incpos(9 * (size_t)NE), csr_ptr(NN + 1),
-        csr_col(std::max(c->NNZ, 1)), is_wall(NN);
+    std::vector<int32_t> inc_ptr(NN + 1), inc(3 * (size_t)NE), incpos(9 * (size_t)NE), ell_len(NN, 0),
+        ell_col(std::max<int64_t>(c->NELL, 1), 0), is_wall(NN);
     int ci = 0;
     for (auto& cs : c->cases) {
         const MeshHost& m = cs.m;
@@ -681,7 +711,7 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
             wnx[g] = m.wnx[s]; wny[g] = m.wny[s];
             is_wall[g] = m.is_wall[s];
             inc_ptr[g] = 3 * cs.eoff + m.inc_ptr[s];
-            csr_ptr[g] = (int32_t)cs.nnz_off + m.csr_ptr[s];
+            if (cs.p.mode == 2) ell_len[g] = cs.ell0.len[s];
         }
         for (int e = 0; e < m.ne; ++e) {
             const int g = cs.eoff + e;
@@ -705,9 +735,10 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         for (size_t j = 0; j < m.inc.size(); ++j) {
             const int ent = m.inc[j];
             inc[3 * (size_t)cs.eoff + j] = 3 * (cs.eoff + ent / 3) + ent % 3;
-            for (int k = 0; k < 3; ++k) incpos[3 * (3 * (size_t)cs.eoff + j) + k] = (int32_t)cs.nnz_off + m.incpos[3 * j + k];
+            for (int k = 0; k < 3; ++k)
+                incpos[3 * (3 * (size_t)cs.eoff + j) + k] = cs.p.mode == 2 ? (int32_t)(cs.ell_off + cs.ell0.map[m.incpos[3 * j + k]]) : 0;
         }
-        for (size_t j = 0; j < m.csr_col.size(); ++j) csr_col[cs.nnz_off + j] = cs.noff + m.csr_col[j];
+        if (cs.p.mode == 2) std::copy(cs.ell0.col.begin(), cs.ell0.col.end(), ell_col.begin() + cs.ell_off);
         for (size_t b = 0; b < m.bc.size(); ++b) {
             BcDev& d = bc[cs.bcoff + b];
             d.type = m.bc[b].type;
@@ -717,7 +748,6 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         ++ci;
     }
     inc_ptr[NN] = 3 * NE;
-    csr_ptr[NN] = c->NNZ;
     TRY(h2d(c, c->d_cases, cd));
     TRY(h2d(c, c->d_tile_case, tile_case));
     TRY(h2d(c, c->d_node_case, node_case));
@@ -734,8 +764,8 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     TRY(h2d(c, c->d_inc_ptr, inc_ptr));
     TRY(h2d(c, c->d_inc, inc));
     TRY(h2d(c, c->d_incpos, incpos));
-    TRY(h2d(c, c->d_csr_ptr, csr_ptr));
-    TRY(h2d(c, c->d_csr_col, csr_col));
+    TRY(h2d(c, c->d_ell_col, ell_col));
+    TRY(h2d(c, c->d_ell_len, ell_len));
     TRY(h2d(c, c->d_is_wall, is_wall));
     std::vector<float> rec32, exy32;
     if (c->prec == PDFMC_FP64) {
@@ -759,7 +789,7 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         int64_t ni = 0, nd = 0;
         for (auto& cs : c->cases) {
             if (!cs.has_amg) continue;
-            for (int h = 0; h < 2; ++h) pack_hier(cs.amg[h], cs.hoff[h], &ai, &ad, ni, nd);
+            for (int h = 0; h < 2; ++h) pack_hier(cs.he[h], cs.hoff[h], &ai, &ad, ni, nd);
         }
         TRY(h2d(c, c->d_amg_i, ai));
         TRY(h2d(c, c->d_amg_d, ad));
@@ -772,34 +802,31 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                 AmgDev& D = amgdev[2 * a + h];
                 D = AmgDev{};
                 D.nlev = (int)H.lv.size();
-                D.r0 = cs.noff;
                 D.coarse_shift = h == 0 ? 1e-12 : 1e-6;
+                const HierEll& E = cs.he[h];
                 for (int l = 0; l < D.nlev; ++l) {
                     D.n[l] = H.lv[l].A.n;
                     D.omega[l] = cs.omega[h][l];
-                    if (l == 0) {
-                        D.Aptr[0] = c->d_csr_ptr + cs.noff;
-                        D.Acol[0] = c->d_csr_col;
-                        D.Aval[0] = h == 0 ? c->d_er_val : c->d_pk_val;
-                    } else {
-                        D.Aptr[l] = c->d_amg_i + o.Aptr[l];
-                        D.Acol[l] = c->d_amg_i + o.Acol[l];
-                        D.Aval[l] = c->d_amg_d + o.Aval[l];
-                    }
+                    if (l == 0)
+                        D.A[0] = EllDev{cs.m.nsn, cs.ell0.w, c->d_ell_col + cs.ell_off,
+                                        (h == 0 ? c->d_er_val : c->d_pk_val) + cs.ell_off};
+                    else
+                        D.A[l] = EllDev{E.A[l].n, E.A[l].w, c->d_amg_i + o.Acol[l], c->d_amg_d + o.Aval[l]};
                     if (l + 1 < D.nlev) {
-                        D.Pptr[l] = c->d_amg_i + o.Pptr[l]; D.Pcol[l] = c->d_amg_i + o.Pcol[l]; D.Pval[l] = c->d_amg_d + o.Pval[l];
-                        D.Rptr[l] = c->d_amg_i + o.Rptr[l]; D.Rcol[l] = c->d_amg_i + o.Rcol[l]; D.Rval[l] = c->d_amg_d + o.Rval[l];
+                        D.P[l] = EllDev{E.P[l].n, E.P[l].w, c->d_amg_i + o.Pcol[l], c->d_amg_d + o.Pval[l]};
+                        D.R[l] = EllDev{E.R[l].n, E.R[l].w, c->d_amg_i + o.Rcol[l], c->d_amg_d + o.Rval[l]};
                     }
                 }
                 // Galerkin jobs: level l -> l+1
                 for (int l = 0; l + 1 < D.nlev; ++l) {
                     GalJob G{};
-                    G.nnz = (int32_t)H.lv[l + 1].A.col.size();
+                    G.nnz = (int32_t)E.gdst[l].size();
                     G.gptr = c->d_amg_i + o.Gptr[l];
                     G.gidx = c->d_amg_i + o.Gidx[l];
+                    G.gdst = c->d_amg_i + o.Gdst[l];
                     G.gcoef = c->d_amg_d + o.Gcoef[l];
-                    G.src = l == 0 ? (h == 0 ? c->d_er_val : c->d_pk_val) + cs.nnz_off : D.Aval[l];
-                    G.dst = D.Aval[l + 1];
+                    G.src = l == 0 ? (h == 0 ? c->d_er_val : c->d_pk_val) + cs.ell_off : c->d_amg_d + o.Aval[l];
+                    G.dst = c->d_amg_d + o.Aval[l + 1];
                     if (h == 0) {
                         gal[(size_t)l * c->n_amg + c->n_gal[l]++] = G;
                         c->gal_max[l] = std::max<int64_t>(c->gal_max[l], G.nnz);
@@ -813,49 +840,40 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         TRY(h2d(c, c->d_amg, amgdev));
         TRY(h2d(c, c->d_gal, gal));
     }
-    // CG jobs: 5 relaxation systems per mode-2 case and one projection system
+    // CG jobs: 5 relaxation systems per mode-2 case, then one projection
+    // system per mode-2 case (one launch solves them all at once)
     std::vector<CgJob> jer, jp;
     double* cg = c->d_cg;
     const int64_t n = NN;
     for (auto& cs : c->cases) {
         if (cs.p.mode != 2) continue;
-        for (int q = 0; q < NER; ++q) {
+        const int cidx = (int)(&cs - &c->cases[0]);
+        int64_t w0 = 0;
+        if (cs.has_amg) for (auto& lv : cs.amg[0].lv) w0 += 5 * (int64_t)lv.A.n;
+        for (int q = 0; q <= NER; ++q) {
+            const bool proj = q == NER;
             CgJob J{};
-            J.r0 = cs.noff; J.n = cs.m.nsn; J.ptr = c->d_csr_ptr; J.col = c->d_csr_col; J.val = c->d_er_val;
-            J.b = c->d_er_b + q * n; J.x = c->d_er_x + q * n;
-            J.r = cg + (4 * q + 0) * n; J.p = cg + (4 * q + 1) * n; J.q = cg + (4 * q + 2) * n; J.dinv = cg + (4 * q + 3) * n;
-            J.tol = cs.p.cg_rtol; J.maxit = cs.p.cg_maxit; J.mean_free = 0;
-            const int cidx = (int)(&cs - &c->cases[0]);
-            J.iters = c->d_counters + (int64_t)cidx * NCNT + C_CG_ER;
+            J.A = EllDev{cs.m.nsn, cs.ell0.w, c->d_ell_col + cs.ell_off, (proj ? c->d_pk_val : c->d_er_val) + cs.ell_off};
+            J.b = (proj ? c->d_pb : c->d_er_b + q * n) + cs.noff;
+            J.x = (proj ? c->d_phi : c->d_er_x + q * n) + cs.noff;
+            J.r = cg + (4 * q + 0) * n + cs.noff;
+            J.p = cg + (4 * q + 1) * n + cs.noff;
+            J.q = cg + (4 * q + 2) * n + cs.noff;
+            J.dinv = cg + (4 * q + 3) * n + cs.noff;
+            J.tol = cs.p.cg_rtol; J.maxit = cs.p.cg_maxit; J.mean_free = proj ? 1 : 0;
+            J.iters = c->d_counters + (int64_t)cidx * NCNT + (proj ? C_CG_P : C_CG_ER);
             J.fails = c->d_counters + (int64_t)cidx * NCNT + C_CG_FAIL;
             if (cs.has_amg) {
-                int64_t w = 0;
-                for (auto& lv : cs.amg[0].lv) w += 4 * (int64_t)lv.A.n;
-                J.amg = c->d_amg + 2 * cs.amg_index;
-                J.amg_work = c->d_amg_work + cs.work_off + q * w;
+                J.amg = c->d_amg + 2 * cs.amg_index + (proj ? 1 : 0);
+                J.amg_work = c->d_amg_work + cs.work_off + (proj ? NER * w0 : q * w0);
             }
-            jer.push_back(J);
+            (proj ? jp : jer).push_back(J);
         }
-        CgJob J{};
-        J.r0 = cs.noff; J.n = cs.m.nsn; J.ptr = c->d_csr_ptr; J.col = c->d_csr_col; J.val = c->d_pk_val;
-        J.b = c->d_pb; J.x = c->d_phi;
-        J.r = cg + (4 * NER + 0) * n; J.p = cg + (4 * NER + 1) * n; J.q = cg + (4 * NER + 2) * n; J.dinv = cg + (4 * NER + 3) * n;
-        J.tol = cs.p.cg_rtol; J.maxit = cs.p.cg_maxit; J.mean_free = 1;
-        const int cidx = (int)(&cs - &c->cases[0]);
-        J.iters = c->d_counters + (int64_t)cidx * NCNT + C_CG_P;
-        J.fails = c->d_counters + (int64_t)cidx * NCNT + C_CG_FAIL;
-        if (cs.has_amg) {
-            int64_t w0 = 0;
-            for (auto& lv : cs.amg[0].lv) w0 += 4 * (int64_t)lv.A.n;
-            J.amg = c->d_amg + 2 * cs.amg_index + 1;
-            J.amg_work = c->d_amg_work + cs.work_off + NER * w0;
-        }
-        jp.push_back(J);
     }
     c->n_jobs_er = (int)jer.size();
     c->n_jobs_p = (int)jp.size();
+    jer.insert(jer.end(), jp.begin(), jp.end());
     TRY(h2d(c, c->d_jobs_er, jer));
-    TRY(h2d(c, c->d_jobs_p, jp));
     // state that starts at zero
     TRY(enqueue_fill(c, c->d_F, (int64_t)NN * NF));
     TRY(enqueue_fill(c, c->d_stats, (int64_t)NN * NST));

@@ -50,8 +50,8 @@ struct CaseDev {
     int32_t eoff, ne, noff, nsn, bcoff, nbc;
     int32_t ns, nbins, nmin, mode;
     uint32_t seed_lo, seed_hi, stream, pad0;
-    int32_t csr_row0, pad1;    // first CSR row (= noff) and nnz offset
-    int64_t nnz_off, nnz;
+    int32_t ell_w, pad1;       // width of the case's Galerkin matrix in ELL form
+    int64_t ell_off;           // its offset in the global ELL arrays
     int64_t inc_off;           // incidence list offset (entries 3*e+k, global e)
     // particle-step constants, computed on the host in FP64 (and rounded for FP32)
     double dt, tnu, sq_nu, C3, c34, hphi;

@@ -15,9 +15,9 @@ struct NodeArgs {
     const int4* tri_s;               // [ne]
     const int32_t* inc_ptr;          // [nn+1] absolute offsets into inc
     const int32_t* inc;              // [3*ne] entries 3*e+k (global e)
-    const int32_t* incpos;           // [3*3*ne] CSR positions of (row, vertex) per incidence entry
-    const int32_t* csr_ptr;          // [nn+1]
-    const int32_t* csr_col;          // [nnz]
+    const int32_t* incpos;           // [3*3*ne] ELL positions of (row, vertex) per incidence entry
+    const int32_t* ell_col;          // Galerkin pattern, ELL column-major per case, local columns
+    const int32_t* ell_len;          // [nn] entries per row
     const int32_t* is_wall;          // [nn]
     const double* wnx;               // [nn]
     const double* wny;
@@ -33,8 +33,8 @@ struct NodeArgs {
     double* er_dval;                 // [5][nn] wall values
     double* er_b;                    // [5][nn] right-hand sides
     double* er_x;                    // [5][nn] relaxed tensor (warm start)
-    double* er_val;                  // [nnz]
-    double* pk_val;                  // [nnz] stiffness of the projection
+    double* er_val;                  // relaxation matrix (ELL)
+    double* pk_val;                  // stiffness of the projection (ELL)
     double* pb;                      // [nn]
     double* phi;                     // [nn]
     double* P;                       // [nn] mean pressure
@@ -44,40 +44,41 @@ struct NodeArgs {
 constexpr int AMG_MAXL = 8;        // multigrid levels
 constexpr int AMG_MAXC = 64;       // largest coarsest level (dense inverse in LDS)
 
-// One multigrid hierarchy. Level 0 is the fine system: its rows are the
-// case's statistics nodes, A0 is a slice of the global CSR (row offset r0,
-// global columns); coarser levels use local indices.
+// Square or rectangular matrix in ELL form, column-major (entry k of row i at
+// k * n + i), local column indices, zero-valued padding.
+struct EllDev {
+    int32_t n, w;
+    const int32_t* col;
+    const double* val;
+};
+
+// One multigrid hierarchy; level 0 is the fine system of one case.
 struct AmgDev {
-    int32_t nlev, r0;
+    int32_t nlev, pad;
     int32_t n[AMG_MAXL];
-    const int32_t* Aptr[AMG_MAXL];
-    const int32_t* Acol[AMG_MAXL];
-    double* Aval[AMG_MAXL];
-    const int32_t* Pptr[AMG_MAXL];
-    const int32_t* Pcol[AMG_MAXL];
-    const double* Pval[AMG_MAXL];
-    const int32_t* Rptr[AMG_MAXL];
-    const int32_t* Rcol[AMG_MAXL];
-    const double* Rval[AMG_MAXL];
+    EllDev A[AMG_MAXL];
+    EllDev P[AMG_MAXL];            // level l <- level l+1
+    EllDev R[AMG_MAXL];            // level l+1 <- level l
     double omega[AMG_MAXL];        // Jacobi smoothing weight per level
     double coarse_shift;           // relative diagonal shift of the coarsest inverse
 };
 
-// Galerkin update of one level of one hierarchy: dst[k] = sum coef src[idx]
+// Galerkin update of one level of one hierarchy:
+// dst[gdst[k]] = sum_j gcoef[j] src[gidx[j]], j in [gptr[k], gptr[k+1])
 struct GalJob {
     int32_t nnz;
     const int32_t* gptr;
-    const int32_t* gidx;           // positions relative to src
+    const int32_t* gidx;
     const double* gcoef;
+    const int32_t* gdst;
     const double* src;
     double* dst;
 };
 
+// One linear system on the rows of one case; every pointer is offset to the
+// case's first row (local indices).
 struct CgJob {
-    int32_t r0, n;                   // global row range
-    const int32_t* ptr;
-    const int32_t* col;
-    const double* val;
+    EllDev A;
     double* b;
     double* x;
     double* r;
@@ -89,7 +90,7 @@ struct CgJob {
     unsigned long long* iters;
     unsigned long long* fails;
     const AmgDev* amg;             // multigrid preconditioner, or null for Jacobi
-    double* amg_work;              // per-job vectors: dinv, x, b, t on every level
+    double* amg_work;              // per-job vectors: 5 per level
 };
 
 }  // namespace pdfmc
