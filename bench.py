@@ -1,16 +1,19 @@
 """Throughput of the particle advance on one MI355X.
 
-One step = one pdfmc_step(1): particle kernel (location by neighbour walk,
-P1 interpolation, GLM velocity / position / frequency SDEs, IECM mixing,
-boundary conditions, scatter of the moments), node statistics, cell means,
-Eulerian fields, elliptic-relaxation and projection CG solves, for every
-particle of the workload. Inputs are synthetic and resident in HBM before the
+One step = one pdfmc_step(1) over every case of the workload: particle kernel
+(location by neighbour walk, P1 interpolation, GLM velocity / position /
+frequency SDEs, IECM mixing, boundary conditions, scatter of the moments),
+node statistics, cell means, Eulerian fields, elliptic-relaxation and
+projection CG solves. Inputs are synthetic and resident in HBM before the
 timed region starts.
 
-    python bench.py [--steps K] [--warmup W] [--workload channel|cavity|small]
+    python bench.py [--steps K] [--warmup W] [--workload batch32|channel|cavity|small]
                     [--precision fp32|fp64] [--graph 0|1] [--sort-interval M]
 
-Prints one JSON line (rank 0). Only one GPU is supported: --gpus N > 1 exits.
+Workloads: batch32 (default) is 32 independent channel and cavity cases
+advanced together; channel and cavity are the single-case flows; small is the
+450-triangle square. Prints one JSON line. Only one GPU is supported:
+--gpus N > 1 exits.
 """
 from __future__ import annotations
 
@@ -34,48 +37,56 @@ def log(msg):
 
 
 def workload(name):
+    """Returns (name, list of cases, options); a case is dict(mesh, params, particles)."""
     import workloads as W
+    if name == "batch32":
+        b = W.config_batched()
+        return b["name"], b["cases"], dict(sort_interval=10)
     if name == "channel":
         cfg = W.config_channel()
-        return cfg, dict(sort_interval=10)
-    if name == "cavity":
+    elif name == "cavity":
         cfg = W.config_cavity()
-        return cfg, dict(sort_interval=10)
-    if name == "small":
+    elif name == "small":
         cfg = W.config_small()
-        return cfg, dict(sort_interval=10)
-    raise SystemExit(f"unknown workload {name}")
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return cfg["name"], [cfg], dict(sort_interval=10)
 
 
-def algorithmic_bytes(prec, ns, n_particles, n_nodes, n_elems):
+def algorithmic_bytes(prec, cases, nsn):
     """Bytes the particle kernel must move per launch: every particle's state
     read and written once, the node fields read and node sums written once,
     element records and cell tables read/written once."""
     R = 4 if prec == "fp32" else 8
-    per_particle = (7 * R + ns * R + 4 + 4 + 1) + (6 * R + ns * R + 4 + 1)
-    per_node = 22 * R + 8 * (11 + 2 * ns)
-    per_elem = 8 * R + 12 + (8 * ns * R + 8 * (1 + ns) * 8 + 8 * 4 if ns else 0)
-    total = n_particles * per_particle + n_nodes * per_node + n_elems * per_elem
-    return total, per_particle
+    total, npart = 0, 0
+    for c, nn in zip(cases, nsn):
+        ns = c["params"]["n_scalars"]
+        n = len(c["particles"]["x"])
+        ne = c["mesh"].n_elems
+        per_particle = (7 * R + ns * R + 4 + 4 + 1) + (6 * R + ns * R + 4 + 1)
+        per_node = 22 * R + 8 * (11 + 2 * ns)
+        per_elem = 8 * R + 12 + (8 * ns * R + 8 * (1 + ns) * 8 + 8 * 4 if ns else 0)
+        total += n * per_particle + nn * per_node + ne * per_elem
+        npart += n
+    return total, total / max(npart, 1)
 
 
-def run_gpu(cfg, prec, steps, warmup, opts):
+def run_gpu(cases, prec, steps, warmup, opts):
     import torch
     from paper_1006_0549_amd import Sim
-    parts = cfg["particles"]
-    n = len(parts["x"])
     sim = Sim(prec, "cuda:0")
-    cs = sim.add_case(cfg["mesh"], cfg["params"], n)
+    ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in cases]
     ws = sim.bind()
-    sim.set_options(sort_interval=opts.get("sort_interval", 0), block_size=256, use_graph=opts.get("graph", False))
-    sim.upload(cs, parts)
+    sim.set_options(sort_interval=opts.get("sort_interval", 0), block_size=opts.get("block_size", 256),
+                    use_graph=opts.get("graph", False))
+    for cs, c in zip(ids, cases):
+        sim.upload(cs, c["particles"])
     sim.init()
-    log(f"{prec}: workspace {ws / 2**20:.1f} MiB, {n} particles; warmup {warmup} steps")
+    n = sum(len(c["particles"]["x"]) for c in cases)
+    log(f"{prec}: {len(cases)} case(s), workspace {ws / 2**20:.1f} MiB, {n} particles; warmup {warmup} steps")
     sim.step(warmup)
     torch.cuda.synchronize()
-    sim.timing(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(sim.stream)
     sim.step(steps)
@@ -83,22 +94,48 @@ def run_gpu(cfg, prec, steps, warmup, opts):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
+    # particle-kernel duration: HIP events around each launch on the library's
+    # stream (eager launches; the kernel is the same one the graph replays)
+    kt = max(1, min(steps, 10))
+    sim.timing(True)
+    sim.step(kt)
+    torch.cuda.synchronize()
     k1_ms, k1_n = sim.timing_read()
     sim.timing(False)
-    log(f"{prec}: {steps} steps in {ms:.2f} ms (wall {wall * 1e3:.1f} ms); particle kernel {k1_ms / max(k1_n, 1):.3f} ms/launch")
-    stats = sim.stats(cs)
-    counters = sim.counters(cs)
-    nsn, sn = sim.case_info(cs)
-    return dict(ms=ms, k1_ms=k1_ms, k1_n=k1_n, stats=stats, counters=counters, n=n, nsn=nsn, rows=np.unique(sn, return_index=True)[1])
+    log(f"{prec}: {steps} steps in {ms:.2f} ms (wall {wall * 1e3:.1f} ms); particle kernel "
+        f"{k1_ms / max(k1_n, 1):.3f} ms/launch over {k1_n} launches")
+    out = dict(ms=ms, k1_ms=k1_ms, k1_n=k1_n, n=n, stats=[], rows=[], nsn=[], counters={})
+    for cs in ids:
+        nsn, sn = sim.case_info(cs)
+        out["nsn"].append(nsn)
+        out["rows"].append(np.unique(sn, return_index=True)[1])
+        out["stats"].append(sim.stats(cs))
+        for k, v in sim.counters(cs).items():
+            out["counters"][k] = out["counters"].get(k, 0) + v
+    del sim
+    torch.cuda.synchronize()
+    return out
 
 
-def cpu_baseline(cfg, budget_s=20.0):
+def one_by_one(cases, prec, steps, warmup, opts):
+    """The same cases advanced one at a time (one context each)."""
+    total_ms, total_n = 0.0, 0
+    for c in cases:
+        r = run_gpu([c], prec, steps, warmup, opts)
+        total_ms += r["ms"]
+        total_n += r["n"] * steps
+    return dict(value=total_n / (total_ms * 1e-3), ms_per_step=total_ms / steps)
+
+
+def cpu_baseline(cases, budget_s=20.0):
+    """The oracle, single-threaded, on a bounded sample: the smallest case of
+    the workload, as many full steps as fit in the budget."""
     import oracle
-    parts = cfg["particles"]
-    n = len(parts["x"])
+    c = min(cases, key=lambda c: len(c["particles"]["x"]))
+    n = len(c["particles"]["x"])
     o = oracle.Oracle()
-    oc = o.add_case(cfg["mesh"], cfg["params"])
-    o.upload(oc, parts)
+    oc = o.add_case(c["mesh"], c["params"])
+    o.upload(oc, c["particles"])
     t0 = time.perf_counter()
     o.init()
     log(f"oracle init {time.perf_counter() - t0:.1f} s")
@@ -109,13 +146,29 @@ def cpu_baseline(cfg, budget_s=20.0):
         t += time.perf_counter() - t1
         done += 1
         log(f"oracle step {done}: {t:.1f} s")
+    what = "the smallest case of the batch" if len(cases) > 1 else "the same workload"
     return dict(value=n * done / t, unit="particle-updates/s", cores=1, kind="oracle",
-                sample=f"{done} full steps of the same workload ({n} particles), single-threaded FP64 C, "
-                       f"timed after initialisation")
+                sample=f"{done} full steps of {what} ({c['mesh'].name}, {n} particles, "
+                       f"{c['params']['n_scalars']} scalars), single-threaded FP64 C, timed after initialisation")
 
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def error_vs_fp64(cases, g, r):
+    """Relative L2 error of each statistic over all statistics nodes of all cases."""
+    groups = {"mean_U": [], "reynolds_stress": [], "mean_omega": [], "mean_psi": [], "psi_variance": []}
+    refs = {k: [] for k in groups}
+    for c, a, b, rows in zip(cases, g["stats"], r["stats"], g["rows"]):
+        ns = c["params"]["n_scalars"]
+        sl = {"mean_U": slice(2, 5), "reynolds_stress": slice(5, 11), "mean_omega": slice(11, 12),
+              "mean_psi": slice(12, 12 + ns), "psi_variance": slice(12 + ns, 12 + 2 * ns)}
+        for k, s in sl.items():
+            if s.stop > s.start:
+                groups[k].append(a[rows, s].reshape(-1))
+                refs[k].append(b[rows, s].reshape(-1))
+    return {k: rel_l2(np.concatenate(groups[k]), np.concatenate(refs[k])) for k in groups if groups[k]}
 
 
 def main():
@@ -123,51 +176,52 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="channel")
+    ap.add_argument("--workload", default="batch32")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--sort-interval", type=int, default=None)
+    ap.add_argument("--block-size", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--no-one-by-one", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the particle advance is not sharded across GPUs); "
+        print("bench.py: only one GPU is measured (the particle advance is not sharded across GPUs); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    rank = int(os.environ.get("RANK", "0"))
 
     t0 = time.perf_counter()
-    cfg, opts = workload(args.workload)
+    name, cases, opts = workload(args.workload)
     if args.sort_interval is not None:
         opts["sort_interval"] = args.sort_interval
     opts["graph"] = bool(args.graph)
-    mesh, params = cfg["mesh"], cfg["params"]
-    n = len(cfg["particles"]["x"])
-    ns = params["n_scalars"]
-    log(f"workload {cfg['name']}: {mesh.n_elems} triangles, {n} particles, {ns} scalars "
+    opts["block_size"] = args.block_size
+    n = sum(len(c["particles"]["x"]) for c in cases)
+    ne = sum(c["mesh"].n_elems for c in cases)
+    scal = [c["params"]["n_scalars"] for c in cases]
+    log(f"workload {name}: {len(cases)} case(s), {ne} triangles, {n} particles "
         f"(inputs built in {time.perf_counter() - t0:.1f} s)")
 
-    g = run_gpu(cfg, args.precision, args.steps, args.warmup, opts)
+    g = run_gpu(cases, args.precision, args.steps, args.warmup, opts)
     ms_per_step = g["ms"] / args.steps
     value = n * args.steps / (g["ms"] * 1e-3)
     k1_avg_s = g["k1_ms"] / max(g["k1_n"], 1) * 1e-3
-    nbytes, per_particle = algorithmic_bytes(args.precision, ns, n, g["nsn"], mesh.n_elems)
+    nbytes, per_particle = algorithmic_bytes(args.precision, cases, g["nsn"])
     achieved = nbytes / k1_avg_s / 1e9
 
     extra = {}
     if args.precision == "fp32" and not args.no_fp64_reference:
-        r = run_gpu(cfg, "fp64", args.steps, args.warmup, opts)
-        rows = r["rows"]
-        a, b = g["stats"][rows], r["stats"][rows]
-        names = {"mean_U": slice(2, 5), "reynolds_stress": slice(5, 11), "mean_omega": slice(11, 12),
-                 "mean_psi": slice(12, 12 + ns), "psi_variance": slice(12 + ns, 12 + 2 * ns)}
-        extra["error_vs_fp64"] = {k: rel_l2(a[:, s], b[:, s]) for k, s in names.items() if s.stop > s.start}
+        r = run_gpu(cases, "fp64", args.steps, args.warmup, opts)
+        extra["error_vs_fp64"] = error_vs_fp64(cases, g, r)
         extra["fp64"] = dict(value=n * args.steps / (r["ms"] * 1e-3), ms_per_step=r["ms"] / args.steps,
-                             particle_kernel_ms=r["k1_ms"] / max(r["k1_n"], 1))
+                             particle_kernel_ms=r["k1_ms"] / max(r["k1_n"], 1),
+                             fp32_speedup=r["ms"] / g["ms"])
+    if len(cases) > 1 and not args.no_one_by_one:
+        s = one_by_one(cases, args.precision, 5, 2, opts)
+        extra["one_by_one"] = dict(value=s["value"], ms_per_step=s["ms_per_step"],
+                                   batched_speedup=value / s["value"], steps=5)
 
-    cpu = None
-    if not args.no_cpu_baseline and rank == 0:
-        cpu = cpu_baseline(cfg)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cases)
 
     out = {
         "metric": METRIC,
@@ -182,9 +236,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": cfg["name"] + "-" + args.precision, "particles": n, "elements": mesh.n_elems,
-                   "stat_nodes": g["nsn"], "scalars": ns, "mode": params["mode"], "dt": params["dt"],
+        "config": {"workload": f"{name}-{args.precision}", "cases": len(cases), "particles": n,
+                   "elements": ne, "stat_nodes": int(sum(g["nsn"])), "scalars": scal if len(scal) > 1 else scal[0],
                    "sort_interval": opts["sort_interval"], "graph": opts["graph"],
+                   "block_size": opts["block_size"],
                    "accumulation": "f64 node sums, f64 Eulerian fields and CG"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -195,8 +250,7 @@ def main():
         "cpu_baseline": cpu,
     }
     out.update(extra)
-    if rank == 0:
-        print(json.dumps(out), flush=True)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -17,6 +17,13 @@
  * Every point the paper leaves open is fixed by a numbered reading (R-nn),
  * listed in the design notes of the repository and restated where used.
  *
+ * Parity unpinned: the production part k H_ijkl d<U_k>/dx_l of the
+ * elliptic-relaxation right-hand side (R-19). The paper only cites the model;
+ * nothing it prints fixes that term, so the oracle's value of it is tied to
+ * the GPU path only. The rest of the relaxation (the Helmholtz solve, the
+ * isotropic part, the wall values, G_ij and C0 eps from the relaxed tensor)
+ * is pinned by manufactured solutions and the kinetic-energy trace identity.
+ *
  * Ownership: every pointer argument is borrowed for the duration of the call.
  * Errors: functions return 0 on success and a positive code otherwise; the
  * message is available from orc_last_error(). Nothing aborts.

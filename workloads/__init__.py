@@ -334,3 +334,32 @@ def config_cavity(ppe: int = 100, n_half: int = 112):
                             src=[(0.25, 0.1, 0.02, 1.0), (0.75, 0.1, 0.02, 1.0)], stream=3)
     parts = init_particles(mesh, ppe, 2, rng_for(3, 0, 1), u_std=0.1)
     return dict(name=f"cavity{mesh.n_elems}", mesh=mesh, params=params, particles=parts, steps=500)
+
+
+def config_batched(n_cases: int = 32, ne_range=(2000, 50000), ppe_range=(50, 200), seed_key=(4,)):
+    """Batch of independent flows advanced together: shapes alternate channel /
+    cavity, element counts log-uniform in ne_range (level counts scaled by
+    sqrt(N_e)), particles per element uniform integer in ppe_range, 0..4
+    scalars released from disks of radius 0.02 whose centres keep 0.1 from the
+    walls, time step log-uniform in [2e-4, 1e-3]; full model."""
+    rng = rng_for(*seed_key, 0)
+    cases = []
+    for c in range(n_cases):
+        ne_t = float(np.exp(rng.uniform(np.log(ne_range[0]), np.log(ne_range[1]))))
+        ppe = int(rng.integers(ppe_range[0], ppe_range[1] + 1))
+        ns = int(rng.integers(0, 5))
+        dt = float(np.exp(rng.uniform(np.log(2e-4), np.log(1e-3))))
+        kind = "channel" if c % 2 == 0 else "cavity"
+        if kind == "channel":
+            s = np.sqrt(ne_t / 20160.0)
+            mesh = channel(n_half=max(4, int(round(48 * s))), nx=max(8, int(round(105 * s))), seed_key=(4, c, 0))
+            Lx, H, ustd, nu, dpdx = 2 * np.pi, 2.0, 1.0, 1.0 / 1080.0, (-1.0, 0.0)
+        else:
+            s = np.sqrt(ne_t / 100352.0)
+            mesh = cavity(n_half=max(6, int(round(112 * s))), seed_key=(4, c, 0))
+            Lx, H, ustd, nu, dpdx = 1.0, 1.0, 0.1, 1.0 / 4000.0, (0.0, 0.0)
+        src = [(float(rng.uniform(0.1, Lx - 0.1)), float(rng.uniform(0.1, H - 0.1)), 0.02, 1.0) for _ in range(ns)]
+        params = default_params(mode=2, dt=dt, nu=nu, n_scalars=ns, dpdx=dpdx, src=src, stream=100 + c)
+        parts = init_particles(mesh, ppe, ns, rng_for(4, c, 1), u_std=ustd)
+        cases.append(dict(name=f"{kind}{mesh.n_elems}", mesh=mesh, params=params, particles=parts, ppe=ppe))
+    return dict(name=f"batch{n_cases}", cases=cases, steps=100)
