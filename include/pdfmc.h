@@ -166,6 +166,21 @@ pdfmc_status pdfmc_counters(pdfmc_ctx* ctx, int32_t case_id, int64_t* out);
  * capture the step sequence into a HIP graph (0/1; needs a non-NULL stream,
  * else PDFMC_E_INVALID). */
 pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t block_size, int32_t use_graph);
+/* Eulerian solver options (the FP64 multigrid-preconditioned CG of the
+ * elliptic relaxation and the projection, reading R-28 of the step contract).
+ * Every step runs `iterations` CG iterations as row-parallel phase kernels
+ * over all systems of all cases (a system that has converged skips the rest
+ * at once), then completes any system that needs more in one workgroup per
+ * system. iterations = 0 (the default) adapts the count to what the previous
+ * steps needed. Multigrid levels with more than tail_rows unknowns (default
+ * 4096) are processed by the row-parallel phases, smaller ones by one
+ * workgroup per system. Results do not depend on either option beyond FP64
+ * summation order. Errors: PDFMC_E_INVALID for iterations outside 0..100000
+ * or tail_rows < 0. */
+pdfmc_status pdfmc_set_solver(pdfmc_ctx* ctx, int32_t iterations, int32_t tail_rows);
+/* Current unrolled iteration count and number of row-parallel levels
+ * (either pointer may be NULL). */
+pdfmc_status pdfmc_solver_info(pdfmc_ctx* ctx, int32_t* iterations, int32_t* large_levels);
 /* Sort the particles of every case by element now (stable counting sort). */
 pdfmc_status pdfmc_sort(pdfmc_ctx* ctx);
 pdfmc_status pdfmc_synchronize(pdfmc_ctx* ctx);

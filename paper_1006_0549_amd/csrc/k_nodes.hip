@@ -10,8 +10,8 @@
 //                  (Eq.(6), R-17, R-18), simplified Langevin G_ij (R-20) or
 //                  the elliptic-relaxation sources, length scale and wall values (R-19)
 //   k_er_assemble  Galerkin (M + K_L) matrix, M r right-hand sides, Dirichlet rows
-//   k_cg           Jacobi-preconditioned conjugate gradients, one workgroup
-//                  per linear system, warm-started (R-28)
+//   k_galerkin     coarse-level values of the relaxation hierarchies; the
+//                  solves themselves are in k_mg.hip (R-28)
 //   k_er_finish    G_ij and C0 eps from the relaxed tensor (R-19)
 //   k_proj_rhs / k_proj_finish  pressure projection (R-27)
 //   k_mirror_f32   FP32 copy of the fields for the FP32 particle kernel
@@ -351,25 +351,7 @@ __global__ void k_mirror_f32(const double* __restrict__ F, float* __restrict__ F
     F32[i] = q < NF ? (float)F[s * NF + q] : 0.0f;
 }
 
-// ---------------------------------------------------------------- CG
-
-__device__ inline void block_sum(double* v, int nv, double* sh)
-{
-    // sh: [16 * 4] doubles of LDS; nv <= 4
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int k = 0; k < nv; ++k) {
-        double x = v[k];
-        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
-        if (lane == 0) sh[wid * 4 + k] = x;
-    }
-    __syncthreads();
-    for (int k = 0; k < nv; ++k) {
-        double x = 0.0;
-        for (int w = 0; w < nw; ++w) x += sh[w * 4 + k];
-        v[k] = x;
-    }
-    __syncthreads();
-}
+// ---------------------------------------------------------------- multigrid
 
 __global__ void k_galerkin(const GalJob* __restrict__ jobs)
 {
@@ -378,242 +360,6 @@ __global__ void k_galerkin(const GalJob* __restrict__ jobs)
         double s = 0.0;
         for (int j = J.gptr[k]; j < J.gptr[k + 1]; ++j) s += J.gcoef[j] * J.src[J.gidx[j]];
         J.dst[J.gdst[k]] = s;
-    }
-}
-
-// y_i = sum_k A(k, i) x(col(k, i)) for one row of an ELL matrix
-__device__ inline double ell_row(const EllDev& A, const double* __restrict__ x, int i)
-{
-    double s0 = 0.0, s1 = 0.0;
-    int k = 0;
-    for (; k + 1 < A.w; k += 2) {
-        const int64_t a0 = (int64_t)k * A.n + i, a1 = a0 + A.n;
-        const int c0 = A.col[a0], c1 = A.col[a1];
-        s0 += A.val[a0] * x[c0];
-        s1 += A.val[a1] * x[c1];
-    }
-    if (k < A.w) {
-        const int64_t a0 = (int64_t)k * A.n + i;
-        s0 += A.val[a0] * x[A.col[a0]];
-    }
-    return s0 + s1;
-}
-
-__device__ inline double ell_diag(const EllDev& A, int i)
-{
-    for (int k = 0; k < A.w; ++k) {
-        const int64_t a = (int64_t)k * A.n + i;
-        if (A.col[a] == i) return A.val[a];
-    }
-    return 1.0;
-}
-
-// Vectors of one level inside the V-cycle: the level's solution is y.
-struct Lvl {
-    int n;
-    double *dinv, *x, *y, *b, *t;
-};
-
-__device__ inline Lvl level(const AmgDev& H, double* work, int l, double* b0, double* y0)
-{
-    Lvl L;
-    L.n = H.n[l];
-    int64_t off = 0;
-    for (int q = 0; q < l; ++q) off += 5 * (int64_t)H.n[q];
-    L.dinv = work + off;
-    L.x = work + off + L.n;
-    L.y = l == 0 ? y0 : work + off + 2 * (int64_t)L.n;
-    L.b = l == 0 ? b0 : work + off + 3 * (int64_t)L.n;
-    L.t = work + off + 4 * (int64_t)L.n;
-    return L;
-}
-
-// out = in + w D^-1 (b - A in), one phase
-__device__ inline void jacobi(const EllDev& A, const Lvl& L, double w, const double* in, double* out)
-{
-    for (int i = threadIdx.x; i < L.n; i += blockDim.x) out[i] = in[i] + w * L.dinv[i] * (L.b[i] - ell_row(A, in, i));
-    __syncthreads();
-}
-
-// z = V(r): symmetric V-cycle, two Jacobi sweeps before and after the
-// coarse correction (ping-pong buffers, one barrier per sweep), dense
-// solve on the coarsest level.
-__device__ void vcycle(const AmgDev& H, double* work, const double* ainv, double* r, double* z)
-{
-    const int nl = H.nlev;
-    for (int l = 0; l < nl - 1; ++l) {
-        const Lvl L = level(H, work, l, r, z);
-        const double w = H.omega[l];
-        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.x[i] = w * L.dinv[i] * L.b[i];
-        __syncthreads();
-        jacobi(H.A[l], L, w, L.x, L.y);
-        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.t[i] = L.b[i] - ell_row(H.A[l], L.y, i);
-        __syncthreads();
-        const Lvl Cl = level(H, work, l + 1, r, z);
-        for (int i = threadIdx.x; i < Cl.n; i += blockDim.x) Cl.b[i] = ell_row(H.R[l], L.t, i);
-        __syncthreads();
-    }
-    {
-        const Lvl Cl = level(H, work, nl - 1, r, z);
-        for (int i = threadIdx.x; i < Cl.n; i += blockDim.x) {
-            double s = 0.0;
-            for (int j = 0; j < Cl.n; ++j) s += ainv[i * AMG_MAXC + j] * Cl.b[j];
-            Cl.y[i] = s;
-        }
-        __syncthreads();
-    }
-    for (int l = nl - 2; l >= 0; --l) {
-        const Lvl L = level(H, work, l, r, z);
-        const Lvl Cl = level(H, work, l + 1, r, z);
-        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.y[i] += ell_row(H.P[l], Cl.y, i);
-        __syncthreads();
-        jacobi(H.A[l], L, H.omega[l], L.y, L.x);
-        jacobi(H.A[l], L, H.omega[l], L.x, L.y);
-    }
-}
-
-// Prologue of a multigrid-preconditioned solve: Jacobi diagonals on every
-// level and the inverse of the (slightly shifted) coarsest matrix, by
-// Gauss-Jordan elimination in LDS (the matrix is symmetric positive).
-__device__ void amg_prepare(const AmgDev& H, double* work, double* ainv, double* r, double* z)
-{
-    for (int l = 0; l < H.nlev; ++l) {
-        const Lvl L = level(H, work, l, r, z);
-        for (int i = threadIdx.x; i < L.n; i += blockDim.x) L.dinv[i] = 1.0 / ell_diag(H.A[l], i);
-    }
-    const EllDev& Ac = H.A[H.nlev - 1];
-    const int nc = Ac.n;
-    for (int q = threadIdx.x; q < AMG_MAXC * AMG_MAXC; q += blockDim.x) ainv[q] = 0.0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < nc; i += blockDim.x)
-        for (int k = 0; k < Ac.w; ++k) {
-            const int64_t a = (int64_t)k * nc + i;
-            ainv[i * AMG_MAXC + Ac.col[a]] += Ac.val[a];
-        }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) ainv[i * AMG_MAXC + i] *= (1.0 + H.coarse_shift);
-    __syncthreads();
-    __shared__ double piv_row[AMG_MAXC], piv_col[AMG_MAXC];
-    for (int k = 0; k < nc; ++k) {
-        const double p = ainv[k * AMG_MAXC + k];
-        for (int j = threadIdx.x; j < nc; j += blockDim.x) {
-            piv_row[j] = ainv[k * AMG_MAXC + j];
-            piv_col[j] = ainv[j * AMG_MAXC + k];
-        }
-        __syncthreads();
-        const double ip = 1.0 / p;
-        for (int q = threadIdx.x; q < nc * nc; q += blockDim.x) {
-            const int i = q / nc, j = q % nc;
-            double v;
-            if (i == k && j == k) v = ip;
-            else if (i == k) v = piv_row[j] * ip;
-            else if (j == k) v = -piv_col[i] * ip;
-            else v = ainv[i * AMG_MAXC + j] - piv_col[i] * piv_row[j] * ip;
-            ainv[i * AMG_MAXC + j] = v;
-        }
-        __syncthreads();
-    }
-}
-
-// One workgroup per system (local rows 0..n); Jacobi or one multigrid
-// V-cycle as preconditioner; warm start from the current x.
-__global__ void __launch_bounds__(1024) k_cg(const CgJob* __restrict__ jobs)
-{
-    const CgJob J = jobs[blockIdx.x];
-    const int n = J.A.n;
-    if (n <= 0) return;
-    __shared__ double sh[16 * 4];
-    __shared__ double ainv[AMG_MAXC * AMG_MAXC];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const bool mg = J.amg != nullptr;
-    double v[4];
-    if (J.mean_free) {
-        v[0] = 0.0;
-        for (int i = tid; i < n; i += nt) v[0] += J.b[i];
-        block_sum(v, 1, sh);
-        const double mb = v[0] / n;
-        for (int i = tid; i < n; i += nt) J.b[i] -= mb;
-        __syncthreads();
-    }
-    if (mg) amg_prepare(*J.amg, J.amg_work, ainv, J.r, J.q);
-    // r = b - A x
-    v[0] = 0.0;
-    for (int i = tid; i < n; i += nt) {
-        J.dinv[i] = 1.0 / ell_diag(J.A, i);
-        J.r[i] = J.b[i] - ell_row(J.A, J.x, i);
-        v[0] += J.b[i] * J.b[i];
-    }
-    block_sum(v, 1, sh);
-    const double bb = v[0];
-    const double tol2 = J.tol * J.tol * bb;
-    // z = M^-1 r into q; returns (r.z, r.r)
-    auto precondition = [&](double* out) {
-        if (mg) {
-            vcycle(*J.amg, J.amg_work, ainv, J.r, J.q);
-            if (J.mean_free) {
-                double m[1] = {0.0};
-                for (int i = tid; i < n; i += nt) m[0] += J.q[i];
-                block_sum(m, 1, sh);
-                const double mz = m[0] / n;
-                for (int i = tid; i < n; i += nt) J.q[i] -= mz;
-            }
-        } else {
-            for (int i = tid; i < n; i += nt) J.q[i] = J.dinv[i] * J.r[i];
-        }
-        __syncthreads();
-        out[0] = 0.0; out[1] = 0.0;
-        for (int i = tid; i < n; i += nt) {
-            out[0] += J.r[i] * J.q[i];
-            out[1] += J.r[i] * J.r[i];
-        }
-        block_sum(out, 2, sh);
-    };
-    precondition(v);
-    double rz = v[0], rr = v[1];
-    for (int i = tid; i < n; i += nt) J.p[i] = J.q[i];
-    __syncthreads();
-    int it = 0;
-    bool ok = (rr <= tol2);
-    while (!ok && it < J.maxit) {
-        v[0] = 0.0;
-        for (int i = tid; i < n; i += nt) {
-            const double q = ell_row(J.A, J.p, i);
-            J.q[i] = q;
-            v[0] += J.p[i] * q;
-        }
-        block_sum(v, 1, sh);
-        const double alpha = rz / v[0];
-        v[0] = 0.0;
-        for (int i = tid; i < n; i += nt) {
-            J.x[i] += alpha * J.p[i];
-            const double rn = J.r[i] - alpha * J.q[i];
-            J.r[i] = rn;
-            v[0] += rn;
-        }
-        block_sum(v, 1, sh);
-        if (J.mean_free) {
-            const double mr = v[0] / n;
-            for (int i = tid; i < n; i += nt) J.r[i] -= mr;
-            __syncthreads();
-        }
-        precondition(v);
-        const double beta = v[0] / rz;
-        rz = v[0]; rr = v[1];
-        for (int i = tid; i < n; i += nt) J.p[i] = J.q[i] + beta * J.p[i];
-        __syncthreads();
-        ++it;
-        ok = (rr <= tol2);
-    }
-    if (J.mean_free) {
-        v[0] = 0.0;
-        for (int i = tid; i < n; i += nt) v[0] += J.x[i];
-        block_sum(v, 1, sh);
-        const double mx = v[0] / n;
-        for (int i = tid; i < n; i += nt) J.x[i] -= mx;
-    }
-    if (tid == 0) {
-        atomicAdd(J.iters, (unsigned long long)it);
-        if (!ok) atomicAdd(J.fails, 1ull);
     }
 }
 

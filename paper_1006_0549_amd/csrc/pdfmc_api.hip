@@ -54,10 +54,11 @@ struct Case {
     bool has_amg = false;
     AmgH amg[2];
     HierEll he[2];
-    double omega[2][AMG_MAXL] = {};
+    double rho[2][AMG_MAXL] = {};  // spectral radius estimate of D^-1 A per level
     HierOff hoff[2];
     int amg_index = -1;           // position among the cases with hierarchies
-    int64_t work_off = 0;         // per-job multigrid vectors
+    int64_t vec_off = 0;          // per-system solver vectors
+    int64_t dinv_off = 0;         // inverse diagonals of both hierarchies
 };
 
 void build_hier_ell(const AmgH& H, const EllH& ell0, HierEll& E)
@@ -107,8 +108,8 @@ void pack_hier(const HierEll& E, HierOff& o, std::vector<int32_t>* ai, std::vect
     }
 }
 
-// spectral radius of D^-1 A (power iteration) -> Jacobi weight 4/(3 rho)
-double jacobi_weight(const CsrH& A)
+// spectral radius of D^-1 A by power iteration, bounded below by 4/3
+double spectral_radius(const CsrH& A)
 {
     std::vector<double> d(A.n, 1.0), v(A.n), w(A.n);
     for (int i = 0; i < A.n; ++i)
@@ -128,8 +129,30 @@ double jacobi_weight(const CsrH& A)
         const double sc = 1.0 / std::sqrt(std::max(nw, 1e-300));
         for (int i = 0; i < A.n; ++i) v[i] = w[i] * sc;
     }
-    return std::min(1.0, std::max(0.2, 4.0 / (3.0 * rho)));
+    return std::min(20.0 / 3.0, std::max(4.0 / 3.0, rho));
 }
+
+// Chebyshev smoother of degree 2 for D^-1 A on [rho/10, 1.1 rho]:
+// y1 = y0 + sa D^-1 (b - A y0); y2 = y1 + (se - 1)(y1 - y0) + sc D^-1 (b - A y1)
+void chebyshev2(double rho, double& sa, double& se, double& sc)
+{
+    const double hi = 1.1 * rho, lo = rho / 10.0;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    const double r0 = 1.0 / sigma, r1 = 1.0 / (2.0 * sigma - r0);
+    sa = 1.0 / theta;
+    se = 1.0 + r1 * r0;
+    sc = 2.0 * r1 / delta;
+}
+
+// Solver-system layout: vectors of one system at [off, off + mg_vec_len)
+int64_t mg_vec_len(const AmgH& H)
+{
+    int64_t n = 5 * (int64_t)H.lv[0].A.n;                  // r[2], p[2], q
+    for (auto& lv : H.lv) n += 4 * (int64_t)lv.A.n;         // lb, ly, la, lt
+    return n;
+}
+
+int64_t mg_blocks(int64_t n) { return (n + 255) / 256; }
 
 // Stiffness matrix of the case on its own Galerkin pattern (host copy used
 // only to build the hierarchies).
@@ -191,9 +214,34 @@ struct pdfmc_ctx {
     int32_t* d_ccnt = nullptr;
     double *d_kf = nullptr, *d_ef = nullptr, *d_L2 = nullptr, *d_er_r = nullptr, *d_er_dval = nullptr, *d_er_b = nullptr,
            *d_er_x = nullptr, *d_er_val = nullptr, *d_pk_val = nullptr, *d_pb = nullptr, *d_phi = nullptr, *d_P = nullptr;
-    double* d_cg = nullptr;         // CG scratch: (5 + 1) systems x 4 vectors x NN
-    CgJob* d_jobs_er = nullptr;
+    // Eulerian solves: systems (relaxation first, then projection), their
+    // vectors, accumulators and state; row-block tables of the phase kernels
+    MgJob* d_mg_jobs = nullptr;
     int n_jobs_er = 0, n_jobs_p = 0;
+    double* d_mg_vec = nullptr;
+    double* d_mg_acc = nullptr;
+    int32_t* d_mg_state = nullptr;
+    unsigned int* d_mg_need = nullptr;
+    double* d_mg_dinv = nullptr;
+    double* d_mg_ainv = nullptr;
+    int2* d_mg_tab = nullptr;
+    int4* d_mg_tab_dinv = nullptr;
+    int64_t MGV = 0, MGD = 0, MGT = 0, MGTD = 0;
+    struct TabRange { int64_t off = 0; int n_er = 0, n_all = 0; };
+    TabRange tab0;                  // level-0 rows of every system
+    TabRange tabl[AMG_MAXL];        // level-l rows of the systems with more than l large levels
+    int n_tab_dinv = 0;
+    int maxbig_er = 0, maxbig_all = 0;
+    // solver options: unrolled iterations (adaptive when mg_auto), small-level threshold
+    int mg_iters = 24, mg_auto = 1, tail_rows = 4096;
+    unsigned int* h_need = nullptr;   // pinned: iterations the last observed solve needed
+    hipEvent_t need_ev = nullptr;
+    bool need_pending = false;
+    int need_low = 0;
+    std::vector<AmgDev> h_amgdev;   // host copies of what the solver tables point at
+    std::vector<MgJob> h_jobs;
+    std::vector<int2> h_tab;
+    std::vector<int4> h_tab_dinv;
     unsigned long long* d_counters = nullptr;
     uint32_t* d_step = nullptr;
     int32_t* d_sort_count = nullptr;
@@ -205,11 +253,10 @@ struct pdfmc_ctx {
     bool any_er = false, any_eul = false, any_scalars = false;
     // multigrid data: flat int/double regions, hierarchy descriptors,
     // Galerkin jobs of the relaxation hierarchies per level, per-job vectors
-    int64_t AMG_I = 0, AMG_D = 0, AMG_W = 0;
+    int64_t AMG_I = 0, AMG_D = 0;
     int n_amg = 0, amg_levels = 0;
     int32_t* d_amg_i = nullptr;
     double* d_amg_d = nullptr;
-    double* d_amg_work = nullptr;
     AmgDev* d_amg = nullptr;
     GalJob* d_gal = nullptr;           // [AMG_MAXL][n_amg]: relaxation, then projection at [AMG_MAXL*n_amg + ...]
     int n_gal[AMG_MAXL] = {};
@@ -302,8 +349,15 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_er_b, (size_t)NER * c->NN); k.take(c->d_er_x, (size_t)NER * c->NN);
     k.take(c->d_er_val, c->NELL); k.take(c->d_pk_val, c->NELL);
     k.take(c->d_pb, c->NN); k.take(c->d_phi, c->NN); k.take(c->d_P, c->NN);
-    k.take(c->d_cg, (size_t)(NER + 1) * 4 * c->NN);
-    k.take(c->d_jobs_er, (NER + 1) * c->cases.size());
+    k.take(c->d_mg_jobs, (NER + 1) * c->cases.size());
+    k.take(c->d_mg_vec, c->MGV);
+    k.take(c->d_mg_acc, (size_t)(NER + 1) * c->cases.size() * MG_NSLOT * MG_SLOT);
+    k.take(c->d_mg_state, (size_t)(NER + 1) * c->cases.size() * 2);
+    k.take(c->d_mg_need, 1);
+    k.take(c->d_mg_dinv, c->MGD);
+    k.take(c->d_mg_ainv, 2 * (size_t)std::max(c->n_amg, 1) * AMG_MAXC * AMG_MAXC);
+    k.take(c->d_mg_tab, c->MGT);
+    k.take(c->d_mg_tab_dinv, c->MGTD);
     k.take(c->d_counters, NCNT * c->cases.size());
     k.take(c->d_step, 1);
     k.take(c->d_sort_count, c->NE);
@@ -311,7 +365,6 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_sort_cursor, c->NE);
     k.take(c->d_amg_i, c->AMG_I);
     k.take(c->d_amg_d, c->AMG_D);
-    k.take(c->d_amg_work, c->AMG_W);
     k.take(c->d_amg, 2 * (size_t)std::max(c->n_amg, 1));
     k.take(c->d_gal, 2 * (size_t)AMG_MAXL * std::max(c->n_amg, 1));
 }
@@ -332,25 +385,28 @@ void compute_offsets(pdfmc_ctx* c)
         cs.ell_off = NELL; NELL += cs.p.mode == 2 ? (int64_t)cs.ell0.w * cs.m.nsn : 0;
         cs.inc_off = 3 * (int64_t)cs.eoff;
     }
-    int64_t ni = 0, nd = 0, nw = 0;
+    int64_t ni = 0, nd = 0, nv = 0, ndv = 0, nt = 0, ntd = 0;
     int na = 0, maxlev = 0;
     for (auto& cs : c->cases) {
         if (!cs.has_amg) { cs.amg_index = -1; continue; }
         cs.amg_index = na++;
+        cs.vec_off = nv;
+        cs.dinv_off = ndv;
         for (int h = 0; h < 2; ++h) {
             pack_hier(cs.he[h], cs.hoff[h], nullptr, nullptr, ni, nd);
             maxlev = std::max(maxlev, (int)cs.amg[h].lv.size());
+            const int nsys = h == 0 ? NER : 1;
+            nv += nsys * mg_vec_len(cs.amg[h]);
+            for (auto& lv : cs.amg[h].lv) {
+                ndv += lv.A.n;
+                ntd += mg_blocks(lv.A.n);
+                nt += nsys * mg_blocks(lv.A.n);
+            }
+            nt += nsys * mg_blocks(cs.amg[h].lv[0].A.n);
         }
-        cs.work_off = nw;
-        int64_t per = 0;
-        for (int h = 0; h < 2; ++h) {
-            int64_t w = 0;
-            for (auto& lv : cs.amg[h].lv) w += 5 * (int64_t)lv.A.n;
-            per += (h == 0 ? NER : 1) * w;
-        }
-        nw += per;
     }
-    c->AMG_I = ni; c->AMG_D = nd; c->AMG_W = nw; c->n_amg = na; c->amg_levels = maxlev;
+    c->AMG_I = ni; c->AMG_D = nd; c->n_amg = na; c->amg_levels = maxlev;
+    c->MGV = nv; c->MGD = ndv; c->MGT = nt; c->MGTD = ntd;
     c->NP = NP; c->PSI = PSI; c->CM = CM; c->CS = CS; c->NE = NE; c->NN = NN; c->NBC = NBC; c->NELL = NELL;
     c->ntiles = (int)(NP / TILE);
 }
@@ -488,6 +544,190 @@ pdfmc_status enqueue_cell_means(pdfmc_ctx* c)
     return PDFMC_OK;
 }
 
+void drop_graphs(pdfmc_ctx* c);
+
+int mg_nbig(const pdfmc_ctx* c, const AmgDev& D)
+{
+    int nb = 0;
+    while (nb < D.nlev - 1 && D.n[nb] > c->tail_rows) ++nb;
+    return nb;
+}
+
+// Systems, accumulator slots and row-block tables of the phase solver.
+pdfmc_status build_mg_jobs(pdfmc_ctx* c)
+{
+    for (auto& D : c->h_amgdev) D.nbig = mg_nbig(c, D);
+    if (c->n_amg > 0) TRY(h2d(c, c->d_amg, c->h_amgdev));
+    std::vector<MgJob> jer, jp;
+    const int64_t n = c->NN;
+    for (size_t ci = 0; ci < c->cases.size(); ++ci) {
+        const Case& cs = c->cases[ci];
+        if (cs.p.mode != 2) continue;
+        int64_t voff = cs.vec_off;
+        for (int q = 0; q <= NER; ++q) {
+            const bool proj = q == NER;
+            const int h = proj ? 1 : 0;
+            const int hi = 2 * cs.amg_index + h;
+            const AmgDev& D = c->h_amgdev[hi];
+            MgJob J{};
+            J.hier = hi;
+            J.mean_free = proj ? 1 : 0;
+            J.maxit = cs.p.cg_maxit;
+            J.n = cs.m.nsn;
+            J.tol = cs.p.cg_rtol;
+            J.b = (proj ? c->d_pb : c->d_er_b + q * n) + cs.noff;
+            J.x = (proj ? c->d_phi : c->d_er_x + q * n) + cs.noff;
+            double* v = c->d_mg_vec + voff;
+            const int n0 = D.n[0];
+            J.r[0] = v; J.r[1] = v + n0; J.p[0] = v + 2 * (int64_t)n0; J.p[1] = v + 3 * (int64_t)n0; J.q = v + 4 * (int64_t)n0;
+            v += 5 * (int64_t)n0;
+            for (int l = 0; l < D.nlev; ++l) {
+                const int64_t nl = D.n[l];
+                J.lb[l] = v; J.ly[l] = v + nl; J.la[l] = v + 2 * nl; J.lt[l] = v + 3 * nl;
+                v += 4 * nl;
+            }
+            voff += mg_vec_len(cs.amg[h]);
+            J.iters = c->d_counters + (int64_t)ci * NCNT + (proj ? C_CG_P : C_CG_ER);
+            J.fails = c->d_counters + (int64_t)ci * NCNT + C_CG_FAIL;
+            J.need = c->d_mg_need;
+            (proj ? jp : jer).push_back(J);
+        }
+    }
+    c->n_jobs_er = (int)jer.size();
+    c->n_jobs_p = (int)jp.size();
+    jer.insert(jer.end(), jp.begin(), jp.end());
+    for (size_t j = 0; j < jer.size(); ++j) {
+        jer[j].acc = c->d_mg_acc + j * MG_NSLOT * MG_SLOT;
+        jer[j].state = c->d_mg_state + 2 * j;
+    }
+    c->h_jobs = jer;
+    TRY(h2d(c, c->d_mg_jobs, c->h_jobs));
+    const int nj = (int)jer.size();
+    std::vector<int2>& tab = c->h_tab;
+    tab.clear();
+    auto add_rows = [&](int j, int rows) {
+        for (int r0 = 0; r0 < rows; r0 += 256) tab.push_back(make_int2(j, r0));
+    };
+    c->tab0.off = 0;
+    for (int j = 0; j < c->n_jobs_er; ++j) add_rows(j, jer[j].n);
+    c->tab0.n_er = (int)tab.size();
+    for (int j = c->n_jobs_er; j < nj; ++j) add_rows(j, jer[j].n);
+    c->tab0.n_all = (int)tab.size();
+    c->maxbig_er = c->maxbig_all = 0;
+    for (int l = 0; l < AMG_MAXL; ++l) {
+        auto& T = c->tabl[l];
+        T.off = (int64_t)tab.size();
+        for (int j = 0; j < nj; ++j) {
+            if (j == c->n_jobs_er) T.n_er = (int)(tab.size() - T.off);
+            const AmgDev& D = c->h_amgdev[jer[j].hier];
+            if (D.nbig > l) {
+                add_rows(j, D.n[l]);
+                if (j < c->n_jobs_er) c->maxbig_er = std::max(c->maxbig_er, l + 1);
+                c->maxbig_all = std::max(c->maxbig_all, l + 1);
+            }
+        }
+        if (c->n_jobs_er == nj) T.n_er = (int)(tab.size() - T.off);
+        T.n_all = (int)(tab.size() - T.off);
+    }
+    if ((int64_t)tab.size() > c->MGT) return fail(c, PDFMC_E_STATE, "solver tables exceed their reservation");
+    TRY(h2d(c, c->d_mg_tab, tab));
+    std::vector<int4>& td = c->h_tab_dinv;
+    td.clear();
+    for (int hi = 0; hi < 2 * c->n_amg; ++hi) {
+        const AmgDev& D = c->h_amgdev[hi];
+        for (int l = 0; l < D.nlev; ++l)
+            for (int r0 = 0; r0 < D.n[l]; r0 += 256) td.push_back(make_int4(hi, l, r0, 0));
+    }
+    if ((int64_t)td.size() > c->MGTD) return fail(c, PDFMC_E_STATE, "solver tables exceed their reservation");
+    c->n_tab_dinv = (int)td.size();
+    TRY(h2d(c, c->d_mg_tab_dinv, td));
+    return PDFMC_OK;
+}
+
+// The Eulerian solves of every case: c->mg_iters PCG iterations as phase
+// kernels over all systems, then k_mg_finish for any system that needs more.
+pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
+{
+    const int nj = c->n_jobs_er + (project ? c->n_jobs_p : 0);
+    if (nj == 0) return PDFMC_OK;
+    auto cnt = [&](const pdfmc_ctx::TabRange& t) { return (unsigned)(project ? t.n_all : t.n_er); };
+    const int maxbig = project ? c->maxbig_all : c->maxbig_er;
+    const MgJob* J = c->d_mg_jobs;
+    const AmgDev* H = c->d_amg;
+    const int2* T0 = c->d_mg_tab + c->tab0.off;
+    const unsigned g0 = cnt(c->tab0);
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_mg_dinv, dim3(c->n_tab_dinv), dim3(256), 0, st, H, (const int4*)c->d_mg_tab_dinv);
+    hipLaunchKernelGGL(k_mg_coarse, dim3(2 * c->n_amg), dim3(1024), 0, st, H);
+    hipLaunchKernelGGL(k_mg_setup1, dim3(g0), dim3(256), 0, st, J, T0);
+    hipLaunchKernelGGL(k_mg_setup2, dim3(g0), dim3(256), 0, st, J, H, T0);
+    LAUNCHCHK(c);
+    auto vcycle = [&](int k) -> pdfmc_status {
+        if (maxbig >= 1)
+            hipLaunchKernelGGL(k_mg_res, dim3(cnt(c->tabl[0])), dim3(256), 0, st, J, H,
+                               (const int2*)(c->d_mg_tab + c->tabl[0].off), 0, k);
+        for (int l = 1; l < maxbig; ++l) {
+            const int2* Tl = c->d_mg_tab + c->tabl[l].off;
+            const dim3 gl(cnt(c->tabl[l]));
+            hipLaunchKernelGGL(k_mg_restrict, gl, dim3(256), 0, st, J, H, Tl, l, k);
+            hipLaunchKernelGGL(k_mg_pre, gl, dim3(256), 0, st, J, H, Tl, l, k);
+            hipLaunchKernelGGL(k_mg_res, gl, dim3(256), 0, st, J, H, Tl, l, k);
+        }
+        hipLaunchKernelGGL(k_mg_tail, dim3(nj), dim3(1024), 0, st, J, H, k);
+        for (int l = maxbig - 1; l >= 0; --l) {
+            const int2* Tl = c->d_mg_tab + c->tabl[l].off;
+            const dim3 gl(cnt(c->tabl[l]));
+            hipLaunchKernelGGL(k_mg_post1, gl, dim3(256), 0, st, J, H, Tl, l, k);
+            hipLaunchKernelGGL(k_mg_post2, gl, dim3(256), 0, st, J, H, Tl, l, k);
+        }
+        LAUNCHCHK(c);
+        return PDFMC_OK;
+    };
+    hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, -1, 1);
+    TRY(vcycle(-1));
+    for (int k = 0; k < c->mg_iters; ++k) {
+        hipLaunchKernelGGL(k_mg_pa, dim3(g0), dim3(256), 0, st, J, H, T0, k);
+        hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, k, 0);
+        TRY(vcycle(k));
+    }
+    hipLaunchKernelGGL(k_mg_finish, dim3(nj), dim3(1024), 0, st, J, H, c->mg_iters);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
+// After a step: fetch the iteration count the solves needed (asynchronously);
+// before a step: adapt the number of unrolled iterations to what was needed.
+pdfmc_status mg_after_step(pdfmc_ctx* c)
+{
+    if (!c->mg_auto || !c->any_er || c->need_pending || !c->h_need) return PDFMC_OK;
+    HIPCHK(c, hipMemcpyAsync(c->h_need, c->d_mg_need, sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipEventRecord(c->need_ev, c->stream));
+    c->need_pending = true;
+    return PDFMC_OK;
+}
+
+void mg_adapt(pdfmc_ctx* c)
+{
+    if (!c->mg_auto || !c->need_pending) return;
+    if (hipEventQuery(c->need_ev) != hipSuccess) return;
+    c->need_pending = false;
+    const int need = (int)*c->h_need;
+    int want = c->mg_iters;
+    if (need > c->mg_iters) {
+        want = need + 2;
+        c->need_low = 0;
+    } else if (need + 6 < c->mg_iters) {
+        if (++c->need_low >= 3) { want = need + 2; c->need_low = 0; }
+    } else {
+        c->need_low = 0;
+    }
+    want = std::max(1, std::min(want, 400));
+    if (want != c->mg_iters) {
+        c->mg_iters = want;
+        drop_graphs(c);
+    }
+}
+
 pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
 {
     NodeArgs A = node_args(c);
@@ -505,8 +745,8 @@ pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
             hipLaunchKernelGGL(k_galerkin, dim3(std::min<int64_t>(nblk(c->gal_max[l], 256), 1024), c->n_gal[l]), dim3(256), 0,
                                c->stream, (const GalJob*)(c->d_gal + (size_t)l * c->n_amg));
         }
-        // relaxation and projection systems of every case in one launch
-        hipLaunchKernelGGL(k_cg, dim3(c->n_jobs_er + (project ? c->n_jobs_p : 0)), dim3(1024), 0, c->stream, c->d_jobs_er);
+        // relaxation and projection systems of every case together
+        TRY(enqueue_solve(c, project));
         hipLaunchKernelGGL(k_er_finish, g, b, 0, c->stream, A);
         LAUNCHCHK(c);
         if (project) {
@@ -614,6 +854,8 @@ void pdfmc_destroy(pdfmc_ctx* c)
     if (c->bound) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     for (auto e : c->ev) (void)hipEventDestroy(e);
+    if (c->need_ev) (void)hipEventDestroy(c->need_ev);
+    if (c->h_need) (void)hipHostFree(c->h_need);
     delete c;
 }
 
@@ -642,8 +884,11 @@ pdfmc_status pdfmc_add_case(pdfmc_ctx* c, const pdfmc_mesh_desc* mesh, const pdf
         amg_setup(K, cs.m.is_wall, cs.amg[0], AMG_MAXC, AMG_MAXL);
         amg_setup(K, std::vector<int>(), cs.amg[1], AMG_MAXC, AMG_MAXL);
         cs.has_amg = cs.amg[0].lv.back().A.n <= AMG_MAXC && cs.amg[1].lv.back().A.n <= AMG_MAXC;
+        if (!cs.has_amg)
+            return fail(c, PDFMC_E_UNSUPPORTED, "add_case: the multigrid hierarchy of the Eulerian solves does not reach a "
+                                                "coarsest level of at most 64 unknowns within 8 levels");
         for (int h = 0; h < 2 && cs.has_amg; ++h) {
-            for (size_t l = 0; l < cs.amg[h].lv.size(); ++l) cs.omega[h][l] = jacobi_weight(cs.amg[h].lv[l].A);
+            for (size_t l = 0; l < cs.amg[h].lv.size(); ++l) cs.rho[h][l] = spectral_radius(cs.amg[h].lv[l].A);
             build_hier_ell(cs.amg[h], cs.ell0, cs.he[h]);
         }
     }
@@ -802,11 +1047,17 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                 AmgDev& D = amgdev[2 * a + h];
                 D = AmgDev{};
                 D.nlev = (int)H.lv.size();
+                D.nbig = 0;                     // set by build_mg_jobs
                 D.coarse_shift = h == 0 ? 1e-12 : 1e-6;
+                D.ainv = c->d_mg_ainv + (size_t)(2 * a + h) * AMG_MAXC * AMG_MAXC;
                 const HierEll& E = cs.he[h];
+                int64_t doff = cs.dinv_off;
+                if (h == 1) for (auto& lv : cs.amg[0].lv) doff += lv.A.n;
                 for (int l = 0; l < D.nlev; ++l) {
                     D.n[l] = H.lv[l].A.n;
-                    D.omega[l] = cs.omega[h][l];
+                    D.dinv[l] = c->d_mg_dinv + doff;
+                    doff += D.n[l];
+                    chebyshev2(cs.rho[h][l], D.sa[l], D.se[l], D.sc[l]);
                     if (l == 0)
                         D.A[0] = EllDev{cs.m.nsn, cs.ell0.w, c->d_ell_col + cs.ell_off,
                                         (h == 0 ? c->d_er_val : c->d_pk_val) + cs.ell_off};
@@ -840,40 +1091,16 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         TRY(h2d(c, c->d_amg, amgdev));
         TRY(h2d(c, c->d_gal, gal));
     }
-    // CG jobs: 5 relaxation systems per mode-2 case, then one projection
-    // system per mode-2 case (one launch solves them all at once)
-    std::vector<CgJob> jer, jp;
-    double* cg = c->d_cg;
-    const int64_t n = NN;
-    for (auto& cs : c->cases) {
-        if (cs.p.mode != 2) continue;
-        const int cidx = (int)(&cs - &c->cases[0]);
-        int64_t w0 = 0;
-        if (cs.has_amg) for (auto& lv : cs.amg[0].lv) w0 += 5 * (int64_t)lv.A.n;
-        for (int q = 0; q <= NER; ++q) {
-            const bool proj = q == NER;
-            CgJob J{};
-            J.A = EllDev{cs.m.nsn, cs.ell0.w, c->d_ell_col + cs.ell_off, (proj ? c->d_pk_val : c->d_er_val) + cs.ell_off};
-            J.b = (proj ? c->d_pb : c->d_er_b + q * n) + cs.noff;
-            J.x = (proj ? c->d_phi : c->d_er_x + q * n) + cs.noff;
-            J.r = cg + (4 * q + 0) * n + cs.noff;
-            J.p = cg + (4 * q + 1) * n + cs.noff;
-            J.q = cg + (4 * q + 2) * n + cs.noff;
-            J.dinv = cg + (4 * q + 3) * n + cs.noff;
-            J.tol = cs.p.cg_rtol; J.maxit = cs.p.cg_maxit; J.mean_free = proj ? 1 : 0;
-            J.iters = c->d_counters + (int64_t)cidx * NCNT + (proj ? C_CG_P : C_CG_ER);
-            J.fails = c->d_counters + (int64_t)cidx * NCNT + C_CG_FAIL;
-            if (cs.has_amg) {
-                J.amg = c->d_amg + 2 * cs.amg_index + (proj ? 1 : 0);
-                J.amg_work = c->d_amg_work + cs.work_off + (proj ? NER * w0 : q * w0);
-            }
-            (proj ? jp : jer).push_back(J);
-        }
+    if (!c->h_need) {
+        HIPCHK(c, hipHostMalloc((void**)&c->h_need, sizeof(unsigned int), hipHostMallocDefault));
+        *c->h_need = 0;
     }
-    c->n_jobs_er = (int)jer.size();
-    c->n_jobs_p = (int)jp.size();
-    jer.insert(jer.end(), jp.begin(), jp.end());
-    TRY(h2d(c, c->d_jobs_er, jer));
+    if (!c->need_ev) HIPCHK(c, hipEventCreateWithFlags(&c->need_ev, hipEventDisableTiming));
+    c->need_pending = false;
+    // solver systems: 5 relaxation systems per mode-2 case, then one
+    // projection system per mode-2 case
+    c->h_amgdev = amgdev;
+    TRY(build_mg_jobs(c));
     // state that starts at zero
     TRY(enqueue_fill(c, c->d_F, (int64_t)NN * NF));
     TRY(enqueue_fill(c, c->d_stats, (int64_t)NN * NST));
@@ -881,7 +1108,10 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     TRY(enqueue_fill(c, c->d_phi, NN));
     TRY(enqueue_fill(c, c->d_P, NN));
     TRY(enqueue_fill(c, c->d_pb, NN));
-    TRY(enqueue_fill(c, c->d_cg, (int64_t)(NER + 1) * 4 * NN));
+    TRY(enqueue_fill(c, c->d_mg_vec, c->MGV));
+    TRY(enqueue_fill(c, c->d_mg_acc, (int64_t)(NER + 1) * c->cases.size() * MG_NSLOT * MG_SLOT));
+    TRY(enqueue_fill_i(c, c->d_mg_state, (int64_t)(NER + 1) * c->cases.size() * 2));
+    TRY(enqueue_fill_i(c, (int32_t*)c->d_mg_need, 1));
     TRY(enqueue_fill(c, (double*)c->d_counters, (int64_t)NCNT * c->cases.size()));
     TRY(enqueue_fill_i(c, (int32_t*)c->d_step, 1));
     if (c->any_er) {
@@ -1081,6 +1311,7 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps)
     if (!c->initialised) return fail(c, PDFMC_E_STATE, "step: call pdfmc_init (or pdfmc_rebin) first");
     if (n_steps < 0) return fail(c, PDFMC_E_INVALID, "step: n_steps < 0");
     for (int s = 0; s < n_steps; ++s) {
+        mg_adapt(c);
         if (c->sort_interval > 0 && c->steps_since_sort >= c->sort_interval) TRY(enqueue_sort(c));
         if (c->use_graph && !c->timing) {
             hipGraphExec_t& g = c->graph[c->cur];
@@ -1099,6 +1330,7 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps)
         } else {
             TRY(enqueue_step_body(c));
         }
+        TRY(mg_after_step(c));
         c->steps_since_sort++;
     }
     return PDFMC_OK;
@@ -1189,6 +1421,32 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* c, int32_t sort_interval, int32_t bloc
     c->sort_interval = sort_interval;
     c->block = block_size;
     c->use_graph = use_graph ? 1 : 0;
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_set_solver(pdfmc_ctx* c, int32_t iterations, int32_t tail_rows)
+{
+    if (!c) return PDFMC_E_INVALID;
+    if (iterations < 0 || iterations > 100000) return fail(c, PDFMC_E_INVALID, "set_solver: iterations must be 0..100000");
+    if (tail_rows < 0) return fail(c, PDFMC_E_INVALID, "set_solver: tail_rows must be >= 0");
+    const bool retable = tail_rows != c->tail_rows;
+    c->mg_auto = iterations == 0 ? 1 : 0;
+    if (iterations > 0 && iterations != c->mg_iters) { c->mg_iters = iterations; drop_graphs(c); }
+    c->tail_rows = tail_rows;
+    if (retable && c->bound) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        drop_graphs(c);
+        TRY(build_mg_jobs(c));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_solver_info(pdfmc_ctx* c, int32_t* iterations, int32_t* large_levels)
+{
+    if (!c) return PDFMC_E_INVALID;
+    if (iterations) *iterations = c->mg_iters;
+    if (large_levels) *large_levels = c->maxbig_all;
     return PDFMC_OK;
 }
 

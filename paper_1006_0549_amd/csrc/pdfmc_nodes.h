@@ -52,14 +52,22 @@ struct EllDev {
     const double* val;
 };
 
-// One multigrid hierarchy; level 0 is the fine system of one case.
+// One multigrid hierarchy; level 0 is the fine system of one case. Levels
+// 0..nbig-1 are processed by row-parallel phase kernels over many
+// workgroups; levels nbig.. by one workgroup per system.
 struct AmgDev {
-    int32_t nlev, pad;
+    int32_t nlev, nbig;
     int32_t n[AMG_MAXL];
     EllDev A[AMG_MAXL];
     EllDev P[AMG_MAXL];            // level l <- level l+1
     EllDev R[AMG_MAXL];            // level l+1 <- level l
-    double omega[AMG_MAXL];        // Jacobi smoothing weight per level
+    double* dinv[AMG_MAXL];        // inverse diagonals, refreshed every solve
+    // two-step polynomial smoother in D^-1 A, from zero:
+    //   y1 = sa D^-1 b,  y2 = se y1 + sc D^-1 (b - A y1)
+    // and from y0: y1 = y0 + sa D^-1 (b - A y0),
+    //   y2 = y1 + (se - 1)(y1 - y0) + sc D^-1 (b - A y1)
+    double sa[AMG_MAXL], se[AMG_MAXL], sc[AMG_MAXL];
+    double* ainv;                  // [AMG_MAXC * AMG_MAXC] inverse of the coarsest matrix
     double coarse_shift;           // relative diagonal shift of the coarsest inverse
 };
 
@@ -76,21 +84,29 @@ struct GalJob {
 };
 
 // One linear system on the rows of one case; every pointer is offset to the
-// case's first row (local indices).
-struct CgJob {
-    EllDev A;
-    double* b;
-    double* x;
-    double* r;
-    double* p;
-    double* q;
-    double* dinv;
-    double tol;
-    int32_t maxit, mean_free;
+// case's first row (local indices). Preconditioned CG whose iterations are
+// split into phases; scalars are accumulated per iteration in rotating slots.
+constexpr int MG_SLOT = 8;         // doubles per accumulator slot
+constexpr int MG_NSLOT = 5;        // 4 iteration slots + 1 set-up slot
+struct MgJob {
+    int32_t hier;                  // index of the hierarchy
+    int32_t mean_free;             // singular system: solution and residual kept mean-free
+    int32_t maxit, n;              // iteration cap, rows
+    double tol;                    // relative residual tolerance
+    double* b;                     // right-hand side (made mean-free in place)
+    double* x;                     // solution, warm start
+    double* r[2];                  // residual, ping-pong by iteration parity
+    double* p[2];                  // search direction, ping-pong
+    double* q;                     // A p
+    double* lb[AMG_MAXL];          // level right-hand sides (level 0 uses r)
+    double* ly[AMG_MAXL];          // level corrections (level 0: z = M^-1 r)
+    double* la[AMG_MAXL];          // smoothing intermediate
+    double* lt[AMG_MAXL];          // residual, then the pre-smoothing copy
+    double* acc;                   // [MG_NSLOT][MG_SLOT]
+    int32_t* state;                // [0] converged, [1] iteration count
     unsigned long long* iters;
     unsigned long long* fails;
-    const AmgDev* amg;             // multigrid preconditioner, or null for Jacobi
-    double* amg_work;              // per-job vectors: 5 per level
+    unsigned int* need;            // largest iteration count of the step (all systems)
 };
 
 }  // namespace pdfmc

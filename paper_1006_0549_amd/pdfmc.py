@@ -62,7 +62,7 @@ EXPORTS = ["pdfmc_create", "pdfmc_destroy", "pdfmc_last_error", "pdfmc_add_case"
            "pdfmc_pressure_download", "pdfmc_init", "pdfmc_rebin", "pdfmc_step", "pdfmc_set_step_index",
            "pdfmc_stats_readback", "pdfmc_node_sums", "pdfmc_cell_means", "pdfmc_counters",
            "pdfmc_set_options", "pdfmc_sort", "pdfmc_synchronize", "pdfmc_timing", "pdfmc_timing_read",
-           "pdfmc_draw_gaussians"]
+           "pdfmc_draw_gaussians", "pdfmc_set_solver", "pdfmc_solver_info"]
 
 
 def lib():
@@ -96,6 +96,8 @@ def lib():
         L.pdfmc_set_step_index.argtypes = [vp, C.c_uint32]
         L.pdfmc_set_options.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
         L.pdfmc_timing.argtypes = [vp, C.c_int32]
+        L.pdfmc_set_solver.argtypes = [vp, C.c_int32, C.c_int32]
+        L.pdfmc_solver_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.pdfmc_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.pdfmc_draw_gaussians.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, C.c_int64, vp]
         for f in EXPORTS:
@@ -199,6 +201,15 @@ class Sim:
 
     def set_options(self, sort_interval=0, block_size=256, use_graph=False):
         self._check(self._L.pdfmc_set_options(self._h, sort_interval, block_size, int(bool(use_graph))), "set_options")
+
+    def set_solver(self, iterations=0, tail_rows=4096):
+        """iterations = 0: adaptive number of row-parallel CG iterations."""
+        self._check(self._L.pdfmc_set_solver(self._h, int(iterations), int(tail_rows)), "set_solver")
+
+    def solver_info(self):
+        it, lv = C.c_int32(), C.c_int32()
+        self._check(self._L.pdfmc_solver_info(self._h, C.byref(it), C.byref(lv)), "solver_info")
+        return it.value, lv.value
 
     # ------------------------------------------------------------ particles and fields
     def upload(self, cs, parts):

@@ -28,13 +28,15 @@ def P():
     return P
 
 
-def _pair(P, oracle_mod, mesh, params, parts, precision="fp64", fields=None, options=None):
+def _pair(P, oracle_mod, mesh, params, parts, precision="fp64", fields=None, options=None, solver=None):
     n = len(parts["x"])
     sim = P.Sim(precision, "cuda:0")
     cs = sim.add_case(mesh, params, n)
     sim.bind()
     if options:
         sim.set_options(**options)
+    if solver:
+        sim.set_solver(**solver)
     if fields is not None:
         sim.fields_upload(cs, fields)
     sim.upload(cs, parts)
@@ -179,11 +181,21 @@ def _small_channel(ppe=20, ns=1, rtol=1e-13):
     return mesh, params, parts
 
 
-def test_elliptic_relaxation_and_projection(P, oracle_mod):
+@pytest.mark.parametrize("solver", [None, dict(iterations=0, tail_rows=64), dict(iterations=2, tail_rows=64),
+                                    dict(iterations=40, tail_rows=0)],
+                         ids=["default", "rowparallel", "finisher", "allrowparallel"])
+def test_elliptic_relaxation_and_projection(P, oracle_mod, solver):
+    """Relaxation and projection fields against the oracle. The solver
+    options move the multigrid levels between the row-parallel phase kernels
+    and the one-workgroup tail, and force the one-workgroup completion of
+    systems that need more iterations than the phases ran."""
     mesh, params, parts = _small_channel()
     n = len(parts["x"])
-    _flush(f"[er] channel {mesh.n_elems} triangles, {n} particles, mode 2")
-    sim, cs, o, oc = _pair(P, oracle_mod, mesh, params, parts)
+    _flush(f"[er] channel {mesh.n_elems} triangles, {n} particles, mode 2, solver {solver}")
+    sim, cs, o, oc = _pair(P, oracle_mod, mesh, params, parts, solver=solver)
+    if solver:
+        it, big = sim.solver_info()
+        assert big >= 1
     sim.init(); o.init()
     rows = _stat_rows(sim, cs)
     gF, rF = sim.fields(cs)[rows], o.fields(oc)[rows]
