@@ -79,12 +79,18 @@ def run_gpu(cases, prec, steps, warmup, opts):
     ws = sim.bind()
     sim.set_options(sort_interval=opts.get("sort_interval", 0), block_size=opts.get("block_size", 256),
                     use_graph=opts.get("graph", False))
+    sim.set_solver(iterations=opts.get("cg_iters", 0), tail_rows=opts.get("tail_rows", 1024))
     for cs, c in zip(ids, cases):
         sim.upload(cs, c["particles"])
     sim.init()
     n = sum(len(c["particles"]["x"]) for c in cases)
     log(f"{prec}: {len(cases)} case(s), workspace {ws / 2**20:.1f} MiB, {n} particles; warmup {warmup} steps")
     sim.step(warmup)
+    tuned = None
+    if opts.get("autotune"):
+        t0 = time.perf_counter()
+        tuned = sim.autotune(steps_per_trial=4)
+        log(f"{prec}: autotuner chose {tuned} in {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -104,7 +110,8 @@ def run_gpu(cases, prec, steps, warmup, opts):
     sim.timing(False)
     log(f"{prec}: {steps} steps in {ms:.2f} ms (wall {wall * 1e3:.1f} ms); particle kernel "
         f"{k1_ms / max(k1_n, 1):.3f} ms/launch over {k1_n} launches")
-    out = dict(ms=ms, k1_ms=k1_ms, k1_n=k1_n, n=n, stats=[], rows=[], nsn=[], counters={})
+    out = dict(ms=ms, k1_ms=k1_ms, k1_n=k1_n, n=n, stats=[], rows=[], nsn=[], counters={},
+               solver=sim.solver_info(), tuned=tuned)
     for cs in ids:
         nsn, sn = sim.case_info(cs)
         out["nsn"].append(nsn)
@@ -181,6 +188,12 @@ def main():
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--sort-interval", type=int, default=None)
     ap.add_argument("--block-size", type=int, default=256)
+    ap.add_argument("--cg-iters", type=int, default=0, help="row-parallel CG iterations per step (0: adaptive)")
+    ap.add_argument("--tail-rows", type=int, default=1024, help="multigrid levels at most this size run in one workgroup")
+    ap.add_argument("--autotune", type=int, default=None,
+                    help="run the autotuner before the timed steps (default: on for batch32)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied by a plain device copy before the workload (reference kernel for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-one-by-one", action="store_true")
@@ -190,12 +203,25 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration > 0:
+        import torch
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read and written, 3 times")
+        del src, dst
     t0 = time.perf_counter()
     name, cases, opts = workload(args.workload)
     if args.sort_interval is not None:
         opts["sort_interval"] = args.sort_interval
     opts["graph"] = bool(args.graph)
     opts["block_size"] = args.block_size
+    opts["cg_iters"] = args.cg_iters
+    opts["tail_rows"] = args.tail_rows
+    opts["autotune"] = bool(args.autotune if args.autotune is not None else args.workload == "batch32")
     n = sum(len(c["particles"]["x"]) for c in cases)
     ne = sum(c["mesh"].n_elems for c in cases)
     scal = [c["params"]["n_scalars"] for c in cases]
@@ -203,6 +229,10 @@ def main():
         f"(inputs built in {time.perf_counter() - t0:.1f} s)")
 
     g = run_gpu(cases, args.precision, args.steps, args.warmup, opts)
+    if g["tuned"]:
+        # the other legs run with the settings the autotuner chose
+        opts.update(block_size=g["tuned"]["block_size"], sort_interval=g["tuned"]["sort_interval"],
+                    tail_rows=g["tuned"]["tail_rows"], autotune=False)
     ms_per_step = g["ms"] / args.steps
     value = n * args.steps / (g["ms"] * 1e-3)
     k1_avg_s = g["k1_ms"] / max(g["k1_n"], 1) * 1e-3
@@ -239,7 +269,9 @@ def main():
         "config": {"workload": f"{name}-{args.precision}", "cases": len(cases), "particles": n,
                    "elements": ne, "stat_nodes": int(sum(g["nsn"])), "scalars": scal if len(scal) > 1 else scal[0],
                    "sort_interval": opts["sort_interval"], "graph": opts["graph"],
-                   "block_size": opts["block_size"],
+                   "block_size": opts["block_size"], "tail_rows": opts["tail_rows"],
+                   "cg_row_parallel_iterations": g["solver"][0], "cg_row_parallel_levels": g["solver"][1],
+                   "autotuned": g["tuned"],
                    "accumulation": "f64 node sums, f64 Eulerian fields and CG"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -88,6 +88,9 @@ typedef struct {
     double k_floor, eps_floor;                     /* R-18                        */
     double cg_rtol; int32_t cg_maxit;              /* R-28                        */
     uint64_t seed; uint32_t stream;                /* RNG key and stream, R-09    */
+    double n_eff_min;    /* least effective sample size W^2/sum (w N)^2 of a
+                            node estimate; below it the node keeps its previous
+                            moments (R-34) */
 } pdfmc_case_params;
 
 /* Particle ensemble on the host, structure of arrays, always FP64 here (the
@@ -148,9 +151,10 @@ pdfmc_status pdfmc_set_step_index(pdfmc_ctx* ctx, uint32_t n);
  * W, rho, <U_1..3>, <u1u1>,<u2u2>,<u3u3>,<u1u2>,<u1u3>,<u2u3>, <omega>,
  * <psi_a> (n_scalars), <psi_a'^2> (n_scalars). Synchronises the stream. */
 pdfmc_status pdfmc_stats_readback(pdfmc_ctx* ctx, int32_t case_id, double* out);
-/* Raw weighted node sums of the last statistics pass, [n_nodes*(11+2*n_s)]:
+/* Raw weighted node sums of the last statistics pass, [n_nodes*(12+2*n_s)]:
  * sum_p w N_n(X_p) Q_p for Q = 1, U_1..3, U1U1,U2U2,U3U3,U1U2,U1U3,U2U3,
- * omega, psi_a, psi_a^2. */
+ * omega, psi_a, psi_a^2, then sum_p (w N_n(X_p))^2 (for the effective
+ * sample size of R-34). */
 pdfmc_status pdfmc_node_sums(pdfmc_ctx* ctx, int32_t case_id, double* out);
 /* Cell means of the IECM conditional mean, [n_elems*8*n_s], and cell
  * particle counts [n_elems*8] (either pointer may be NULL). */
@@ -162,7 +166,8 @@ pdfmc_status pdfmc_cell_means(pdfmc_ctx* ctx, int32_t case_id, double* mean, int
 pdfmc_status pdfmc_counters(pdfmc_ctx* ctx, int32_t case_id, int64_t* out);
 
 /* Execution options: re-sort the particles by element every sort_interval
- * steps (0 = never), particle-kernel block size (64, 128, 192 or 256),
+ * steps (0 = never), particle-kernel block size (64, 128 or 256: a divisor of
+ * the 256-particle tile, so that a workgroup never spans two cases),
  * capture the step sequence into a HIP graph (0/1; needs a non-NULL stream,
  * else PDFMC_E_INVALID). */
 pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t block_size, int32_t use_graph);
@@ -173,7 +178,7 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t bl
  * at once), then completes any system that needs more in one workgroup per
  * system. iterations = 0 (the default) adapts the count to what the previous
  * steps needed. Multigrid levels with more than tail_rows unknowns (default
- * 4096) are processed by the row-parallel phases, smaller ones by one
+ * 1024) are processed by the row-parallel phases, smaller ones by one
  * workgroup per system. Results do not depend on either option beyond FP64
  * summation order. Errors: PDFMC_E_INVALID for iterations outside 0..100000
  * or tail_rows < 0. */
@@ -181,6 +186,24 @@ pdfmc_status pdfmc_set_solver(pdfmc_ctx* ctx, int32_t iterations, int32_t tail_r
 /* Current unrolled iteration count and number of row-parallel levels
  * (either pointer may be NULL). */
 pdfmc_status pdfmc_solver_info(pdfmc_ctx* ctx, int32_t* iterations, int32_t* large_levels);
+/* Autotuner of the batched step (what the step's cost depends on besides the
+ * workload): times real steps of the bound workload for each trial setting
+ * and keeps the fastest, by coordinate descent over
+ *   particle-kernel block size   64, 128, 256
+ *   sort interval                1, 2, 5, 10, 20 steps
+ *   multigrid tail threshold     256, 1024, 4096 rows (pdfmc_set_solver)
+ * Each trial runs one untimed step, then max(steps_per_trial, a multiple of
+ * the sort interval) timed steps. The trial steps advance the simulation
+ * exactly like pdfmc_step (the results do not depend on the settings beyond
+ * FP64 summation order). Fills *out (may be NULL) with the chosen settings
+ * and their time per step. Errors: PDFMC_E_STATE before init or while live
+ * timing is enabled, PDFMC_E_INVALID for steps_per_trial outside 1..1000. */
+typedef struct {
+    int32_t block_size, sort_interval, tail_rows;
+    int32_t trials, steps;       /* trial settings timed, time steps advanced */
+    double ms_per_step;
+} pdfmc_tune_result;
+pdfmc_status pdfmc_autotune(pdfmc_ctx* ctx, int32_t steps_per_trial, pdfmc_tune_result* out);
 /* Sort the particles of every case by element now (stable counting sort). */
 pdfmc_status pdfmc_sort(pdfmc_ctx* ctx);
 pdfmc_status pdfmc_synchronize(pdfmc_ctx* ctx);

@@ -63,7 +63,7 @@ class _Params(C.Structure):
                 ("src", (C.c_double * 4) * 4),
                 ("k_floor", C.c_double), ("eps_floor", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
-                ("seed", C.c_uint64), ("stream", C.c_uint32)]
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("n_eff_min", C.c_double)]
 
 
 class _Particles(C.Structure):
@@ -288,7 +288,7 @@ class Oracle:
 
     def node_sums(self, cs):
         mesh, p = self._cases[cs]
-        out = np.zeros((mesh.n_nodes, 11 + 2 * p["n_scalars"]))
+        out = np.zeros((mesh.n_nodes, 12 + 2 * p["n_scalars"]))
         self._check(self._L.orc_node_sums(self._c, cs, _dp(out)), "node_sums")
         return out
 

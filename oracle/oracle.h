@@ -71,6 +71,7 @@ typedef struct {
     double k_floor, eps_floor;                    /* R-18 */
     double cg_rtol; int32_t cg_maxit;             /* R-28 */
     uint64_t seed; uint32_t stream;               /* R-09 key and counter word 2 */
+    double n_eff_min;    /* R-34: least effective sample size of a node estimate */
 } orc_params;
 
 typedef struct {

@@ -43,6 +43,7 @@ int orc_add_case(orc_ctx* c, const orc_mesh_desc* m, const orc_params* p, int32_
     if (p->n_bins != 1 && p->n_bins != 8) return orc_err(c, ORC_E_INVALID, "add_case: n_bins must be 1 or 8");
     if (p->mode < 0 || p->mode > 2) return orc_err(c, ORC_E_INVALID, "add_case: bad mode");
     if (!(p->dt > 0.0) || !(p->nu >= 0.0)) return orc_err(c, ORC_E_INVALID, "add_case: dt must be > 0, nu >= 0");
+    if (!(p->n_eff_min >= 0.0)) return orc_err(c, ORC_E_INVALID, "add_case: n_eff_min must be >= 0");
     ocase* cs = orc_alloc(sizeof(ocase));
     cs->p = *p;
     int rc = omesh_build(c, &cs->m, m);
@@ -50,7 +51,7 @@ int orc_add_case(orc_ctx* c, const orc_mesh_desc* m, const orc_params* p, int32_
     int nsn = cs->m.nsn, ne = cs->m.ne, ns = p->n_scalars;
     cs->F = orc_alloc(sizeof(double) * (size_t)nsn * ORC_NF);
     cs->stats = orc_alloc(sizeof(double) * (size_t)nsn * (12 + 2 * ns));
-    cs->sums = orc_alloc(sizeof(double) * (size_t)nsn * (11 + 2 * ns));
+    cs->sums = orc_alloc(sizeof(double) * (size_t)nsn * (12 + 2 * ns));
     cs->cmean = orc_alloc(sizeof(double) * (size_t)ne * 8 * (ns > 0 ? ns : 1));
     cs->ccount = orc_alloc(sizeof(int32_t) * (size_t)ne * 8);
     cs->P = orc_alloc(sizeof(double) * nsn);
@@ -197,7 +198,7 @@ int orc_node_sums(orc_ctx* c, int32_t ci, double* out)
 {
     ocase* cs = get_case(c, ci);
     if (!cs || !out) return orc_err(c, ORC_E_INVALID, "node_sums: bad argument");
-    int nsu = 11 + 2 * cs->p.n_scalars;
+    int nsu = 12 + 2 * cs->p.n_scalars;
     for (int i = 0; i < cs->m.nn; ++i)
         memcpy(out + (size_t)i * nsu, cs->sums + (size_t)cs->m.snode[i] * nsu, sizeof(double) * nsu);
     return ORC_OK;

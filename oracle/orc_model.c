@@ -14,7 +14,7 @@
 #include <string.h>
 
 static int nstat_of(const ocase* cs) { return 12 + 2 * cs->p.n_scalars; }
-static int nsum_of(const ocase* cs) { return 11 + 2 * cs->p.n_scalars; }
+static int nsum_of(const ocase* cs) { return 12 + 2 * cs->p.n_scalars; }
 
 /* R-06: f = fma(l3, f3, fma(l2, f2, l1*f1)) for every field slot */
 static void interpolate(const ocase* cs, int e, const double lam[3], double f[ORC_NF])
@@ -119,6 +119,7 @@ int orc_node_moments(ocase* cs)
             r[4] += wn * Q[0] * Q[0]; r[5] += wn * Q[1] * Q[1]; r[6] += wn * Q[2] * Q[2];
             r[7] += wn * Q[0] * Q[1]; r[8] += wn * Q[0] * Q[2]; r[9] += wn * Q[1] * Q[2];
             r[10] += wn * cs->om[p];
+            r[11 + 2 * ns] += wn * wn;
             for (int a = 0; a < ns; ++a) {
                 double ps = cs->psi[(size_t)a * cs->np + p];
                 r[11 + a] += wn * ps;
@@ -126,12 +127,14 @@ int orc_node_moments(ocase* cs)
             }
         }
     }
-    /* means; an empty node keeps its previous statistics */
+    /* means; an empty node, or (once there are previous statistics) one whose
+     * effective sample size W^2 / sum (w N)^2 is below n_eff_min, keeps its
+     * previous statistics (R-34) */
     char* live = orc_alloc((size_t)nsn);
     for (int s = 0; s < nsn; ++s) {
         double* st = cs->stats + (size_t)s * nst;
         const double* r = S + (size_t)s * nsu;
-        if (r[0] > 0.0) {
+        if (r[0] > 0.0 && (!cs->have_stats || r[0] * r[0] >= cs->p.n_eff_min * r[11 + 2 * ns])) {
             live[s] = 1;
             st[0] = r[0];
             st[1] = r[0] / m->vol[s];
@@ -142,7 +145,8 @@ int orc_node_moments(ocase* cs)
             for (int a = 0; a < ns; ++a) st[12 + ns + a] = 0.0;
         } else {
             live[s] = 0;
-            st[0] = 0.0; st[1] = 0.0;
+            st[0] = r[0];
+            st[1] = r[0] / m->vol[s];
             cs->cnt[CNT_EMPTY_NODE]++;
         }
     }

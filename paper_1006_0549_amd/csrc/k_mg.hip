@@ -11,10 +11,11 @@
 //   V-cycle on r_{k+1}: residual -> restriction -> [pre-smoothing, residual,
 //          restriction on further large levels] -> one workgroup per system
 //          for the small levels and the dense coarsest solve -> prolongation
-//          fused with the first post-smoothing step -> second step, whose
-//          level-0 output is z_{k+1}, with r.z and sum z accumulated.
+//          -> two post-smoothing steps, the second of which gives z_{k+1} on
+//          level 0 and accumulates r.z and sum z.
 // Scalars are accumulated with FP64 atomics into rotating per-iteration slots
-// (slot k mod 4); a slot is cleared two phases after its last reader. Level
+// (slot k mod 4); a slot is cleared two phases after its last reader. Thread 0
+// of each workgroup reads the scalars and broadcasts them through LDS. Level
 // sizes are fixed per system, so a fixed number of iterations can be replayed
 // from a graph; systems that have converged leave every later phase at once,
 // and k_mg_finish completes any system that needs more iterations in one
@@ -27,6 +28,8 @@ namespace {
 
 constexpr int MGB = 256;   // rows per workgroup in the row-parallel phases
 
+// loads that bypass the non-coherent L1 (values written by atomics of the
+// same kernel)
 __device__ inline double aload(const double* p)
 {
     return __longlong_as_double(
@@ -74,31 +77,85 @@ __device__ inline void block_accumulate(const double (&v)[NV], double* const (&d
     __syncthreads();
 }
 
+// Scalars of a phase, computed by thread 0 and broadcast through LDS.
+struct Scal {
+    double a, b;
+    int flag;
+};
+
+__device__ inline Scal broadcast(Scal v)
+{
+    __shared__ double sa, sb;
+    __shared__ int sf;
+    if (threadIdx.x == 0) { sa = v.a; sb = v.b; sf = v.flag; }
+    __syncthreads();
+    Scal r{sa, sb, sf};
+    __syncthreads();
+    return r;
+}
+
+// PA scalars: flag = converged; a = beta, b = mean of z (singular systems)
+__device__ inline Scal pa_scalars(const MgJob& J, int k)
+{
+    Scal s{0.0, 0.0, 0};
+    if (threadIdx.x == 0) {
+        s.flag = converged(J, k) ? 1 : 0;
+        if (!s.flag) {
+            const double* sp = slot(J, k - 1);
+            s.a = k == 0 ? 0.0 : rz_of(J, sp) / rz_of(J, slot(J, k - 2));
+            s.b = J.mean_free ? aload(sp + 4) / J.n : 0.0;
+        }
+    }
+    return broadcast(s);
+}
+
+// PB scalars: a = alpha; flag = zero right-hand side (first pass only)
+__device__ inline Scal pb_scalars(const MgJob& J, int k, bool first)
+{
+    Scal s{0.0, 0.0, 0};
+    if (threadIdx.x == 0) {
+        const double* su = setup_slot(J);
+        s.flag = first && (aload(su + 2) <= 1e-28 * aload(su + 1)) ? 1 : 0;
+        s.a = first ? 0.0 : rz_of(J, slot(J, k - 1)) / aload(slot(J, k));
+    }
+    return broadcast(s);
+}
+
+// y_i = sum_k A(k, i) x(col(k, i)); the width is a multiple of 4 and the
+// four loads of a group are issued together
 __device__ inline double ell_row(const EllDev& A, const double* __restrict__ x, int i)
 {
-    double s0 = 0.0, s1 = 0.0;
-    int k = 0;
-    for (; k + 1 < A.w; k += 2) {
-        const int64_t a0 = (int64_t)k * A.n + i, a1 = a0 + A.n;
-        s0 += A.val[a0] * x[A.col[a0]];
-        s1 += A.val[a1] * x[A.col[a1]];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int64_t n = A.n;
+    for (int k = 0; k < A.w; k += 4) {
+        const int64_t a = (int64_t)k * n + i;
+        const int c0 = A.col[a], c1 = A.col[a + n], c2 = A.col[a + 2 * n], c3 = A.col[a + 3 * n];
+        const double v0 = A.val[a], v1 = A.val[a + n], v2 = A.val[a + 2 * n], v3 = A.val[a + 3 * n];
+        const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+        s0 += v0 * x0;
+        s1 += v1 * x1;
+        s2 += v2 * x2;
+        s3 += v3 * x3;
     }
-    if (k < A.w) {
-        const int64_t a0 = (int64_t)k * A.n + i;
-        s0 += A.val[a0] * x[A.col[a0]];
-    }
-    return s0 + s1;
+    return (s0 + s1) + (s2 + s3);
 }
 
 template <typename F>
 __device__ inline double ell_row_f(const EllDev& A, F get, int i)
 {
-    double s = 0.0;
-    for (int k = 0; k < A.w; ++k) {
-        const int64_t a = (int64_t)k * A.n + i;
-        s += A.val[a] * get(A.col[a]);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const int64_t n = A.n;
+    for (int k = 0; k < A.w; k += 4) {
+        const int64_t a = (int64_t)k * n + i;
+        const int c0 = A.col[a], c1 = A.col[a + n], c2 = A.col[a + 2 * n], c3 = A.col[a + 3 * n];
+        const double v0 = A.val[a], v1 = A.val[a + n], v2 = A.val[a + 2 * n], v3 = A.val[a + 3 * n];
+        const double x0 = get(c0), x1 = get(c1), x2 = get(c2), x3 = get(c3);
+        s0 += v0 * x0;
+        s1 += v1 * x1;
+        s2 += v2 * x2;
+        s3 += v3 * x3;
     }
-    return s;
+    return (s0 + s1) + (s2 + s3);
 }
 
 // two smoothing steps from zero for row i; b(j) gives the right-hand side
@@ -119,13 +176,11 @@ __device__ inline const double* level_rhs(const MgJob& J, int l, int k)
 
 // ---------------------------------------------------------------- phase bodies
 // Each body handles rows i0, i0 + st, ... < i1 of one system. All threads of
-// the workgroup call it (the accumulating bodies synchronise).
+// the workgroup call the accumulating bodies (they synchronise).
 
-__device__ void pa_body(const MgJob& J, const AmgDev& H, int k, int i0, int i1, int st)
+__device__ void pa_body(const MgJob& J, const AmgDev& H, int k, Scal sc, int i0, int i1, int st)
 {
-    const double* sp = slot(J, k - 1);
-    const double beta = k == 0 ? 0.0 : rz_of(J, sp) / rz_of(J, slot(J, k - 2));
-    const double mz = J.mean_free ? aload(sp + 4) / J.n : 0.0;
+    const double beta = sc.a, mz = sc.b;
     const double* z = J.ly[0];
     const double* pold = J.p[(k - 1) & 1];
     double* pnew = J.p[k & 1];
@@ -141,11 +196,11 @@ __device__ void pa_body(const MgJob& J, const AmgDev& H, int k, int i0, int i1, 
     block_accumulate<1>({pq}, {slot(J, k)});
 }
 
-__device__ void pb_body(const MgJob& J, const AmgDev& H, int k, bool first, bool leader, int i0, int i1, int st)
+__device__ void pb_body(const MgJob& J, const AmgDev& H, int k, bool first, Scal sc, bool leader, int i0, int i1,
+                        int st)
 {
-    const double* su = setup_slot(J);
-    const bool zero_rhs = first && (aload(su + 2) <= 1e-28 * aload(su + 1));
-    const double alpha = first ? 0.0 : rz_of(J, slot(J, k - 1)) / aload(slot(J, k));
+    const bool zero_rhs = sc.flag != 0;
+    const double alpha = sc.a;
     if (leader) {
         double* sn = slot(J, k + 1);
         for (int t = 0; t < MG_SLOT; ++t) sn[t] = 0.0;
@@ -186,21 +241,19 @@ __device__ inline void pre_rows(const MgJob& J, const AmgDev& H, int l, int k, i
     for (int i = i0; i < i1; i += st) J.ly[l][i] = pre_row(H, l, [&](int j) { return b[j]; }, i);
 }
 
-// prolongation + first post-smoothing step: lt = y + P y_c, la = lt + sa D^-1 (b - A lt)
+// prolongation: lt = y + P y_c
+__device__ inline void prolong_rows(const MgJob& J, const AmgDev& H, int l, int i0, int i1, int st)
+{
+    for (int i = i0; i < i1; i += st) J.lt[l][i] = J.ly[l][i] + ell_row(H.P[l], J.ly[l + 1], i);
+}
+
+// first post-smoothing step: la = lt + sa D^-1 (b - A lt)
 __device__ inline void post1_rows(const MgJob& J, const AmgDev& H, int l, int k, int i0, int i1, int st)
 {
     const double* b = level_rhs(J, l, k);
-    const double* y = J.ly[l];
-    const double* yc = J.ly[l + 1];
-    const EllDev& P = H.P[l];
-    auto y0 = [&](int j) { return y[j] + ell_row(P, yc, j); };
     const double* dinv = H.dinv[l];
-    for (int i = i0; i < i1; i += st) {
-        const double s = ell_row_f(H.A[l], y0, i);
-        const double yi = y0(i);
-        J.lt[l][i] = yi;
-        J.la[l][i] = yi + H.sa[l] * dinv[i] * (b[i] - s);
-    }
+    for (int i = i0; i < i1; i += st)
+        J.la[l][i] = J.lt[l][i] + H.sa[l] * dinv[i] * (b[i] - ell_row(H.A[l], J.lt[l], i));
 }
 
 // second post-smoothing step: y = la + (se - 1)(la - lt) + sc D^-1 (b - A la)
@@ -247,6 +300,8 @@ __device__ void tail_body(const MgJob& J, const AmgDev& H, int k)
         __syncthreads();
     }
     for (int l = nl - 2; l >= l0; --l) {
+        prolong_rows(J, H, l, tid, H.n[l], nt);
+        __syncthreads();
         post1_rows(J, H, l, k, tid, H.n[l], nt);
         __syncthreads();
         double rz = 0.0, sz = 0.0;
@@ -264,6 +319,9 @@ __device__ void tail_body(const MgJob& J, const AmgDev& H, int k)
         block_accumulate<2>({rz, sz}, {slot(J, k) + 3, slot(J, k) + 4});
     }
 }
+
+// state of a system as seen by a row-parallel phase (written by earlier kernels)
+__device__ inline bool inactive(const MgJob& J, int k) { return J.state[0] != 0 || k >= J.maxit; }
 
 }  // namespace
 
@@ -345,7 +403,7 @@ __global__ void __launch_bounds__(MGB) k_mg_setup2(const MgJob* __restrict__ job
     const MgJob& J = jobs[e.x];
     const AmgDev& H = hs[J.hier];
     double* su = setup_slot(J);
-    const double mb = J.mean_free ? aload(su) / J.n : 0.0;
+    const double mb = J.mean_free ? su[0] / J.n : 0.0;
     const int i = e.y + threadIdx.x;
     double bb = 0.0;
     if (i < J.n) {
@@ -362,12 +420,13 @@ __global__ void __launch_bounds__(MGB) k_mg_pa(const MgJob* __restrict__ jobs, c
 {
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (aloadi(J.state) != 0 || k >= J.maxit) return;
-    if (converged(J, k)) {
+    if (inactive(J, k)) return;
+    const Scal sc = pa_scalars(J, k);
+    if (sc.flag) {
         if (e.y == 0 && threadIdx.x == 0) { J.state[0] = 1; J.state[1] = k; }
         return;
     }
-    pa_body(J, hs[J.hier], k, e.y + threadIdx.x, min(e.y + MGB, J.n), MGB);
+    pa_body(J, hs[J.hier], k, sc, e.y + threadIdx.x, min(e.y + MGB, J.n), MGB);
 }
 
 __global__ void __launch_bounds__(MGB) k_mg_pb(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
@@ -375,8 +434,10 @@ __global__ void __launch_bounds__(MGB) k_mg_pb(const MgJob* __restrict__ jobs, c
 {
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (aloadi(J.state) != 0 || k >= J.maxit) return;
-    pb_body(J, hs[J.hier], k, first != 0, e.y == 0 && threadIdx.x == 0, e.y + threadIdx.x, min(e.y + MGB, J.n), MGB);
+    if (inactive(J, k)) return;
+    const Scal sc = pb_scalars(J, k, first != 0);
+    pb_body(J, hs[J.hier], k, first != 0, sc, e.y == 0 && threadIdx.x == 0, e.y + threadIdx.x, min(e.y + MGB, J.n),
+            MGB);
 }
 
 // residual of level l (tab: rows of level l of the systems with nbig > l)
@@ -385,20 +446,20 @@ __global__ void __launch_bounds__(MGB) k_mg_res(const MgJob* __restrict__ jobs, 
 {
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (aloadi(J.state) != 0 || k >= J.maxit) return;
+    if (inactive(J, k)) return;
     const AmgDev& H = hs[J.hier];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) res_rows(J, H, l, k, i, i + 1, 1);
 }
 
-// restriction to level l >= 1 followed by nothing else (the pre-smoothing of
-// level l needs every row of the restricted right-hand side)
+// restriction to level l >= 1 (the pre-smoothing of level l needs every row
+// of the restricted right-hand side, so it is a phase of its own)
 __global__ void __launch_bounds__(MGB) k_mg_restrict(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
                                                      const int2* __restrict__ tab, int l, int k)
 {
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (aloadi(J.state) != 0 || k >= J.maxit) return;
+    if (inactive(J, k)) return;
     const AmgDev& H = hs[J.hier];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) restrict_rows(J, H, l, i, i + 1, 1);
@@ -409,7 +470,7 @@ __global__ void __launch_bounds__(MGB) k_mg_pre(const MgJob* __restrict__ jobs, 
 {
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (aloadi(J.state) != 0 || k >= J.maxit) return;
+    if (inactive(J, k)) return;
     const AmgDev& H = hs[J.hier];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) pre_rows(J, H, l, k, i, i + 1, 1);
@@ -418,8 +479,19 @@ __global__ void __launch_bounds__(MGB) k_mg_pre(const MgJob* __restrict__ jobs, 
 __global__ void __launch_bounds__(1024) k_mg_tail(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs, int k)
 {
     const MgJob& J = jobs[blockIdx.x];
-    if (J.n <= 0 || aloadi(J.state) != 0 || k >= J.maxit) return;
+    if (J.n <= 0 || inactive(J, k)) return;
     tail_body(J, hs[J.hier], k);
+}
+
+__global__ void __launch_bounds__(MGB) k_mg_prolong(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
+                                                    const int2* __restrict__ tab, int l, int k)
+{
+    const int2 e = tab[blockIdx.x];
+    const MgJob& J = jobs[e.x];
+    if (inactive(J, k)) return;
+    const AmgDev& H = hs[J.hier];
+    const int i = e.y + threadIdx.x;
+    if (i < H.n[l]) prolong_rows(J, H, l, i, i + 1, 1);
 }
 
 __global__ void __launch_bounds__(MGB) k_mg_post1(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
@@ -427,7 +499,7 @@ __global__ void __launch_bounds__(MGB) k_mg_post1(const MgJob* __restrict__ jobs
 {
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (aloadi(J.state) != 0 || k >= J.maxit) return;
+    if (inactive(J, k)) return;
     const AmgDev& H = hs[J.hier];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) post1_rows(J, H, l, k, i, i + 1, 1);
@@ -438,7 +510,7 @@ __global__ void __launch_bounds__(MGB) k_mg_post2(const MgJob* __restrict__ jobs
 {
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (aloadi(J.state) != 0 || k >= J.maxit) return;
+    if (inactive(J, k)) return;
     const AmgDev& H = hs[J.hier];
     const int i = e.y + threadIdx.x;
     double rz = 0.0, sz = 0.0;
@@ -457,14 +529,18 @@ __global__ void __launch_bounds__(1024) k_mg_finish(const MgJob* __restrict__ jo
     if (n <= 0) return;
     const AmgDev& H = hs[J.hier];
     const int tid = threadIdx.x, nt = blockDim.x;
-    bool done = aloadi(J.state) != 0;
-    int it = done ? aloadi(J.state + 1) : 0;
+    Scal st{0.0, 0.0, 0};
+    if (tid == 0) { st.flag = aloadi(J.state); st.a = st.flag ? (double)aloadi(J.state + 1) : 0.0; }
+    st = broadcast(st);
+    bool done = st.flag != 0;
+    int it = (int)st.a;
     for (int k = min(k0, J.maxit); !done; ++k) {
-        if (converged(J, k)) { done = true; it = k; break; }
+        const Scal sa = pa_scalars(J, k);
+        if (sa.flag) { done = true; it = k; break; }
         if (k >= J.maxit) { it = k; break; }
-        pa_body(J, H, k, tid, n, nt);
-        pb_body(J, H, k, false, tid == 0, tid, n, nt);
-        __syncthreads();
+        pa_body(J, H, k, sa, tid, n, nt);
+        const Scal sb = pb_scalars(J, k, false);
+        pb_body(J, H, k, false, sb, tid == 0, tid, n, nt);
         if (H.nbig >= 1) {
             res_rows(J, H, 0, k, tid, n, nt);
             __syncthreads();
@@ -480,6 +556,8 @@ __global__ void __launch_bounds__(1024) k_mg_finish(const MgJob* __restrict__ jo
         tail_body(J, H, k);
         __syncthreads();
         for (int l = H.nbig - 1; l >= 0; --l) {
+            prolong_rows(J, H, l, tid, H.n[l], nt);
+            __syncthreads();
             post1_rows(J, H, l, k, tid, H.n[l], nt);
             __syncthreads();
             double rz = 0.0, sz = 0.0;

@@ -42,9 +42,12 @@ __global__ void k_node_stats(NodeArgs A)
     const double* r = A.nsum + (int64_t)s * NQ;
     double* st = A.stats + (int64_t)s * NST;
     const double W = r[0];
-    if (W > 0.0) {
-        st[0] = W;
-        st[1] = W / A.vol[s];
+    // an empty node, or (once there are previous statistics) one whose
+    // effective sample size W^2 / sum (w N)^2 is below n_eff_min, keeps its
+    // previous moments (R-34)
+    st[0] = W;
+    st[1] = W / A.vol[s];
+    if (W > 0.0 && (A.first_stats || W * W >= C.neff_min * r[11 + 2 * ns])) {
         const double m1 = r[1] / W, m2 = r[2] / W, m3 = r[3] / W;
         st[2] = m1; st[3] = m2; st[4] = m3;
         st[5] = r[4] / W - m1 * m1;
@@ -60,7 +63,6 @@ __global__ void k_node_stats(NodeArgs A)
             st[12 + ns + a] = r[11 + ns + a] / W - m * m;
         }
     } else {
-        st[0] = 0.0; st[1] = 0.0;     // empty node: keep the previous moments
         atomicAdd(A.counters + (int64_t)c * NCNT + C_EMPTY_NODE, 1ull);
     }
 }

@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     // shuffles; the run heads add the run sums into a per-workgroup LDS table
     // keyed by element; after the barrier the table is flushed with one FP64
     // atomic per (element, value). A table overflow falls back to direct atomics.
-    const int nq = 11 + 2 * ns;
+    const int nq = 12 + 2 * ns;
     {
         const int key = valid ? e : -1;
         const Runs r = make_runs(key);
@@ -368,6 +368,11 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             for (int q = 0; q < 11; ++q) {
                 const double sum = run_sum(val[q], r);
                 if (r.head && key >= 0) put(s_val, slot, k * nq + q, A.nsum + (int64_t)s3[k] * NQ + q, sum);
+            }
+            {
+                const double s2 = run_sum(wn * wn, r);
+                if (r.head && key >= 0)
+                    put(s_val, slot, k * nq + 11 + 2 * ns, A.nsum + (int64_t)s3[k] * NQ + 11 + 2 * ns, s2);
             }
             for (int a = 0; a < ns; ++a) {
                 const double ps = (double)psi[a];

@@ -235,6 +235,7 @@ void to_ell(const CsrH& A, bool pad_self, EllH& E)
     E.w = 0;
     for (int i = 0; i < A.n; ++i) E.w = std::max(E.w, A.ptr[i + 1] - A.ptr[i]);
     E.w = std::max(E.w, 1);
+    E.w = (E.w + 3) / 4 * 4;   // the device loops take four entries at a time
     E.col.assign((size_t)E.w * A.n, 0);
     E.val.assign((size_t)E.w * A.n, 0.0);
     E.len.assign(A.n, 0);

@@ -28,8 +28,8 @@ struct AmgH {
 };
 
 // ELL form of a CSR matrix, column-major: entry k of row i at k * n + i.
-// Rows shorter than the width are padded with value 0 and column i itself
-// (pad_self) or column 0.
+// The width is the longest row rounded up to a multiple of 4; shorter rows
+// are padded with value 0 and column i itself (pad_self) or column 0.
 struct EllH {
     int n = 0, w = 0;
     std::vector<int> col, len;

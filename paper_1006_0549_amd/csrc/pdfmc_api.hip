@@ -193,6 +193,7 @@ struct pdfmc_ctx {
     int64_t NELL = 0;
     // workspace
     bool bound = false, initialised = false;
+    bool have_stats = false;        // node statistics have been formed once
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
     // device arrays
@@ -233,7 +234,7 @@ struct pdfmc_ctx {
     int n_tab_dinv = 0;
     int maxbig_er = 0, maxbig_all = 0;
     // solver options: unrolled iterations (adaptive when mg_auto), small-level threshold
-    int mg_iters = 24, mg_auto = 1, tail_rows = 4096;
+    int mg_iters = 32, mg_auto = 1, tail_rows = 1024;
     unsigned int* h_need = nullptr;   // pinned: iterations the last observed solve needed
     hipEvent_t need_ev = nullptr;
     bool need_pending = false;
@@ -430,7 +431,7 @@ CaseDev make_case_dev(const pdfmc_ctx* c, const Case& cs)
     d.nu = p.nu; d.C0 = p.C0; d.Cw1 = p.Cw1; d.Cw2 = p.Cw2; d.C1 = p.C1; d.C2 = p.C2; d.gamma5 = p.gamma5;
     d.Cv = p.Cv; d.CL = p.CL; d.Ceta = p.Ceta; d.nu34 = std::sqrt(p.nu * std::sqrt(p.nu));
     d.k_floor = p.k_floor; d.eps_floor = p.eps_floor; d.dpdx[0] = p.dpdx[0]; d.dpdx[1] = p.dpdx[1];
-    d.cg_rtol = p.cg_rtol; d.cg_maxit = p.cg_maxit;
+    d.cg_rtol = p.cg_rtol; d.cg_maxit = p.cg_maxit; d.neff_min = p.n_eff_min;
     (void)c;
     return d;
 }
@@ -448,6 +449,7 @@ pdfmc_status h2d(pdfmc_ctx* c, T* dst, const std::vector<T>& src)
 NodeArgs node_args(pdfmc_ctx* c)
 {
     NodeArgs A{};
+    A.first_stats = c->have_stats ? 0 : 1;
     A.nn = c->NN; A.ne = c->NE; A.cases = c->d_cases; A.node_case = c->d_node_case; A.elem_case = c->d_elem_case;
     A.rec = c->d_rec64; A.area = c->d_area; A.vol = c->d_vol; A.tri_s = c->d_tri_s;
     A.inc_ptr = c->d_inc_ptr; A.inc = c->d_inc; A.incpos = c->d_incpos; A.ell_col = c->d_ell_col; A.ell_len = c->d_ell_len;
@@ -677,6 +679,7 @@ pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
         for (int l = maxbig - 1; l >= 0; --l) {
             const int2* Tl = c->d_mg_tab + c->tabl[l].off;
             const dim3 gl(cnt(c->tabl[l]));
+            hipLaunchKernelGGL(k_mg_prolong, gl, dim3(256), 0, st, J, H, Tl, l, k);
             hipLaunchKernelGGL(k_mg_post1, gl, dim3(256), 0, st, J, H, Tl, l, k);
             hipLaunchKernelGGL(k_mg_post2, gl, dim3(256), 0, st, J, H, Tl, l, k);
         }
@@ -712,12 +715,15 @@ void mg_adapt(pdfmc_ctx* c)
     if (hipEventQuery(c->need_ev) != hipSuccess) return;
     c->need_pending = false;
     const int need = (int)*c->h_need;
+    // the one-workgroup completion is many times slower per iteration than
+    // the phases, so keep a margin above what was needed
+    const int margin = std::max(3, need / 8);
     int want = c->mg_iters;
-    if (need > c->mg_iters) {
-        want = need + 2;
+    if (need + 1 > c->mg_iters) {
+        want = need + margin;
         c->need_low = 0;
-    } else if (need + 6 < c->mg_iters) {
-        if (++c->need_low >= 3) { want = need + 2; c->need_low = 0; }
+    } else if (need + 2 * margin < c->mg_iters) {
+        if (++c->need_low >= 4) { want = need + margin; c->need_low = 0; }
     } else {
         c->need_low = 0;
     }
@@ -871,6 +877,7 @@ pdfmc_status pdfmc_add_case(pdfmc_ctx* c, const pdfmc_mesh_desc* mesh, const pdf
     if (p->n_bins != 1 && p->n_bins != 8) return fail(c, PDFMC_E_INVALID, "add_case: n_bins must be 1 or 8");
     if (p->mode < 0 || p->mode > 2) return fail(c, PDFMC_E_INVALID, "add_case: mode must be 0, 1 or 2");
     if (!(p->dt > 0.0) || !(p->nu >= 0.0)) return fail(c, PDFMC_E_INVALID, "add_case: need dt > 0 and nu >= 0");
+    if (!(p->n_eff_min >= 0.0)) return fail(c, PDFMC_E_INVALID, "add_case: n_eff_min must be >= 0");
     if (capacity < 0 || capacity > ((int64_t)1 << 31)) return fail(c, PDFMC_E_INVALID, "add_case: bad capacity");
     Case cs;
     cs.p = *p;
@@ -1125,6 +1132,7 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         }
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_stats = false;
     c->bound = true;
     c->initialised = false;
     return PDFMC_OK;
@@ -1276,6 +1284,7 @@ pdfmc_status pdfmc_init(pdfmc_ctx* c)
     TRY(enqueue_particles(c, 0, 0));
     hipLaunchKernelGGL(k_node_stats, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, node_args(c));
     LAUNCHCHK(c);
+    c->have_stats = true;
     // Eulerian fields (no projection at initialisation: <P> starts at 0)
     TRY(enqueue_fields(c, false));
     // bins and cell means against those fields
@@ -1368,7 +1377,7 @@ pdfmc_status pdfmc_node_sums(pdfmc_ctx* c, int32_t ci, double* out)
     TRY(check_bound(c));
     if (!out) return fail(c, PDFMC_E_INVALID, "node_sums: null");
     const Case& cs = c->cases[ci];
-    const int ns = cs.p.n_scalars, nq = 11 + 2 * ns;
+    const int ns = cs.p.n_scalars, nq = 12 + 2 * ns;
     std::vector<double> tmp((size_t)std::max(cs.m.nsn, 1) * NQ);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(tmp.data(), c->d_nsum + (size_t)cs.noff * NQ, (size_t)cs.m.nsn * NQ * 8, hipMemcpyDeviceToHost));
@@ -1414,7 +1423,9 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* c, int32_t sort_interval, int32_t bloc
 {
     if (!c) return PDFMC_E_INVALID;
     if (sort_interval < 0) return fail(c, PDFMC_E_INVALID, "set_options: sort_interval < 0");
-    if (block_size < 64 || block_size > 256 || block_size % 64) return fail(c, PDFMC_E_INVALID, "set_options: block size must be 64, 128, 192 or 256");
+    // a workgroup must not straddle two particle tiles (two cases)
+    if (block_size != 64 && block_size != 128 && block_size != 256)
+        return fail(c, PDFMC_E_INVALID, "set_options: block size must be 64, 128 or 256");
     if (use_graph && c->stream == nullptr)
         return fail(c, PDFMC_E_INVALID, "set_options: graph capture needs a stream other than the default (NULL) stream");
     if (block_size != c->block) drop_graphs(c);
@@ -1487,6 +1498,81 @@ pdfmc_status pdfmc_timing_read(pdfmc_ctx* c, double* total_ms, int64_t* launches
     *total_ms = sum;
     *launches = (int64_t)(c->ev_used / 2);
     c->ev_used = 0;
+    return PDFMC_OK;
+}
+
+// Milliseconds of n steps with the options in force (one untimed step first,
+// which also captures a new graph when graphs are enabled).
+static pdfmc_status tune_time(pdfmc_ctx* c, int n, double* ms)
+{
+    TRY(pdfmc_step(c, 1));
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    pdfmc_status st = PDFMC_OK;
+    float f = 0.0f;
+    if (hipEventRecord(a, c->stream) != hipSuccess) st = fail(c, PDFMC_E_HIP, "autotune: event record");
+    if (st == PDFMC_OK) st = pdfmc_step(c, n);
+    if (st == PDFMC_OK && hipEventRecord(b, c->stream) != hipSuccess) st = fail(c, PDFMC_E_HIP, "autotune: event record");
+    if (st == PDFMC_OK && hipEventSynchronize(b) != hipSuccess) st = fail(c, PDFMC_E_HIP, "autotune: event sync");
+    if (st == PDFMC_OK && hipEventElapsedTime(&f, a, b) != hipSuccess) st = fail(c, PDFMC_E_HIP, "autotune: elapsed");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = f;
+    return st;
+}
+
+pdfmc_status pdfmc_autotune(pdfmc_ctx* c, int32_t steps_per_trial, pdfmc_tune_result* out)
+{
+    if (!c) return PDFMC_E_INVALID;
+    TRY(check_bound(c));
+    if (!c->initialised) return fail(c, PDFMC_E_STATE, "autotune: call pdfmc_init first");
+    if (steps_per_trial < 1 || steps_per_trial > 1000) return fail(c, PDFMC_E_INVALID, "autotune: steps_per_trial must be 1..1000");
+    if (c->timing) return fail(c, PDFMC_E_STATE, "autotune: disable timing first");
+    int best_b = c->block, best_s = c->sort_interval > 0 ? c->sort_interval : 10, best_t = c->tail_rows;
+    double best = 1e300;
+    int trials = 0, steps = 0;
+    auto trial = [&](int b, int s, int t, int n, double& per) -> pdfmc_status {
+        TRY(pdfmc_set_options(c, s, b, c->use_graph));
+        TRY(pdfmc_set_solver(c, c->mg_auto ? 0 : c->mg_iters, t));
+        double ms = 0.0;
+        TRY(tune_time(c, n, &ms));
+        per = ms / n;
+        ++trials;
+        steps += n + 1;
+        return PDFMC_OK;
+    };
+    // coordinate descent: block size, then sort interval, then the small-level threshold
+    const int blocks[] = {64, 128, 256};
+    const int sorts[] = {1, 2, 5, 10, 20};
+    const int tails[] = {256, 1024, 4096};
+    for (int b : blocks) {
+        double per;
+        TRY(trial(b, best_s, best_t, std::max(steps_per_trial, best_s), per));
+        if (per < best) { best = per; best_b = b; }
+    }
+    best = 1e300;
+    for (int s : sorts) {
+        double per;
+        TRY(trial(best_b, s, best_t, std::max(steps_per_trial, 2 * s), per));
+        if (per < best) { best = per; best_s = s; }
+    }
+    best = 1e300;
+    for (int t : tails) {
+        double per;
+        TRY(trial(best_b, best_s, t, std::max(steps_per_trial, best_s), per));
+        if (per < best) { best = per; best_t = t; }
+    }
+    TRY(pdfmc_set_options(c, best_s, best_b, c->use_graph));
+    TRY(pdfmc_set_solver(c, c->mg_auto ? 0 : c->mg_iters, best_t));
+    if (out) {
+        out->block_size = best_b;
+        out->sort_interval = best_s;
+        out->tail_rows = best_t;
+        out->trials = trials;
+        out->steps = steps;
+        out->ms_per_step = best;
+    }
     return PDFMC_OK;
 }
 

@@ -13,7 +13,7 @@ namespace pdfmc {
 constexpr int NF = 22;         // Eulerian field slots per node
 constexpr int NF32 = 24;       // padded FP32 mirror stride
 constexpr int MAXS = 4;        // scalars per case
-constexpr int NQ = 19;         // node-sum stride: 11 + 2*MAXS
+constexpr int NQ = 20;         // node-sum stride: 12 + 2*MAXS
 constexpr int NST = 20;        // statistics stride: 12 + 2*MAXS
 constexpr int NCNT = 12;       // counters per case
 constexpr int TILE = 256;      // particle ranges of cases are padded to this
@@ -62,6 +62,7 @@ struct CaseDev {
     double nu, C0, Cw1, Cw2, C1, C2, gamma5, Cv, CL, Ceta, nu34, k_floor, eps_floor;
     double dpdx[2];
     double cg_rtol;
+    double neff_min;           // least effective sample size of a node estimate
     int32_t cg_maxit, pad2;
 };
 

@@ -33,6 +33,7 @@ __global__ void k_mg_res(const MgJob* jobs, const AmgDev* hs, const int2* tab, i
 __global__ void k_mg_restrict(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
 __global__ void k_mg_pre(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
 __global__ void k_mg_tail(const MgJob* jobs, const AmgDev* hs, int k);
+__global__ void k_mg_prolong(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
 __global__ void k_mg_post1(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
 __global__ void k_mg_post2(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
 __global__ void k_mg_finish(const MgJob* jobs, const AmgDev* hs, int k0);

@@ -6,6 +6,8 @@ namespace pdfmc {
 
 struct NodeArgs {
     int32_t nn, ne;                  // global statistics nodes and elements
+    int32_t first_stats;             // 1: no previous node statistics exist yet
+    int32_t pad;
     const CaseDev* cases;
     const int32_t* node_case;        // [nn]
     const int32_t* elem_case;        // [ne]

@@ -47,7 +47,12 @@ class _CaseParams(C.Structure):
                 ("dpdx", C.c_double * 2), ("n_scalars", C.c_int32), ("n_bins", C.c_int32),
                 ("n_min", C.c_int32), ("src", (C.c_double * 4) * 4), ("k_floor", C.c_double),
                 ("eps_floor", C.c_double), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
-                ("seed", C.c_uint64), ("stream", C.c_uint32)]
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("n_eff_min", C.c_double)]
+
+
+class _TuneResult(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("sort_interval", C.c_int32), ("tail_rows", C.c_int32),
+                ("trials", C.c_int32), ("steps", C.c_int32), ("ms_per_step", C.c_double)]
 
 
 class _Particles(C.Structure):
@@ -62,7 +67,7 @@ EXPORTS = ["pdfmc_create", "pdfmc_destroy", "pdfmc_last_error", "pdfmc_add_case"
            "pdfmc_pressure_download", "pdfmc_init", "pdfmc_rebin", "pdfmc_step", "pdfmc_set_step_index",
            "pdfmc_stats_readback", "pdfmc_node_sums", "pdfmc_cell_means", "pdfmc_counters",
            "pdfmc_set_options", "pdfmc_sort", "pdfmc_synchronize", "pdfmc_timing", "pdfmc_timing_read",
-           "pdfmc_draw_gaussians", "pdfmc_set_solver", "pdfmc_solver_info"]
+           "pdfmc_draw_gaussians", "pdfmc_set_solver", "pdfmc_solver_info", "pdfmc_autotune"]
 
 
 def lib():
@@ -97,6 +102,7 @@ def lib():
         L.pdfmc_set_options.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
         L.pdfmc_timing.argtypes = [vp, C.c_int32]
         L.pdfmc_set_solver.argtypes = [vp, C.c_int32, C.c_int32]
+        L.pdfmc_autotune.argtypes = [vp, C.c_int32, C.POINTER(_TuneResult)]
         L.pdfmc_solver_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.pdfmc_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.pdfmc_draw_gaussians.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, C.c_int64, vp]
@@ -202,9 +208,17 @@ class Sim:
     def set_options(self, sort_interval=0, block_size=256, use_graph=False):
         self._check(self._L.pdfmc_set_options(self._h, sort_interval, block_size, int(bool(use_graph))), "set_options")
 
-    def set_solver(self, iterations=0, tail_rows=4096):
+    def set_solver(self, iterations=0, tail_rows=1024):
         """iterations = 0: adaptive number of row-parallel CG iterations."""
         self._check(self._L.pdfmc_set_solver(self._h, int(iterations), int(tail_rows)), "set_solver")
+
+    def autotune(self, steps_per_trial=4):
+        """Pick block size, sort interval and multigrid tail threshold by timing
+        real steps (the trial steps advance the simulation)."""
+        r = _TuneResult()
+        self._check(self._L.pdfmc_autotune(self._h, int(steps_per_trial), C.byref(r)), "autotune")
+        return dict(block_size=r.block_size, sort_interval=r.sort_interval, tail_rows=r.tail_rows,
+                    trials=r.trials, steps=r.steps, ms_per_step=r.ms_per_step)
 
     def solver_info(self):
         it, lv = C.c_int32(), C.c_int32()
@@ -278,7 +292,7 @@ class Sim:
 
     def node_sums(self, cs):
         mesh, p, _ = self._cases[cs]
-        out = np.zeros((mesh.n_nodes, 11 + 2 * p["n_scalars"]))
+        out = np.zeros((mesh.n_nodes, 12 + 2 * p["n_scalars"]))
         self._check(self._L.pdfmc_node_sums(self._h, cs, out.ctypes.data), "node_sums")
         return out
 

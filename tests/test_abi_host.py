@@ -74,6 +74,14 @@ def test_argument_rejections(pkg):
         s.step(1)
     with pytest.raises(pkg.PdfmcError, match="INVALID"):
         s.set_options(0, 100, False)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*block size"):
+        s.set_options(0, 192, False)          # would let a workgroup span two cases
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*n_eff_min"):
+        s.add_case(mesh, W.default_params(n_eff_min=-1.0), 10)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*tail_rows"):
+        s.set_solver(0, -5)
+    with pytest.raises(pkg.PdfmcError, match="STATE"):
+        s.autotune(2)
 
 
 @pytest.mark.parametrize("which", ["square", "channel"])

@@ -302,3 +302,34 @@ def test_batched_equals_sequential(P):
         assert np.max(np.abs(G["u"] - S["u"])) <= 1e-10
         sb, ss = s_b.stats(c_b), s_s.stats(c_s)
         assert np.max(np.abs(sb - ss) / np.maximum(np.abs(ss), 1e-3)) <= 1e-8
+
+
+def test_autotune_settings_and_invariance(P):
+    """The autotuner picks settings from its candidate sets, and the steps it
+    takes are ordinary steps: the state afterwards equals that of a context
+    stepped the same number of times with the default settings."""
+    cfg = W.config_small()
+    mesh2, params2, parts2 = _small_channel(ppe=10, ns=2, rtol=1e-12)
+    _flush("[autotune] two cases, one step per trial")
+    sims = []
+    for tune in (True, False):
+        sim = P.Sim("fp64", "cuda:0")
+        c1 = sim.add_case(cfg["mesh"], cfg["params"], len(cfg["particles"]["x"]))
+        c2 = sim.add_case(mesh2, params2, len(parts2["x"]))
+        sim.bind()
+        sim.set_options(sort_interval=10, use_graph=True)
+        sim.upload(c1, cfg["particles"]); sim.upload(c2, parts2)
+        sim.init()
+        sims.append((sim, c1, c2))
+    r = sims[0][0].autotune(steps_per_trial=1)
+    assert r["block_size"] in (64, 128, 256)
+    assert r["sort_interval"] in (1, 2, 5, 10, 20)
+    assert r["tail_rows"] in (256, 1024, 4096)
+    assert r["trials"] == 11 and r["ms_per_step"] > 0.0
+    sims[1][0].step(r["steps"])
+    (a, a1, a2), (b, b1, b2) = sims
+    for ca, cb in ((a1, b1), (a2, b2)):
+        sa, sb = a.stats(ca), b.stats(cb)
+        assert np.max(np.abs(sa - sb) / np.maximum(np.abs(sb), 1e-3)) <= 1e-8
+        cnt = a.counters(ca)
+        assert cnt["nan"] == 0 and cnt["cg_fail"] == 0

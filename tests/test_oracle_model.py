@@ -320,3 +320,48 @@ def test_estimator_constant_field(oracle_mod):
     assert np.allclose(st[:, 2:5], [1.5, -2.0, 0.25], rtol=1e-14)
     assert np.allclose(st[:, 11], 3.0, rtol=1e-14)
     assert np.abs(st[:, 5:11]).max() < 1e-28
+
+
+def test_thin_nodes_keep_previous_moments(oracle_mod):
+    """R-34: the effective sample size W^2 / sum (w N)^2 of each node, from
+    brute-force shape functions, against the oracle's node sums. The first
+    statistics take every node's estimate; afterwards nodes below n_eff_min
+    keep their previous moments while W and the density are updated."""
+    mesh = W.unit_square(6, 0.2, periodic_x=False)
+    rng = np.random.default_rng(23)
+    parts = W.init_particles(mesh, 5, 0, rng, u_std=1.0)
+    parts["weight"] = parts["weight"] * rng.uniform(0.2, 5.0, size=len(parts["x"]))   # uneven weights
+    Wn = np.zeros(mesh.n_nodes)
+    W2 = np.zeros(mesh.n_nodes)
+    for p in range(len(parts["x"])):
+        e = parts["elem"][p]
+        P = mesh.xy[mesh.tri[e]]
+        lam = np.linalg.solve(np.vstack([P.T, np.ones(3)]), [parts["x"][p], parts["y"][p], 1.0])
+        for k in range(3):
+            wn = parts["weight"][p] * lam[k]
+            Wn[mesh.tri[e, k]] += wn
+            W2[mesh.tri[e, k]] += wn * wn
+    neff = Wn ** 2 / W2
+    thr = float(np.median(neff))
+    o = oracle_mod.Oracle()
+    cs = o.add_case(mesh, W.default_params(mode=0, n_scalars=0, n_eff_min=thr))
+    o.fields_upload(cs, np.zeros((mesh.n_nodes, 22)))
+    o.upload(cs, parts)
+    o.init()
+    S = o.node_sums(cs)
+    assert np.allclose(S[:, -1], W2, rtol=1e-12)
+    st1 = o.stats(cs)
+    assert o.counters(cs)["empty_node"] == 0          # first statistics: every node estimated
+    # same positions and weights, new velocities: thin nodes keep st1's moments
+    parts2 = dict(parts)
+    for key in ("u", "v", "w"):
+        parts2[key] = rng.normal(0.0, 1.0, size=len(parts["x"]))
+    o.upload(cs, parts2)
+    o.init()
+    st2 = o.stats(cs)
+    thin = neff < thr
+    assert 0 < thin.sum() < mesh.n_nodes
+    assert np.allclose(st2[:, 0], Wn, rtol=1e-12)
+    assert np.array_equal(st2[thin, 2:], st1[thin, 2:])
+    assert np.all(np.abs(st2[~thin, 2:5] - st1[~thin, 2:5]).sum(1) > 0.0)
+    assert o.counters(cs)["empty_node"] == int(thin.sum())
