@@ -14,10 +14,10 @@
 //          -> two post-smoothing steps, the second of which gives z_{k+1} on
 //          level 0 and accumulates r.z and sum z.
 // Scalars are accumulated with FP64 atomics into rotating per-iteration slots
-// (slot k mod 4); a slot is cleared two phases after its last reader. Thread 0
-// of each workgroup reads the scalars and broadcasts them through LDS. Level
-// sizes are fixed per system, so a fixed number of iterations can be replayed
-// from a graph; systems that have converged leave every later phase at once,
+// (slot k mod 4); a slot is cleared two phases after its last reader. The
+// first lanes of each workgroup gather the slot words in one round trip and
+// share them through LDS. Level sizes are fixed per system, so a fixed number
+// of iterations can be replayed from a graph; systems that have converged leave every later phase at once,
 // and k_mg_finish completes any system that needs more iterations in one
 // workgroup, with the same phase bodies.
 #include "pdfmc_kernels.h"
@@ -41,18 +41,30 @@ __device__ inline double* slot(const MgJob& J, int k) { return J.acc + ((k + 4) 
 __device__ inline double* setup_slot(const MgJob& J) { return J.acc + 4 * MG_SLOT; }
 // slot layout: [0] p.q  [1] r.r  [2] sum r  [3] r.z  [4] sum z
 
-// r_{k+1}.z_{k+1} from slot k, with z made mean-free for singular systems
-__device__ inline double rz_of(const MgJob& J, const double* s)
+// The accumulator words a phase needs, gathered by the first lanes in one
+// round trip and shared through LDS:
+//   w[0..4]   slot k      w[5..9]  slot k-1     w[10..14] slot k-2
+//   w[15..17] set-up slot
+// COHERENT: the words were written by atomics of this same kernel (one
+// workgroup completing a system), so the loads must bypass the L1.
+constexpr int NW = 18;
+template <bool COHERENT>
+__device__ inline void gather_words(const MgJob& J, int k, double* w)
 {
-    const double rz = aload(s + 3);
-    return J.mean_free ? rz - (aload(s + 4) / J.n) * aload(s + 2) : rz;
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NW) {
+        const double* src = t < 5 ? slot(J, k) + t : t < 10 ? slot(J, k - 1) + (t - 5)
+                          : t < 15 ? slot(J, k - 2) + (t - 10) : setup_slot(J) + (t - 15);
+        w[t] = COHERENT ? aload(src) : *src;
+    }
+    __syncthreads();
 }
 
-__device__ inline bool converged(const MgJob& J, int k)
+// r.z of a slot (words s[0..4]), with z made mean-free for singular systems
+__device__ inline double rz_w(const MgJob& J, const double* s)
 {
-    const double rr = aload(slot(J, k - 1) + 1);
-    const double bb = aload(setup_slot(J) + 2);
-    return rr <= J.tol * J.tol * bb;
+    return J.mean_free ? s[3] - (s[4] / J.n) * s[2] : s[3];
 }
 
 // Sum NV per-thread values over the workgroup and add them to dst[k].
@@ -77,48 +89,37 @@ __device__ inline void block_accumulate(const double (&v)[NV], double* const (&d
     __syncthreads();
 }
 
-// Scalars of a phase, computed by thread 0 and broadcast through LDS.
+// Scalars of a phase.
 struct Scal {
     double a, b;
     int flag;
 };
 
-__device__ inline Scal broadcast(Scal v)
-{
-    __shared__ double sa, sb;
-    __shared__ int sf;
-    if (threadIdx.x == 0) { sa = v.a; sb = v.b; sf = v.flag; }
-    __syncthreads();
-    Scal r{sa, sb, sf};
-    __syncthreads();
-    return r;
-}
-
-// PA scalars: flag = converged; a = beta, b = mean of z (singular systems)
+// PA: flag = converged (||r_k||^2 <= tol^2 ||b||^2); a = beta, b = mean of z
+template <bool COHERENT>
 __device__ inline Scal pa_scalars(const MgJob& J, int k)
 {
+    __shared__ double w[NW];
+    gather_words<COHERENT>(J, k, w);
     Scal s{0.0, 0.0, 0};
-    if (threadIdx.x == 0) {
-        s.flag = converged(J, k) ? 1 : 0;
-        if (!s.flag) {
-            const double* sp = slot(J, k - 1);
-            s.a = k == 0 ? 0.0 : rz_of(J, sp) / rz_of(J, slot(J, k - 2));
-            s.b = J.mean_free ? aload(sp + 4) / J.n : 0.0;
-        }
+    s.flag = w[5 + 1] <= J.tol * J.tol * w[15 + 2] ? 1 : 0;
+    if (!s.flag) {
+        s.a = k == 0 ? 0.0 : rz_w(J, w + 5) / rz_w(J, w + 10);
+        s.b = J.mean_free ? w[5 + 4] / J.n : 0.0;
     }
-    return broadcast(s);
+    return s;
 }
 
-// PB scalars: a = alpha; flag = zero right-hand side (first pass only)
+// PB: a = alpha; flag = zero right-hand side (first pass only)
+template <bool COHERENT>
 __device__ inline Scal pb_scalars(const MgJob& J, int k, bool first)
 {
+    __shared__ double w[NW];
+    gather_words<COHERENT>(J, k, w);
     Scal s{0.0, 0.0, 0};
-    if (threadIdx.x == 0) {
-        const double* su = setup_slot(J);
-        s.flag = first && (aload(su + 2) <= 1e-28 * aload(su + 1)) ? 1 : 0;
-        s.a = first ? 0.0 : rz_of(J, slot(J, k - 1)) / aload(slot(J, k));
-    }
-    return broadcast(s);
+    s.flag = first && (w[15 + 2] <= 1e-28 * w[15 + 1]) ? 1 : 0;
+    s.a = first ? 0.0 : rz_w(J, w + 5) / w[0];
+    return s;
 }
 
 // y_i = sum_k A(k, i) x(col(k, i)); the width is a multiple of 4 and the
@@ -290,12 +291,19 @@ __device__ void tail_body(const MgJob& J, const AmgDev& H, int k)
         __syncthreads();
     }
     {
+        // dense coarse solve, 16 lanes per row (nc <= 64 rows)
         const int l = nl - 1, nc = H.n[l];
         const double* b = level_rhs(J, l, k);
-        for (int i = tid; i < nc; i += nt) {
+        for (int t = tid; t < 16 * AMG_MAXC; t += nt) {
+            const int i = t >> 4, part = t & 15;
             double s = 0.0;
-            for (int j = 0; j < nc; ++j) s += H.ainv[i * AMG_MAXC + j] * b[j];
-            J.ly[l][i] = s;
+            if (i < nc)
+                for (int j = part; j < nc; j += 16) s += H.ainv[i * AMG_MAXC + j] * b[j];
+            s += __shfl_xor(s, 8);
+            s += __shfl_xor(s, 4);
+            s += __shfl_xor(s, 2);
+            s += __shfl_xor(s, 1);
+            if (i < nc && part == 0) J.ly[l][i] = s;
         }
         __syncthreads();
     }
@@ -421,7 +429,7 @@ __global__ void __launch_bounds__(MGB) k_mg_pa(const MgJob* __restrict__ jobs, c
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
     if (inactive(J, k)) return;
-    const Scal sc = pa_scalars(J, k);
+    const Scal sc = pa_scalars<false>(J, k);
     if (sc.flag) {
         if (e.y == 0 && threadIdx.x == 0) { J.state[0] = 1; J.state[1] = k; }
         return;
@@ -435,7 +443,7 @@ __global__ void __launch_bounds__(MGB) k_mg_pb(const MgJob* __restrict__ jobs, c
     const int2 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
     if (inactive(J, k)) return;
-    const Scal sc = pb_scalars(J, k, first != 0);
+    const Scal sc = pb_scalars<false>(J, k, first != 0);
     pb_body(J, hs[J.hier], k, first != 0, sc, e.y == 0 && threadIdx.x == 0, e.y + threadIdx.x, min(e.y + MGB, J.n),
             MGB);
 }
@@ -529,17 +537,17 @@ __global__ void __launch_bounds__(1024) k_mg_finish(const MgJob* __restrict__ jo
     if (n <= 0) return;
     const AmgDev& H = hs[J.hier];
     const int tid = threadIdx.x, nt = blockDim.x;
-    Scal st{0.0, 0.0, 0};
-    if (tid == 0) { st.flag = aloadi(J.state); st.a = st.flag ? (double)aloadi(J.state + 1) : 0.0; }
-    st = broadcast(st);
-    bool done = st.flag != 0;
-    int it = (int)st.a;
+    __shared__ int st[2];
+    if (tid == 0) { st[0] = aloadi(J.state); st[1] = aloadi(J.state + 1); }
+    __syncthreads();
+    bool done = st[0] != 0;
+    int it = done ? st[1] : 0;
     for (int k = min(k0, J.maxit); !done; ++k) {
-        const Scal sa = pa_scalars(J, k);
+        const Scal sa = pa_scalars<true>(J, k);
         if (sa.flag) { done = true; it = k; break; }
         if (k >= J.maxit) { it = k; break; }
         pa_body(J, H, k, sa, tid, n, nt);
-        const Scal sb = pb_scalars(J, k, false);
+        const Scal sb = pb_scalars<true>(J, k, false);
         pb_body(J, H, k, false, sb, tid == 0, tid, n, nt);
         if (H.nbig >= 1) {
             res_rows(J, H, 0, k, tid, n, nt);

@@ -306,30 +306,43 @@ def test_batched_equals_sequential(P):
 
 def test_autotune_settings_and_invariance(P):
     """The autotuner picks settings from its candidate sets, and the steps it
-    takes are ordinary steps: the state afterwards equals that of a context
-    stepped the same number of times with the default settings."""
-    cfg = W.config_small()
+    takes are ordinary steps. With frozen fields and no scalars a particle's
+    path depends on nothing but its own state, so the autotuned context must
+    hold the same particles as a context stepped as often with the default
+    settings (a relaxation + projection case rides along in the same context
+    and must stay finite and converged)."""
+    mesh = W.unit_square(16, 0.2, periodic_x=True, seed_key=(0, 0, 0))
+    params = W.default_params(mode=0, n_scalars=0, dt=1e-3, nu=1e-3)
+    parts = W.init_particles(mesh, 30, 0, W.rng_for(0, 0, 7), u_std=0.1)
+    F = W.frozen_fields(mesh, C0=2.1, omega=1.0, k=0.015)
     mesh2, params2, parts2 = _small_channel(ppe=10, ns=2, rtol=1e-12)
-    _flush("[autotune] two cases, one step per trial")
+    _flush("[autotune] frozen-field case + relaxation case, one step per trial")
     sims = []
     for tune in (True, False):
         sim = P.Sim("fp64", "cuda:0")
-        c1 = sim.add_case(cfg["mesh"], cfg["params"], len(cfg["particles"]["x"]))
+        c1 = sim.add_case(mesh, params, len(parts["x"]))
         c2 = sim.add_case(mesh2, params2, len(parts2["x"]))
         sim.bind()
         sim.set_options(sort_interval=10, use_graph=True)
-        sim.upload(c1, cfg["particles"]); sim.upload(c2, parts2)
+        sim.fields_upload(c1, F)
+        sim.upload(c1, parts); sim.upload(c2, parts2)
         sim.init()
         sims.append((sim, c1, c2))
     r = sims[0][0].autotune(steps_per_trial=1)
     assert r["block_size"] in (64, 128, 256)
     assert r["sort_interval"] in (1, 2, 5, 10, 20)
     assert r["tail_rows"] in (256, 1024, 4096)
-    assert r["trials"] == 11 and r["ms_per_step"] > 0.0
+    assert r["trials"] == 11 and r["ms_per_step"] > 0.0 and r["steps"] > 11
     sims[1][0].step(r["steps"])
     (a, a1, a2), (b, b1, b2) = sims
-    for ca, cb in ((a1, b1), (a2, b2)):
-        sa, sb = a.stats(ca), b.stats(cb)
-        assert np.max(np.abs(sa - sb) / np.maximum(np.abs(sb), 1e-3)) <= 1e-8
-        cnt = a.counters(ca)
-        assert cnt["nan"] == 0 and cnt["cg_fail"] == 0
+    n = len(parts["x"])
+    A, B = _by_id(a.download(a1, n)), _by_id(b.download(b1, n))
+    assert np.array_equal(A["elem"], B["elem"])
+    for k in ("x", "y", "u", "v", "w", "omega"):
+        assert np.array_equal(A[k], B[k]), k
+    sa, sb = a.stats(a1), b.stats(b1)
+    assert np.max(np.abs(sa - sb) / np.maximum(np.abs(sb), 1e-3)) <= 1e-10
+    st2 = a.stats(a2)
+    assert np.all(np.isfinite(st2))
+    cnt = a.counters(a2)
+    assert cnt["nan"] == 0 and cnt["cg_fail"] == 0

@@ -241,14 +241,26 @@ def element_areas(mesh: Mesh) -> np.ndarray:
 
 def init_particles(mesh: Mesh, ppe: int, n_scalars: int, rng: np.random.Generator, *,
                    u_std: float = 0.1, omega_shape: float = 4.0, omega_scale: float = 0.25,
-                   psi_disks=()) -> dict:
-    """ppe particles per element, uniform in each element (R-29), velocities
+                   psi_disks=(), equal_mass: bool = False) -> dict:
+    """ne * ppe particles, uniform within each element (R-29), velocities
     N(0, u_std^2) per component, frequency Gamma(omega_shape, omega_scale),
     scalar alpha = value inside its initial disk (cx, cy, r, value) else 0,
-    mass weight = element area / ppe (R-31), id = index (R-32)."""
+    id = index (R-32). Mass weights (R-31): ppe particles per element of
+    weight area / ppe, or with equal_mass the same total count spread in
+    proportion to element area (largest remainders), every particle weighing
+    total area / count."""
     ne = mesh.n_elems
     n = ne * ppe
-    elem = np.repeat(np.arange(ne, dtype=np.int32), ppe)
+    if equal_mass:
+        area = element_areas(mesh)
+        share = area / area.sum() * n
+        cnt = np.floor(share).astype(np.int64)
+        rest = n - int(cnt.sum())
+        if rest > 0:
+            cnt[np.argsort(-(share - cnt), kind="stable")[:rest]] += 1
+        elem = np.repeat(np.arange(ne, dtype=np.int32), cnt)
+    else:
+        elem = np.repeat(np.arange(ne, dtype=np.int32), ppe)
     r1 = rng.random(n)
     r2 = rng.random(n)
     s1 = np.sqrt(r1)
@@ -264,7 +276,10 @@ def init_particles(mesh: Mesh, ppe: int, n_scalars: int, rng: np.random.Generato
         cx, cy, r, val = disk
         inside = (xy[:, 0] - cx) ** 2 + (xy[:, 1] - cy) ** 2 < r * r
         psi[a, inside] = val
-    weight = (element_areas(mesh) / ppe)[elem]
+    if equal_mass:
+        weight = np.full(n, element_areas(mesh).sum() / n)
+    else:
+        weight = (element_areas(mesh) / ppe)[elem]
     return dict(x=xy[:, 0].copy(), y=xy[:, 1].copy(), u=u[0].copy(), v=u[1].copy(), w=u[2].copy(),
                 omega=om, weight=weight, psi=psi, elem=elem, id=np.arange(n, dtype=np.uint32),
                 bin=np.zeros(n, np.uint8))
