@@ -53,6 +53,37 @@ def workload(name):
     return cfg["name"], [cfg], dict(sort_interval=10)
 
 
+PARTICLE_KERNEL_SOURCES = ["k_particle.hip", "pdfmc_dev.h", "pdfmc_math.h"]
+
+
+def particle_kernel_hash():
+    """SHA-1 of the particle kernel's sources: HBM counter readings are only
+    valid for the kernel they were taken on."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in PARTICLE_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1006_0549_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(workload_name, prec):
+    """HBM bytes per particle-kernel launch from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes recorded in profiles/hbm_traffic.md (scaled by the
+    readings of a plain copy of known size), or None when no row matches the
+    workload, precision and current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    src = particle_kernel_hash()
+    for line in open(path):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 9 and cells[0] == "k_particle_step" and cells[1] == workload_name and \
+                cells[2] == prec and cells[3] == src:
+            return float(cells[8])
+    return None
+
+
 def algorithmic_bytes(prec, cases, nsn):
     """Bytes the particle kernel must move per launch: every particle's state
     read and written once, the node fields read and node sums written once,
@@ -274,7 +305,8 @@ def main():
                    "autotuned": g["tuned"],
                    "accumulation": "f64 node sums, f64 Eulerian fields and CG"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name, args.precision),
+                     "kernel_source": particle_kernel_hash(),
                      "kernel": "k_particle_step", "kernel_ms": k1_avg_s * 1e3,
                      "algorithmic_bytes_per_launch": nbytes, "bytes_per_particle": per_particle},
         "particle_kernel_updates_per_s": n / k1_avg_s,

@@ -403,7 +403,8 @@ __global__ void __launch_bounds__(MGB) k_mg_setup1(const MgJob* __restrict__ job
     block_accumulate<2>({b, b * b}, {su, su + 1});
 }
 
-// Set-up 2: mean-free right-hand side, r = b - A x (warm start), ||b||^2
+// Set-up 2: mean-free right-hand side, r = b - A x (warm start) or r = b
+// with x = 0, ||b||^2
 __global__ void __launch_bounds__(MGB) k_mg_setup2(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
                                                    const int2* __restrict__ tab)
 {
@@ -417,7 +418,12 @@ __global__ void __launch_bounds__(MGB) k_mg_setup2(const MgJob* __restrict__ job
     if (i < J.n) {
         const double b = J.b[i] - mb;
         J.b[i] = b;
-        J.r[1][i] = b - ell_row(H.A[0], J.x, i);
+        if (J.warm) {
+            J.r[1][i] = b - ell_row(H.A[0], J.x, i);
+        } else {
+            J.x[i] = 0.0;
+            J.r[1][i] = b;
+        }
         bb = b * b;
     }
     block_accumulate<1>({bb}, {su + 2});

@@ -189,6 +189,8 @@ __device__ inline int wave_sum_int(int v)
 constexpr int HS = 32;                           // element slots per workgroup
 constexpr int NV = 3 * NQ + 8 * (2 + MAXS);      // node sums of 3 vertices + 8 cells
 
+constexpr int NREC = 8 + MAXS;                  // record: lambda_0..2, w, U_1..3, omega, psi_a
+
 __device__ inline void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
 // slot of element e in the table (claimed on first use), or -1 when full
@@ -224,6 +226,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
 {
     __shared__ int s_key[HS];
     __shared__ double s_val[HS * NV];
+    __shared__ R s_rec[256 * NREC];       // per-lane records for the node-sum reduction
     for (int i = threadIdx.x; i < HS; i += blockDim.x) s_key[i] = -1;
     for (int i = threadIdx.x; i < HS * NV; i += blockDim.x) s_val[i] = 0.0;
     __syncthreads();
@@ -347,40 +350,63 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     // atomic per (element, value). A table overflow falls back to direct atomics.
     const int nq = 12 + 2 * ns;
     {
+        // Node sums. Every lane stores its particle's record in LDS; then, for
+        // each run of equal element in the wavefront, lane j = k * nq + q sums
+        // term q of vertex k over the run's particles (the record reads are
+        // the same for all lanes of a step, so they broadcast) and adds the
+        // run total to the element's slot of the workgroup table. The terms
+        // are the FP64 products w lambda_k Q of R-11, as in the oracle.
+        static_assert(256 * NREC * sizeof(R) + HS * NV * 8 < 64 * 1024, "LDS");
         const int key = valid ? e : -1;
-        const Runs r = make_runs(key);
-        int slot = -1;
-        if (r.head && key >= 0) slot = lds_slot(s_key, key);
-        const double w = (double)wt;
-        const double Q[3] = {(double)u3[0], (double)u3[1], (double)u3[2]};
-        const double dom = (double)om;
-        const int s3[3] = {sn.x, sn.y, sn.z};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const double wn = valid ? w * (double)lam[k] : 0.0;
-            double val[11];
-            val[0] = wn;
-            val[1] = wn * Q[0]; val[2] = wn * Q[1]; val[3] = wn * Q[2];
-            val[4] = wn * Q[0] * Q[0]; val[5] = wn * Q[1] * Q[1]; val[6] = wn * Q[2] * Q[2];
-            val[7] = wn * Q[0] * Q[1]; val[8] = wn * Q[0] * Q[2]; val[9] = wn * Q[1] * Q[2];
-            val[10] = wn * dom;
-#pragma unroll
-            for (int q = 0; q < 11; ++q) {
-                const double sum = run_sum(val[q], r);
-                if (r.head && key >= 0) put(s_val, slot, k * nq + q, A.nsum + (int64_t)s3[k] * NQ + q, sum);
+        const int lane = __lane_id(), wid = threadIdx.x >> 6;
+        R* my = s_rec + (wid * 64 + lane) * NREC;
+        my[0] = lam[0]; my[1] = lam[1]; my[2] = lam[2]; my[3] = wt;
+        my[4] = u3[0]; my[5] = u3[1]; my[6] = u3[2]; my[7] = om;
+        for (int a = 0; a < ns; ++a) my[8 + a] = psi[a];
+        const int prev = __shfl_up(key, 1);
+        const unsigned long long heads = __ballot(lane == 0 || prev != key);
+        __syncthreads();
+        // term of this lane: w lambda_k [* rec[ia]] [* rec[ib]], or (w lambda_k)^2
+        const int j = lane;
+        const bool act = j < 3 * nq;
+        const int k = act ? j / nq : 0, q = act ? j % nq : 0;
+        int ia = -1, ib = -1;
+        bool sq = false;
+        if (q >= 1 && q <= 3) ia = 4 + (q - 1);
+        else if (q >= 4 && q <= 6) ia = ib = 4 + (q - 4);
+        else if (q == 7) { ia = 4; ib = 5; }
+        else if (q == 8) { ia = 4; ib = 6; }
+        else if (q == 9) { ia = 5; ib = 6; }
+        else if (q == 10) ia = 7;
+        else if (q >= 11 && q < 11 + ns) ia = 8 + (q - 11);
+        else if (q >= 11 + ns && q < 11 + 2 * ns) ia = ib = 8 + (q - 11 - ns);
+        else if (q == 11 + 2 * ns) sq = true;
+        const R* wave_rec = s_rec + wid * 64 * NREC;
+        unsigned long long hm = heads;
+        while (hm) {
+            const int s0 = __ffsll((long long)hm) - 1;
+            hm &= hm - 1;
+            const int s1 = hm ? __ffsll((long long)hm) - 1 : 64;
+            const int ks = __shfl(key, s0);
+            if (ks < 0) continue;
+            double acc = 0.0;
+            for (int pp = s0; pp < s1; ++pp) {
+                const R* rq = wave_rec + pp * NREC;
+                const double wn = (double)rq[3] * (double)rq[k];
+                double t = sq ? wn * wn : wn;
+                if (ia >= 0) t = t * (double)rq[ia];
+                if (ib >= 0) t = t * (double)rq[ib];
+                acc += t;
             }
-            {
-                const double s2 = run_sum(wn * wn, r);
-                if (r.head && key >= 0)
-                    put(s_val, slot, k * nq + 11 + 2 * ns, A.nsum + (int64_t)s3[k] * NQ + 11 + 2 * ns, s2);
-            }
-            for (int a = 0; a < ns; ++a) {
-                const double ps = (double)psi[a];
-                const double s1 = run_sum(wn * ps, r);
-                const double s2 = run_sum(wn * ps * ps, r);
-                if (r.head && key >= 0) {
-                    put(s_val, slot, k * nq + 11 + a, A.nsum + (int64_t)s3[k] * NQ + 11 + a, s1);
-                    put(s_val, slot, k * nq + 11 + ns + a, A.nsum + (int64_t)s3[k] * NQ + 11 + ns + a, s2);
+            int slot = 0;
+            if (lane == 0) slot = lds_slot(s_key, ks);
+            slot = __shfl(slot, 0);
+            if (act) {
+                if (slot >= 0) {
+                    lds_add(&s_val[slot * NV + j], acc);
+                } else {
+                    const int node = pick(A.M.tri_s[ks], k);
+                    unsafeAtomicAdd(A.nsum + (int64_t)node * NQ + q, acc);
                 }
             }
         }

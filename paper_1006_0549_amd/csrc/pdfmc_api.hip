@@ -574,6 +574,9 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
             MgJob J{};
             J.hier = hi;
             J.mean_free = proj ? 1 : 0;
+            // the relaxed tensor changes slowly between steps; the pressure
+            // increment is new every step, so its solve starts from zero
+            J.warm = proj ? 0 : 1;
             J.maxit = cs.p.cg_maxit;
             J.n = cs.m.nsn;
             J.tol = cs.p.cg_rtol;

@@ -93,6 +93,8 @@ constexpr int MG_NSLOT = 5;        // 4 iteration slots + 1 set-up slot
 struct MgJob {
     int32_t hier;                  // index of the hierarchy
     int32_t mean_free;             // singular system: solution and residual kept mean-free
+    int32_t warm;                  // 1: start from the current x; 0: start from zero
+    int32_t pad;
     int32_t maxit, n;              // iteration cap, rows
     double tol;                    // relative residual tolerance
     double* b;                     // right-hand side (made mean-free in place)
