@@ -85,7 +85,11 @@ __device__ inline void block_accumulate(const double (&v)[NV], double* const (&d
         for (int w = 0; w < nw; ++w) s += sh[w * 4 + threadIdx.x];
         unsafeAtomicAdd(dst[threadIdx.x], s);
     }
-    __threadfence();
+    // workgroup-scope release: the atomics above have completed before any
+    // thread of this workgroup reads the accumulators again (k_mg_finish);
+    // other workgroups read them only in later kernels. An agent-scope fence
+    // here would write back the whole L2 of the XCD from every workgroup.
+    __threadfence_block();
     __syncthreads();
 }
 
