@@ -332,8 +332,6 @@ __device__ void tail_body(const MgJob& J, const AmgDev& H, int k)
     }
 }
 
-// state of a system as seen by a row-parallel phase (written by earlier kernels)
-__device__ inline bool inactive(const MgJob& J, int k) { return J.state[0] != 0 || k >= J.maxit; }
 
 }  // namespace
 
@@ -396,9 +394,9 @@ __global__ void __launch_bounds__(1024) k_mg_coarse(const AmgDev* __restrict__ h
 }
 
 // Set-up 1: sum b and sum b^2 (tab entries: (job, first row) over level 0)
-__global__ void __launch_bounds__(MGB) k_mg_setup1(const MgJob* __restrict__ jobs, const int2* __restrict__ tab)
+__global__ void __launch_bounds__(MGB) k_mg_setup1(const MgJob* __restrict__ jobs, const int4* __restrict__ tab, const int32_t* __restrict__ st)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
     if (blockIdx.x == 0 && threadIdx.x == 0) *J.need = 0u;
     const int i = e.y + threadIdx.x;
@@ -410,11 +408,11 @@ __global__ void __launch_bounds__(MGB) k_mg_setup1(const MgJob* __restrict__ job
 // Set-up 2: mean-free right-hand side, r = b - A x (warm start) or r = b
 // with x = 0, ||b||^2
 __global__ void __launch_bounds__(MGB) k_mg_setup2(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                                   const int2* __restrict__ tab)
+                                                   const int4* __restrict__ tab, const int32_t* __restrict__ st)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    const AmgDev& H = hs[J.hier];
+    const AmgDev& H = hs[e.z];
     double* su = setup_slot(J);
     const double mb = J.mean_free ? su[0] / J.n : 0.0;
     const int i = e.y + threadIdx.x;
@@ -434,38 +432,38 @@ __global__ void __launch_bounds__(MGB) k_mg_setup2(const MgJob* __restrict__ job
 }
 
 __global__ void __launch_bounds__(MGB) k_mg_pa(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                               const int2* __restrict__ tab, int k)
+                                               const int4* __restrict__ tab, const int32_t* __restrict__ st, int k)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (inactive(J, k)) return;
+    if (st[2 * e.x] != 0 || k >= J.maxit) return;
     const Scal sc = pa_scalars<false>(J, k);
     if (sc.flag) {
         if (e.y == 0 && threadIdx.x == 0) { J.state[0] = 1; J.state[1] = k; }
         return;
     }
-    pa_body(J, hs[J.hier], k, sc, e.y + threadIdx.x, min(e.y + MGB, J.n), MGB);
+    pa_body(J, hs[e.z], k, sc, e.y + threadIdx.x, min(e.y + MGB, J.n), MGB);
 }
 
 __global__ void __launch_bounds__(MGB) k_mg_pb(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                               const int2* __restrict__ tab, int k, int first)
+                                               const int4* __restrict__ tab, const int32_t* __restrict__ st, int k, int first)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (inactive(J, k)) return;
+    if (st[2 * e.x] != 0 || k >= J.maxit) return;
     const Scal sc = pb_scalars<false>(J, k, first != 0);
-    pb_body(J, hs[J.hier], k, first != 0, sc, e.y == 0 && threadIdx.x == 0, e.y + threadIdx.x, min(e.y + MGB, J.n),
+    pb_body(J, hs[e.z], k, first != 0, sc, e.y == 0 && threadIdx.x == 0, e.y + threadIdx.x, min(e.y + MGB, J.n),
             MGB);
 }
 
 // residual of level l (tab: rows of level l of the systems with nbig > l)
 __global__ void __launch_bounds__(MGB) k_mg_res(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                                const int2* __restrict__ tab, int l, int k)
+                                                const int4* __restrict__ tab, const int32_t* __restrict__ st, int l, int k)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (inactive(J, k)) return;
-    const AmgDev& H = hs[J.hier];
+    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    const AmgDev& H = hs[e.z];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) res_rows(J, H, l, k, i, i + 1, 1);
 }
@@ -473,63 +471,64 @@ __global__ void __launch_bounds__(MGB) k_mg_res(const MgJob* __restrict__ jobs, 
 // restriction to level l >= 1 (the pre-smoothing of level l needs every row
 // of the restricted right-hand side, so it is a phase of its own)
 __global__ void __launch_bounds__(MGB) k_mg_restrict(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                                     const int2* __restrict__ tab, int l, int k)
+                                                     const int4* __restrict__ tab, const int32_t* __restrict__ st, int l, int k)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (inactive(J, k)) return;
-    const AmgDev& H = hs[J.hier];
+    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    const AmgDev& H = hs[e.z];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) restrict_rows(J, H, l, i, i + 1, 1);
 }
 
 __global__ void __launch_bounds__(MGB) k_mg_pre(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                                const int2* __restrict__ tab, int l, int k)
+                                                const int4* __restrict__ tab, const int32_t* __restrict__ st, int l, int k)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (inactive(J, k)) return;
-    const AmgDev& H = hs[J.hier];
+    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    const AmgDev& H = hs[e.z];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) pre_rows(J, H, l, k, i, i + 1, 1);
 }
 
-__global__ void __launch_bounds__(1024) k_mg_tail(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs, int k)
+__global__ void __launch_bounds__(1024) k_mg_tail(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
+                                                 const int32_t* __restrict__ st, int k)
 {
     const MgJob& J = jobs[blockIdx.x];
-    if (J.n <= 0 || inactive(J, k)) return;
+    if (st[2 * blockIdx.x] != 0 || J.n <= 0 || k >= J.maxit) return;
     tail_body(J, hs[J.hier], k);
 }
 
 __global__ void __launch_bounds__(MGB) k_mg_prolong(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                                    const int2* __restrict__ tab, int l, int k)
+                                                    const int4* __restrict__ tab, const int32_t* __restrict__ st, int l, int k)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (inactive(J, k)) return;
-    const AmgDev& H = hs[J.hier];
+    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    const AmgDev& H = hs[e.z];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) prolong_rows(J, H, l, i, i + 1, 1);
 }
 
 __global__ void __launch_bounds__(MGB) k_mg_post1(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                                  const int2* __restrict__ tab, int l, int k)
+                                                  const int4* __restrict__ tab, const int32_t* __restrict__ st, int l, int k)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (inactive(J, k)) return;
-    const AmgDev& H = hs[J.hier];
+    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    const AmgDev& H = hs[e.z];
     const int i = e.y + threadIdx.x;
     if (i < H.n[l]) post1_rows(J, H, l, k, i, i + 1, 1);
 }
 
 __global__ void __launch_bounds__(MGB) k_mg_post2(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
-                                                  const int2* __restrict__ tab, int l, int k)
+                                                  const int4* __restrict__ tab, const int32_t* __restrict__ st, int l, int k)
 {
-    const int2 e = tab[blockIdx.x];
+    const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (inactive(J, k)) return;
-    const AmgDev& H = hs[J.hier];
+    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    const AmgDev& H = hs[e.z];
     const int i = e.y + threadIdx.x;
     double rz = 0.0, sz = 0.0;
     if (i < H.n[l]) post2_rows(J, H, l, k, i, i + 1, 1, rz, sz);

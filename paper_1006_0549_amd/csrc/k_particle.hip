@@ -261,15 +261,24 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         if (A.advance) {
             R f[NF];
             {
-                R F0[NF], F1[NF], F2[NF];
-                load_field_row<R>(A.F, A.fstride, sn.x, F0);
-                load_field_row<R>(A.F, A.fstride, sn.y, F1);
-                load_field_row<R>(A.F, A.fstride, sn.z, F2);
+                // R-06, row by row: f = fma(l2, F2, fma(l1, F1, l0 F0)), so
+                // only one gathered node row is live at a time
+                const R* F0 = A.F + (int64_t)sn.x * A.fstride;
+                const R* F1 = A.F + (int64_t)sn.y * A.fstride;
+                const R* F2 = A.F + (int64_t)sn.z * A.fstride;
+                R om_n[3];
 #pragma unroll
-                for (int q = 0; q < NF; ++q) f[q] = rfma<R>(lam[2], F2[q], rfma<R>(lam[1], F1[q], lam[0] * F0[q]));
+                for (int q = 0; q < NF; ++q) f[q] = lam[0] * F0[q];
+                om_n[0] = F0[F_OMEGA];
+#pragma unroll
+                for (int q = 0; q < NF; ++q) f[q] = rfma<R>(lam[1], F1[q], f[q]);
+                om_n[1] = F1[F_OMEGA];
+#pragma unroll
+                for (int q = 0; q < NF; ++q) f[q] = rfma<R>(lam[2], F2[q], f[q]);
+                om_n[2] = F2[F_OMEGA];
                 // Eq.(9) IECM with the cell means of this state (R-23, R-24)
                 if (ns > 0) {
-                    R om_e = ((F0[F_OMEGA] + F1[F_OMEGA]) + F2[F_OMEGA]) / R(3);
+                    R om_e = ((om_n[0] + om_n[1]) + om_n[2]) / R(3);
                     R hphi, dt;
                     if constexpr (sizeof(R) == 8) { hphi = C.hphi; dt = C.dt; } else { hphi = C.fhphi; dt = C.fdt; }
                     R fm = dt * (hphi * om_e);

@@ -225,7 +225,7 @@ struct pdfmc_ctx {
     unsigned int* d_mg_need = nullptr;
     double* d_mg_dinv = nullptr;
     double* d_mg_ainv = nullptr;
-    int2* d_mg_tab = nullptr;
+    int4* d_mg_tab = nullptr;      // (system, first row, hierarchy, 0)
     int4* d_mg_tab_dinv = nullptr;
     int64_t MGV = 0, MGD = 0, MGT = 0, MGTD = 0;
     struct TabRange { int64_t off = 0; int n_er = 0, n_all = 0; };
@@ -241,7 +241,7 @@ struct pdfmc_ctx {
     int need_low = 0;
     std::vector<AmgDev> h_amgdev;   // host copies of what the solver tables point at
     std::vector<MgJob> h_jobs;
-    std::vector<int2> h_tab;
+    std::vector<int4> h_tab;
     std::vector<int4> h_tab_dinv;
     unsigned long long* d_counters = nullptr;
     uint32_t* d_step = nullptr;
@@ -608,10 +608,10 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
     c->h_jobs = jer;
     TRY(h2d(c, c->d_mg_jobs, c->h_jobs));
     const int nj = (int)jer.size();
-    std::vector<int2>& tab = c->h_tab;
+    std::vector<int4>& tab = c->h_tab;
     tab.clear();
     auto add_rows = [&](int j, int rows) {
-        for (int r0 = 0; r0 < rows; r0 += 256) tab.push_back(make_int2(j, r0));
+        for (int r0 = 0; r0 < rows; r0 += 256) tab.push_back(make_int4(j, r0, jer[j].hier, 0));
     };
     c->tab0.off = 0;
     for (int j = 0; j < c->n_jobs_er; ++j) add_rows(j, jer[j].n);
@@ -659,41 +659,42 @@ pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
     const int maxbig = project ? c->maxbig_all : c->maxbig_er;
     const MgJob* J = c->d_mg_jobs;
     const AmgDev* H = c->d_amg;
-    const int2* T0 = c->d_mg_tab + c->tab0.off;
+    const int4* T0 = c->d_mg_tab + c->tab0.off;
+    const int32_t* S = c->d_mg_state;
     const unsigned g0 = cnt(c->tab0);
     hipStream_t st = c->stream;
     hipLaunchKernelGGL(k_mg_dinv, dim3(c->n_tab_dinv), dim3(256), 0, st, H, (const int4*)c->d_mg_tab_dinv);
     hipLaunchKernelGGL(k_mg_coarse, dim3(2 * c->n_amg), dim3(1024), 0, st, H);
-    hipLaunchKernelGGL(k_mg_setup1, dim3(g0), dim3(256), 0, st, J, T0);
-    hipLaunchKernelGGL(k_mg_setup2, dim3(g0), dim3(256), 0, st, J, H, T0);
+    hipLaunchKernelGGL(k_mg_setup1, dim3(g0), dim3(256), 0, st, J, T0, S);
+    hipLaunchKernelGGL(k_mg_setup2, dim3(g0), dim3(256), 0, st, J, H, T0, S);
     LAUNCHCHK(c);
     auto vcycle = [&](int k) -> pdfmc_status {
         if (maxbig >= 1)
             hipLaunchKernelGGL(k_mg_res, dim3(cnt(c->tabl[0])), dim3(256), 0, st, J, H,
-                               (const int2*)(c->d_mg_tab + c->tabl[0].off), 0, k);
+                               (const int4*)(c->d_mg_tab + c->tabl[0].off), S, 0, k);
         for (int l = 1; l < maxbig; ++l) {
-            const int2* Tl = c->d_mg_tab + c->tabl[l].off;
+            const int4* Tl = c->d_mg_tab + c->tabl[l].off;
             const dim3 gl(cnt(c->tabl[l]));
-            hipLaunchKernelGGL(k_mg_restrict, gl, dim3(256), 0, st, J, H, Tl, l, k);
-            hipLaunchKernelGGL(k_mg_pre, gl, dim3(256), 0, st, J, H, Tl, l, k);
-            hipLaunchKernelGGL(k_mg_res, gl, dim3(256), 0, st, J, H, Tl, l, k);
+            hipLaunchKernelGGL(k_mg_restrict, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
+            hipLaunchKernelGGL(k_mg_pre, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
+            hipLaunchKernelGGL(k_mg_res, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
         }
-        hipLaunchKernelGGL(k_mg_tail, dim3(nj), dim3(1024), 0, st, J, H, k);
+        hipLaunchKernelGGL(k_mg_tail, dim3(nj), dim3(1024), 0, st, J, H, S, k);
         for (int l = maxbig - 1; l >= 0; --l) {
-            const int2* Tl = c->d_mg_tab + c->tabl[l].off;
+            const int4* Tl = c->d_mg_tab + c->tabl[l].off;
             const dim3 gl(cnt(c->tabl[l]));
-            hipLaunchKernelGGL(k_mg_prolong, gl, dim3(256), 0, st, J, H, Tl, l, k);
-            hipLaunchKernelGGL(k_mg_post1, gl, dim3(256), 0, st, J, H, Tl, l, k);
-            hipLaunchKernelGGL(k_mg_post2, gl, dim3(256), 0, st, J, H, Tl, l, k);
+            hipLaunchKernelGGL(k_mg_prolong, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
+            hipLaunchKernelGGL(k_mg_post1, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
+            hipLaunchKernelGGL(k_mg_post2, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
         }
         LAUNCHCHK(c);
         return PDFMC_OK;
     };
-    hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, -1, 1);
+    hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, S, -1, 1);
     TRY(vcycle(-1));
     for (int k = 0; k < c->mg_iters; ++k) {
-        hipLaunchKernelGGL(k_mg_pa, dim3(g0), dim3(256), 0, st, J, H, T0, k);
-        hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, k, 0);
+        hipLaunchKernelGGL(k_mg_pa, dim3(g0), dim3(256), 0, st, J, H, T0, S, k);
+        hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, S, k, 0);
         TRY(vcycle(k));
     }
     hipLaunchKernelGGL(k_mg_finish, dim3(nj), dim3(1024), 0, st, J, H, c->mg_iters);
@@ -720,13 +721,13 @@ void mg_adapt(pdfmc_ctx* c)
     const int need = (int)*c->h_need;
     // the one-workgroup completion is many times slower per iteration than
     // the phases, so keep a margin above what was needed
-    const int margin = std::max(3, need / 8);
+    const int margin = std::max(4, need / 6);
     int want = c->mg_iters;
     if (need + 1 > c->mg_iters) {
         want = need + margin;
         c->need_low = 0;
     } else if (need + 2 * margin < c->mg_iters) {
-        if (++c->need_low >= 4) { want = need + margin; c->need_low = 0; }
+        if (++c->need_low >= 8) { want = need + margin; c->need_low = 0; }
     } else {
         c->need_low = 0;
     }

@@ -25,17 +25,17 @@ __global__ void k_proj_grad(NodeArgs A);
 __global__ void k_mirror_f32(const double* F, float* F32, int nn);
 __global__ void k_mg_dinv(const AmgDev* hs, const int4* tab);
 __global__ void k_mg_coarse(const AmgDev* hs);
-__global__ void k_mg_setup1(const MgJob* jobs, const int2* tab);
-__global__ void k_mg_setup2(const MgJob* jobs, const AmgDev* hs, const int2* tab);
-__global__ void k_mg_pa(const MgJob* jobs, const AmgDev* hs, const int2* tab, int k);
-__global__ void k_mg_pb(const MgJob* jobs, const AmgDev* hs, const int2* tab, int k, int first);
-__global__ void k_mg_res(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
-__global__ void k_mg_restrict(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
-__global__ void k_mg_pre(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
-__global__ void k_mg_tail(const MgJob* jobs, const AmgDev* hs, int k);
-__global__ void k_mg_prolong(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
-__global__ void k_mg_post1(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
-__global__ void k_mg_post2(const MgJob* jobs, const AmgDev* hs, const int2* tab, int l, int k);
+__global__ void k_mg_setup1(const MgJob* jobs, const int4* tab, const int32_t* st);
+__global__ void k_mg_setup2(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st);
+__global__ void k_mg_pa(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int k);
+__global__ void k_mg_pb(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int k, int first);
+__global__ void k_mg_res(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int l, int k);
+__global__ void k_mg_restrict(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int l, int k);
+__global__ void k_mg_pre(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int l, int k);
+__global__ void k_mg_tail(const MgJob* jobs, const AmgDev* hs, const int32_t* st, int k);
+__global__ void k_mg_prolong(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int l, int k);
+__global__ void k_mg_post1(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int l, int k);
+__global__ void k_mg_post2(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int l, int k);
 __global__ void k_mg_finish(const MgJob* jobs, const AmgDev* hs, int k0);
 __global__ void k_galerkin(const GalJob* jobs);
 __global__ void k_sort_hist(SortArgs A);
