@@ -1,0 +1,112 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (graph replay, 256-thread blocks, sort every 10 steps), on what the
+oracle can check one particle at a time.
+
+Given the fields F^n, a particle's position, velocity, frequency, element and
+velocity bin after one step depend on nothing but its own state and its
+Wiener increments (the scalars also depend on the cell means, so they are not
+compared). The oracle therefore advances a sample of particles, with the GPU's
+F^n uploaded as frozen fields, and must reproduce the GPU's FP64 results bit
+for bit. The total node weight must equal the total particle weight at any
+size (R-11, mass conservation of the estimator).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1006_0549_amd as P
+    return P
+
+
+def _sample_ids(n, k, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=min(k, n), replace=False))
+
+
+def _check_sampled(oracle_mod, mesh, params, parts, F, after, ids):
+    """Oracle: frozen fields F, the sampled particles, one step; compare."""
+    sub = {k: (v[..., ids] if isinstance(v, np.ndarray) and v.shape[-1] == len(parts["x"]) else v)
+           for k, v in parts.items()}
+    p0 = dict(params)
+    p0["mode"] = 0
+    o = oracle_mod.Oracle()
+    oc = o.add_case(mesh, p0)
+    o.fields_upload(oc, F)
+    o.upload(oc, sub)
+    o.init()
+    o.step(1)
+    r = o.download(oc, len(ids))
+    g = {k: after[k][np.searchsorted(after["id"], r["id"])] for k in ("x", "y", "u", "v", "w", "omega", "elem", "bin", "id")}
+    assert np.array_equal(g["id"], r["id"])
+    assert np.array_equal(g["elem"], r["elem"]), np.nonzero(g["elem"] != r["elem"])[0][:5]
+    for k in ("x", "y", "u", "v", "w", "omega"):
+        bad = np.nonzero(g[k] != r[k])[0]
+        assert bad.size == 0, (k, bad[:5], g[k][bad[:5]], r[k][bad[:5]])
+    assert np.array_equal(g["bin"], r["bin"])
+
+
+def _by_id(d):
+    order = np.argsort(d["id"])
+    return {k: (v[..., order] if isinstance(v, np.ndarray) and v.shape[-1] == len(order) else v) for k, v in d.items()}
+
+
+def test_channel_full_size_sampled_fp64(P, oracle_mod):
+    cfg = W.config_channel()
+    mesh, params, parts = cfg["mesh"], cfg["params"], cfg["particles"]
+    n = len(parts["x"])
+    _flush(f"[fullsize] channel {mesh.n_elems} triangles, {n} particles, FP64, graph replay")
+    sim = P.Sim("fp64", "cuda:0")
+    cs = sim.add_case(mesh, params, n)
+    sim.bind()
+    sim.set_options(sort_interval=10, block_size=256, use_graph=True)
+    sim.upload(cs, parts)
+    sim.init()
+    F = sim.fields(cs)
+    sim.step(1)
+    after = _by_id(sim.download(cs, n))
+    S = sim.node_sums(cs)
+    rows = np.unique(sim.case_info(cs)[1], return_index=True)[1]
+    wsum = float(after["weight"].sum())
+    assert abs(S[rows, 0].sum() - wsum) <= 1e-12 * wsum
+    cnt = sim.counters(cs)
+    assert cnt["nan"] == 0 and cnt["cg_fail"] == 0
+    _flush("[fullsize] channel: oracle on 4096 sampled particles")
+    _check_sampled(oracle_mod, mesh, params, parts, F, after, _sample_ids(n, 4096, 1))
+
+
+def test_batch32_full_size_sampled_fp64(P, oracle_mod):
+    b = W.config_batched()
+    cases = b["cases"]
+    ntot = sum(len(c["particles"]["x"]) for c in cases)
+    _flush(f"[fullsize] batch32: {len(cases)} cases, {ntot} particles, FP64, graph replay")
+    sim = P.Sim("fp64", "cuda:0")
+    ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in cases]
+    sim.bind()
+    sim.set_options(sort_interval=10, block_size=256, use_graph=True)
+    for cs, c in zip(ids, cases):
+        sim.upload(cs, c["particles"])
+    sim.init()
+    Fs = [sim.fields(cs) for cs in ids]
+    sim.step(1)
+    _flush("[fullsize] batch32: stepped; checking every case")
+    for ci, (cs, c) in enumerate(zip(ids, cases)):
+        n = len(c["particles"]["x"])
+        after = _by_id(sim.download(cs, n))
+        S = sim.node_sums(cs)
+        rows = np.unique(sim.case_info(cs)[1], return_index=True)[1]
+        wsum = float(after["weight"].sum())
+        assert abs(S[rows, 0].sum() - wsum) <= 1e-12 * wsum, ci
+        cnt = sim.counters(cs)
+        assert cnt["nan"] == 0 and cnt["cg_fail"] == 0, (ci, cnt)
+        _check_sampled(oracle_mod, c["mesh"], c["params"], c["particles"], Fs[ci], after, _sample_ids(n, 256, 100 + ci))
+    _flush("[fullsize] batch32: all cases checked")
