@@ -63,7 +63,8 @@ class _Params(C.Structure):
                 ("src", (C.c_double * 4) * 4),
                 ("k_floor", C.c_double), ("eps_floor", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
-                ("seed", C.c_uint64), ("stream", C.c_uint32), ("n_eff_min", C.c_double)]
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("n_eff_min", C.c_double),
+                ("reaction", C.c_int32), ("k_react", C.c_double * 4)]
 
 
 class _Particles(C.Structure):
@@ -170,10 +171,14 @@ def _mesh_struct(mesh):
 def _params_struct(p):
     s = _Params()
     for name, _ in _Params._fields_:
-        if name in ("dpdx", "src"):
+        if name in ("dpdx", "src", "reaction", "k_react"):
             continue
         setattr(s, name, p[name])
     s.dpdx[0], s.dpdx[1] = p["dpdx"]
+    s.reaction = int(p.get("reaction", 0))
+    kr = list(p.get("k_react", ()))
+    for a in range(4):
+        s.k_react[a] = float(kr[a]) if a < len(kr) else 0.0
     src = np.zeros((4, 4))
     if len(p.get("src", [])):
         src[:len(p["src"])] = np.asarray(p["src"], dtype=np.float64)

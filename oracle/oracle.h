@@ -72,6 +72,11 @@ typedef struct {
     double cg_rtol; int32_t cg_maxit;             /* R-28 */
     uint64_t seed; uint32_t stream;               /* R-09 key and counter word 2 */
     double n_eff_min;    /* R-34: least effective sample size of a node estimate */
+    int32_t reaction;    /* R-35: closed chemistry S_alpha(psi) of Eq.(8)-(9):
+                            0 none; 1 first-order decay S_a = -k_a psi_a;
+                            2 A + B -> P on scalars 0, 1, 2 at the rate
+                              k_0 psi_0 psi_1 (further scalars inert) */
+    double k_react[ORC_MAXS];   /* rate constants, >= 0 */
 } orc_params;
 
 typedef struct {

@@ -44,6 +44,12 @@ int orc_add_case(orc_ctx* c, const orc_mesh_desc* m, const orc_params* p, int32_
     if (p->mode < 0 || p->mode > 2) return orc_err(c, ORC_E_INVALID, "add_case: bad mode");
     if (!(p->dt > 0.0) || !(p->nu >= 0.0)) return orc_err(c, ORC_E_INVALID, "add_case: dt must be > 0, nu >= 0");
     if (!(p->n_eff_min >= 0.0)) return orc_err(c, ORC_E_INVALID, "add_case: n_eff_min must be >= 0");
+    if (p->reaction < 0 || p->reaction > 2) return orc_err(c, ORC_E_INVALID, "add_case: reaction must be 0, 1 or 2");
+    if (p->reaction == 2 && p->n_scalars < 3)
+        return orc_err(c, ORC_E_INVALID, "add_case: reaction 2 (A + B -> P) needs at least 3 scalars");
+    for (int a = 0; a < ORC_MAXS; ++a)
+        if (!(p->k_react[a] >= 0.0 && p->k_react[a] < 1e300))
+            return orc_err(c, ORC_E_INVALID, "add_case: k_react must be finite and >= 0");
     ocase* cs = orc_alloc(sizeof(ocase));
     cs->p = *p;
     int rc = omesh_build(c, &cs->m, m);

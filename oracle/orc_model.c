@@ -26,6 +26,22 @@ static void interpolate(const ocase* cs, int e, const double lam[3], double f[OR
 }
 
 /* One particle, Eq.(2), (4), (5) and (9) by forward Euler (R-03). */
+/* Closed reaction source S_alpha(psi) of the scalar equation, Eq.(8)-(9),
+ * for particle p (R-35): first-order decay, or A + B -> P with the rate
+ * k_0 psi_A psi_B consuming A and B and producing P. */
+static void reaction_source(const orc_params* P, const double* psi, int64_t np, int64_t p, double S[ORC_MAXS])
+{
+    const int ns = P->n_scalars;
+    if (P->reaction == 1) {
+        for (int a = 0; a < ns; ++a) S[a] = -P->k_react[a] * psi[(size_t)a * np + p];
+    } else if (P->reaction == 2) {
+        double r = P->k_react[0] * psi[p] * psi[(size_t)np + p];
+        S[0] = -r;
+        S[1] = -r;
+        S[2] = r;
+    }
+}
+
 static void advance_particle(ocase* cs, int64_t p, uint32_t n)
 {
     const orc_params* P = &cs->p;
@@ -38,9 +54,13 @@ static void advance_particle(ocase* cs, int64_t p, uint32_t n)
     interpolate(cs, e, lam, f);
     orc_gauss6(P->seed, cs->id[p], n, P->stream, xi);
 
-    /* Eq.(9), IECM: psi <- psi - (dt/t_m)(psi - <phi|V>), with the cell
-     * estimate of the conditional mean (R-23), 1/t_m = Cphi/2 <omega>_e (R-24) */
+    /* Eq.(9), IECM plus the closed reaction source, forward Euler:
+     * psi <- psi - (dt/t_m)(psi - <phi|V>) + dt S(psi), with the cell
+     * estimate of the conditional mean (R-23), 1/t_m = Cphi/2 <omega>_e
+     * (R-24), and S evaluated on the composition before the step (R-35) */
     if (ns > 0) {
+        double S[ORC_MAXS] = {0.0, 0.0, 0.0, 0.0};
+        reaction_source(P, cs->psi, cs->np, p, S);
         const int* s = m->tri_s + 3 * e;
         double om_e = ((cs->F[(size_t)s[0] * ORC_NF + F_OMEGA] + cs->F[(size_t)s[1] * ORC_NF + F_OMEGA])
                        + cs->F[(size_t)s[2] * ORC_NF + F_OMEGA]) / 3.0;
@@ -50,7 +70,7 @@ static void advance_particle(ocase* cs, int64_t p, uint32_t n)
         for (int a = 0; a < ns; ++a) {
             double mean = cs->cmean[((size_t)e * 8 + b) * ns + a];
             double* ps = cs->psi + (size_t)a * cs->np + p;
-            *ps = *ps - fm * (*ps - mean);
+            *ps = (*ps - fm * (*ps - mean)) + dt * S[a];
         }
     }
 

@@ -365,3 +365,107 @@ def test_thin_nodes_keep_previous_moments(oracle_mod):
     assert np.array_equal(st2[thin, 2:], st1[thin, 2:])
     assert np.all(np.abs(st2[~thin, 2:5] - st1[~thin, 2:5]).sum(1) > 0.0)
     assert o.counters(cs)["empty_node"] == int(thin.sum())
+
+
+def _reaction_case(oracle_mod, mesh, parts, ns, reaction, k, dt, steps, n_bins=8):
+    F = np.zeros((mesh.n_nodes, 22))
+    F[:, 19] = 1.5
+    p = W.default_params(mode=0, nu=0.0, dt=dt, n_scalars=ns, n_bins=n_bins, reaction=reaction, k_react=k)
+    o = oracle_mod.Oracle()
+    cs = o.add_case(mesh, p)
+    o.fields_upload(cs, F)
+    o.upload(cs, parts)
+    o.init()
+    N = len(parts["x"])
+    out = [o.download(cs, N)]
+    for _ in range(steps):
+        o.step(1)
+        out.append(o.download(cs, N))
+    return out
+
+
+def _resting(mesh, ppe, seed, ns):
+    parts = _parts(mesh, ppe, seed, ns=ns)
+    rng = np.random.default_rng(seed + 1)
+    N = len(parts["x"])
+    parts["u"], parts["v"], parts["w"] = rng.standard_normal((3, N)) * 1e-13
+    return parts, rng, N
+
+
+def test_reaction_first_order_decay_closed_form(oracle_mod):
+    """Eq.(9) with S_a = -k_a psi_a (R-35). A uniform composition does not
+    mix, so every particle follows the forward-Euler recursion
+    psi_n = psi_0 (1 - k dt)^n, which lies below exp(-k t) by at most
+    n (k dt)^2 / 2. With a random composition the IECM step conserves the
+    mass-weighted sum, so that sum decays by exactly (1 - k dt) per step."""
+    mesh = _box(10)
+    dt, k, steps = 0.01, (2.0, 0.5), 40
+    parts, rng, N = _resting(mesh, 30, 31, 2)
+    parts["psi"] = np.stack([np.full(N, 1.0), np.full(N, 0.6)])
+    out = _reaction_case(oracle_mod, mesh, parts, 2, 1, k + (0.0, 0.0), dt, steps)
+    for a in range(2):
+        h = k[a] * dt
+        want = parts["psi"][a][0] * (1.0 - h) ** steps
+        assert np.allclose(out[-1]["psi"][a], want, rtol=1e-12, atol=0)
+        exact = parts["psi"][a][0] * math.exp(-k[a] * dt * steps)
+        gap = exact - out[-1]["psi"][a]
+        assert np.all(gap >= 0) and np.all(gap <= parts["psi"][a][0] * steps * h * h / 2)
+    parts["psi"] = rng.random((2, N))
+    out = _reaction_case(oracle_mod, mesh, parts, 2, 1, k + (0.0, 0.0), dt, 10)
+    w = parts["weight"]
+    for a in range(2):
+        s = np.array([np.sum(w * q["psi"][a]) for q in out])
+        assert np.allclose(s[1:] / s[:-1], 1.0 - k[a] * dt, rtol=1e-12, atol=0)
+        # the scalar still mixes: its weighted variance falls faster than the mean squared
+        m = s / np.sum(w)
+        var = np.array([np.sum(w * (q["psi"][a] - mm) ** 2) for q, mm in zip(out, m)])
+        assert var[-1] / var[0] < (1.0 - k[a] * dt) ** 20
+
+
+def test_reaction_a_plus_b_invariants(oracle_mod):
+    """A + B -> P at the rate k psi_A psi_B (R-35). Mixing conserves every
+    mass-weighted sum, the reaction consumes A and B at the same rate and
+    produces P at that rate: sum w (A + P) and sum w (B + P) are invariant,
+    and sum w A falls by exactly dt k sum w A B over a step. A uniform
+    composition follows a_{n+1} = a_n - dt k a_n^2, within O(dt) of the exact
+    a_0 / (1 + k a_0 t)."""
+    mesh = _box(10)
+    dt, k = 0.01, 3.0
+    parts, rng, N = _resting(mesh, 30, 37, 3)
+    parts["psi"] = np.stack([0.5 + 0.5 * rng.random(N), 0.2 + 0.6 * rng.random(N), np.zeros(N)])
+    out = _reaction_case(oracle_mod, mesh, parts, 3, 2, (k, 0.0, 0.0, 0.0), dt, 3)
+    w = parts["weight"]
+    for q0, q1 in zip(out[:-1], out[1:]):
+        A0, B0, P0 = q0["psi"]
+        A1, B1, P1 = q1["psi"]
+        assert np.isclose(np.sum(w * (A1 + P1)), np.sum(w * (A0 + P0)), rtol=1e-13, atol=0)
+        assert np.isclose(np.sum(w * (B1 + P1)), np.sum(w * (B0 + P0)), rtol=1e-13, atol=0)
+        drop = np.sum(w * A0) - np.sum(w * A1)
+        assert np.isclose(drop, dt * k * np.sum(w * A0 * B0), rtol=1e-9, atol=0)
+        assert np.all(P1 >= P0)
+    steps, a0 = 30, 0.8
+    parts["psi"] = np.stack([np.full(N, a0), np.full(N, a0), np.zeros(N)])
+    out = _reaction_case(oracle_mod, mesh, parts, 3, 2, (k, 0.0, 0.0, 0.0), dt, steps)
+    a = a0
+    for n in range(1, steps + 1):
+        a = a - dt * k * a * a
+        assert np.allclose(out[n]["psi"][0], a, rtol=1e-12, atol=0)
+        assert np.allclose(out[n]["psi"][1], a, rtol=1e-12, atol=0)
+        assert np.allclose(out[n]["psi"][2], a0 - a, rtol=1e-11, atol=1e-15)
+    t = steps * dt
+    assert abs(a - a0 / (1 + k * a0 * t)) < 2 * dt * (k * a0) ** 2 * t
+
+
+def test_reaction_rejections(oracle_mod):
+    mesh = _box(6)
+    o = oracle_mod.Oracle()
+    for bad in (dict(reaction=3), dict(reaction=2, n_scalars=2), dict(reaction=1, k_react=(-1.0, 0, 0, 0))):
+        p = W.default_params(mode=0, **{"n_scalars": 3, **bad})
+        with pytest.raises(RuntimeError):
+            o.add_case(mesh, p)
+    # reaction 0 ignores the rate constants
+    parts, rng, N = _resting(mesh, 20, 41, 1)
+    parts["psi"] = rng.random((1, N))
+    a = _reaction_case(oracle_mod, mesh, parts, 1, 0, (5.0, 0, 0, 0), 0.01, 3)
+    b = _reaction_case(oracle_mod, mesh, parts, 1, 0, (0.0, 0, 0, 0), 0.01, 3)
+    assert np.array_equal(a[-1]["psi"], b[-1]["psi"])
