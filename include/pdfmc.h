@@ -91,6 +91,11 @@ typedef struct {
     double n_eff_min;    /* least effective sample size W^2/sum (w N)^2 of a
                             node estimate; below it the node keeps its previous
                             moments (R-34) */
+    int32_t reaction;    /* closed scalar source S(psi) of Eq.(8)-(9), R-35:
+                            0 none; 1 first-order decay S_a = -k_a psi_a;
+                            2 A + B -> P on scalars 0, 1, 2 at the rate
+                              k_0 psi_0 psi_1 (needs n_scalars >= 3)        */
+    double k_react[PDFMC_MAX_SCALARS];  /* rate constants, finite and >= 0    */
 } pdfmc_case_params;
 
 /* Particle ensemble on the host, structure of arrays, always FP64 here (the
@@ -162,7 +167,9 @@ pdfmc_status pdfmc_cell_means(pdfmc_ctx* ctx, int32_t case_id, double* mean, int
 /* Counters since upload, [PDFMC_N_COUNTERS]: walk fallbacks, reflections,
  * periodic crossings, omega sign flips, empty nodes, non-finite particles,
  * walk steps, ER CG iterations, projection CG iterations, CG failures,
- * k floor hits, eps floor hits. */
+ * k floor hits, eps floor hits. The five relaxation components of a case
+ * are solved as one system with five right-hand sides: its iterations count
+ * once per component (the iterations until every component converged). */
 pdfmc_status pdfmc_counters(pdfmc_ctx* ctx, int32_t case_id, int64_t* out);
 
 /* Execution options: re-sort the particles by element every sort_interval
@@ -172,7 +179,9 @@ pdfmc_status pdfmc_counters(pdfmc_ctx* ctx, int32_t case_id, int64_t* out);
  * else PDFMC_E_INVALID). */
 pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t block_size, int32_t use_graph);
 /* Eulerian solver options (the FP64 multigrid-preconditioned CG of the
- * elliptic relaxation and the projection, reading R-28 of the step contract).
+ * elliptic relaxation and the projection, reading R-28 of the step contract;
+ * the relaxation's five components share their matrix and run as one system
+ * with five right-hand sides, each with its own Krylov sequence).
  * Every step runs `iterations` CG iterations as row-parallel phase kernels
  * over all systems of all cases (a system that has converged skips the rest
  * at once), then completes any system that needs more in one workgroup per

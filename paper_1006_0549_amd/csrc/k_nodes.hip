@@ -244,7 +244,7 @@ __global__ void k_er_assemble(NodeArgs A)
     }
     if (A.is_wall[s]) {
         for (int k = 0; k < len; ++k) val[(int64_t)k * n + i] = (col[(int64_t)k * n + i] == i) ? 1.0 : 0.0;
-        for (int q = 0; q < NER; ++q) A.er_b[(int64_t)q * A.nn + s] = A.er_dval[(int64_t)q * A.nn + s];
+        for (int q = 0; q < NER; ++q) A.er_b[(int64_t)s * NER + q] = A.er_dval[(int64_t)q * A.nn + s];
         return;
     }
     for (int k = 0; k < len; ++k) {
@@ -255,7 +255,7 @@ __global__ void k_er_assemble(NodeArgs A)
             val[at] = 0.0;
         }
     }
-    for (int q = 0; q < NER; ++q) A.er_b[(int64_t)q * A.nn + s] = rhs[q];
+    for (int q = 0; q < NER; ++q) A.er_b[(int64_t)s * NER + q] = rhs[q];
 }
 
 // Stiffness matrix of the projection (constant; assembled once).
@@ -286,9 +286,8 @@ __global__ void k_er_finish(NodeArgs A)
     double* F = A.F + (int64_t)s * NF;
     const double* st = A.stats + (int64_t)s * NST;
     const double K = A.kf[s], E = A.ef[s];
-    const int64_t n = A.nn;
-    const double w11 = A.er_x[s], w12 = A.er_x[n + s], w21 = A.er_x[2 * n + s], w22 = A.er_x[3 * n + s],
-                 w33 = A.er_x[4 * n + s];
+    const double* wx = A.er_x + (int64_t)s * NER;
+    const double w11 = wx[0], w12 = wx[1], w21 = wx[2], w22 = wx[3], w33 = wx[4];
     F[F_G11] = (w11 - 0.5 * E) / K;
     F[F_G12] = w12 / K;
     F[F_G21] = w21 / K;

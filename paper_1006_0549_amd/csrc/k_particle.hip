@@ -32,6 +32,11 @@ template <typename R> __device__ inline R r_sqrt(R a);
 template <> __device__ inline double r_sqrt<double>(double a) { return __builtin_sqrt(a); }
 template <> __device__ inline float r_sqrt<float>(float a) { return __builtin_sqrtf(a); }
 
+// reaction rate constant a of the case, in the particle precision
+template <typename R> __device__ inline R kr(const CaseDev& C, int a);
+template <> __device__ inline double kr<double>(const CaseDev& C, int a) { return C.kr[a]; }
+template <> __device__ inline float kr<float>(const CaseDev& C, int a) { return C.fkr[a]; }
+
 __device__ inline int pick(const int4& v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
 
 // R-05: lambda_k = fma(c_k, dy, fma(b_k, dx, delta_k1)), dx = x - x1, dy = y - y1
@@ -276,7 +281,9 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
 #pragma unroll
                 for (int q = 0; q < NF; ++q) f[q] = rfma<R>(lam[2], F2[q], f[q]);
                 om_n[2] = F2[F_OMEGA];
-                // Eq.(9) IECM with the cell means of this state (R-23, R-24)
+                // Eq.(9) IECM with the cell means of this state (R-23, R-24),
+                // plus the closed reaction source on the composition before
+                // the step (R-35)
                 if (ns > 0) {
                     R om_e = ((om_n[0] + om_n[1]) + om_n[2]) / R(3);
                     R hphi, dt;
@@ -285,7 +292,16 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
                     if (fm > R(1)) fm = R(1);
                     const int b = A.P.bin[p];
                     const R* cm = A.cmean + C.cmoff + ((int64_t)(e - C.eoff) * 8 + b) * ns;
-                    for (int a = 0; a < ns; ++a) psi[a] = psi[a] - fm * (psi[a] - cm[a]);
+                    R s[MAXS] = {R(0), R(0), R(0), R(0)};
+                    if (C.reaction == 1) {
+                        for (int a = 0; a < ns; ++a) s[a] = -(kr<R>(C, a) * psi[a]);
+                    } else if (C.reaction == 2) {
+                        const R r = (kr<R>(C, 0) * psi[0]) * psi[1];
+                        s[0] = -r;
+                        s[1] = -r;
+                        s[2] = r;
+                    }
+                    for (int a = 0; a < ns; ++a) psi[a] = (psi[a] - fm * (psi[a] - cm[a])) + dt * s[a];
                 }
             }
             R xi[6];

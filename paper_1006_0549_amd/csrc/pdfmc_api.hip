@@ -153,6 +153,9 @@ int64_t mg_vec_len(const AmgH& H)
 }
 
 int64_t mg_blocks(int64_t n) { return (n + 255) / 256; }
+// row blocks of a row-parallel solver phase: one lane per (row, column) pair
+int mg_rows_per_block(int nv) { return 256 / nv; }
+int64_t mg_blocks_nv(int64_t n, int nv) { return (n + mg_rows_per_block(nv) - 1) / mg_rows_per_block(nv); }
 
 // Stiffness matrix of the case on its own Galerkin pattern (host copy used
 // only to build the hierarchies).
@@ -396,14 +399,14 @@ void compute_offsets(pdfmc_ctx* c)
         for (int h = 0; h < 2; ++h) {
             pack_hier(cs.he[h], cs.hoff[h], nullptr, nullptr, ni, nd);
             maxlev = std::max(maxlev, (int)cs.amg[h].lv.size());
-            const int nsys = h == 0 ? NER : 1;
-            nv += nsys * mg_vec_len(cs.amg[h]);
+            const int ncol = h == 0 ? NER : 1;      // right-hand sides of the system
+            nv += ncol * mg_vec_len(cs.amg[h]);
             for (auto& lv : cs.amg[h].lv) {
                 ndv += lv.A.n;
                 ntd += mg_blocks(lv.A.n);
-                nt += nsys * mg_blocks(lv.A.n);
+                nt += mg_blocks_nv(lv.A.n, ncol);
             }
-            nt += nsys * mg_blocks(cs.amg[h].lv[0].A.n);
+            nt += mg_blocks_nv(cs.amg[h].lv[0].A.n, ncol);
         }
     }
     c->AMG_I = ni; c->AMG_D = nd; c->n_amg = na; c->amg_levels = maxlev;
@@ -432,6 +435,8 @@ CaseDev make_case_dev(const pdfmc_ctx* c, const Case& cs)
     d.Cv = p.Cv; d.CL = p.CL; d.Ceta = p.Ceta; d.nu34 = std::sqrt(p.nu * std::sqrt(p.nu));
     d.k_floor = p.k_floor; d.eps_floor = p.eps_floor; d.dpdx[0] = p.dpdx[0]; d.dpdx[1] = p.dpdx[1];
     d.cg_rtol = p.cg_rtol; d.cg_maxit = p.cg_maxit; d.neff_min = p.n_eff_min;
+    d.reaction = p.reaction;
+    for (int a = 0; a < MAXS; ++a) { d.kr[a] = p.k_react[a]; d.fkr[a] = (float)p.k_react[a]; }
     (void)c;
     return d;
 }
@@ -561,14 +566,15 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
     for (auto& D : c->h_amgdev) D.nbig = mg_nbig(c, D);
     if (c->n_amg > 0) TRY(h2d(c, c->d_amg, c->h_amgdev));
     std::vector<MgJob> jer, jp;
-    const int64_t n = c->NN;
     for (size_t ci = 0; ci < c->cases.size(); ++ci) {
         const Case& cs = c->cases[ci];
         if (cs.p.mode != 2) continue;
         int64_t voff = cs.vec_off;
-        for (int q = 0; q <= NER; ++q) {
-            const bool proj = q == NER;
-            const int h = proj ? 1 : 0;
+        // one system of NER columns for the relaxed tensor, one of a single
+        // column for the pressure increment
+        for (int h = 0; h < 2; ++h) {
+            const bool proj = h == 1;
+            const int nv = proj ? 1 : NER;
             const int hi = 2 * cs.amg_index + h;
             const AmgDev& D = c->h_amgdev[hi];
             MgJob J{};
@@ -580,18 +586,19 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
             J.maxit = cs.p.cg_maxit;
             J.n = cs.m.nsn;
             J.tol = cs.p.cg_rtol;
-            J.b = (proj ? c->d_pb : c->d_er_b + q * n) + cs.noff;
-            J.x = (proj ? c->d_phi : c->d_er_x + q * n) + cs.noff;
+            J.nv = nv;
+            J.b = proj ? c->d_pb + cs.noff : c->d_er_b + (int64_t)NER * cs.noff;
+            J.x = proj ? c->d_phi + cs.noff : c->d_er_x + (int64_t)NER * cs.noff;
             double* v = c->d_mg_vec + voff;
-            const int n0 = D.n[0];
-            J.r[0] = v; J.r[1] = v + n0; J.p[0] = v + 2 * (int64_t)n0; J.p[1] = v + 3 * (int64_t)n0; J.q = v + 4 * (int64_t)n0;
-            v += 5 * (int64_t)n0;
+            const int64_t n0 = (int64_t)nv * D.n[0];
+            J.r[0] = v; J.r[1] = v + n0; J.p[0] = v + 2 * n0; J.p[1] = v + 3 * n0; J.q = v + 4 * n0;
+            v += 5 * n0;
             for (int l = 0; l < D.nlev; ++l) {
-                const int64_t nl = D.n[l];
+                const int64_t nl = (int64_t)nv * D.n[l];
                 J.lb[l] = v; J.ly[l] = v + nl; J.la[l] = v + 2 * nl; J.lt[l] = v + 3 * nl;
                 v += 4 * nl;
             }
-            voff += mg_vec_len(cs.amg[h]);
+            voff += nv * mg_vec_len(cs.amg[h]);
             J.iters = c->d_counters + (int64_t)ci * NCNT + (proj ? C_CG_P : C_CG_ER);
             J.fails = c->d_counters + (int64_t)ci * NCNT + C_CG_FAIL;
             J.need = c->d_mg_need;
@@ -601,8 +608,10 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
     c->n_jobs_er = (int)jer.size();
     c->n_jobs_p = (int)jp.size();
     jer.insert(jer.end(), jp.begin(), jp.end());
+    int64_t aoff = 0;
     for (size_t j = 0; j < jer.size(); ++j) {
-        jer[j].acc = c->d_mg_acc + j * MG_NSLOT * MG_SLOT;
+        jer[j].acc = c->d_mg_acc + aoff;
+        aoff += (int64_t)jer[j].nv * MG_NSLOT * MG_SLOT;
         jer[j].state = c->d_mg_state + 2 * j;
     }
     c->h_jobs = jer;
@@ -611,7 +620,8 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
     std::vector<int4>& tab = c->h_tab;
     tab.clear();
     auto add_rows = [&](int j, int rows) {
-        for (int r0 = 0; r0 < rows; r0 += 256) tab.push_back(make_int4(j, r0, jer[j].hier, 0));
+        const int rpb = mg_rows_per_block(jer[j].nv);
+        for (int r0 = 0; r0 < rows; r0 += rpb) tab.push_back(make_int4(j, r0, jer[j].hier, 0));
     };
     c->tab0.off = 0;
     for (int j = 0; j < c->n_jobs_er; ++j) add_rows(j, jer[j].n);
@@ -679,7 +689,7 @@ pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
             hipLaunchKernelGGL(k_mg_pre, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
             hipLaunchKernelGGL(k_mg_res, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
         }
-        hipLaunchKernelGGL(k_mg_tail, dim3(nj), dim3(1024), 0, st, J, H, S, k);
+        hipLaunchKernelGGL(k_mg_tail, dim3(nj), dim3(512), 0, st, J, H, S, k);
         for (int l = maxbig - 1; l >= 0; --l) {
             const int4* Tl = c->d_mg_tab + c->tabl[l].off;
             const dim3 gl(cnt(c->tabl[l]));
@@ -697,7 +707,7 @@ pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
         hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, S, k, 0);
         TRY(vcycle(k));
     }
-    hipLaunchKernelGGL(k_mg_finish, dim3(nj), dim3(1024), 0, st, J, H, c->mg_iters);
+    hipLaunchKernelGGL(k_mg_finish, dim3(nj), dim3(512), 0, st, J, H, c->mg_iters);
     LAUNCHCHK(c);
     return PDFMC_OK;
 }
@@ -882,6 +892,12 @@ pdfmc_status pdfmc_add_case(pdfmc_ctx* c, const pdfmc_mesh_desc* mesh, const pdf
     if (p->mode < 0 || p->mode > 2) return fail(c, PDFMC_E_INVALID, "add_case: mode must be 0, 1 or 2");
     if (!(p->dt > 0.0) || !(p->nu >= 0.0)) return fail(c, PDFMC_E_INVALID, "add_case: need dt > 0 and nu >= 0");
     if (!(p->n_eff_min >= 0.0)) return fail(c, PDFMC_E_INVALID, "add_case: n_eff_min must be >= 0");
+    if (p->reaction < 0 || p->reaction > 2) return fail(c, PDFMC_E_INVALID, "add_case: reaction must be 0, 1 or 2");
+    if (p->reaction == 2 && p->n_scalars < 3)
+        return fail(c, PDFMC_E_INVALID, "add_case: reaction 2 (A + B -> P) needs at least 3 scalars");
+    for (int a = 0; a < PDFMC_MAX_SCALARS; ++a)
+        if (!(p->k_react[a] >= 0.0 && p->k_react[a] < 1e300))
+            return fail(c, PDFMC_E_INVALID, "add_case: k_react must be finite and >= 0");
     if (capacity < 0 || capacity > ((int64_t)1 << 31)) return fail(c, PDFMC_E_INVALID, "add_case: bad capacity");
     Case cs;
     cs.p = *p;

@@ -63,7 +63,9 @@ struct CaseDev {
     double dpdx[2];
     double cg_rtol;
     double neff_min;           // least effective sample size of a node estimate
-    int32_t cg_maxit, pad2;
+    int32_t cg_maxit, reaction;  // reaction: closed scalar source kind (0, 1, 2)
+    double kr[MAXS];           // reaction rate constants
+    float fkr[MAXS];
 };
 
 template <typename R>

@@ -33,8 +33,8 @@ struct NodeArgs {
     double* L2;                      // [nn]
     double* er_r;                    // [5][nn] relaxation sources
     double* er_dval;                 // [5][nn] wall values
-    double* er_b;                    // [5][nn] right-hand sides
-    double* er_x;                    // [5][nn] relaxed tensor (warm start)
+    double* er_b;                    // [nn][5] right-hand sides (components interleaved)
+    double* er_x;                    // [nn][5] relaxed tensor (warm start)
     double* er_val;                  // relaxation matrix (ELL)
     double* pk_val;                  // stiffness of the projection (ELL)
     double* pb;                      // [nn]
@@ -94,9 +94,10 @@ struct MgJob {
     int32_t hier;                  // index of the hierarchy
     int32_t mean_free;             // singular system: solution and residual kept mean-free
     int32_t warm;                  // 1: start from the current x; 0: start from zero
-    int32_t pad;
+    int32_t nv;                    // right-hand sides sharing the matrix (1 or NER)
     int32_t maxit, n;              // iteration cap, rows
     double tol;                    // relative residual tolerance
+    // every vector below holds nv interleaved columns: entry v of row i at i * nv + v
     double* b;                     // right-hand side (made mean-free in place)
     double* x;                     // solution, warm start
     double* r[2];                  // residual, ping-pong by iteration parity
@@ -106,7 +107,7 @@ struct MgJob {
     double* ly[AMG_MAXL];          // level corrections (level 0: z = M^-1 r)
     double* la[AMG_MAXL];          // smoothing intermediate
     double* lt[AMG_MAXL];          // residual, then the pre-smoothing copy
-    double* acc;                   // [MG_NSLOT][MG_SLOT]
+    double* acc;                   // [MG_NSLOT][nv][MG_SLOT]
     int32_t* state;                // [0] converged, [1] iteration count
     unsigned long long* iters;
     unsigned long long* fails;

@@ -47,7 +47,8 @@ class _CaseParams(C.Structure):
                 ("dpdx", C.c_double * 2), ("n_scalars", C.c_int32), ("n_bins", C.c_int32),
                 ("n_min", C.c_int32), ("src", (C.c_double * 4) * 4), ("k_floor", C.c_double),
                 ("eps_floor", C.c_double), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
-                ("seed", C.c_uint64), ("stream", C.c_uint32), ("n_eff_min", C.c_double)]
+                ("seed", C.c_uint64), ("stream", C.c_uint32), ("n_eff_min", C.c_double),
+                ("reaction", C.c_int32), ("k_react", C.c_double * 4)]
 
 
 class _TuneResult(C.Structure):
@@ -173,9 +174,13 @@ class Sim:
                        len(mesh.bcs), bcs)
         p = _CaseParams()
         for name, _ in _CaseParams._fields_:
-            if name not in ("dpdx", "src"):
+            if name not in ("dpdx", "src", "reaction", "k_react"):
                 setattr(p, name, params[name])
         p.dpdx[0], p.dpdx[1] = params["dpdx"]
+        p.reaction = int(params.get("reaction", 0))
+        kr = list(params.get("k_react", ()))
+        for a in range(4):
+            p.k_react[a] = float(kr[a]) if a < len(kr) else 0.0
         for a, s in enumerate(params.get("src", [])):
             for j in range(4):
                 p.src[a][j] = float(s[j])

@@ -78,6 +78,12 @@ def test_argument_rejections(pkg):
         s.set_options(0, 192, False)          # would let a workgroup span two cases
     with pytest.raises(pkg.PdfmcError, match="INVALID.*n_eff_min"):
         s.add_case(mesh, W.default_params(n_eff_min=-1.0), 10)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*reaction"):
+        s.add_case(mesh, W.default_params(reaction=3), 10)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*reaction 2"):
+        s.add_case(mesh, W.default_params(reaction=2, n_scalars=2), 10)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*k_react"):
+        s.add_case(mesh, W.default_params(reaction=1, k_react=(1.0, -2.0, 0.0, 0.0)), 10)
     with pytest.raises(pkg.PdfmcError, match="INVALID.*tail_rows"):
         s.set_solver(0, -5)
     with pytest.raises(pkg.PdfmcError, match="STATE"):

@@ -114,8 +114,11 @@ def _frozen_case(ns=1, nb=8, n=16, ppe=33, seed=5):
         l_ = np.nonzero((mesh.xy[:, 0] == 0.0) & (mesh.xy[:, 1] == mesh.xy[r_, 1]))[0][0]
         F[r_] = F[l_]
     params = W.default_params(mode=0, dt=2e-3, nu=2e-3, n_scalars=ns, n_bins=nb,
-                              src=[(0.3, 0.7, 0.08, 1.0), (0.6, 0.2, 0.1, 0.5)][:ns])
-    parts = W.init_particles(mesh, ppe, ns, rng, u_std=0.4, psi_disks=[(0.5, 0.5, 0.25, 1.0), (0.2, 0.8, 0.3, 2.0)][:ns])
+                              src=[(0.3, 0.7, 0.08, 1.0), (0.6, 0.2, 0.1, 0.5), (0.8, 0.8, 0.1, 0.0),
+                                   (0.15, 0.3, 0.1, 0.7)][:ns])
+    parts = W.init_particles(mesh, ppe, ns, rng, u_std=0.4,
+                             psi_disks=[(0.5, 0.5, 0.25, 1.0), (0.2, 0.8, 0.3, 2.0), (0.7, 0.3, 0.2, 0.0),
+                                        (0.4, 0.6, 0.3, 1.5)][:ns])
     return mesh, params, parts, F
 
 
@@ -150,6 +153,62 @@ def test_one_step_frozen_bitwise(P, oracle_mod, ns, nb):
     for k in ("walk_fallback", "reflect", "periodic", "omega_flip", "nan", "walk_steps"):
         assert gc_[k] == rc_[k], (k, gc_[k], rc_[k])
     assert rc_["reflect"] > 0 and rc_["periodic"] > 0
+
+
+@pytest.mark.parametrize("reaction,ns,k", [(1, 2, (3.0, 0.7, 0.0, 0.0)), (2, 3, (4.0, 0.0, 0.0, 0.0)),
+                                            (2, 4, (2.5, 0.0, 0.0, 0.0))])
+def test_reaction_frozen_bitwise(P, oracle_mod, reaction, ns, k):
+    """Reactive scalars (R-35): the FP64 particle state after each of three
+    frozen-field steps equals the oracle's (scalars to the cell-mean rounding
+    bound), with sources, walls, periodic edges and 8 velocity bins."""
+    mesh, params, parts, F = _frozen_case(ns, 8)
+    params.update(reaction=reaction, k_react=k)
+    n = len(parts["x"])
+    _flush(f"[reaction_frozen] reaction={reaction} ns={ns} particles={n}")
+    sim, cs, o, oc = _pair(P, oracle_mod, mesh, params, parts, fields=F)
+    sim.init(); o.init()
+    p0 = sim.download(cs, n)["psi"].copy()
+    for step in range(3):
+        sim.step(1); o.step(1)
+        g, r = sim.download(cs, n), o.download(oc, n)
+        _assert_state_equal(g, r)
+        gst, rst = sim.stats(cs), o.stats(oc)
+        rows = _stat_rows(sim, cs)
+        d = np.abs(gst - rst)[rows] / _scale(rst, ns)[rows]
+        assert d.max() <= 1e-12, (step, d.max())
+    # the source acted: compositions differ from a passive run of the same case
+    passive = dict(params, reaction=0)
+    sim2, cs2, _, _ = _pair(P, oracle_mod, mesh, passive, parts, fields=F)
+    sim2.init(); sim2.step(3)
+    assert np.abs(sim2.download(cs2, n)["psi"] - g["psi"]).max() > 1e-4
+    assert not np.array_equal(p0, g["psi"])
+
+
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-13), ("fp32", 1e-5)])
+def test_reaction_uniform_recursion(P, precision, rtol):
+    """A uniform composition never mixes, so under A + B -> P every particle
+    follows a_{n+1} = a_n - dt k a_n^2 (computed here in FP64); in FP32 to the
+    rounding of the FP32 recursion."""
+    mesh, params, parts, F = _frozen_case(3, 8)
+    k, a0, steps = 5.0, 0.8, 25
+    params.update(reaction=2, k_react=(k, 0.0, 0.0, 0.0), src=[])
+    n = len(parts["x"])
+    parts["psi"] = np.stack([np.full(n, a0), np.full(n, a0), np.zeros(n)])
+    _flush(f"[reaction_uniform] {precision} particles={n} steps={steps}")
+    sim = P.Sim(precision, "cuda:0")
+    cs = sim.add_case(mesh, params, n)
+    sim.bind()
+    sim.fields_upload(cs, F)
+    sim.upload(cs, parts)
+    sim.init()
+    sim.step(steps)
+    psi = sim.download(cs, n)["psi"]
+    a = a0
+    for _ in range(steps):
+        a = a - params["dt"] * k * a * a
+    np.testing.assert_allclose(psi[0], a, rtol=rtol, atol=0)
+    np.testing.assert_allclose(psi[1], a, rtol=rtol, atol=0)
+    np.testing.assert_allclose(psi[2], a0 - a, rtol=50 * rtol, atol=1e-5 if precision == "fp32" else 1e-15)
 
 
 def test_small_config_100_steps(P, oracle_mod):
