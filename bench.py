@@ -110,7 +110,8 @@ def run_gpu(cases, prec, steps, warmup, opts, repeats=1):
     ws = sim.bind()
     sim.set_options(sort_interval=opts.get("sort_interval", 0), block_size=opts.get("block_size", 256),
                     use_graph=opts.get("graph", False))
-    sim.set_solver(iterations=opts.get("cg_iters", 0), tail_rows=opts.get("tail_rows", 1024))
+    sim.set_solver(iterations=opts.get("cg_iters", 0), tail_rows=opts.get("tail_rows", 64))
+    sim.set_projection_solver(opts.get("projection", "direct"))
     for cs, c in zip(ids, cases):
         sim.upload(cs, c["particles"])
     sim.init()
@@ -147,7 +148,7 @@ def run_gpu(cases, prec, steps, warmup, opts, repeats=1):
         f"{k1_ms / max(k1_n, 1):.3f} ms/launch over {k1_n} launches")
     out = dict(ms=ms, k1_ms=k1_ms, k1_n=k1_n, n=n, stats=[], rows=[], nsn=[], counters={},
                windows_ms=[w[0] for w in windows],
-               solver=sim.solver_info(), tuned=tuned)
+               solver=sim.solver_info(), projection=sim.projection_info(), tuned=tuned)
     for cs in ids:
         nsn, sn = sim.case_info(cs)
         out["nsn"].append(nsn)
@@ -235,7 +236,9 @@ def main():
     ap.add_argument("--block-size", type=int, default=256)
     ap.add_argument("--repeats", type=int, default=3, help="timed windows of --steps steps; the median is reported")
     ap.add_argument("--cg-iters", type=int, default=0, help="row-parallel CG iterations per step (0: adaptive)")
-    ap.add_argument("--tail-rows", type=int, default=1024, help="multigrid levels at most this size run in one workgroup")
+    ap.add_argument("--tail-rows", type=int, default=64, help="multigrid levels at most this size run in one workgroup")
+    ap.add_argument("--projection", default="direct", choices=["direct", "pcg"],
+                    help="projection solve: Cholesky factor sweeps or multigrid PCG")
     ap.add_argument("--autotune", type=int, default=None,
                     help="run the autotuner before the timed steps (default: on for batch32)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -267,6 +270,7 @@ def main():
     opts["block_size"] = args.block_size
     opts["cg_iters"] = args.cg_iters
     opts["tail_rows"] = args.tail_rows
+    opts["projection"] = args.projection
     opts["autotune"] = bool(args.autotune if args.autotune is not None else args.workload == "batch32")
     n = sum(len(c["particles"]["x"]) for c in cases)
     ne = sum(c["mesh"].n_elems for c in cases)
@@ -288,8 +292,8 @@ def main():
     extra = {}
     if args.precision == "fp32" and not args.no_fp64_reference:
         # the same number of steps as the FP32 run (its autotuner trials included)
-        extra = g["tuned"]["steps"] if g["tuned"] else 0
-        r = run_gpu(cases, "fp64", args.steps, args.warmup + extra, opts, repeats=args.repeats)
+        more = g["tuned"]["steps"] if g["tuned"] else 0
+        r = run_gpu(cases, "fp64", args.steps, args.warmup + more, opts, repeats=args.repeats)
         extra["error_vs_fp64"] = error_vs_fp64(cases, g, r)
         extra["fp64"] = dict(value=n * args.steps / (r["ms"] * 1e-3), ms_per_step=r["ms"] / args.steps,
                              particle_kernel_ms=r["k1_ms"] / max(r["k1_n"], 1),
@@ -320,6 +324,8 @@ def main():
                    "sort_interval": opts["sort_interval"], "graph": opts["graph"],
                    "block_size": opts["block_size"], "tail_rows": opts["tail_rows"],
                    "cg_row_parallel_iterations": g["solver"][0], "cg_row_parallel_levels": g["solver"][1],
+                   "projection": g["projection"]["method"],
+                   "projection_factor_values": g["projection"]["factor_values"],
                    "autotuned": g["tuned"],
                    "accumulation": "f64 node sums, f64 Eulerian fields and CG"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -187,7 +187,7 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t bl
  * at once), then completes any system that needs more in one workgroup per
  * system. iterations = 0 (the default) adapts the count to what the previous
  * steps needed. Multigrid levels with more than tail_rows unknowns (default
- * 1024) are processed by the row-parallel phases, smaller ones by one
+ * 64) are processed by the row-parallel phases, smaller ones by one
  * workgroup per system. Results do not depend on either option beyond FP64
  * summation order. Errors: PDFMC_E_INVALID for iterations outside 0..100000
  * or tail_rows < 0. */
@@ -195,12 +195,30 @@ pdfmc_status pdfmc_set_solver(pdfmc_ctx* ctx, int32_t iterations, int32_t tail_r
 /* Current unrolled iteration count and number of row-parallel levels
  * (either pointer may be NULL). */
 pdfmc_status pdfmc_solver_info(pdfmc_ctx* ctx, int32_t* iterations, int32_t* large_levels);
+
+/* Projection solver (the mean-pressure projection, reading R-27). The
+ * projection matrix of a case is constant for the whole run, so by default
+ * pdfmc_add_case factors it once on the host (nested dissection by
+ * coordinate bisection, supernodal Cholesky with statistics node 0
+ * decoupled, FP64) and every projection is two sweeps over the factor on the
+ * GPU, followed by removing the mean: the same solution as the iterative
+ * solve, to rounding. PDFMC_PROJ_PCG solves it with the multigrid PCG of the
+ * relaxation instead. The factor is used only when every mode-2 case has one
+ * (a case whose factor has a supernode or reach above 2048 unknowns has
+ * none). Results do not depend on the choice beyond the solver tolerance.
+ * Errors: PDFMC_E_INVALID for another method. */
+typedef enum { PDFMC_PROJ_DIRECT = 0, PDFMC_PROJ_PCG = 1 } pdfmc_projection_method;
+pdfmc_status pdfmc_set_projection_solver(pdfmc_ctx* ctx, int32_t method);
+/* Method in effect (or that would be, before binding), height of the tallest
+ * supernode tree (-1: no factor) and FP64 values stored in all factors
+ * (any pointer may be NULL). */
+pdfmc_status pdfmc_projection_info(pdfmc_ctx* ctx, int32_t* method, int32_t* height, int64_t* factor_values);
 /* Autotuner of the batched step (what the step's cost depends on besides the
  * workload): times real steps of the bound workload for each trial setting
  * and keeps the fastest, by coordinate descent over
  *   particle-kernel block size   64, 128, 256
  *   sort interval                1, 2, 5, 10, 20 steps
- *   multigrid tail threshold     256, 1024, 4096 rows (pdfmc_set_solver)
+ *   multigrid tail threshold     0, 64, 256, 1024 rows (pdfmc_set_solver)
  * Each trial runs one untimed step, then max(steps_per_trial, a multiple of
  * the sort interval) timed steps. The trial steps advance the simulation
  * exactly like pdfmc_step (the results do not depend on the settings beyond

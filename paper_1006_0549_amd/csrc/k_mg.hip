@@ -36,7 +36,8 @@ namespace pdfmc {
 namespace {
 
 constexpr int MGB = 256;   // threads of the row-parallel phases
-constexpr int MGW = 512;   // threads of the one-workgroup-per-system kernels
+constexpr int MGT = 1024;  // threads of the one-workgroup-per-system tail
+constexpr int MGW = 512;   // threads of the one-workgroup-per-system completion
 constexpr int NVMAX = NER;
 
 // loads that bypass the non-coherent L1 (values written by atomics of the
@@ -103,7 +104,7 @@ __device__ inline void block_accumulate(const double (&val)[M], D dst)
     } else {
         // lanes t and t + 64 NV hold the same column: fold each wave group of
         // 64 NV lanes... simply stage everything in LDS and let NV * M lanes sum
-        __shared__ double sh[MGW * M];
+        __shared__ double sh[MGT * M];
 #pragma unroll
         for (int m = 0; m < M; ++m) sh[m * nt + t] = val[m];
         __syncthreads();
@@ -715,14 +716,14 @@ __global__ void __launch_bounds__(MGB) k_mg_pre(const MgJob* __restrict__ jobs, 
 #undef PRE
 }
 
-__global__ void __launch_bounds__(MGW) k_mg_tail(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
+__global__ void __launch_bounds__(MGT) k_mg_tail(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
                                                  const int32_t* __restrict__ st, int k)
 {
     const MgJob& J = jobs[blockIdx.x];
     if (st[2 * blockIdx.x] != 0 || J.n <= 0 || k >= J.maxit) return;
     // the pair loops use a multiple of NV lanes; the others only join the
     // barriers and reductions
-#define TAIL(NV) tail_body<NV>(J, hs[J.hier], k, (MGW / NV) * NV)
+#define TAIL(NV) tail_body<NV>(J, hs[J.hier], k, (MGT / NV) * NV)
     MG_DISPATCH(J, TAIL);
 #undef TAIL
 }

@@ -19,6 +19,7 @@
 
 #include "../../include/pdfmc.h"
 #include "pdfmc_amg.h"
+#include "pdfmc_chol.h"
 #include "pdfmc_kernels.h"
 #include "pdfmc_mesh.h"
 
@@ -59,6 +60,10 @@ struct Case {
     int amg_index = -1;           // position among the cases with hierarchies
     int64_t vec_off = 0;          // per-system solver vectors
     int64_t dinv_off = 0;         // inverse diagonals of both hierarchies
+    // nested-dissection Cholesky factor of the projection matrix (mode 2)
+    bool has_chol = false;
+    CholFactor chol;
+    int ds_case_index = -1;
 };
 
 void build_hier_ell(const AmgH& H, const EllH& ell0, HierEll& E)
@@ -237,7 +242,7 @@ struct pdfmc_ctx {
     int n_tab_dinv = 0;
     int maxbig_er = 0, maxbig_all = 0;
     // solver options: unrolled iterations (adaptive when mg_auto), small-level threshold
-    int mg_iters = 32, mg_auto = 1, tail_rows = 1024;
+    int mg_iters = 32, mg_auto = 1, tail_rows = 64;
     unsigned int* h_need = nullptr;   // pinned: iterations the last observed solve needed
     hipEvent_t need_ev = nullptr;
     bool need_pending = false;
@@ -266,6 +271,18 @@ struct pdfmc_ctx {
     int n_gal[AMG_MAXL] = {};
     int n_gal_p[AMG_MAXL] = {};
     int64_t gal_max[AMG_MAXL] = {}, gal_max_p[AMG_MAXL] = {};
+    // projection by the Cholesky factors: supernodes, their unknown indices
+    // and values, the factored cases, supernodes ordered by height
+    DsNode* d_ds_nodes = nullptr;
+    int32_t* d_ds_idx = nullptr;
+    double* d_ds_val = nullptr;
+    DsCase* d_ds_cases = nullptr;
+    int32_t* d_ds_list = nullptr;
+    int64_t DSN = 0, DSI = 0, DSV = 0;
+    int DSC = 0, ds_height = -1;
+    std::vector<int64_t> ds_hoff;      // list offsets per height
+    int proj_method = PDFMC_PROJ_DIRECT;   // requested
+    bool proj_direct = false;              // in effect (every mode-2 case factored)
     // live timing of the particle kernel: one event pair per launch
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -371,6 +388,11 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_amg_d, c->AMG_D);
     k.take(c->d_amg, 2 * (size_t)std::max(c->n_amg, 1));
     k.take(c->d_gal, 2 * (size_t)AMG_MAXL * std::max(c->n_amg, 1));
+    k.take(c->d_ds_nodes, c->DSN);
+    k.take(c->d_ds_idx, c->DSI);
+    k.take(c->d_ds_val, c->DSV);
+    k.take(c->d_ds_cases, c->DSC);
+    k.take(c->d_ds_list, c->DSN);
 }
 
 void compute_offsets(pdfmc_ctx* c)
@@ -410,6 +432,17 @@ void compute_offsets(pdfmc_ctx* c)
         }
     }
     c->AMG_I = ni; c->AMG_D = nd; c->n_amg = na; c->amg_levels = maxlev;
+    int64_t dsn = 0, dsi = 0, dsv = 0;
+    int dsc = 0, dsh = -1;
+    for (auto& cs : c->cases) {
+        if (!cs.has_chol) { cs.ds_case_index = -1; continue; }
+        cs.ds_case_index = dsc++;
+        dsn += (int64_t)cs.chol.nodes.size();
+        dsi += cs.chol.n_idx;
+        dsv += cs.chol.n_val;
+        dsh = std::max(dsh, cs.chol.height);
+    }
+    c->DSN = dsn; c->DSI = dsi; c->DSV = dsv; c->DSC = dsc; c->ds_height = dsh;
     c->MGV = nv; c->MGD = ndv; c->MGT = nt; c->MGTD = ntd;
     c->NP = NP; c->PSI = PSI; c->CM = CM; c->CS = CS; c->NE = NE; c->NN = NN; c->NBC = NBC; c->NELL = NELL;
     c->ntiles = (int)(NP / TILE);
@@ -659,9 +692,37 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
     return PDFMC_OK;
 }
 
-// The Eulerian solves of every case: c->mg_iters PCG iterations as phase
-// kernels over all systems, then k_mg_finish for any system that needs more.
-pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
+// The projection of every case by its Cholesky factor: mean-free right-hand
+// side, forward sweep by increasing supernode height, backward sweep by
+// decreasing height, mean-free solution.
+pdfmc_status enqueue_direct_projection(pdfmc_ctx* c)
+{
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_ds_prep, dim3(c->DSC), dim3(1024), 0, st, (const DsCase*)c->d_ds_cases,
+                       (const double*)c->d_pb, c->d_phi);
+    for (int h = 0; h <= c->ds_height; ++h) {
+        const int64_t n = c->ds_hoff[h + 1] - c->ds_hoff[h];
+        if (n > 0)
+            hipLaunchKernelGGL(k_ds_forward, dim3((unsigned)n), dim3(256), 0, st, (const DsNode*)c->d_ds_nodes,
+                               (const int32_t*)(c->d_ds_list + c->ds_hoff[h]), (const int32_t*)c->d_ds_idx,
+                               (const double*)c->d_ds_val, c->d_phi);
+    }
+    for (int h = c->ds_height; h >= 0; --h) {
+        const int64_t n = c->ds_hoff[h + 1] - c->ds_hoff[h];
+        if (n > 0)
+            hipLaunchKernelGGL(k_ds_backward, dim3((unsigned)n), dim3(256), 0, st, (const DsNode*)c->d_ds_nodes,
+                               (const int32_t*)(c->d_ds_list + c->ds_hoff[h]), (const int32_t*)c->d_ds_idx,
+                               (const double*)c->d_ds_val, c->d_phi);
+    }
+    hipLaunchKernelGGL(k_ds_post, dim3(c->DSC), dim3(1024), 0, st, (const DsCase*)c->d_ds_cases, c->d_phi);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
+// The multigrid-PCG solves: the relaxation systems of every case, and the
+// projection systems when `project` (c->mg_iters PCG iterations as phase
+// kernels over all systems, then k_mg_finish for any system that needs more).
+pdfmc_status enqueue_mg(pdfmc_ctx* c, bool project)
 {
     const int nj = c->n_jobs_er + (project ? c->n_jobs_p : 0);
     if (nj == 0) return PDFMC_OK;
@@ -689,7 +750,7 @@ pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
             hipLaunchKernelGGL(k_mg_pre, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
             hipLaunchKernelGGL(k_mg_res, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
         }
-        hipLaunchKernelGGL(k_mg_tail, dim3(nj), dim3(512), 0, st, J, H, S, k);
+        hipLaunchKernelGGL(k_mg_tail, dim3(nj), dim3(1024), 0, st, J, H, S, k);
         for (int l = maxbig - 1; l >= 0; --l) {
             const int4* Tl = c->d_mg_tab + c->tabl[l].off;
             const dim3 gl(cnt(c->tabl[l]));
@@ -708,6 +769,17 @@ pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
         TRY(vcycle(k));
     }
     hipLaunchKernelGGL(k_mg_finish, dim3(nj), dim3(512), 0, st, J, H, c->mg_iters);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
+// The Eulerian solves of every case: the relaxation (multigrid PCG) and, when
+// `project`, the projection (Cholesky sweeps, or multigrid PCG together with
+// the relaxation).
+pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
+{
+    TRY(enqueue_mg(c, project && !c->proj_direct));
+    if (project && c->proj_direct && c->DSC > 0) TRY(enqueue_direct_projection(c));
     LAUNCHCHK(c);
     return PDFMC_OK;
 }
@@ -918,6 +990,15 @@ pdfmc_status pdfmc_add_case(pdfmc_ctx* c, const pdfmc_mesh_desc* mesh, const pdf
             for (size_t l = 0; l < cs.amg[h].lv.size(); ++l) cs.rho[h][l] = spectral_radius(cs.amg[h].lv[l].A);
             build_hier_ell(cs.amg[h], cs.ell0, cs.he[h]);
         }
+        // the projection matrix is constant: factor it once (statistics
+        // node 0 decoupled); without a factor the projection runs on the
+        // multigrid PCG like the relaxation
+        std::vector<double> sx(cs.m.nsn), sy(cs.m.nsn);
+        for (int sn = 0; sn < cs.m.nsn; ++sn) { sx[sn] = cs.m.x[cs.m.rep[sn]]; sy[sn] = cs.m.y[cs.m.rep[sn]]; }
+        std::string ferr;
+        cs.has_chol = chol_factor(K, sx, sy, 0, 64, cs.chol, ferr) && cs.chol.max_s <= DS_MAXS &&
+                      cs.chol.max_m <= DS_MAXS;
+        if (!cs.has_chol) cs.chol = CholFactor();
     }
     c->cases.push_back(std::move(cs));
     *case_id = (int32_t)c->cases.size() - 1;
@@ -1124,8 +1205,47 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     }
     if (!c->need_ev) HIPCHK(c, hipEventCreateWithFlags(&c->need_ev, hipEventDisableTiming));
     c->need_pending = false;
-    // solver systems: 5 relaxation systems per mode-2 case, then one
-    // projection system per mode-2 case
+    // projection factors: supernodes with global unknown indices, listed by height
+    c->ds_hoff.assign(1, 0);
+    if (c->DSC > 0) {
+        std::vector<DsNode> nodes;
+        std::vector<int32_t> idx;
+        std::vector<double> val;
+        std::vector<DsCase> dcs;
+        idx.reserve(c->DSI);
+        val.reserve(c->DSV);
+        std::vector<std::vector<int32_t>> byh(c->ds_height + 1);
+        for (auto& cs : c->cases) {
+            if (!cs.has_chol) continue;
+            dcs.push_back(DsCase{cs.noff, cs.m.nsn, cs.chol.pin, 0});
+            for (const CholNode& S : cs.chol.nodes) {
+                DsNode d;
+                d.s = (int32_t)S.vars.size();
+                d.m = (int32_t)S.str.size();
+                d.idx = (int64_t)idx.size();
+                d.val = (int64_t)val.size();
+                for (int v : S.vars) idx.push_back(cs.noff + v);
+                for (int u : S.str) idx.push_back(cs.noff + u);
+                val.insert(val.end(), S.linv.begin(), S.linv.end());
+                val.insert(val.end(), S.l21.begin(), S.l21.end());
+                byh[S.height].push_back((int32_t)nodes.size());
+                nodes.push_back(d);
+            }
+        }
+        std::vector<int32_t> list;
+        for (auto& v : byh) {
+            list.insert(list.end(), v.begin(), v.end());
+            c->ds_hoff.push_back((int64_t)list.size());
+        }
+        TRY(h2d(c, c->d_ds_nodes, nodes));
+        TRY(h2d(c, c->d_ds_idx, idx));
+        TRY(h2d(c, c->d_ds_val, val));
+        TRY(h2d(c, c->d_ds_cases, dcs));
+        TRY(h2d(c, c->d_ds_list, list));
+    }
+    c->proj_direct = c->proj_method == PDFMC_PROJ_DIRECT && c->n_amg > 0 && c->DSC == c->n_amg;
+    // solver systems: one five-column relaxation system per mode-2 case,
+    // then one projection system per mode-2 case
     c->h_amgdev = amgdev;
     TRY(build_mg_jobs(c));
     // state that starts at zero
@@ -1477,7 +1597,35 @@ pdfmc_status pdfmc_solver_info(pdfmc_ctx* c, int32_t* iterations, int32_t* large
 {
     if (!c) return PDFMC_E_INVALID;
     if (iterations) *iterations = c->mg_iters;
-    if (large_levels) *large_levels = c->maxbig_all;
+    if (large_levels) *large_levels = c->proj_direct ? c->maxbig_er : c->maxbig_all;
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_set_projection_solver(pdfmc_ctx* c, int32_t method)
+{
+    if (!c) return PDFMC_E_INVALID;
+    if (method != PDFMC_PROJ_DIRECT && method != PDFMC_PROJ_PCG)
+        return fail(c, PDFMC_E_INVALID, "set_projection_solver: method must be PDFMC_PROJ_DIRECT or PDFMC_PROJ_PCG");
+    c->proj_method = method;
+    if (c->bound) {
+        const bool direct = method == PDFMC_PROJ_DIRECT && c->n_amg > 0 && c->DSC == c->n_amg;
+        if (direct != c->proj_direct) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            drop_graphs(c);
+            c->proj_direct = direct;
+        }
+    }
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_projection_info(pdfmc_ctx* c, int32_t* method, int32_t* height, int64_t* factor_values)
+{
+    if (!c) return PDFMC_E_INVALID;
+    const bool direct = c->bound ? c->proj_direct
+                                 : (c->proj_method == PDFMC_PROJ_DIRECT && c->n_amg > 0 && c->DSC == c->n_amg);
+    if (method) *method = direct ? PDFMC_PROJ_DIRECT : PDFMC_PROJ_PCG;
+    if (height) *height = c->ds_height;
+    if (factor_values) *factor_values = c->DSV;
     return PDFMC_OK;
 }
 
@@ -1565,7 +1713,7 @@ pdfmc_status pdfmc_autotune(pdfmc_ctx* c, int32_t steps_per_trial, pdfmc_tune_re
     // coordinate descent: block size, then sort interval, then the small-level threshold
     const int blocks[] = {64, 128, 256};
     const int sorts[] = {1, 2, 5, 10, 20};
-    const int tails[] = {256, 1024, 4096};
+    const int tails[] = {0, 64, 256, 1024};
     for (int b : blocks) {
         double per;
         TRY(trial(b, best_s, best_t, std::max(steps_per_trial, best_s), per));

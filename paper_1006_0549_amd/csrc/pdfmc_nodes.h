@@ -114,4 +114,16 @@ struct MgJob {
     unsigned int* need;            // largest iteration count of the step (all systems)
 };
 
+// One supernode of a case's projection factor (nested-dissection Cholesky of
+// the constant projection matrix), with global unknown indices.
+constexpr int DS_MAXS = 2048;      // largest supernode and reach the sweeps stage in LDS
+struct DsNode {
+    int32_t s, m;                  // own unknowns, later unknowns reached
+    int64_t idx;                   // own unknowns at idx[idx .. idx+s), later ones at [idx+s .. idx+s+m)
+    int64_t val;                   // L11^-1 (s x s, row-major, lower) at val, then L21 (m x s, row-major)
+};
+struct DsCase {
+    int32_t noff, n, pin, pad;     // first statistics node, unknowns, decoupled unknown (case-local)
+};
+
 }  // namespace pdfmc

@@ -68,7 +68,8 @@ EXPORTS = ["pdfmc_create", "pdfmc_destroy", "pdfmc_last_error", "pdfmc_add_case"
            "pdfmc_pressure_download", "pdfmc_init", "pdfmc_rebin", "pdfmc_step", "pdfmc_set_step_index",
            "pdfmc_stats_readback", "pdfmc_node_sums", "pdfmc_cell_means", "pdfmc_counters",
            "pdfmc_set_options", "pdfmc_sort", "pdfmc_synchronize", "pdfmc_timing", "pdfmc_timing_read",
-           "pdfmc_draw_gaussians", "pdfmc_set_solver", "pdfmc_solver_info", "pdfmc_autotune"]
+           "pdfmc_draw_gaussians", "pdfmc_set_solver", "pdfmc_solver_info", "pdfmc_autotune",
+           "pdfmc_set_projection_solver", "pdfmc_projection_info"]
 
 
 def lib():
@@ -105,6 +106,8 @@ def lib():
         L.pdfmc_set_solver.argtypes = [vp, C.c_int32, C.c_int32]
         L.pdfmc_autotune.argtypes = [vp, C.c_int32, C.POINTER(_TuneResult)]
         L.pdfmc_solver_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.pdfmc_set_projection_solver.argtypes = [vp, C.c_int32]
+        L.pdfmc_projection_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.pdfmc_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.pdfmc_draw_gaussians.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, C.c_int64, vp]
         for f in EXPORTS:
@@ -213,7 +216,7 @@ class Sim:
     def set_options(self, sort_interval=0, block_size=256, use_graph=False):
         self._check(self._L.pdfmc_set_options(self._h, sort_interval, block_size, int(bool(use_graph))), "set_options")
 
-    def set_solver(self, iterations=0, tail_rows=1024):
+    def set_solver(self, iterations=0, tail_rows=64):
         """iterations = 0: adaptive number of row-parallel CG iterations."""
         self._check(self._L.pdfmc_set_solver(self._h, int(iterations), int(tail_rows)), "set_solver")
 
@@ -229,6 +232,21 @@ class Sim:
         it, lv = C.c_int32(), C.c_int32()
         self._check(self._L.pdfmc_solver_info(self._h, C.byref(it), C.byref(lv)), "solver_info")
         return it.value, lv.value
+
+    PROJECTION_METHODS = {"direct": 0, "pcg": 1}
+
+    def set_projection_solver(self, method="direct"):
+        """"direct": sweeps over the Cholesky factor of the constant projection
+        matrix; "pcg": the multigrid PCG of the relaxation."""
+        if method not in self.PROJECTION_METHODS:
+            raise ValueError(f"projection method must be one of {list(self.PROJECTION_METHODS)}")
+        self._check(self._L.pdfmc_set_projection_solver(self._h, self.PROJECTION_METHODS[method]),
+                    "set_projection_solver")
+
+    def projection_info(self):
+        m, h, v = C.c_int32(), C.c_int32(), C.c_int64()
+        self._check(self._L.pdfmc_projection_info(self._h, C.byref(m), C.byref(h), C.byref(v)), "projection_info")
+        return dict(method="direct" if m.value == 0 else "pcg", height=h.value, factor_values=v.value)
 
     # ------------------------------------------------------------ particles and fields
     def upload(self, cs, parts):

@@ -110,3 +110,27 @@ def test_workspace_grows_with_capacity(pkg):
     b = _sim(pkg)
     b.add_case(mesh, W.default_params(), 100000)
     assert b.workspace_bytes() > a.workspace_bytes() + 2 * 99000 * 8 * 7
+
+
+def test_projection_factor_host(pkg):
+    """add_case factors the projection matrix of a mode-2 case on the host:
+    the direct projection is the default, with a supernode tree of several
+    levels and O(n log n) stored values; the method can be switched, and
+    other methods are rejected."""
+    cfg = W.config_channel(ppe=1, n_half=16, nx=40)
+    s = _sim(pkg)
+    info0 = s.projection_info()
+    assert info0["factor_values"] == 0 and info0["height"] == -1
+    s.add_case(cfg["mesh"], dict(cfg["params"], mode=2), 10)
+    info = s.projection_info()
+    assert info["method"] == "direct"
+    assert info["height"] >= 3
+    nsn, _ = s.case_info(0)
+    assert nsn < info["factor_values"] < 200 * nsn
+    s.set_projection_solver("pcg")
+    assert s.projection_info()["method"] == "pcg"
+    s.set_projection_solver("direct")
+    with pytest.raises(ValueError):
+        s.set_projection_solver("lu")
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*method"):
+        s._check(s._L.pdfmc_set_projection_solver(s._h, 7), "set_projection_solver")
