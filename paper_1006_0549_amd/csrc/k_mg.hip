@@ -164,14 +164,16 @@ __device__ inline Scal pb_scalars(const MgJob& J, int k, bool first, int v)
     return s;
 }
 
-// sum_k A(k, i) get(col(k, i)); the width is a multiple of 4 and the loads
-// of a group of four entries are issued together
+// sum_k A(k, i) get(col(k, i)) over the row's entries rounded up to a
+// multiple of 4 (padding entries are zero); the loads of a group of four
+// entries are issued together
 template <typename F>
 __device__ inline double ell_row_f(const EllDev& A, F get, int i)
 {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     const int64_t n = A.n;
-    for (int k = 0; k < A.w; k += 4) {
+    const int w = A.len ? min((A.len[i] + 3) & ~3, A.w) : A.w;
+    for (int k = 0; k < w; k += 4) {
         const int64_t a = (int64_t)k * n + i;
         const int c0 = A.col[a], c1 = A.col[a + n], c2 = A.col[a + 2 * n], c3 = A.col[a + 3 * n];
         const double v0 = A.val[a], v1 = A.val[a + n], v2 = A.val[a + 2 * n], v3 = A.val[a + 3 * n];

@@ -7,7 +7,8 @@
 // slots with atomics); results do not depend on it beyond the summation
 // order of the FP64 node sums.
 //   k_sort_hist     per-element counts (one atomic per run of equal element)
-//   k_sort_scan     exclusive scan of the counts, one workgroup
+//   k_sort_scan_*   exclusive scan of the counts (blocks, block totals), and
+//   k_sort_cursor   the per-case slot cursors
 //   k_sort_scatter  move every particle field to the other buffer set
 #include "pdfmc_dev.h"
 #include "pdfmc_sort.h"
@@ -43,37 +44,66 @@ __global__ void k_sort_hist(SortArgs A)
     if (head && key >= 0) atomicAdd(A.count + key, len);
 }
 
-// exclusive scan of count[0..ne) into offset, then rebased per case so that
-// offset[e] = poff(case) + sum of counts of the case's earlier elements;
-// cursor[e] is reset to offset[e].
-__global__ void __launch_bounds__(1024) k_sort_scan(SortArgs A)
+// Exclusive scan of count[0..ne) in three passes: a scan inside each block of
+// SCAN_B elements with its total, a scan of the block totals, and the
+// cursors: cursor[e] = poff(case) + sum of the counts of the case's earlier
+// elements.
+
+__device__ inline int64_t block_excl_scan(int64_t v, int64_t& total)
 {
-    __shared__ int64_t part[1024];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t chunk = (A.ne + nt - 1) / nt;
-    const int64_t lo = tid * chunk, hi = lo + chunk < A.ne ? lo + chunk : A.ne;
-    int64_t s = 0;
-    for (int64_t e = lo; e < hi; ++e) s += A.count[e];
-    part[tid] = s;
+    // SCAN_B threads: wave scans by shuffles, then the wave totals
+    __shared__ int64_t wsum[SCAN_B / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    for (int d = 1; d < nt; d <<= 1) {
-        int64_t v = tid >= d ? part[tid - d] : 0;
+    int64_t before = 0;
+    total = 0;
+    for (int k = 0; k < SCAN_B / 64; ++k) {
+        if (k < w) before += wsum[k];
+        total += wsum[k];
+    }
+    return before + x - v;
+}
+
+__global__ void __launch_bounds__(SCAN_B) k_sort_scan_blocks(SortArgs A)
+{
+    const int64_t e = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
+    const int64_t v = e < A.ne ? A.count[e] : 0;
+    int64_t total;
+    const int64_t x = block_excl_scan(v, total);
+    if (e < A.ne) A.scan[e] = x;
+    if (threadIdx.x == 0) A.bsum[blockIdx.x] = total;
+}
+
+// one workgroup: exclusive scan of the nb block totals, SCAN_B at a time
+__global__ void __launch_bounds__(SCAN_B) k_sort_scan_totals(SortArgs A, int nb)
+{
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += SCAN_B) {
+        const int b = b0 + threadIdx.x;
+        const int64_t v = b < nb ? A.bsum[b] : 0;
+        int64_t total;
+        const int64_t x = block_excl_scan(v, total);
         __syncthreads();
-        part[tid] += v;
+        if (b < nb) A.bsum[b] = carry + x;
+        carry += total;
         __syncthreads();
     }
-    int64_t run = part[tid] - s;
-    for (int64_t e = lo; e < hi; ++e) {
-        A.scan[e] = run;
-        run += A.count[e];
-    }
-    __syncthreads();
-    __threadfence_block();
-    for (int64_t e = lo; e < hi; ++e) {
-        const CaseDev& C = A.cases[A.elem_case[e]];
-        const int64_t off = A.scan[e] - A.scan[C.eoff] + C.poff;
-        A.cursor[e] = off;
-    }
+}
+
+__global__ void __launch_bounds__(SCAN_B) k_sort_cursor(SortArgs A)
+{
+    const int64_t e = (int64_t)blockIdx.x * SCAN_B + threadIdx.x;
+    if (e >= A.ne) return;
+    const CaseDev& C = A.cases[A.elem_case[e]];
+    const int64_t here = A.scan[e] + A.bsum[e / SCAN_B];
+    const int64_t first = A.scan[C.eoff] + A.bsum[C.eoff / SCAN_B];
+    A.cursor[e] = here - first + C.poff;
 }
 
 template <typename R>

@@ -254,7 +254,7 @@ struct pdfmc_ctx {
     unsigned long long* d_counters = nullptr;
     uint32_t* d_step = nullptr;
     int32_t* d_sort_count = nullptr;
-    int64_t *d_sort_scan = nullptr, *d_sort_cursor = nullptr;
+    int64_t *d_sort_scan = nullptr, *d_sort_bsum = nullptr, *d_sort_cursor = nullptr;
     // options
     int sort_interval = 0, block = 256, use_graph = 0;
     int steps_since_sort = 0;
@@ -383,6 +383,7 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_step, 1);
     k.take(c->d_sort_count, c->NE);
     k.take(c->d_sort_scan, c->NE);
+    k.take(c->d_sort_bsum, c->NE / SCAN_B + 1);
     k.take(c->d_sort_cursor, c->NE);
     k.take(c->d_amg_i, c->AMG_I);
     k.take(c->d_amg_d, c->AMG_D);
@@ -875,11 +876,14 @@ pdfmc_status enqueue_sort(pdfmc_ctx* c)
     SortArgs S{};
     S.cases = c->d_cases; S.tile_case = c->d_tile_case; S.elem_case = c->d_elem_case;
     S.ntiles = c->ntiles; S.ne = c->NE; S.elem = c->part[c->cur].elem;
-    S.count = c->d_sort_count; S.scan = c->d_sort_scan; S.cursor = c->d_sort_cursor;
+    S.count = c->d_sort_count; S.scan = c->d_sort_scan; S.bsum = c->d_sort_bsum; S.cursor = c->d_sort_cursor;
     TRY(enqueue_fill_i(c, c->d_sort_count, c->NE));
     const int64_t threads = (int64_t)c->ntiles * TILE;
     hipLaunchKernelGGL(k_sort_hist, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, c->stream, S);
+    const int nb = (int)nblk(c->NE, SCAN_B);
+    hipLaunchKernelGGL(k_sort_scan_blocks, dim3(nb), dim3(SCAN_B), 0, c->stream, S);
+    hipLaunchKernelGGL(k_sort_scan_totals, dim3(1), dim3(SCAN_B), 0, c->stream, S, nb);
+    hipLaunchKernelGGL(k_sort_cursor, dim3(nb), dim3(SCAN_B), 0, c->stream, S);
     LAUNCHCHK(c);
     PartBufs& A = c->part[c->cur];
     PartBufs& B = c->part[1 - c->cur];
@@ -1168,12 +1172,12 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                     chebyshev2(cs.rho[h][l], D.sa[l], D.se[l], D.sc[l]);
                     if (l == 0)
                         D.A[0] = EllDev{cs.m.nsn, cs.ell0.w, c->d_ell_col + cs.ell_off,
-                                        (h == 0 ? c->d_er_val : c->d_pk_val) + cs.ell_off};
+                                        (h == 0 ? c->d_er_val : c->d_pk_val) + cs.ell_off, c->d_ell_len + cs.noff};
                     else
-                        D.A[l] = EllDev{E.A[l].n, E.A[l].w, c->d_amg_i + o.Acol[l], c->d_amg_d + o.Aval[l]};
+                        D.A[l] = EllDev{E.A[l].n, E.A[l].w, c->d_amg_i + o.Acol[l], c->d_amg_d + o.Aval[l], nullptr};
                     if (l + 1 < D.nlev) {
-                        D.P[l] = EllDev{E.P[l].n, E.P[l].w, c->d_amg_i + o.Pcol[l], c->d_amg_d + o.Pval[l]};
-                        D.R[l] = EllDev{E.R[l].n, E.R[l].w, c->d_amg_i + o.Rcol[l], c->d_amg_d + o.Rval[l]};
+                        D.P[l] = EllDev{E.P[l].n, E.P[l].w, c->d_amg_i + o.Pcol[l], c->d_amg_d + o.Pval[l], nullptr};
+                        D.R[l] = EllDev{E.R[l].n, E.R[l].w, c->d_amg_i + o.Rcol[l], c->d_amg_d + o.Rval[l], nullptr};
                     }
                 }
                 // Galerkin jobs: level l -> l+1

@@ -43,7 +43,9 @@ __global__ void k_ds_forward(const DsNode* nodes, const int32_t* list, const int
 __global__ void k_ds_backward(const DsNode* nodes, const int32_t* list, const int32_t* idx, const double* val, double* x);
 __global__ void k_ds_post(const DsCase* cs, double* x);
 __global__ void k_sort_hist(SortArgs A);
-__global__ void k_sort_scan(SortArgs A);
+__global__ void k_sort_scan_blocks(SortArgs A);
+__global__ void k_sort_scan_totals(SortArgs A, int nb);
+__global__ void k_sort_cursor(SortArgs A);
 template <typename R> __global__ void k_sort_scatter(SortArgs A, Particles<R> src, Particles<R> dst);
 
 }  // namespace pdfmc

@@ -52,6 +52,7 @@ struct EllDev {
     int32_t n, w;
     const int32_t* col;
     const double* val;
+    const int32_t* len;            // entries of each row (padding after them), or null: w for every row
 };
 
 // One multigrid hierarchy; level 0 is the fine system of one case. Levels

@@ -11,8 +11,11 @@ struct SortArgs {
     int32_t ntiles, ne;
     const int32_t* elem;     // keys of the source buffer set (hist)
     int32_t* count;          // [ne]
-    int64_t* scan;           // [ne]
+    int64_t* scan;           // [ne] exclusive scan of the counts inside each block of SCAN_B elements
+    int64_t* bsum;           // [ne / SCAN_B + 1] block totals, then their exclusive scan
     int64_t* cursor;         // [ne]
 };
+
+constexpr int SCAN_B = 1024;     // elements per block of the count scan
 
 }  // namespace pdfmc

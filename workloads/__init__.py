@@ -205,11 +205,16 @@ def channel(n_half: int = 48, nx: int = 105, first: float = 1e-3, Lx: float = 2 
     return Mesh(f"channel{tri.shape[0]}", xy, tri, tag, bcs)
 
 
-def cavity(n_half: int = 112, first: float = 1e-3, lid: float = 1.0, seed_key=(3, 0, 0)) -> Mesh:
+def cavity(n_half: int = 112, first: float = 1e-3, lid: float = 1.0, seed_key=(3, 0, 0),
+           regularized: bool = True) -> Mesh:
     """Unit-square cavity with walls everywhere, the top one moving at `lid`.
     Tensor levels graded geometrically from every wall (n_half levels to the
     middle), interior points jittered +-0.2 of the local spacing. Delaunay.
-    Boundaries: 0 bottom, 1 top (lid), 2 left, 3 right."""
+    Boundaries: 0 bottom, 1 top (lid), 2 left, 3 right. With `regularized`,
+    every lid edge carries a wall of its own moving at lid * 16 x^2 (1-x)^2
+    (x at the edge midpoint): the lid speed then falls to zero at the two top
+    corners instead of jumping there, which removes the corner singularity of
+    the mean pressure."""
     rng = rng_for(*seed_key)
     half = _geometric_levels(first, n_half, 0.5)
     lev = np.concatenate([half, 1.0 - half[-2::-1]])
@@ -229,6 +234,12 @@ def cavity(n_half: int = 112, first: float = 1e-3, lid: float = 1.0, seed_key=(3
     tag = _tag_edges(xy, tri, _rect_classifier(0.0, 1.0, 0.0, 1.0, (0, 1, 2, 3)))
     bcs = [dict(type=BC_WALL, u_wall=(0.0, 0.0, 0.0)), dict(type=BC_WALL, u_wall=(lid, 0.0, 0.0)),
            dict(type=BC_WALL, u_wall=(0.0, 0.0, 0.0)), dict(type=BC_WALL, u_wall=(0.0, 0.0, 0.0))]
+    if regularized:
+        va, vb = tri[:, [1, 2, 0]], tri[:, [2, 0, 1]]
+        for e, k in np.argwhere(tag == 1):
+            xm = 0.5 * (xy[va[e, k], 0] + xy[vb[e, k], 0])
+            tag[e, k] = len(bcs)
+            bcs.append(dict(type=BC_WALL, u_wall=(lid * 16.0 * xm * xm * (1.0 - xm) ** 2, 0.0, 0.0)))
     return Mesh(f"cavity{tri.shape[0]}", xy, tri, tag, bcs)
 
 
