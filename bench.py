@@ -295,6 +295,15 @@ def main():
         more = g["tuned"]["steps"] if g["tuned"] else 0
         r = run_gpu(cases, "fp64", args.steps, args.warmup + more, opts, repeats=args.repeats)
         extra["error_vs_fp64"] = error_vs_fp64(cases, g, r)
+        # the statistical noise of the same comparison: FP64 against FP64 on
+        # another random-number stream (the statistics are one-step particle
+        # estimates, so two runs differ by their sampling noise)
+        alt = [dict(c, params=dict(c["params"], stream=int(c["params"]["stream"]) + 977)) for c in cases]
+        r2 = run_gpu(alt, "fp64", args.steps, args.warmup + more, opts, repeats=1)
+        noise = error_vs_fp64(cases, r2, r)
+        extra["fp64_vs_fp64_other_stream"] = noise
+        extra["error_over_noise"] = {k: extra["error_vs_fp64"][k] / max(v, 1e-300) for k, v in noise.items()
+                                     if k in extra["error_vs_fp64"]}
         extra["fp64"] = dict(value=n * args.steps / (r["ms"] * 1e-3), ms_per_step=r["ms"] / args.steps,
                              particle_kernel_ms=r["k1_ms"] / max(r["k1_n"], 1),
                              fp32_speedup=r["ms"] / g["ms"])

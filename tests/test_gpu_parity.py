@@ -414,3 +414,32 @@ def test_autotune_settings_and_invariance(P):
     assert np.all(np.isfinite(st2))
     cnt = a.counters(a2)
     assert cnt["nan"] == 0 and cnt["cg_fail"] == 0
+
+
+def test_row_parallel_phases_match_one_workgroup_completion(P):
+    """The row-parallel phases (every level but the coarsest, tail_rows 0)
+    apply the same preconditioner as the one-workgroup completion: the
+    relaxation needs the same iterations either way, up to rounding, and
+    reaches the same fields."""
+    mesh = W.channel(n_half=24, nx=60, seed_key=(1, 2, 0))
+    params = W.default_params(mode=2, dt=5e-4, nu=1.0 / 1080.0, n_scalars=0, dpdx=(-1.0, 0.0),
+                              cg_rtol=1e-12, cg_maxit=20000, stream=1)
+    parts = W.init_particles(mesh, 10, 0, W.rng_for(1, 2, 1), u_std=1.0)
+    n = len(parts["x"])
+    _flush(f"[phases_vs_completion] channel {mesh.n_elems} triangles, {n} particles")
+    out = []
+    for iters in (60, 1):
+        sim = P.Sim("fp64", "cuda:0")
+        cs = sim.add_case(mesh, params, n)
+        sim.bind()
+        sim.set_solver(iterations=iters, tail_rows=0)
+        sim.upload(cs, parts)
+        sim.init()
+        sim.step(3)
+        out.append((sim.counters(cs), sim.solver_info(), sim.fields(cs)))
+    (ca, ia, Fa), (cb, ib, Fb) = out
+    assert ia[1] >= 3, ia            # three levels ran as row-parallel phases
+    assert ca["cg_fail"] == 0 and cb["cg_fail"] == 0
+    assert abs(ca["cg_iters_er"] - cb["cg_iters_er"]) <= 5 * 4, (ca["cg_iters_er"], cb["cg_iters_er"])
+    sc = np.maximum(np.abs(Fb).max(0), 1e-12)
+    assert np.max(np.abs(Fa - Fb) / sc) <= 1e-8
