@@ -407,6 +407,11 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         else if (q >= 11 + ns && q < 11 + 2 * ns) ia = ib = 8 + (q - 11 - ns);
         else if (q == 11 + 2 * ns) sq = true;
         const R* wave_rec = s_rec + wid * 64 * NREC;
+        // branch-free term: (w lambda_k) * (w lambda_k | rec[ia] | 1) * (rec[ib] | 1),
+        // the same products in the same order as above; every lane reads its
+        // four record words at once
+        const int ia0 = ia >= 0 ? ia : 0, ib0 = ib >= 0 ? ib : 0;
+        const bool has_a = ia >= 0, has_b = ib >= 0;
         unsigned long long hm = heads;
         while (hm) {
             const int s0 = __ffsll((long long)hm) - 1;
@@ -415,13 +420,14 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             const int ks = __shfl(key, s0);
             if (ks < 0) continue;
             double acc = 0.0;
+#pragma unroll 2
             for (int pp = s0; pp < s1; ++pp) {
                 const R* rq = wave_rec + pp * NREC;
-                const double wn = (double)rq[3] * (double)rq[k];
-                double t = sq ? wn * wn : wn;
-                if (ia >= 0) t = t * (double)rq[ia];
-                if (ib >= 0) t = t * (double)rq[ib];
-                acc += t;
+                const R rw = rq[3], rl = rq[k], ra = rq[ia0], rb = rq[ib0];
+                const double wn = (double)rw * (double)rl;
+                const double fa = sq ? wn : (has_a ? (double)ra : 1.0);
+                const double fb = has_b ? (double)rb : 1.0;
+                acc += (wn * fa) * fb;
             }
             int slot = 0;
             if (lane == 0) slot = lds_slot(s_key, ks);
