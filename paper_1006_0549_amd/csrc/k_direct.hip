@@ -14,7 +14,6 @@ namespace pdfmc {
 
 namespace {
 
-constexpr int DSB = 256;
 
 __device__ inline double wave_sum(double a)
 {
@@ -59,7 +58,11 @@ __global__ void __launch_bounds__(1024) k_ds_post(const DsCase* __restrict__ cs,
     for (int i = threadIdx.x; i < C.n; i += blockDim.x) x[C.noff + i] -= mean;
 }
 
-// forward sweep over the supernodes list[0 .. gridDim.x) (one height)
+// forward sweep over the supernodes list[0 .. gridDim.x) (one height);
+// DSB threads per supernode (more for the few large separators near the
+// root), LDS for CAP unknowns (small for the many leaves, so that more of
+// them share a CU)
+template <int DSB, int CAP>
 __global__ void __launch_bounds__(DSB) k_ds_forward(const DsNode* __restrict__ nodes, const int32_t* __restrict__ list,
                                                     const int32_t* __restrict__ idx, const double* __restrict__ val,
                                                     double* __restrict__ x)
@@ -69,7 +72,7 @@ __global__ void __launch_bounds__(DSB) k_ds_forward(const DsNode* __restrict__ n
     const int32_t* vi = idx + N.idx;
     const double* Li = val + N.val;
     const double* L21 = Li + (int64_t)s * s;
-    __shared__ double bs[DS_MAXS], ys[DS_MAXS];
+    __shared__ double bs[CAP], ys[CAP];
     for (int t = threadIdx.x; t < s; t += DSB) bs[t] = x[vi[t]];
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -95,6 +98,7 @@ __global__ void __launch_bounds__(DSB) k_ds_forward(const DsNode* __restrict__ n
 }
 
 // backward sweep over the supernodes list[0 .. gridDim.x) (one height)
+template <int DSB, int CAP>
 __global__ void __launch_bounds__(DSB) k_ds_backward(const DsNode* __restrict__ nodes, const int32_t* __restrict__ list,
                                                      const int32_t* __restrict__ idx, const double* __restrict__ val,
                                                      double* __restrict__ x)
@@ -104,13 +108,32 @@ __global__ void __launch_bounds__(DSB) k_ds_backward(const DsNode* __restrict__ 
     const int32_t* vi = idx + N.idx;
     const double* Li = val + N.val;
     const double* L21 = Li + (int64_t)s * s;
-    __shared__ double xr[DS_MAXS], ts[DS_MAXS];
+    __shared__ double xr[CAP], ts[CAP], part[DSB];
     for (int r = threadIdx.x; r < m; r += DSB) xr[r] = x[vi[s + r]];
     __syncthreads();
-    for (int j = threadIdx.x; j < s; j += DSB) {
-        double a = x[vi[j]];
-        for (int r = 0; r < m; ++r) a -= L21[(int64_t)r * s + j] * xr[r];
-        ts[j] = a;
+    // t_j = y_j - sum_r L21[r][j] x_r: for a supernode of at most DSB / 2
+    // unknowns the rows r are split over G groups of lanes whose partial
+    // sums are added through LDS
+    const int sp = (s + 63) & ~63;
+    const int G = sp > 0 && sp <= DSB / 2 ? DSB / sp : 1;
+    if (G > 1) {
+        const int g = threadIdx.x / sp, j = threadIdx.x - g * sp;
+        double a = 0.0;
+        if (j < s)
+            for (int r = g; r < m; r += G) a += L21[(int64_t)r * s + j] * xr[r];
+        part[threadIdx.x] = a;
+        __syncthreads();
+        if (threadIdx.x < s) {
+            double t = x[vi[threadIdx.x]];
+            for (int q = 0; q < G; ++q) t -= part[q * sp + threadIdx.x];
+            ts[threadIdx.x] = t;
+        }
+    } else {
+        for (int j = threadIdx.x; j < s; j += DSB) {
+            double a = x[vi[j]];
+            for (int r = 0; r < m; ++r) a -= L21[(int64_t)r * s + j] * xr[r];
+            ts[j] = a;
+        }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < s; j += DSB) {
@@ -119,5 +142,13 @@ __global__ void __launch_bounds__(DSB) k_ds_backward(const DsNode* __restrict__ 
         x[vi[j]] = a;
     }
 }
+
+#define DS_INST(B, C)                                                                                           \
+    template __global__ void k_ds_forward<B, C>(const DsNode*, const int32_t*, const int32_t*, const double*, double*); \
+    template __global__ void k_ds_backward<B, C>(const DsNode*, const int32_t*, const int32_t*, const double*, double*);
+DS_INST(256, DS_SMALL)
+DS_INST(256, DS_MAXS)
+DS_INST(1024, DS_MAXS)
+#undef DS_INST
 
 }  // namespace pdfmc

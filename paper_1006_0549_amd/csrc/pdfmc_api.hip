@@ -281,6 +281,7 @@ struct pdfmc_ctx {
     int64_t DSN = 0, DSI = 0, DSV = 0;
     int DSC = 0, ds_height = -1;
     std::vector<int64_t> ds_hoff;      // list offsets per height
+    std::vector<int> ds_hwide;         // per height: sweep variant (small, 256 threads, 1024 threads)
     int proj_method = PDFMC_PROJ_DIRECT;   // requested
     bool proj_direct = false;              // in effect (every mode-2 case factored)
     // live timing of the particle kernel: one event pair per launch
@@ -701,19 +702,34 @@ pdfmc_status enqueue_direct_projection(pdfmc_ctx* c)
     hipStream_t st = c->stream;
     hipLaunchKernelGGL(k_ds_prep, dim3(c->DSC), dim3(1024), 0, st, (const DsCase*)c->d_ds_cases,
                        (const double*)c->d_pb, c->d_phi);
+    // per height, the variant its largest supernode needs
     for (int h = 0; h <= c->ds_height; ++h) {
         const int64_t n = c->ds_hoff[h + 1] - c->ds_hoff[h];
-        if (n > 0)
-            hipLaunchKernelGGL(k_ds_forward, dim3((unsigned)n), dim3(256), 0, st, (const DsNode*)c->d_ds_nodes,
-                               (const int32_t*)(c->d_ds_list + c->ds_hoff[h]), (const int32_t*)c->d_ds_idx,
-                               (const double*)c->d_ds_val, c->d_phi);
+        if (n == 0) continue;
+        const int32_t* lst = c->d_ds_list + c->ds_hoff[h];
+        const DsNode* nd = c->d_ds_nodes;
+        const int32_t* ix = c->d_ds_idx;
+        const double* vl = c->d_ds_val;
+        if (c->ds_hwide[h] == 2)
+            hipLaunchKernelGGL((k_ds_forward<1024, DS_MAXS>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi);
+        else if (c->ds_hwide[h] == 1)
+            hipLaunchKernelGGL((k_ds_forward<256, DS_MAXS>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
+        else
+            hipLaunchKernelGGL((k_ds_forward<256, DS_SMALL>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
     }
     for (int h = c->ds_height; h >= 0; --h) {
         const int64_t n = c->ds_hoff[h + 1] - c->ds_hoff[h];
-        if (n > 0)
-            hipLaunchKernelGGL(k_ds_backward, dim3((unsigned)n), dim3(256), 0, st, (const DsNode*)c->d_ds_nodes,
-                               (const int32_t*)(c->d_ds_list + c->ds_hoff[h]), (const int32_t*)c->d_ds_idx,
-                               (const double*)c->d_ds_val, c->d_phi);
+        if (n == 0) continue;
+        const int32_t* lst = c->d_ds_list + c->ds_hoff[h];
+        const DsNode* nd = c->d_ds_nodes;
+        const int32_t* ix = c->d_ds_idx;
+        const double* vl = c->d_ds_val;
+        if (c->ds_hwide[h] == 2)
+            hipLaunchKernelGGL((k_ds_backward<1024, DS_MAXS>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi);
+        else if (c->ds_hwide[h] == 1)
+            hipLaunchKernelGGL((k_ds_backward<256, DS_MAXS>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
+        else
+            hipLaunchKernelGGL((k_ds_backward<256, DS_SMALL>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
     }
     hipLaunchKernelGGL(k_ds_post, dim3(c->DSC), dim3(1024), 0, st, (const DsCase*)c->d_ds_cases, c->d_phi);
     LAUNCHCHK(c);
@@ -1237,7 +1253,17 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
             }
         }
         std::vector<int32_t> list;
+        c->ds_hwide.clear();
         for (auto& v : byh) {
+            // 0: small supernodes (LDS for DS_SMALL unknowns), 1: 256 threads,
+            // 2: 1024 threads for more than 64 products per thread of 256
+            int wide = 0;
+            for (int32_t q : v) {
+                const int64_t work = (int64_t)nodes[q].s * nodes[q].s / 2 + (int64_t)nodes[q].m * nodes[q].s;
+                const int kind = work > 64 * 256 ? 2 : (nodes[q].s > DS_SMALL || nodes[q].m > DS_SMALL ? 1 : 0);
+                wide = std::max(wide, kind);
+            }
+            c->ds_hwide.push_back(wide);
             list.insert(list.end(), v.begin(), v.end());
             c->ds_hoff.push_back((int64_t)list.size());
         }

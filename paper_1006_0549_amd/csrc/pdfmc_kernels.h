@@ -39,7 +39,9 @@ __global__ void k_mg_post2(const MgJob* jobs, const AmgDev* hs, const int4* tab,
 __global__ void k_mg_finish(const MgJob* jobs, const AmgDev* hs, int k0);
 __global__ void k_galerkin(const GalJob* jobs);
 __global__ void k_ds_prep(const DsCase* cs, const double* b, double* x);
+template <int DSB, int CAP>
 __global__ void k_ds_forward(const DsNode* nodes, const int32_t* list, const int32_t* idx, const double* val, double* x);
+template <int DSB, int CAP>
 __global__ void k_ds_backward(const DsNode* nodes, const int32_t* list, const int32_t* idx, const double* val, double* x);
 __global__ void k_ds_post(const DsCase* cs, double* x);
 __global__ void k_sort_hist(SortArgs A);

@@ -118,6 +118,7 @@ struct MgJob {
 // One supernode of a case's projection factor (nested-dissection Cholesky of
 // the constant projection matrix), with global unknown indices.
 constexpr int DS_MAXS = 2048;      // largest supernode and reach the sweeps stage in LDS
+constexpr int DS_SMALL = 256;      // LDS capacity of the sweep variant for small supernodes
 struct DsNode {
     int32_t s, m;                  // own unknowns, later unknowns reached
     int64_t idx;                   // own unknowns at idx[idx .. idx+s), later ones at [idx+s .. idx+s+m)

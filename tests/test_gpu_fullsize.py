@@ -110,3 +110,36 @@ def test_batch32_full_size_sampled_fp64(P, oracle_mod):
         assert cnt["nan"] == 0 and cnt["cg_fail"] == 0, (ci, cnt)
         _check_sampled(oracle_mod, c["mesh"], c["params"], c["particles"], Fs[ci], after, _sample_ids(n, 256, 100 + ci))
     _flush("[fullsize] batch32: all cases checked")
+
+
+def test_batch32_projection_factor_matches_pcg(P):
+    """The projection by the Cholesky factors (default; the tallest supernode
+    trees and separators of more than 128 unknowns, which run with wide
+    workgroups, occur only at these sizes) against the multigrid PCG of the
+    same systems: after initialisation and two full FP64 steps of the 32-case
+    batch, mean pressure and pressure gradients agree to far better than the
+    PCG's own tolerance allows to matter."""
+    b = W.config_batched()
+    cases = b["cases"]
+    _flush(f"[fullsize] batch32 projection: Cholesky sweeps against PCG, {len(cases)} cases")
+    out = {}
+    for method in ("direct", "pcg"):
+        sim = P.Sim("fp64", "cuda:0")
+        ids = [sim.add_case(c["mesh"], dict(c["params"], cg_rtol=1e-12), len(c["particles"]["x"])) for c in cases]
+        sim.bind()
+        sim.set_options(sort_interval=10, block_size=256, use_graph=True)
+        sim.set_projection_solver(method)
+        assert sim.projection_info()["method"] == method
+        for cs, c in zip(ids, cases):
+            sim.upload(cs, c["particles"])
+        sim.init()
+        sim.step(2)
+        out[method] = [(sim.pressure(cs), sim.fields(cs)[:, 3:5], sim.counters(cs)) for cs in ids]
+        _flush(f"[fullsize] batch32 projection: {method} done")
+        del sim
+    for ci, ((Pd, Gd, cd), (Pp, Gp, cp)) in enumerate(zip(out["direct"], out["pcg"])):
+        assert cd["cg_iters_p"] == 0 and cp["cg_iters_p"] > 0 and cd["cg_fail"] == 0 and cp["cg_fail"] == 0
+        sp = max(np.abs(Pp).max(), 1e-30)
+        assert np.abs(Pd - Pp).max() <= 1e-6 * sp, (ci, np.abs(Pd - Pp).max() / sp)
+        sg = max(np.abs(Gp).max(), 1e-30)
+        assert np.abs(Gd - Gp).max() <= 1e-6 * sg, (ci, np.abs(Gd - Gp).max() / sg)
