@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(DSB) k_ds_backward(const DsNode* __restrict__ 
     template __global__ void k_ds_forward<B, C>(const DsNode*, const int32_t*, const int32_t*, const double*, double*); \
     template __global__ void k_ds_backward<B, C>(const DsNode*, const int32_t*, const int32_t*, const double*, double*);
 DS_INST(256, DS_SMALL)
-DS_INST(256, DS_MAXS)
+DS_INST(1024, DS_SMALL)
 DS_INST(1024, DS_MAXS)
 #undef DS_INST
 

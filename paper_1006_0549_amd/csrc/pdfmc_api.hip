@@ -713,7 +713,7 @@ pdfmc_status enqueue_direct_projection(pdfmc_ctx* c)
         if (c->ds_hwide[h] == 2)
             hipLaunchKernelGGL((k_ds_forward<1024, DS_MAXS>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi);
         else if (c->ds_hwide[h] == 1)
-            hipLaunchKernelGGL((k_ds_forward<256, DS_MAXS>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
+            hipLaunchKernelGGL((k_ds_forward<1024, DS_SMALL>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi);
         else
             hipLaunchKernelGGL((k_ds_forward<256, DS_SMALL>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
     }
@@ -727,7 +727,7 @@ pdfmc_status enqueue_direct_projection(pdfmc_ctx* c)
         if (c->ds_hwide[h] == 2)
             hipLaunchKernelGGL((k_ds_backward<1024, DS_MAXS>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi);
         else if (c->ds_hwide[h] == 1)
-            hipLaunchKernelGGL((k_ds_backward<256, DS_MAXS>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
+            hipLaunchKernelGGL((k_ds_backward<1024, DS_SMALL>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi);
         else
             hipLaunchKernelGGL((k_ds_backward<256, DS_SMALL>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
     }
@@ -1255,12 +1255,14 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         std::vector<int32_t> list;
         c->ds_hwide.clear();
         for (auto& v : byh) {
-            // 0: small supernodes (LDS for DS_SMALL unknowns), 1: 256 threads,
-            // 2: 1024 threads for more than 64 products per thread of 256
+            // variant by the largest supernode of the height: 0: 256 threads,
+            // LDS for DS_SMALL unknowns; 1: 1024 threads (16 waves share the
+            // rows of L11 and L21, each a latency-bound reduction) with the
+            // same LDS; 2: 1024 threads, LDS for DS_MAXS unknowns
             int wide = 0;
             for (int32_t q : v) {
-                const int64_t work = (int64_t)nodes[q].s * nodes[q].s / 2 + (int64_t)nodes[q].m * nodes[q].s;
-                const int kind = work > 64 * 256 ? 2 : (nodes[q].s > DS_SMALL || nodes[q].m > DS_SMALL ? 1 : 0);
+                const int sq = nodes[q].s, mq = nodes[q].m;
+                const int kind = (sq > DS_SMALL || mq > DS_SMALL) ? 2 : (sq + mq > 128 ? 1 : 0);
                 wide = std::max(wide, kind);
             }
             c->ds_hwide.push_back(wide);
