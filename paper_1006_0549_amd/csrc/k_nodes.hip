@@ -114,6 +114,33 @@ __device__ inline void recover_grad(const NodeArgs& A, const double* f, int fstr
     gx = sx / Asum; gy = sy / Asum;
 }
 
+// the same for three consecutive fields f[0], f[1], f[2] in one pass over
+// the incident elements (each component's sums in the same order)
+__device__ inline void recover_grad3(const NodeArgs& A, const double* f, int fstride, int s, double (&gx)[3],
+                                     double (&gy)[3])
+{
+    double Asum = 0.0, sx[3] = {0.0, 0.0, 0.0}, sy[3] = {0.0, 0.0, 0.0};
+    for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
+        const int e = A.inc[j] / 3;
+        const double* r = A.rec + 8 * (int64_t)e;
+        const int4 t = A.tri_s[e];
+        const double ae = A.area[e];
+        const double* p0 = f + (int64_t)t.x * fstride;
+        const double* p1 = f + (int64_t)t.y * fstride;
+        const double* p2 = f + (int64_t)t.z * fstride;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double f0 = p0[i], f1 = p1[i], f2 = p2[i];
+            const double ex = (f0 * r[2] + f1 * r[3]) + f2 * r[4];
+            const double ey = (f0 * r[5] + f1 * r[6]) + f2 * r[7];
+            sx[i] += ae * ex; sy[i] += ae * ey;
+        }
+        Asum += ae;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { gx[i] = sx[i] / Asum; gy[i] = sy[i] / Asum; }
+}
+
 __global__ void k_fields_grad(NodeArgs A)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,11 +151,11 @@ __global__ void k_fields_grad(NodeArgs A)
     const double* st = A.stats + (int64_t)s * NST;
     F[F_U1] = st[2]; F[F_U2] = st[3]; F[F_U3] = st[4];
     F[F_OMEGA] = st[11];
+    double gx[3], gy[3];
+    recover_grad3(A, A.stats + 2, NST, s, gx, gy);
     for (int i = 0; i < 3; ++i) {
-        double gx, gy;
-        recover_grad(A, A.stats + 2 + i, NST, s, gx, gy);
-        F[F_DU1X + 2 * i] = gx;
-        F[F_DU1X + 2 * i + 1] = gy;
+        F[F_DU1X + 2 * i] = gx[i];
+        F[F_DU1X + 2 * i + 1] = gy[i];
     }
 }
 
@@ -148,22 +175,28 @@ __global__ void k_fields_derived(NodeArgs A)
     if (C.mode == 0) return;
     double* F = A.F + (int64_t)s * NF;
     const double* st = A.stats + (int64_t)s * NST;
-    // Laplacian: area-weighted element divergence of the recovered gradient (R-16)
-    for (int i = 0; i < 3; ++i) {
-        double Asum = 0.0, sd = 0.0;
+    // Laplacian: area-weighted element divergence of the recovered gradient
+    // (R-16), the three components in one pass over the incident elements
+    {
+        double Asum = 0.0, sd[3] = {0.0, 0.0, 0.0};
         for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
             const int e = A.inc[j] / 3;
             const double* r = A.rec + 8 * (int64_t)e;
             const int4 t = A.tri_s[e];
             const int tt[3] = {t.x, t.y, t.z};
-            double div = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                const double* Fk = A.F + (int64_t)tt[k] * NF;
-                div += r[2 + k] * Fk[F_DU1X + 2 * i] + r[5 + k] * Fk[F_DU1X + 2 * i + 1];
+            const double ae = A.area[e];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                double div = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double* Fk = A.F + (int64_t)tt[k] * NF;
+                    div += r[2 + k] * Fk[F_DU1X + 2 * i] + r[5 + k] * Fk[F_DU1X + 2 * i + 1];
+                }
+                sd[i] += ae * div;
             }
-            sd += A.area[e] * div; Asum += A.area[e];
+            Asum += ae;
         }
-        F[F_LAP1 + i] = sd / Asum;
+        for (int i = 0; i < 3; ++i) F[F_LAP1 + i] = sd[i] / Asum;
     }
     const double k = 0.5 * ((st[5] + st[6]) + st[7]);
     const double om = st[11];
@@ -354,14 +387,23 @@ __global__ void k_mirror_f32(const double* __restrict__ F, float* __restrict__ F
 
 // ---------------------------------------------------------------- multigrid
 
+// LPE lanes per coarse entry (more on the coarser levels, whose entries
+// gather longer contribution lists); the group's partial sums meet by shuffles
+template <int LPE>
 __global__ void k_galerkin(const GalJob* __restrict__ jobs)
 {
     const GalJob J = jobs[blockIdx.y];
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < J.nnz; k += gridDim.x * blockDim.x) {
+    const int sub = threadIdx.x % LPE;
+    const int g0 = (blockIdx.x * blockDim.x + threadIdx.x) / LPE, gs = gridDim.x * blockDim.x / LPE;
+    for (int k = g0; k < J.nnz; k += gs) {
         double s = 0.0;
-        for (int j = J.gptr[k]; j < J.gptr[k + 1]; ++j) s += J.gcoef[j] * J.src[J.gidx[j]];
-        J.dst[J.gdst[k]] = s;
+        for (int j = J.gptr[k] + sub; j < J.gptr[k + 1]; j += LPE) s += J.gcoef[j] * J.src[J.gidx[j]];
+        for (int d = LPE / 2; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+        if (sub == 0) J.dst[J.gdst[k]] = s;
     }
 }
+template __global__ void k_galerkin<1>(const GalJob*);
+template __global__ void k_galerkin<4>(const GalJob*);
+template __global__ void k_galerkin<16>(const GalJob*);
 
 }  // namespace pdfmc

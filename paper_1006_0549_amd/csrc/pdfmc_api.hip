@@ -271,6 +271,7 @@ struct pdfmc_ctx {
     int n_gal[AMG_MAXL] = {};
     int n_gal_p[AMG_MAXL] = {};
     int64_t gal_max[AMG_MAXL] = {}, gal_max_p[AMG_MAXL] = {};
+    int gal_lpe[AMG_MAXL] = {}, gal_lpe_p[AMG_MAXL] = {};   // lanes per coarse entry
     // projection by the Cholesky factors: supernodes, their unknown indices
     // and values, the factored cases, supernodes ordered by height
     DsNode* d_ds_nodes = nullptr;
@@ -837,6 +838,17 @@ void mg_adapt(pdfmc_ctx* c)
     }
 }
 
+// Coarse operators of one level for n hierarchies: lpe lanes per coarse entry
+pdfmc_status enqueue_galerkin(pdfmc_ctx* c, const GalJob* jobs, int n, int64_t max_nnz, int lpe)
+{
+    const dim3 g(std::min<int64_t>(nblk(max_nnz * lpe, 256), 1024), n);
+    if (lpe >= 16) hipLaunchKernelGGL(k_galerkin<16>, g, dim3(256), 0, c->stream, jobs);
+    else if (lpe >= 4) hipLaunchKernelGGL(k_galerkin<4>, g, dim3(256), 0, c->stream, jobs);
+    else hipLaunchKernelGGL(k_galerkin<1>, g, dim3(256), 0, c->stream, jobs);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
 pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
 {
     NodeArgs A = node_args(c);
@@ -851,8 +863,7 @@ pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
         if (project) hipLaunchKernelGGL(k_proj_rhs, g, b, 0, c->stream, A);
         for (int l = 0; l < AMG_MAXL; ++l) {
             if (c->n_gal[l] == 0) continue;
-            hipLaunchKernelGGL(k_galerkin, dim3(std::min<int64_t>(nblk(c->gal_max[l], 256), 1024), c->n_gal[l]), dim3(256), 0,
-                               c->stream, (const GalJob*)(c->d_gal + (size_t)l * c->n_amg));
+            TRY(enqueue_galerkin(c, c->d_gal + (size_t)l * c->n_amg, c->n_gal[l], c->gal_max[l], c->gal_lpe[l]));
         }
         // relaxation and projection systems of every case together
         TRY(enqueue_solve(c, project));
@@ -1153,7 +1164,10 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     // multigrid hierarchies: flat arrays, descriptors, Galerkin jobs
     std::vector<AmgDev> amgdev(2 * (size_t)std::max(c->n_amg, 1));
     std::vector<GalJob> gal(2 * (size_t)AMG_MAXL * std::max(c->n_amg, 1));
-    for (int l = 0; l < AMG_MAXL; ++l) { c->n_gal[l] = 0; c->n_gal_p[l] = 0; c->gal_max[l] = 0; c->gal_max_p[l] = 0; }
+    for (int l = 0; l < AMG_MAXL; ++l) {
+        c->n_gal[l] = 0; c->n_gal_p[l] = 0; c->gal_max[l] = 0; c->gal_max_p[l] = 0;
+        c->gal_lpe[l] = 1; c->gal_lpe_p[l] = 1;
+    }
     if (c->n_amg > 0) {
         std::vector<int32_t> ai;
         std::vector<double> ad;
@@ -1206,12 +1220,17 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                     G.gcoef = c->d_amg_d + o.Gcoef[l];
                     G.src = l == 0 ? (h == 0 ? c->d_er_val : c->d_pk_val) + cs.ell_off : c->d_amg_d + o.Aval[l];
                     G.dst = c->d_amg_d + o.Aval[l + 1];
+                    // lanes per coarse entry from the mean contribution-list length
+                    const double terms = G.nnz > 0 ? (double)E.gidx[l].size() / G.nnz : 0.0;
+                    const int lpe = terms >= 24.0 ? 16 : (terms >= 4.0 ? 4 : 1);
                     if (h == 0) {
                         gal[(size_t)l * c->n_amg + c->n_gal[l]++] = G;
                         c->gal_max[l] = std::max<int64_t>(c->gal_max[l], G.nnz);
+                        c->gal_lpe[l] = std::max(c->gal_lpe[l], lpe);
                     } else {
                         gal[(size_t)(AMG_MAXL + l) * c->n_amg + c->n_gal_p[l]++] = G;
                         c->gal_max_p[l] = std::max<int64_t>(c->gal_max_p[l], G.nnz);
+                        c->gal_lpe_p[l] = std::max(c->gal_lpe_p[l], lpe);
                     }
                 }
             }
@@ -1298,8 +1317,8 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         LAUNCHCHK(c);
         for (int l = 0; l < AMG_MAXL; ++l) {
             if (c->n_gal_p[l] == 0) continue;
-            hipLaunchKernelGGL(k_galerkin, dim3(std::min<int64_t>(nblk(c->gal_max_p[l], 256), 1024), c->n_gal_p[l]), dim3(256), 0,
-                               c->stream, (const GalJob*)(c->d_gal + (size_t)(AMG_MAXL + l) * c->n_amg));
+            TRY(enqueue_galerkin(c, c->d_gal + (size_t)(AMG_MAXL + l) * c->n_amg, c->n_gal_p[l], c->gal_max_p[l],
+                                 c->gal_lpe_p[l]));
             LAUNCHCHK(c);
         }
     }

@@ -37,7 +37,7 @@ __global__ void k_mg_prolong(const MgJob* jobs, const AmgDev* hs, const int4* ta
 __global__ void k_mg_post1(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int l, int k);
 __global__ void k_mg_post2(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int l, int k);
 __global__ void k_mg_finish(const MgJob* jobs, const AmgDev* hs, int k0);
-__global__ void k_galerkin(const GalJob* jobs);
+template <int LPE> __global__ void k_galerkin(const GalJob* jobs);
 __global__ void k_ds_prep(const DsCase* cs, const double* b, double* x);
 template <int DSB, int CAP>
 __global__ void k_ds_forward(const DsNode* nodes, const int32_t* list, const int32_t* idx, const double* val, double* x);
