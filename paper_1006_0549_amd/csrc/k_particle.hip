@@ -230,6 +230,7 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
 {
     __shared__ int s_key[HS];
+    __shared__ int s_used[HS + 1];        // flush: the used slots, then their count
     __shared__ double s_val[HS * NV];
     __shared__ R s_rec[256 * NREC];       // per-lane records for the node-sum reduction
     for (int i = threadIdx.x; i < HS; i += blockDim.x) s_key[i] = -1;
@@ -466,13 +467,26 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         }
     }
     __syncthreads();
-    // flush the table
+    // flush the table: the first wave lists the used slots, then the
+    // workgroup walks (used slot, value) pairs; the pair index is split by a
+    // multiply-shift that equals idx / per for idx < 2^20 / per
+    static_assert(HS <= 64, "one wave lists the slots");
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const bool used = lane < HS && s_key[lane] >= 0;
+        const unsigned long long um = __ballot(used);
+        if (used) s_used[__popcll(um & ((1ull << lane) - 1))] = lane;
+        if (lane == 0) s_used[HS] = __popcll(um);
+    }
+    __syncthreads();
     {
         const int per = 3 * nq + ((A.do_bins && ns > 0) ? 8 * (2 + ns) : 0);
-        for (int idx = threadIdx.x; idx < HS * per; idx += blockDim.x) {
-            const int slot = idx / per, v = idx % per;
+        const unsigned magic = ((1u << 20) + per - 1) / per;
+        const int npair = s_used[HS] * per;
+        for (int idx = threadIdx.x; idx < npair; idx += blockDim.x) {
+            const int u = (int)(((unsigned)idx * magic) >> 20), v = idx - u * per;
+            const int slot = s_used[u];
             const int el = s_key[slot];
-            if (el < 0) continue;
             const double x = s_val[slot * NV + v];
             if (x == 0.0) continue;
             if (v < 3 * nq) {
