@@ -143,3 +143,39 @@ def test_batch32_projection_factor_matches_pcg(P):
         assert np.abs(Pd - Pp).max() <= 1e-6 * sp, (ci, np.abs(Pd - Pp).max() / sp)
         sg = max(np.abs(Gp).max(), 1e-30)
         assert np.abs(Gd - Gp).max() <= 1e-6 * sg, (ci, np.abs(Gd - Gp).max() / sg)
+
+
+def test_batch32_sort_is_a_permutation_at_full_size(P):
+    """The periodic sort at the benchmark size (452,500 elements, so the
+    element-count scan spans 442 blocks): right after a sort every case's
+    particles are ordered by element and still form the uploaded set, and a
+    run that sorts every step follows the unsorted run (FP64, two steps)."""
+    b = W.config_batched()
+    cases = b["cases"]
+    _flush(f"[fullsize] batch32 sort: {len(cases)} cases, FP64, sort every step against no sort")
+    res = {}
+    for si in (1, 0):
+        sim = P.Sim("fp64", "cuda:0")
+        ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in cases]
+        sim.bind()
+        sim.set_options(sort_interval=si, block_size=256, use_graph=True)
+        for cs, c in zip(ids, cases):
+            sim.upload(cs, c["particles"])
+        sim.init()
+        sim.step(2)
+        if si == 1:
+            sim.sort()
+        res[si] = [sim.download(cs, len(c["particles"]["x"])) for cs, c in zip(ids, cases)]
+        del sim
+        _flush(f"[fullsize] batch32 sort: sort_interval={si} done")
+    for ci, (a, b0) in enumerate(zip(res[1], res[0])):
+        n = len(cases[ci]["particles"]["x"])
+        assert np.array_equal(np.sort(a["id"]), np.arange(n)), ci
+        assert np.all(np.diff(a["elem"]) >= 0), ci
+        A, B = _by_id(a), _by_id(b0)
+        # the node sums add in another order, so a particle on an element edge
+        # may end in the neighbour; all others take the same path
+        same = A["elem"] == B["elem"]
+        assert same.mean() >= 1.0 - 1e-5, (ci, same.mean())
+        for k in ("x", "y", "u", "v", "w", "omega"):
+            assert np.allclose(A[k][same], B[k][same], rtol=1e-9, atol=1e-12), (ci, k)
