@@ -232,13 +232,17 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     __shared__ int s_key[HS];
     __shared__ int s_used[HS + 1];        // flush: the used slots, then their count
     __shared__ double s_val[HS * NV];
-    __shared__ R s_rec[256 * NREC];       // per-lane records for the node-sum reduction
+    __shared__ __align__(16) R s_rec[256 * NREC];   // per-lane records for the node-sum reduction
     for (int i = threadIdx.x; i < HS; i += blockDim.x) s_key[i] = -1;
     for (int i = threadIdx.x; i < HS * NV; i += blockDim.x) s_val[i] = 0.0;
     __syncthreads();
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int tile = (int)(gid / TILE);
-    const int c = A.tile_case[tile < A.ntiles ? tile : A.ntiles - 1];
+    // block sizes are multiples of 64 and TILE of the block size, so a
+    // wavefront lies inside one tile: the tile, the case and its constants
+    // are the same for all lanes and are taken from the first lane (scalar
+    // registers and loads)
+    const int tile = __builtin_amdgcn_readfirstlane((int)(gid / TILE));
+    const int c = __builtin_amdgcn_readfirstlane(A.tile_case[tile < A.ntiles ? tile : A.ntiles - 1]);
     const CaseDev& C = A.cases[c];
     const int64_t i = gid - C.poff;
     const bool valid = tile < A.ntiles && (i >= 0) && (i < C.np);
@@ -370,18 +374,22 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     }
 
     // ---- shape-weighted node sums of the new state (R-11) and cell sums
-    // (R-23), FP64. Runs of equal element inside a wavefront are summed with
-    // shuffles; the run heads add the run sums into a per-workgroup LDS table
-    // keyed by element; after the barrier the table is flushed with one FP64
-    // atomic per (element, value). A table overflow falls back to direct atomics.
+    // (R-23), FP64. The particles of one element inside a wavefront (node
+    // sums) or runs of equal (element, bin) (cell sums) are summed in the
+    // wavefront, and the sums go into a per-workgroup LDS table keyed by
+    // element; after the barrier the table is flushed with one FP64 atomic
+    // per (element, value). A table overflow falls back to direct atomics.
     const int nq = 12 + 2 * ns;
     {
-        // Node sums. Every lane stores its particle's record in LDS; then, for
-        // each run of equal element in the wavefront, lane j = k * nq + q sums
-        // term q of vertex k over the run's particles (the record reads are
-        // the same for all lanes of a step, so they broadcast) and adds the
-        // run total to the element's slot of the workgroup table. The terms
-        // are the FP64 products w lambda_k Q of R-11, as in the oracle.
+        // Node sums. Every lane stores its particle's record in LDS. Then the
+        // wavefront takes the elements present in it one at a time (a ballot
+        // per element, so the particles of an element form one set however
+        // far the order has frayed since the last sort). For a set, the
+        // wavefront splits into G groups of lanes; lane q of group g sums
+        // term q of all three vertices over the set's g-th, (g+G)-th, ...
+        // particles, the group sums are combined with shuffles, and group 0
+        // adds the totals to the element's slot of the workgroup table. The
+        // terms are the FP64 products w lambda_k Q of R-11, as in the oracle.
         static_assert(256 * NREC * sizeof(R) + HS * NV * 8 < 64 * 1024, "LDS");
         const int key = valid ? e : -1;
         const int lane = __lane_id(), wid = threadIdx.x >> 6;
@@ -389,13 +397,10 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         my[0] = lam[0]; my[1] = lam[1]; my[2] = lam[2]; my[3] = wt;
         my[4] = u3[0]; my[5] = u3[1]; my[6] = u3[2]; my[7] = om;
         for (int a = 0; a < ns; ++a) my[8 + a] = psi[a];
-        const int prev = __shfl_up(key, 1);
-        const unsigned long long heads = __ballot(lane == 0 || prev != key);
         __syncthreads();
-        // term of this lane: w lambda_k [* rec[ia]] [* rec[ib]], or (w lambda_k)^2
-        const int j = lane;
-        const bool act = j < 3 * nq;
-        const int k = act ? j / nq : 0, q = act ? j % nq : 0;
+        // lane roles: 4 groups of 16 lanes when nq <= 16, else 3 groups of 21
+        const int G = nq <= 16 ? 4 : 3, GS = nq <= 16 ? 16 : 21;
+        const int g = lane / GS, q = lane - g * GS;
         int ia = -1, ib = -1;
         bool sq = false;
         if (q >= 1 && q <= 3) ia = 4 + (q - 1);
@@ -407,38 +412,73 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         else if (q >= 11 && q < 11 + ns) ia = 8 + (q - 11);
         else if (q >= 11 + ns && q < 11 + 2 * ns) ia = ib = 8 + (q - 11 - ns);
         else if (q == 11 + 2 * ns) sq = true;
-        const R* wave_rec = s_rec + wid * 64 * NREC;
-        // branch-free term: (w lambda_k) * (w lambda_k | rec[ia] | 1) * (rec[ib] | 1),
-        // the same products in the same order as above; every lane reads its
-        // four record words at once
+        // term of vertex k: (w lambda_k) * fa_k * fb with fb = rec[ib] or 1
+        // and fa_k = fma(sqm, w lambda_k, fa): fa = rec[ia] or 1 when sqm = 0
+        // (then fa_k = fa exactly), fa = 0 and sqm = 1 for the square term
+        // (then fa_k = w lambda_k exactly), so each term is the same product,
+        // in the same order, as (w lambda_k) [* rec[ia]] [* rec[ib]] or
+        // (w lambda_k)^2
         const int ia0 = ia >= 0 ? ia : 0, ib0 = ib >= 0 ? ib : 0;
         const bool has_a = ia >= 0, has_b = ib >= 0;
-        unsigned long long hm = heads;
-        while (hm) {
-            const int s0 = __ffsll((long long)hm) - 1;
-            hm &= hm - 1;
-            const int s1 = hm ? __ffsll((long long)hm) - 1 : 64;
-            const int ks = __shfl(key, s0);
-            if (ks < 0) continue;
-            double acc = 0.0;
-#pragma unroll 2
-            for (int pp = s0; pp < s1; ++pp) {
-                const R* rq = wave_rec + pp * NREC;
-                const R rw = rq[3], rl = rq[k], ra = rq[ia0], rb = rq[ib0];
-                const double wn = (double)rw * (double)rl;
-                const double fa = sq ? wn : (has_a ? (double)ra : 1.0);
-                const double fb = has_b ? (double)rb : 1.0;
-                acc += (wn * fa) * fb;
+        const R ca = sq ? R(0) : R(1);
+        const double sqm = sq ? 1.0 : 0.0;
+        const R* wave_rec = s_rec + wid * 64 * NREC;
+        unsigned long long rem = __ballot(key >= 0);
+        while (rem) {
+            const int ks = __shfl(key, __ffsll((long long)rem) - 1);
+            const unsigned long long set = __ballot(key == ks);
+            rem &= ~set;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            unsigned long long m = set;
+            while (m) {
+                // the set's next G particles, one per group
+                int pk[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    pk[t] = -1;
+                    if (t < G && m) { pk[t] = __ffsll((long long)m) - 1; m &= m - 1; }
+                }
+                // g <= 3 always, and pk[3] = -1 when G = 3
+                int pp = pk[0];
+                pp = g == 1 ? pk[1] : pp;
+                pp = g == 2 ? pk[2] : pp;
+                pp = g == 3 ? pk[3] : pp;
+                if (pp >= 0) {
+                    const R* rq = wave_rec + pp * NREC;
+                    const R l0 = rq[0], l1 = rq[1], l2 = rq[2], rw = rq[3];
+                    const R xa = rq[ia0], xb = rq[ib0];
+                    const double fa = has_a ? (double)xa : (double)ca;
+                    const double fb = has_b ? (double)xb : 1.0;
+                    const double w = (double)rw;
+                    const double wn0 = w * (double)l0, wn1 = w * (double)l1, wn2 = w * (double)l2;
+                    a0 += (wn0 * __builtin_fma(sqm, wn0, fa)) * fb;
+                    a1 += (wn1 * __builtin_fma(sqm, wn1, fa)) * fb;
+                    a2 += (wn2 * __builtin_fma(sqm, wn2, fa)) * fb;
+                }
+            }
+            if (G == 4) {
+                a0 += __shfl_xor(a0, 16); a1 += __shfl_xor(a1, 16); a2 += __shfl_xor(a2, 16);
+                a0 += __shfl_xor(a0, 32); a1 += __shfl_xor(a1, 32); a2 += __shfl_xor(a2, 32);
+            } else {
+                // lanes 0..20 gather groups 1 and 2 (source lanes 21..62)
+                a0 = (a0 + __shfl(a0, lane + 21)) + __shfl(a0, lane + 42);
+                a1 = (a1 + __shfl(a1, lane + 21)) + __shfl(a1, lane + 42);
+                a2 = (a2 + __shfl(a2, lane + 21)) + __shfl(a2, lane + 42);
             }
             int slot = 0;
             if (lane == 0) slot = lds_slot(s_key, ks);
             slot = __shfl(slot, 0);
-            if (act) {
+            if (g == 0 && q < nq) {
                 if (slot >= 0) {
-                    lds_add(&s_val[slot * NV + j], acc);
+                    double* sv = &s_val[slot * NV + q];
+                    lds_add(sv, a0);
+                    lds_add(sv + nq, a1);
+                    lds_add(sv + 2 * nq, a2);
                 } else {
-                    const int node = pick(A.M.tri_s[ks], k);
-                    unsafeAtomicAdd(A.nsum + (int64_t)node * NQ + q, acc);
+                    const int4 t = A.M.tri_s[ks];
+                    unsafeAtomicAdd(A.nsum + (int64_t)t.x * NQ + q, a0);
+                    unsafeAtomicAdd(A.nsum + (int64_t)t.y * NQ + q, a1);
+                    unsafeAtomicAdd(A.nsum + (int64_t)t.z * NQ + q, a2);
                 }
             }
         }
