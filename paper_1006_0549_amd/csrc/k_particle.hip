@@ -12,11 +12,11 @@
 //   three statistics nodes (R-11) and cell sums for the next mixing step.
 //
 // Layout: structure of arrays, one lane per particle, tiles of 256 particles
-// that never straddle two cases. The scatter first reduces runs of equal
-// element inside each wavefront (segmented shuffle reduction; particles are
-// kept sorted by element so runs are long) and only the run head issues the
-// FP64 atomic adds, so a node sees a few atomics per wavefront instead of one
-// per particle. Arithmetic of the FP64 instantiation follows the operation
+// that never straddle two cases. The scatter first sums the particles of each
+// element inside a wavefront (particles are kept sorted by element, so a
+// wavefront holds few elements), adds the sums into a per-workgroup LDS table
+// keyed by element, and flushes the table with FP64 atomic adds, so a node
+// sees a few atomics per workgroup instead of one per particle. Arithmetic of the FP64 instantiation follows the operation
 // order of the readings exactly (no contraction; explicit fma only where the
 // readings put one), so that it reproduces the CPU oracle bit for bit.
 #include "pdfmc_dev.h"
@@ -146,41 +146,6 @@ __device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R 
 }
 
 // ---------------------------------------------------------------- wave helpers
-
-struct Runs {
-    bool head;
-    unsigned long long same;   // bit j set: lane + 2^j is in the same run
-};
-
-__device__ inline Runs make_runs(int key)
-{
-    const int lane = __lane_id();
-    int prev = __shfl_up(key, 1);
-    bool head = (lane == 0) || (prev != key);
-    unsigned long long hm = __ballot(head);
-    int rid = __popcll(hm & (~0ull >> (63 - lane)));
-    Runs r;
-    r.head = head;
-    r.same = 0;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        int d = 1 << j;
-        int o = __shfl_down(rid, d);
-        if (lane + d < 64 && o == rid) r.same |= (1ull << j);
-    }
-    return r;
-}
-
-// sum over the lane's run, valid in the run head
-__device__ inline double run_sum(double v, const Runs& r)
-{
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        double t = __shfl_down(v, 1 << j);
-        if (r.same & (1ull << j)) v += t;
-    }
-    return v;
-}
 
 __device__ inline int wave_sum_int(int v)
 {
@@ -374,12 +339,13 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     }
 
     // ---- shape-weighted node sums of the new state (R-11) and cell sums
-    // (R-23), FP64. The particles of one element inside a wavefront (node
-    // sums) or runs of equal (element, bin) (cell sums) are summed in the
-    // wavefront, and the sums go into a per-workgroup LDS table keyed by
-    // element; after the barrier the table is flushed with one FP64 atomic
-    // per (element, value). A table overflow falls back to direct atomics.
+    // (R-23), FP64, into a per-workgroup LDS table keyed by element: the node
+    // sums of the particles of one element are summed in the wavefront first,
+    // the cell sums are added particle by particle. After the barrier the
+    // table is flushed with one FP64 atomic per (element, value). A table
+    // overflow falls back to direct atomics.
     const int nq = 12 + 2 * ns;
+    int myslot = -1;   // table slot of this lane's element, found by the node-sum pass
     {
         // Node sums. Every lane stores its particle's record in LDS. Then the
         // wavefront takes the elements present in it one at a time (a ballot
@@ -468,6 +434,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             int slot = 0;
             if (lane == 0) slot = lds_slot(s_key, ks);
             slot = __shfl(slot, 0);
+            if ((set >> lane) & 1ull) myslot = slot;
             if (g == 0 && q < nq) {
                 if (slot >= 0) {
                     double* sv = &s_val[slot * NV + q];
@@ -483,27 +450,20 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             }
         }
     }
-    if (A.do_bins && ns > 0) {
-        const int key = valid ? e * 8 + bin : -1;
-        const Runs r = make_runs(key);
-        int slot = -1;
-        if (r.head && key >= 0) slot = lds_slot(s_key, e);
-        const double cnt = run_sum(valid ? 1.0 : 0.0, r);
-        const double sw = run_sum(valid ? (double)wt : 0.0, r);
-        double swp[MAXS];
-        for (int a = 0; a < ns; ++a) swp[a] = run_sum(valid ? (double)wt * (double)psi[a] : 0.0, r);
-        if (r.head && key >= 0) {
-            const int base = 3 * nq + bin * (2 + ns);
+    if (A.do_bins && ns > 0 && valid) {
+        // cell sums: every particle adds its count, weight and weighted
+        // scalars to its (element, bin) cell in the element's table slot
+        const int base = 3 * nq + bin * (2 + ns);
+        if (myslot >= 0) {
+            double* sv = &s_val[myslot * NV + base];
+            lds_add(sv, 1.0);
+            lds_add(sv + 1, (double)wt);
+            for (int a = 0; a < ns; ++a) lds_add(sv + 2 + a, (double)wt * (double)psi[a]);
+        } else {
             double* dst = A.csum + C.csoff + ((int64_t)(e - C.eoff) * 8 + bin) * (1 + ns);
-            if (slot >= 0) {
-                lds_add(&s_val[slot * NV + base], cnt);
-                lds_add(&s_val[slot * NV + base + 1], sw);
-                for (int a = 0; a < ns; ++a) lds_add(&s_val[slot * NV + base + 2 + a], swp[a]);
-            } else {
-                atomicAdd(A.ccnt + key, (int)cnt);
-                unsafeAtomicAdd(dst, sw);
-                for (int a = 0; a < ns; ++a) unsafeAtomicAdd(dst + 1 + a, swp[a]);
-            }
+            atomicAdd(A.ccnt + (int64_t)e * 8 + bin, 1);
+            unsafeAtomicAdd(dst, (double)wt);
+            for (int a = 0; a < ns; ++a) unsafeAtomicAdd(dst + 1 + a, (double)wt * (double)psi[a]);
         }
     }
     __syncthreads();
