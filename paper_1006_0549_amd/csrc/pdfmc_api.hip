@@ -38,6 +38,7 @@ struct HierEll {
 // Offsets of one hierarchy's arrays inside the flat int/double regions.
 struct HierOff {
     int64_t Acol[AMG_MAXL], Aval[AMG_MAXL], Pcol[AMG_MAXL], Pval[AMG_MAXL], Rcol[AMG_MAXL], Rval[AMG_MAXL];
+    int64_t Alen[AMG_MAXL], Plen[AMG_MAXL], Rlen[AMG_MAXL];   // entries per row (padding after them)
     int64_t Gptr[AMG_MAXL], Gidx[AMG_MAXL], Gdst[AMG_MAXL], Gcoef[AMG_MAXL];
 };
 
@@ -103,10 +104,10 @@ void pack_hier(const HierEll& E, HierOff& o, std::vector<int32_t>* ai, std::vect
     };
     const int L = (int)E.A.size();
     for (int l = 0; l < L; ++l) {
-        if (l >= 1) { o.Acol[l] = puti(E.A[l].col); o.Aval[l] = putd(E.A[l].val); }
+        if (l >= 1) { o.Acol[l] = puti(E.A[l].col); o.Aval[l] = putd(E.A[l].val); o.Alen[l] = puti(E.A[l].len); }
         if (l + 1 < L) {
-            o.Pcol[l] = puti(E.P[l].col); o.Pval[l] = putd(E.P[l].val);
-            o.Rcol[l] = puti(E.R[l].col); o.Rval[l] = putd(E.R[l].val);
+            o.Pcol[l] = puti(E.P[l].col); o.Pval[l] = putd(E.P[l].val); o.Plen[l] = puti(E.P[l].len);
+            o.Rcol[l] = puti(E.R[l].col); o.Rval[l] = putd(E.R[l].val); o.Rlen[l] = puti(E.R[l].len);
             o.Gptr[l] = puti(E.gptr[l]); o.Gidx[l] = puti(E.gidx[l]); o.Gdst[l] = puti(E.gdst[l]);
             o.Gcoef[l] = putd(E.gcoef[l]);
         }
@@ -1204,10 +1205,13 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                         D.A[0] = EllDev{cs.m.nsn, cs.ell0.w, c->d_ell_col + cs.ell_off,
                                         (h == 0 ? c->d_er_val : c->d_pk_val) + cs.ell_off, c->d_ell_len + cs.noff};
                     else
-                        D.A[l] = EllDev{E.A[l].n, E.A[l].w, c->d_amg_i + o.Acol[l], c->d_amg_d + o.Aval[l], nullptr};
+                        D.A[l] = EllDev{E.A[l].n, E.A[l].w, c->d_amg_i + o.Acol[l], c->d_amg_d + o.Aval[l],
+                                        c->d_amg_i + o.Alen[l]};
                     if (l + 1 < D.nlev) {
-                        D.P[l] = EllDev{E.P[l].n, E.P[l].w, c->d_amg_i + o.Pcol[l], c->d_amg_d + o.Pval[l], nullptr};
-                        D.R[l] = EllDev{E.R[l].n, E.R[l].w, c->d_amg_i + o.Rcol[l], c->d_amg_d + o.Rval[l], nullptr};
+                        D.P[l] = EllDev{E.P[l].n, E.P[l].w, c->d_amg_i + o.Pcol[l], c->d_amg_d + o.Pval[l],
+                                        c->d_amg_i + o.Plen[l]};
+                        D.R[l] = EllDev{E.R[l].n, E.R[l].w, c->d_amg_i + o.Rcol[l], c->d_amg_d + o.Rval[l],
+                                        c->d_amg_i + o.Rlen[l]};
                     }
                 }
                 // Galerkin jobs: level l -> l+1
