@@ -1,12 +1,12 @@
 // Counting sort of the particle arrays by element (periodic re-sort).
 //
 // Keeping each case's particles grouped by element keeps the gathers of
-// element records and nodal fields cache-resident and the runs of equal
-// element long, which is what the particle kernel's segmented scatter
-// relies on. Order inside an element is not kept (the run heads claim their
-// slots with atomics); results do not depend on it beyond the summation
-// order of the FP64 node sums.
-//   k_sort_hist     per-element counts (one atomic per run of equal element)
+// element records and nodal fields cache-resident and the elements per
+// wavefront few, which is what the particle kernel's scatter relies on.
+// Order inside an element is not kept (the first lane of an element in a
+// wavefront claims the slots of its element's lanes with an atomic); results
+// do not depend on it beyond the summation order of the FP64 node sums.
+//   k_sort_hist     per-element counts (one atomic per element per wavefront)
 //   k_sort_scan_*   exclusive scan of the counts (blocks, block totals), and
 //   k_sort_cursor   the per-case slot cursors
 //   k_sort_scatter  move every particle field to the other buffer set
@@ -15,33 +15,44 @@
 
 namespace pdfmc {
 
-__device__ inline void sort_runs(int key, bool& head, int& rank, int& len)
+// The lanes of the wavefront that hold the same key as this lane, wherever
+// they sit (one ballot per distinct key: particles leave their element
+// between sorts, so the lanes of one element are rarely contiguous by then).
+// rank = this lane's position among them, len = their count, first = the
+// lowest of them, head = this lane is first. Keys < 0 get len = 0.
+__device__ inline void sort_sets(int key, bool& head, int& rank, int& len, int& first)
 {
     const int lane = __lane_id();
-    const int prev = __shfl_up(key, 1);
-    head = (lane == 0) || (prev != key);
-    const unsigned long long hm = __ballot(head);
-    // first lane of my run, last lane of my run
-    const unsigned long long below = hm & (~0ull >> (63 - lane));
-    const int first = 63 - __clzll(below);
-    const unsigned long long above = hm & ~(~0ull >> (63 - lane));
-    const int next = above ? (__ffsll(above) - 1) : 64;
-    rank = lane - first;
-    len = next - first;
+    unsigned long long mine = 0;
+    unsigned long long rem = __ballot(key >= 0);
+    while (rem) {
+        const int k = __shfl(key, __ffsll((long long)rem) - 1);
+        const unsigned long long set = __ballot(key == k);
+        if (key == k) mine = set;
+        rem &= ~set;
+    }
+    first = mine ? __ffsll((long long)mine) - 1 : lane;
+    head = mine != 0 && first == lane;
+    rank = __popcll(mine & ((1ull << lane) - 1));
+    len = __popcll(mine);
 }
+
+// the tile of a wavefront: block sizes are multiples of 64 and TILE of the
+// block size, so a wavefront lies inside one tile
+__device__ inline int wave_tile(int64_t gid) { return __builtin_amdgcn_readfirstlane((int)(gid / TILE)); }
 
 __global__ void k_sort_hist(SortArgs A)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int tile = (int)(gid / TILE);
+    const int tile = wave_tile(gid);
     if (tile >= A.ntiles) return;
-    const CaseDev& C = A.cases[A.tile_case[tile]];
+    const CaseDev& C = A.cases[__builtin_amdgcn_readfirstlane(A.tile_case[tile])];
     const int64_t i = gid - C.poff;
     const bool valid = i >= 0 && i < C.np;
     const int key = valid ? A.elem[gid] : -1;
-    bool head; int rank, len;
-    sort_runs(key, head, rank, len);
-    if (head && key >= 0) atomicAdd(A.count + key, len);
+    bool head; int rank, len, first;
+    sort_sets(key, head, rank, len, first);
+    if (head) atomicAdd(A.count + key, len);
 }
 
 // Exclusive scan of count[0..ne) in three passes: a scan inside each block of
@@ -110,19 +121,17 @@ template <typename R>
 __global__ void k_sort_scatter(SortArgs A, Particles<R> src, Particles<R> dst)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int tile = (int)(gid / TILE);
+    const int tile = wave_tile(gid);
     if (tile >= A.ntiles) return;
-    const CaseDev& C = A.cases[A.tile_case[tile]];
+    const CaseDev& C = A.cases[__builtin_amdgcn_readfirstlane(A.tile_case[tile])];
     const int64_t i = gid - C.poff;
     const bool valid = i >= 0 && i < C.np;
     const int key = valid ? src.elem[gid] : -1;
-    bool head; int rank, len;
-    sort_runs(key, head, rank, len);
+    bool head; int rank, len, first;
+    sort_sets(key, head, rank, len, first);
     unsigned long long base = 0;
-    if (head && key >= 0) base = atomicAdd((unsigned long long*)(A.cursor + key), (unsigned long long)len);
-    // broadcast the run head's base to the run
-    const int lane = __lane_id();
-    const int first = lane - rank;
+    if (head) base = atomicAdd((unsigned long long*)(A.cursor + key), (unsigned long long)len);
+    // broadcast the head's base to the lanes of its element
     base = __shfl(base, first);
     if (!valid) return;
     const int64_t q = (int64_t)base + rank;
