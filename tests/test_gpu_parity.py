@@ -160,6 +160,39 @@ def test_one_step_frozen_bitwise(P, oracle_mod, ns, nb):
     assert rc_["reflect"] > 0 and rc_["periodic"] > 0
 
 
+def test_frozen_table_overflow(P, oracle_mod):
+    """Two particles per element: a workgroup of 256 particles meets about
+    128 elements, more than the 32 slots of its LDS table, so most elements'
+    node and cell sums take the direct-atomic path. The FP64 state, node sums,
+    cell means and statistics still match the oracle after each step."""
+    ns, nb = 2, 8
+    mesh, params, parts, F = _frozen_case(ns, nb, ppe=2)
+    n = len(parts["x"])
+    _flush(f"[frozen_table_overflow] ns={ns} nb={nb} particles={n} tiles={(n + 255) // 256}")
+    sim, cs, o, oc = _pair(P, oracle_mod, mesh, params, parts, fields=F)
+    sim.init(); o.init()
+    gm, gc = sim.cell_means(cs)
+    rm, rc = o.cell_means(oc)
+    assert np.array_equal(gc, rc)
+    np.testing.assert_allclose(gm, rm, rtol=1e-13, atol=1e-15)
+    for step in range(3):
+        sim.step(1); o.step(1)
+        g, r = sim.download(cs, n), o.download(oc, n)
+        _assert_state_equal(g, r)
+        assert np.array_equal(g["bin"], r["bin"])
+        gs, rs = sim.node_sums(cs), o.node_sums(oc)
+        tol = 1e-13 * np.abs(rs).max(0) + 1e-300
+        assert np.all(np.abs(gs - rs) <= np.maximum(tol, 1e-13 * np.abs(rs))), np.max(np.abs(gs - rs))
+        gm, gc = sim.cell_means(cs)
+        rm, rc = o.cell_means(oc)
+        assert np.array_equal(gc, rc)
+        np.testing.assert_allclose(gm, rm, rtol=1e-12, atol=1e-14)
+        gst, rst = sim.stats(cs), o.stats(oc)
+        rows = _stat_rows(sim, cs)
+        d = np.abs(gst - rst)[rows] / _scale(rst, ns)[rows]
+        assert d.max() <= 1e-12, (step, d.max())
+
+
 @pytest.mark.parametrize("reaction,ns,k", [(1, 2, (3.0, 0.7, 0.0, 0.0)), (2, 3, (4.0, 0.0, 0.0, 0.0)),
                                             (2, 4, (2.5, 0.0, 0.0, 0.0))])
 def test_reaction_frozen_bitwise(P, oracle_mod, reaction, ns, k):
