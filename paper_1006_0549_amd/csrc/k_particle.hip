@@ -59,7 +59,8 @@ struct WalkCount { int refl, per, steps, fallback; };
 // FP32, whose rounding near thin wall cells can make every element look
 // slightly outside, keeps the visited element with the largest min lambda.
 template <typename R>
-__device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R u3[3], R lam[3], WalkCount& wc)
+__device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R u3[3], R lam[3], WalkCount& wc,
+                    const int4 nb_start)
 {
     int nrefl = 0;
     int prev = -1;
@@ -76,7 +77,8 @@ __device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R 
         if constexpr (sizeof(R) == 4) {
             if (lam[k] > best_min) { best = e; best_min = lam[k]; best_x = x; best_y = y; }
         }
-        const int nb = pick(M.nbr[e], k);
+        // the start element's neighbours were loaded with its other tables
+        const int nb = pick(it == 0 ? nb_start : M.nbr[e], k);
         const BcDev* bc = nb >= 0 ? nullptr : &M.bc[-1 - nb];
         const int next = nb >= 0 ? nb : (bc->type == 1 ? pick(M.partner[e], k) : e);
         if constexpr (sizeof(R) == 4) {
@@ -234,6 +236,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         bary<R>(A.M.rec, e, x, y, lam);
         sn = A.M.tri_s[e];
         if (A.advance) {
+            const int4 nbe = A.M.nbr[e];
             R f[NF];
             {
                 // R-06, row by row: f = fma(l2, F2, fma(l1, F1, l0 F0)), so
@@ -305,7 +308,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             om = omn;
             // tracking (R-12..R-15)
             if (__builtin_isfinite(x) && __builtin_isfinite(y)) {
-                e = walk<R>(A.M, C, e, x, y, u3, lam, wc);
+                e = walk<R>(A.M, C, e, x, y, u3, lam, wc, nbe);
             } else {
                 nans = 1;
             }

@@ -189,8 +189,17 @@ def test_frozen_table_overflow(P, oracle_mod):
         np.testing.assert_allclose(gm, rm, rtol=1e-12, atol=1e-14)
         gst, rst = sim.stats(cs), o.stats(oc)
         rows = _stat_rows(sim, cs)
-        d = np.abs(gst - rst)[rows] / _scale(rst, ns)[rows]
-        assert d.max() <= 1e-12, (step, d.max())
+        # With about a dozen particles per node a mean of U or psi can be a
+        # near-cancelling sum: the summation order (atomics here, particle
+        # order in the oracle) moves it by about n eps sum|w Q| / W, which is
+        # at most n eps <Q^2>^(1/2). So the means are scaled by their RMS
+        # here, the size of what is summed, as the central moments already are.
+        sc = _scale(rst, ns)
+        sc[:, 2:5] = np.maximum(sc[:, 2:5], np.sqrt(np.maximum(rst[:, 5:8] + rst[:, 2:5] ** 2, 0.0)))
+        for a in range(ns):
+            sc[:, 12 + a] = np.maximum(sc[:, 12 + a], np.sqrt(np.maximum(rst[:, 12 + ns + a] + rst[:, 12 + a] ** 2, 0.0)))
+        d = np.abs(gst - rst)[rows] / sc[rows]
+        assert d.max() <= 1e-12, (step, d.max(), np.unravel_index(np.argmax(d), d.shape))
 
 
 @pytest.mark.parametrize("reaction,ns,k", [(1, 2, (3.0, 0.7, 0.0, 0.0)), (2, 3, (4.0, 0.0, 0.0, 0.0)),
