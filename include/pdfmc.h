@@ -218,7 +218,7 @@ pdfmc_status pdfmc_projection_info(pdfmc_ctx* ctx, int32_t* method, int32_t* hei
  * and keeps the fastest, by coordinate descent over
  *   particle-kernel block size   64, 128, 256
  *   sort interval                1, 2, 5, 10, 20 steps
- *   multigrid tail threshold     0, 64, 256, 1024 rows (pdfmc_set_solver)
+ *   multigrid tail threshold     0, 64, 256, 512, 1024, 2048 rows (pdfmc_set_solver)
  * Each trial runs one untimed step, then max(steps_per_trial, a multiple of
  * the sort interval) timed steps. The trial steps advance the simulation
  * exactly like pdfmc_step (the results do not depend on the settings beyond

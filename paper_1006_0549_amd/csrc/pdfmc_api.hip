@@ -1768,7 +1768,7 @@ pdfmc_status pdfmc_autotune(pdfmc_ctx* c, int32_t steps_per_trial, pdfmc_tune_re
     // coordinate descent: block size, then sort interval, then the small-level threshold
     const int blocks[] = {64, 128, 256};
     const int sorts[] = {1, 2, 5, 10, 20};
-    const int tails[] = {0, 64, 256, 1024};
+    const int tails[] = {0, 64, 256, 512, 1024, 2048};
     for (int b : blocks) {
         double per;
         TRY(trial(b, best_s, best_t, std::max(steps_per_trial, best_s), per));

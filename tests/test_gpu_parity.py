@@ -441,8 +441,8 @@ def test_autotune_settings_and_invariance(P):
     r = sims[0][0].autotune(steps_per_trial=1)
     assert r["block_size"] in (64, 128, 256)
     assert r["sort_interval"] in (1, 2, 5, 10, 20)
-    assert r["tail_rows"] in (0, 64, 256, 1024)
-    assert r["trials"] == 3 + 5 + 4 and r["ms_per_step"] > 0.0 and r["steps"] > 12
+    assert r["tail_rows"] in (0, 64, 256, 512, 1024, 2048)
+    assert r["trials"] == 3 + 5 + 6 and r["ms_per_step"] > 0.0 and r["steps"] > 12
     sims[1][0].step(r["steps"])
     (a, a1, a2), (b, b1, b2) = sims
     n = len(parts["x"])
