@@ -67,32 +67,46 @@ __global__ void k_node_stats(NodeArgs A)
     }
 }
 
+// Eight lanes per element, lane b for velocity bin b, so that the cell sums
+// are read and the means written in contiguous runs. The sums pooled over the
+// element's sparse bins are gathered by shuffles in bin order, the order of a
+// loop over the bins.
 template <typename R>
 __global__ void k_cell_means(NodeArgs A, R* __restrict__ cmean)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= A.ne) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = (int)(t >> 3), b = (int)(t & 7);
+    if (e >= A.ne) return;            // the eight lanes of an element leave together
     const int c = A.elem_case[e];
     const CaseDev& C = A.cases[c];
     const int ns = C.ns;
     if (ns == 0) return;
     const int el = e - C.eoff;
-    const int32_t* cnt = A.ccnt + (int64_t)e * 8;
-    const double* cs = A.csum + C.csoff + (int64_t)el * 8 * (1 + ns);
+    const int cnt = A.ccnt[(int64_t)e * 8 + b];
+    const double* cs = A.csum + C.csoff + ((int64_t)el * 8 + b) * (1 + ns);
+    const bool pool = cnt > 0 && cnt < C.nmin;
+    const double w = cs[0];
+    double p[MAXS] = {0.0, 0.0, 0.0, 0.0};
+    for (int a = 0; a < ns; ++a) p[a] = cs[1 + a];
     double rw = 0.0, rp[MAXS] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = 0; b < 8; ++b)
-        if (cnt[b] > 0 && cnt[b] < C.nmin) {
-            rw += cs[b * (1 + ns)];
-            for (int a = 0; a < ns; ++a) rp[a] += cs[b * (1 + ns) + 1 + a];
+#pragma unroll
+    for (int bb = 0; bb < 8; ++bb) {
+        const bool pb = __shfl(pool ? 1 : 0, bb, 8) != 0;
+        const double wb = __shfl(w, bb, 8);
+        if (pb) rw += wb;
+#pragma unroll
+        for (int a = 0; a < MAXS; ++a) {
+            const double pa = __shfl(p[a], bb, 8);
+            if (pb && a < ns) rp[a] += pa;
         }
-    R* out = cmean + C.cmoff + (int64_t)el * 8 * ns;
-    for (int b = 0; b < 8; ++b)
-        for (int a = 0; a < ns; ++a) {
-            double m = 0.0;
-            if (cnt[b] >= C.nmin) m = cs[b * (1 + ns) + 1 + a] / cs[b * (1 + ns)];
-            else if (rw > 0.0) m = rp[a] / rw;
-            out[b * ns + a] = (R)m;
-        }
+    }
+    R* out = cmean + C.cmoff + ((int64_t)el * 8 + b) * ns;
+    for (int a = 0; a < ns; ++a) {
+        double m = 0.0;
+        if (cnt >= C.nmin) m = p[a] / w;
+        else if (rw > 0.0) m = rp[a] / rw;
+        out[a] = (R)m;
+    }
 }
 template __global__ void k_cell_means<double>(NodeArgs, double*);
 template __global__ void k_cell_means<float>(NodeArgs, float*);
@@ -236,7 +250,7 @@ __global__ void k_fields_derived(NodeArgs A)
         for (int l = 0; l < 3; ++l) h -= C.gamma5 * b[i][l] * dU[j][l];
         double val = kf * h;
         if (i == j) val += 0.5 * (1.0 - C.C1) * ef;
-        A.er_r[(int64_t)q * A.nn + s] = val;
+        A.er_r[(int64_t)s * NER + q] = val;
         A.er_dval[(int64_t)q * A.nn + s] = -4.5 * ef * nvec[i] * nvec[j];
     }
     const double lt = kf * __builtin_sqrt(kf) / ef;
@@ -272,7 +286,7 @@ __global__ void k_er_assemble(NodeArgs A)
             const double Mab = Ae / 12.0 * (a == cc ? 2.0 : 1.0);
             const double Kab = Ae * (rc[2 + a] * rc[2 + cc] + rc[5 + a] * rc[5 + cc]);
             A.er_val[A.incpos[3 * (int64_t)j + cc]] += Mab + L2e * Kab;
-            for (int q = 0; q < NER; ++q) rhs[q] += Mab * A.er_r[(int64_t)q * A.nn + t[cc]];
+            for (int q = 0; q < NER; ++q) rhs[q] += Mab * A.er_r[(int64_t)t[cc] * NER + q];
         }
     }
     if (A.is_wall[s]) {

@@ -581,9 +581,9 @@ pdfmc_status enqueue_cell_means(pdfmc_ctx* c)
     if (!c->any_scalars) return PDFMC_OK;
     NodeArgs A = node_args(c);
     if (c->prec == PDFMC_FP64)
-        hipLaunchKernelGGL(k_cell_means<double>, dim3(nblk(c->NE, 256)), dim3(256), 0, c->stream, A, (double*)c->d_cmean);
+        hipLaunchKernelGGL(k_cell_means<double>, dim3(nblk(8 * (int64_t)c->NE, 256)), dim3(256), 0, c->stream, A, (double*)c->d_cmean);
     else
-        hipLaunchKernelGGL(k_cell_means<float>, dim3(nblk(c->NE, 256)), dim3(256), 0, c->stream, A, (float*)c->d_cmean);
+        hipLaunchKernelGGL(k_cell_means<float>, dim3(nblk(8 * (int64_t)c->NE, 256)), dim3(256), 0, c->stream, A, (float*)c->d_cmean);
     LAUNCHCHK(c);
     return PDFMC_OK;
 }

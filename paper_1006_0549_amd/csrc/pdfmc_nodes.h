@@ -31,7 +31,7 @@ struct NodeArgs {
     double* kf;                      // [nn] floored k
     double* ef;                      // [nn] floored eps
     double* L2;                      // [nn]
-    double* er_r;                    // [5][nn] relaxation sources
+    double* er_r;                    // [nn][5] relaxation sources (a node's five together)
     double* er_dval;                 // [5][nn] wall values
     double* er_b;                    // [nn][5] right-hand sides (components interleaved)
     double* er_x;                    // [nn][5] relaxed tensor (warm start)
