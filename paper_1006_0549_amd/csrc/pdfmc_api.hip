@@ -246,6 +246,7 @@ struct pdfmc_ctx {
     int mg_iters = 32, mg_auto = 1, tail_rows = 64;
     unsigned int* h_need = nullptr;   // pinned: iterations the last observed solve needed
     hipEvent_t need_ev = nullptr;
+    int need_tick = 0;                 // steps since the last readback of the needed iterations
     bool need_pending = false;
     int need_low = 0;
     std::vector<AmgDev> h_amgdev;   // host copies of what the solver tables point at
@@ -805,9 +806,17 @@ pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
 
 // After a step: fetch the iteration count the solves needed (asynchronously);
 // before a step: adapt the number of unrolled iterations to what was needed.
+constexpr int NEED_EVERY = 8;
+
 pdfmc_status mg_after_step(pdfmc_ctx* c)
 {
     if (!c->mg_auto || !c->any_er || c->need_pending || !c->h_need) return PDFMC_OK;
+    // one readback every NEED_EVERY steps: a copy between two graph launches
+    // costs more than the adaptation gains from reacting a few steps sooner
+    // (a system that needs more iterations meanwhile is completed by
+    // k_mg_finish)
+    if (++c->need_tick < NEED_EVERY) return PDFMC_OK;
+    c->need_tick = 0;
     HIPCHK(c, hipMemcpyAsync(c->h_need, c->d_mg_need, sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipEventRecord(c->need_ev, c->stream));
     c->need_pending = true;
@@ -828,7 +837,8 @@ void mg_adapt(pdfmc_ctx* c)
         want = need + margin;
         c->need_low = 0;
     } else if (need + 2 * margin < c->mg_iters) {
-        if (++c->need_low >= 8) { want = need + margin; c->need_low = 0; }
+        // two low readings in a row (16 steps) before unrolling fewer
+        if (++c->need_low >= 2) { want = need + margin; c->need_low = 0; }
     } else {
         c->need_low = 0;
     }
