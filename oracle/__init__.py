@@ -105,8 +105,11 @@ def lib():
         for name in ("orc_add_case", "orc_mesh_info", "orc_particles_upload", "orc_particles_download",
                      "orc_fields_upload", "orc_fields_download", "orc_pressure_download", "orc_init",
                      "orc_rebin", "orc_step", "orc_stats", "orc_node_sums", "orc_cell_means",
-                     "orc_counters", "orc_bary", "orc_recover"):
+                     "orc_counters", "orc_bary", "orc_recover", "orc_set_stats", "orc_derive"):
             getattr(L, name).restype = C.c_int
+        L.orc_relax_source.restype = C.c_int
+        L.orc_relax_source.argtypes = [C.c_void_p] + [C.POINTER(C.c_double)] * 2 + [C.c_double, C.c_double] + \
+            [C.POINTER(C.c_double)] * 5
         _lib = L
     return _lib
 
@@ -143,6 +146,23 @@ def gauss6(seed, pid, step, stream):
     o = (C.c_double * 6)()
     lib().orc_gauss6(seed, pid, step, stream, o)
     return np.array(o[:])
+
+
+def relax_source(params, stress, grad, k, eps, normal=(0.0, 0.0)):
+    """Elliptic-relaxation source of R-19 at one node: stress = <u1u1>,
+    <u2u2>, <u3u3>, <u1u2>, <u1u3>, <u2u3>; grad = d<U_i>/dx_j (i-major,
+    j = x, y). Returns (r, dval) for the components 11, 12, 21, 22, 33, L^2
+    and A_v."""
+    ps = _params_struct(params)
+    st = (C.c_double * 6)(*[float(v) for v in stress])
+    gr = (C.c_double * 6)(*[float(v) for v in grad])
+    nn = (C.c_double * 2)(*[float(v) for v in normal])
+    r, dv = (C.c_double * 5)(), (C.c_double * 5)()
+    L2, Av = C.c_double(), C.c_double()
+    rc = lib().orc_relax_source(C.byref(ps), st, gr, float(k), float(eps), nn, r, dv, C.byref(L2), C.byref(Av))
+    if rc != 0:
+        raise RuntimeError("orc_relax_source failed")
+    return np.array(r[:]), np.array(dv[:]), L2.value, Av.value
 
 
 def uniform6(seed, pid, step, stream):
@@ -309,6 +329,16 @@ class Oracle:
         out = np.zeros(NCOUNT, np.int64)
         self._check(self._L.orc_counters(self._c, cs, out.ctypes.data_as(C.POINTER(C.c_int64))), "counters")
         return dict(zip(COUNTER_NAMES, out.tolist()))
+
+    def set_stats(self, cs, stats):
+        """Overwrite the node statistics (per raw node, the layout of stats())."""
+        st = np.ascontiguousarray(stats, dtype=np.float64)
+        self._check(self._L.orc_set_stats(self._c, cs, _dp(st)), "set_stats")
+
+    def derive(self, cs, project=False):
+        """Eulerian fields from the current node statistics (and the
+        projection when `project`)."""
+        self._check(self._L.orc_derive(self._c, cs, int(bool(project))), "derive")
 
     def bary(self, cs, e, x, y):
         lam = (C.c_double * 3)()

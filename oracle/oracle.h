@@ -17,12 +17,22 @@
  * Every point the paper leaves open is fixed by a numbered reading (R-nn),
  * listed in the design notes of the repository and restated where used.
  *
- * Parity unpinned: the production part k H_ijkl d<U_k>/dx_l of the
- * elliptic-relaxation right-hand side (R-19). The paper only cites the model;
- * nothing it prints fixes that term, so the oracle's value of it is tied to
- * the GPU path only. The rest of the relaxation (the Helmholtz solve, the
- * isotropic part, the wall values, G_ij and C0 eps from the relaxed tensor)
- * is pinned by manufactured solutions and the kinetic-energy trace identity.
+ * Pins (CPU tests, each tied to something other than this code): the
+ * generator (rocRAND's Philox, libm, distributions), location against brute
+ * force, the boundary conditions against their closed forms, the SDEs against
+ * Ornstein-Uhlenbeck, Gamma and SLM-decay recurrences, interpolation through
+ * a frozen linear mean velocity, mixing invariants and its clamp, the
+ * estimator against partition of unity and brute force, recovery and the
+ * FEM solves against exact and manufactured solutions, production and
+ * S_omega under homogeneous shear, and the elliptic-relaxation source (its
+ * production part under simple shear, A_v and length-scale limits,
+ * isotropic part, wall values, G_ij and C0 eps) against hand-derived closed
+ * forms.
+ *
+ * Parity unpinned: the fully coupled model over many steps (relaxation and
+ * projection feeding back into the particles). The paper prints no numbers
+ * for it (its figures are not part of the text), so beyond the pins of each
+ * part its output is tied to the GPU path only.
  *
  * Ownership: every pointer argument is borrowed for the duration of the call.
  * Errors: functions return 0 on success and a positive code otherwise; the
@@ -142,6 +152,19 @@ int orc_fem_helmholtz(orc_ctx* c, int32_t cs, const double* L2, const double* r,
 /* P1 projection solve: int grad N . grad phi = (1/dt) int grad N . U, zero mean */
 int orc_fem_projection(orc_ctx* c, int32_t cs, const double* U1, const double* U2,
                        double dt, double tol, double* phi);
+
+/* ---- test hooks of the Eulerian side ---- */
+/* overwrite the node statistics (per raw node, the layout of orc_stats) */
+int orc_set_stats(orc_ctx* c, int32_t cs, const double* stats);
+/* derive the Eulerian fields from the current node statistics (R-16..R-20,
+ * R-19 relaxation, and with project != 0 the projection of R-27) */
+int orc_derive(orc_ctx* c, int32_t cs, int32_t project);
+/* the elliptic-relaxation source of R-19 at one node:
+ * stress = <u1u1>,<u2u2>,<u3u3>,<u1u2>,<u1u3>,<u2u3>; grad = d<U_i>/dx_j,
+ * i-major, j = x, y; k and eps as used (floored); n = wall normal.
+ * Out: r and dval for the components 11, 12, 21, 22, 33, L^2 and A_v. */
+int orc_relax_source(const orc_params* p, const double stress[6], const double grad[6], double k, double eps,
+                     const double n[2], double r[5], double dval[5], double* L2, double* Av);
 
 #ifdef __cplusplus
 }

@@ -316,3 +316,32 @@ int orc_fem_projection(orc_ctx* c, int32_t ci, const double* U1, const double* U
     free(t);
     return rc ? orc_err(c, 3, "projection: no convergence") : ORC_OK;
 }
+
+int orc_set_stats(orc_ctx* c, int32_t ci, const double* stats)
+{
+    ocase* cs = get_case(c, ci);
+    if (!cs || !stats) return orc_err(c, ORC_E_INVALID, "set_stats: bad argument");
+    int nst = 12 + 2 * cs->p.n_scalars;
+    for (int s = 0; s < cs->m.nsn; ++s)
+        memcpy(cs->stats + (size_t)s * nst, stats + (size_t)cs->m.rep[s] * nst, sizeof(double) * nst);
+    cs->have_stats = 1;
+    return ORC_OK;
+}
+
+int orc_derive(orc_ctx* c, int32_t ci, int32_t project)
+{
+    ocase* cs = get_case(c, ci);
+    if (!cs) return orc_err(c, ORC_E_INVALID, "derive: bad case");
+    return orc_derive_fields(c, cs, project != 0);
+}
+
+int orc_relax_source(const orc_params* p, const double stress[6], const double grad[6], double k, double eps,
+                     const double n[2], double r[5], double dval[5], double* L2, double* Av)
+{
+    if (!p || !stress || !grad || !n || !r || !dval || !L2) return ORC_E_INVALID;
+    double R[3][3] = {{stress[0], stress[3], stress[4]}, {stress[3], stress[1], stress[5]},
+                      {stress[4], stress[5], stress[2]}};
+    double dU[3][3] = {{grad[0], grad[1], 0.0}, {grad[2], grad[3], 0.0}, {grad[4], grad[5], 0.0}};
+    orc_relax_node(p, R, dU, k, eps, n[0], n[1], r, dval, L2, Av);
+    return ORC_OK;
+}

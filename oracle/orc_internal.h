@@ -85,6 +85,8 @@ int  orc_case_step(orc_ctx* c, ocase* cs, uint32_t n);
 int  orc_case_rebin(ocase* cs);
 int  orc_node_moments(ocase* cs);
 int  orc_derive_fields(orc_ctx* c, ocase* cs, int project);
+void orc_relax_node(const orc_params* P, const double R[3][3], const double dU[3][3], double K, double E,
+                    double nx, double ny, double r[5], double dval[5], double* L2, double* Av_out);
 void orc_recover_grad(const omesh* m, const double* f, double* gx, double* gy);
 void orc_recover_lap(const omesh* m, const double* gx, const double* gy, double* lap);
 

@@ -294,6 +294,47 @@ static double det3(const double R[3][3])
          + R[0][2] * (R[1][0] * R[2][1] - R[1][1] * R[2][0]);
 }
 
+/* R-19 at one node (the elliptic relaxation of Dreeben & Pope, cited after
+ * Eq.(4)): for the five components (11, 12, 21, 22, 33) of the relaxed
+ * tensor, the right-hand side
+ *   r_ij = 1/2 (1 - C1) eps delta_ij + k H_ijkl d<U_k>/dx_l,
+ *   H_ijkl d_l U_k = (C2 A_v + g5/3) d_j U_i - (g5/3) d_i U_j
+ *                    + g5 b_ik d_j U_k - g5 b_il d_l U_j,
+ * b_ij = <u_i u_j>/(2k) - delta_ij/3, A_v = min(1, Cv det<uu> / (2k/3)^3),
+ * the wall value -4.5 eps n_i n_j (used where the node is on a wall), and the
+ * squared length scale L^2, L = CL max(k^3/2 / eps, Ceta nu^3/4 / eps^1/4).
+ * R is <u_i u_j>, dU[i][j] = d<U_i>/dx_j (j = 3 is zero, R-01); K and E are
+ * the floored k and eps (R-18). */
+void orc_relax_node(const orc_params* P, const double R[3][3], const double dU[3][3], double K, double E,
+                    double nx, double ny, double r[5], double dval[5], double* L2, double* Av_out)
+{
+    static const int ci[5] = {0, 0, 1, 1, 2}, cj[5] = {0, 1, 0, 1, 2};
+    double b[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) b[i][j] = R[i][j] / (2.0 * K) - (i == j ? 1.0 / 3.0 : 0.0);
+    double k23 = (2.0 / 3.0) * K;
+    double Av = P->Cv * det3(R) / (k23 * k23 * k23);
+    if (Av > 1.0) Av = 1.0;
+    double cA = P->C2 * Av + P->gamma5 / 3.0;
+    for (int q = 0; q < 5; ++q) {
+        int i = ci[q], j = cj[q];
+        double h = cA * dU[i][j] - (P->gamma5 / 3.0) * dU[j][i];
+        for (int kk = 0; kk < 3; ++kk) h += P->gamma5 * b[i][kk] * dU[kk][j];
+        for (int l = 0; l < 3; ++l) h -= P->gamma5 * b[i][l] * dU[j][l];
+        double val = K * h;
+        if (i == j) val += 0.5 * (1.0 - P->C1) * E;
+        r[q] = val;
+        double nvec[3] = {nx, ny, 0.0};
+        dval[q] = -4.5 * E * nvec[i] * nvec[j];
+    }
+    double nu34 = sqrt(P->nu * sqrt(P->nu));
+    double lt = K * sqrt(K) / E;
+    double lk = P->Ceta * nu34 / sqrt(sqrt(E));
+    double L = P->CL * (lt > lk ? lt : lk);
+    *L2 = L * L;
+    if (Av_out) *Av_out = Av;
+}
+
 /* Eulerian fields from the node statistics (R-16..R-20, R-27). */
 int orc_derive_fields(orc_ctx* c, ocase* cs, int project)
 {
@@ -343,45 +384,26 @@ int orc_derive_fields(orc_ctx* c, ocase* cs, int project)
     }
     int rc = ORC_OK;
     if (P->mode == ORC_MODE_ER) {
-        /* R-19: elliptic relaxation, wp_ij - div(L^2 grad wp_ij) = r_ij,
-         * r_ij = 1/2 (1 - C1) eps delta_ij + k H_ijkl d<U_k>/dx_l,
-         * wall: wp_ij = -4.5 eps n_i n_j; G_ij = (wp_ij - eps/2 delta_ij)/k */
-        static const int ci[5] = {0, 0, 1, 1, 2}, cj[5] = {0, 1, 0, 1, 2};
+        /* R-19: elliptic relaxation, wp_ij - div(L^2 grad wp_ij) = r_ij with
+         * the nodal sources, wall values and length scale of orc_relax_node;
+         * G_ij = (wp_ij - eps/2 delta_ij)/k */
         double* L2 = orc_alloc(sizeof(double) * nsn);
         double* r = orc_alloc(sizeof(double) * (size_t)nsn * 5);
         double* dv = orc_alloc(sizeof(double) * (size_t)nsn * 5);
         int* dm = orc_alloc(sizeof(int) * nsn);
-        double nu34 = sqrt(P->nu * sqrt(P->nu));
         for (int s = 0; s < nsn; ++s) {
             const double* st = cs->stats + (size_t)s * nst;
             const double* F = cs->F + (size_t)s * ORC_NF;
-            double K = kf[s], E = ef[s];
             double R[3][3] = {{st[5], st[8], st[9]}, {st[8], st[6], st[10]}, {st[9], st[10], st[7]}};
             double dU[3][3] = {{F[F_DU1X], F[F_DU1Y], 0.0}, {F[F_DU2X], F[F_DU2Y], 0.0},
                                {F[F_DU3X], F[F_DU3Y], 0.0}};   /* dU[i][j] = d<U_i>/dx_j */
-            double b[3][3];
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) b[i][j] = R[i][j] / (2.0 * K) - (i == j ? 1.0 / 3.0 : 0.0);
-            double k23 = (2.0 / 3.0) * K;
-            double Av = P->Cv * det3(R) / (k23 * k23 * k23);
-            if (Av > 1.0) Av = 1.0;
-            double cA = P->C2 * Av + P->gamma5 / 3.0;
+            double rq[5], dq[5], av;
+            orc_relax_node(P, R, dU, kf[s], ef[s], m->wnx[s], m->wny[s], rq, dq, &L2[s], &av);
             for (int q = 0; q < 5; ++q) {
-                int i = ci[q], j = cj[q];
-                double h = cA * dU[i][j] - (P->gamma5 / 3.0) * dU[j][i];
-                for (int kk = 0; kk < 3; ++kk) h += P->gamma5 * b[i][kk] * dU[kk][j];
-                for (int l = 0; l < 3; ++l) h -= P->gamma5 * b[i][l] * dU[j][l];
-                double val = K * h;
-                if (i == j) val += 0.5 * (1.0 - P->C1) * E;
-                r[(size_t)q * nsn + s] = val;
-                double nvec[3] = {m->wnx[s], m->wny[s], 0.0};
-                dv[(size_t)q * nsn + s] = -4.5 * E * nvec[i] * nvec[j];
+                r[(size_t)q * nsn + s] = rq[q];
+                dv[(size_t)q * nsn + s] = dq[q];
             }
             dm[s] = m->is_wall[s];
-            double lt = K * sqrt(K) / E;
-            double lk = P->Ceta * nu34 / sqrt(sqrt(E));
-            double L = P->CL * (lt > lk ? lt : lk);
-            L2[s] = L * L;
         }
         double* wp = orc_alloc(sizeof(double) * (size_t)nsn * 5);
         for (int q = 0; q < 5 && rc == ORC_OK; ++q) {

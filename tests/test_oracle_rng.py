@@ -125,15 +125,3 @@ def test_streams_differ_by_step_id_and_stream(oracle_mod):
     assert not np.array_equal(a, oracle_mod.gauss6(1, 0, 0, 1))
     assert not np.array_equal(a, oracle_mod.gauss6(2, 0, 0, 0))
     np.testing.assert_array_equal(a, oracle_mod.gauss6(1, 0, 0, 0))
-
-
-def test_philox_known_answer_vectors(oracle_mod):
-    """The oracle's Philox4x32-10 against the generator authors' published
-    known-answer vectors (tests/golden/philox4x32_10_kat.txt)."""
-    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
-    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
-    assert len(rows) == 3
-    for r in rows:
-        v = [int(t, 16) for t in r]
-        ctr, key, want = v[0:4], v[4:6], v[6:10]
-        assert list(oracle_mod.philox(ctr, key)) == want
