@@ -59,7 +59,7 @@ typedef enum { PDFMC_MODE_FROZEN = 0, PDFMC_MODE_SLM = 1, PDFMC_MODE_ER = 2 } pd
 
 #define PDFMC_NF 22        /* Eulerian field slots per node (R-06)          */
 #define PDFMC_MAX_SCALARS 4
-#define PDFMC_N_COUNTERS 12
+#define PDFMC_N_COUNTERS 13
 
 typedef struct {
     int32_t type;          /* pdfmc_bc_type                                  */
@@ -167,7 +167,10 @@ pdfmc_status pdfmc_cell_means(pdfmc_ctx* ctx, int32_t case_id, double* mean, int
 /* Counters since upload, [PDFMC_N_COUNTERS]: walk fallbacks, reflections,
  * periodic crossings, omega sign flips, empty nodes, non-finite particles,
  * walk steps, ER CG iterations, projection CG iterations, CG failures,
- * k floor hits, eps floor hits. The five relaxation components of a case
+ * k floor hits, eps floor hits, scatter overflows (a workgroup's element sums
+ * that found no record slot or record list entry and were added with FP64
+ * atomics instead: while this counter is 0, every statistic is summed in a
+ * fixed order and a step repeats bit for bit). The five relaxation components of a case
  * are solved as one system with five right-hand sides: its iterations count
  * once per component (the iterations until every component converged). */
 pdfmc_status pdfmc_counters(pdfmc_ctx* ctx, int32_t case_id, int64_t* out);

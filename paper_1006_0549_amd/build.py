@@ -16,7 +16,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdfmc.so")
-HIP_SOURCES = ["pdfmc_api.hip", "k_particle.hip", "k_nodes.hip", "k_sort.hip", "k_mg.hip", "k_direct.hip"]
+HIP_SOURCES = ["pdfmc_api.hip", "k_particle.hip", "k_scatter.hip", "k_nodes.hip", "k_sort.hip", "k_mg.hip", "k_direct.hip"]
 CXX_SOURCES = ["pdfmc_mesh.cpp", "pdfmc_amg.cpp", "pdfmc_chol.cpp"]
 ARCH = os.environ.get("PDFMC_ARCH", "gfx950")
 

@@ -3,8 +3,7 @@
 // solves). Each kernel covers every case of the context in one launch:
 // threads map to global statistics nodes or elements and look up their case.
 //
-//   k_node_stats   node sums -> weighted means, central moments, density (R-11)
-//   k_cell_means   cell sums -> IECM cell means with the residual rule (R-23)
+//   (node statistics and cell means come from the scatter passes, k_scatter.hip)
 //   k_fields_grad  <U>, <omega>, recovered gradients of <U> (R-16)
 //   k_fields_derived  Laplacians (R-16), k, eps, production, S_omega
 //                  (Eq.(6), R-17, R-18), simplified Langevin G_ij (R-20) or
@@ -31,85 +30,6 @@ __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v)
 }
 
 __global__ void k_step_increment(uint32_t* step) { if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += 1u; }
-
-__global__ void k_node_stats(NodeArgs A)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= A.nn) return;
-    const int c = A.node_case[s];
-    const CaseDev& C = A.cases[c];
-    const int ns = C.ns;
-    const double* r = A.nsum + (int64_t)s * NQ;
-    double* st = A.stats + (int64_t)s * NST;
-    const double W = r[0];
-    // an empty node, or (once there are previous statistics) one whose
-    // effective sample size W^2 / sum (w N)^2 is below n_eff_min, keeps its
-    // previous moments (R-34)
-    st[0] = W;
-    st[1] = W / A.vol[s];
-    if (W > 0.0 && (A.first_stats || W * W >= C.neff_min * r[11 + 2 * ns])) {
-        const double m1 = r[1] / W, m2 = r[2] / W, m3 = r[3] / W;
-        st[2] = m1; st[3] = m2; st[4] = m3;
-        st[5] = r[4] / W - m1 * m1;
-        st[6] = r[5] / W - m2 * m2;
-        st[7] = r[6] / W - m3 * m3;
-        st[8] = r[7] / W - m1 * m2;
-        st[9] = r[8] / W - m1 * m3;
-        st[10] = r[9] / W - m2 * m3;
-        st[11] = r[10] / W;
-        for (int a = 0; a < ns; ++a) {
-            double m = r[11 + a] / W;
-            st[12 + a] = m;
-            st[12 + ns + a] = r[11 + ns + a] / W - m * m;
-        }
-    } else {
-        atomicAdd(A.counters + (int64_t)c * NCNT + C_EMPTY_NODE, 1ull);
-    }
-}
-
-// Eight lanes per element, lane b for velocity bin b, so that the cell sums
-// are read and the means written in contiguous runs. The sums pooled over the
-// element's sparse bins are gathered by shuffles in bin order, the order of a
-// loop over the bins.
-template <typename R>
-__global__ void k_cell_means(NodeArgs A, R* __restrict__ cmean)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int e = (int)(t >> 3), b = (int)(t & 7);
-    if (e >= A.ne) return;            // the eight lanes of an element leave together
-    const int c = A.elem_case[e];
-    const CaseDev& C = A.cases[c];
-    const int ns = C.ns;
-    if (ns == 0) return;
-    const int el = e - C.eoff;
-    const int cnt = A.ccnt[(int64_t)e * 8 + b];
-    const double* cs = A.csum + C.csoff + ((int64_t)el * 8 + b) * (1 + ns);
-    const bool pool = cnt > 0 && cnt < C.nmin;
-    const double w = cs[0];
-    double p[MAXS] = {0.0, 0.0, 0.0, 0.0};
-    for (int a = 0; a < ns; ++a) p[a] = cs[1 + a];
-    double rw = 0.0, rp[MAXS] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int bb = 0; bb < 8; ++bb) {
-        const bool pb = __shfl(pool ? 1 : 0, bb, 8) != 0;
-        const double wb = __shfl(w, bb, 8);
-        if (pb) rw += wb;
-#pragma unroll
-        for (int a = 0; a < MAXS; ++a) {
-            const double pa = __shfl(p[a], bb, 8);
-            if (pb && a < ns) rp[a] += pa;
-        }
-    }
-    R* out = cmean + C.cmoff + ((int64_t)el * 8 + b) * ns;
-    for (int a = 0; a < ns; ++a) {
-        double m = 0.0;
-        if (cnt >= C.nmin) m = p[a] / w;
-        else if (rw > 0.0) m = rp[a] / rw;
-        out[a] = (R)m;
-    }
-}
-template __global__ void k_cell_means<double>(NodeArgs, double*);
-template __global__ void k_cell_means<float>(NodeArgs, float*);
 
 // R-16: area-weighted average of the element gradients of a P1 field
 __device__ inline void recover_grad(const NodeArgs& A, const double* f, int fstride, int s, double& gx, double& gy)

@@ -9,16 +9,21 @@
 //   neighbour walk with wall reflection and periodic shift (R-12..R-15) ->
 //   concentrated sources (R-26) -> velocity bin against the fields of this
 //   step (R-23) -> shape-weighted sums of the new state at the element's
-//   three statistics nodes (R-11) and cell sums for the next mixing step.
+//   three vertices (R-11) and cell sums for the next mixing step.
 //
 // Layout: structure of arrays, one lane per particle, tiles of 256 particles
-// that never straddle two cases. The scatter first sums the particles of each
-// element inside a wavefront (particles are kept sorted by element, so a
-// wavefront holds few elements), adds the sums into a per-workgroup LDS table
-// keyed by element, and flushes the table with FP64 atomic adds, so a node
-// sees a few atomics per workgroup instead of one per particle. Arithmetic of the FP64 instantiation follows the operation
-// order of the readings exactly (no contraction; explicit fma only where the
-// readings put one), so that it reproduces the CPU oracle bit for bit.
+// that never straddle two cases. The scatter is deterministic and uses no
+// floating-point atomics: the workgroup lists the distinct elements of its
+// particles in a fixed order (first appearance in particle order), one
+// wavefront per element sums that element's particles from the whole
+// workgroup in particle order, and the sums go out as one record per
+// (workgroup, element) with plain stores. The records of an element are
+// summed in key order by the element pass, and the vertex sums of the
+// elements around a node by the node pass (k_scatter.hip). Arithmetic of the
+// FP64 instantiation follows the operation order of the readings exactly (no
+// contraction; explicit fma only where the readings put one), so that it
+// reproduces the CPU oracle bit for bit; only the summation order of the node
+// and cell sums differs.
 #include "pdfmc_dev.h"
 #include "pdfmc_math.h"
 
@@ -106,7 +111,9 @@ __device__ int walk(const MeshDev<R>& M, const CaseDev& C, int e, R& x, R& y, R 
             continue;
         }
         prev = -1;
-        if constexpr (sizeof(R) == 4) { ring[0] = ring[1] = ring[2] = ring[3] = -1; }  // a reflection turns the walk back
+        // a reflection turns the walk back: forget the cycle ring and the best
+        // element seen so far, whose position predates the mirrored velocity
+        if constexpr (sizeof(R) == 4) { ring[0] = ring[1] = ring[2] = ring[3] = -1; best_min = R(-1e30); }
         if (nrefl == 8) break;
         const R* v = M.exy + 6 * (int64_t)e;
         int ka = (k + 1) % 3, kb = (k + 2) % 3;
@@ -156,32 +163,26 @@ __device__ inline int wave_sum_int(int v)
     return v;
 }
 
-// ---------------------------------------------------------------- LDS table
+// ---------------------------------------------------------------- scatter helpers
 
-constexpr int HS = 32;                           // element slots per workgroup
-constexpr int NV = 3 * NQ + 8 * (2 + MAXS);      // node sums of 3 vertices + 8 cells
+constexpr int NREC = 8 + MAXS;                  // per-lane record: lambda_0..2, w, U_1..3, omega, psi_a
 
-constexpr int NREC = 8 + MAXS;                  // record: lambda_0..2, w, U_1..3, omega, psi_a
-
-__device__ inline void lds_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-// slot of element e in the table (claimed on first use), or -1 when full
-__device__ inline int lds_slot(int* keys, int e)
-{
-    int h = (int)(((unsigned)e * 2654435761u) >> 27) & (HS - 1);
-    for (int probe = 0; probe < HS; ++probe) {
-        const int old = atomicCAS(&keys[h], -1, e);
-        if (old == -1 || old == e) return h;
-        h = (h + 1) & (HS - 1);
+// A set of the workgroup's particles: one 64-bit lane mask per wavefront
+// (at most four), kept in separate scalars so that they stay in registers.
+struct WgSet {
+    unsigned long long m0, m1, m2, m3;
+    __device__ bool any() const { return (m0 | m1 | m2 | m3) != 0ull; }
+    __device__ int count() const { return __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3); }
+    // the lowest particle of the set, removed from it; -1 when empty
+    __device__ int pop()
+    {
+        if (m0) { const int l = __ffsll((long long)m0) - 1; m0 &= m0 - 1; return l; }
+        if (m1) { const int l = __ffsll((long long)m1) - 1; m1 &= m1 - 1; return 64 + l; }
+        if (m2) { const int l = __ffsll((long long)m2) - 1; m2 &= m2 - 1; return 128 + l; }
+        if (m3) { const int l = __ffsll((long long)m3) - 1; m3 &= m3 - 1; return 192 + l; }
+        return -1;
     }
-    return -1;
-}
-
-__device__ inline void put(double* vals, int slot, int v, double* global, double x)
-{
-    if (slot >= 0) lds_add(&vals[slot * NV + v], x);
-    else unsafeAtomicAdd(global, x);
-}
+};
 
 // ---------------------------------------------------------------- the kernel
 
@@ -196,13 +197,9 @@ __device__ inline void load_field_row(const R* __restrict__ F, int stride, int s
 template <typename R>
 __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
 {
-    __shared__ int s_key[HS];
-    __shared__ int s_used[HS + 1];        // flush: the used slots, then their count
-    __shared__ double s_val[HS * NV];
-    __shared__ __align__(16) R s_rec[256 * NREC];   // per-lane records for the node-sum reduction
-    for (int i = threadIdx.x; i < HS; i += blockDim.x) s_key[i] = -1;
-    for (int i = threadIdx.x; i < HS * NV; i += blockDim.x) s_val[i] = 0.0;
-    __syncthreads();
+    __shared__ __align__(16) R s_rec[256 * NREC];   // per-lane records of the new state
+    __shared__ int s_key[256];                       // element of each lane (-1: no particle)
+    __shared__ int s_bin[256];                       // velocity bin of each lane
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // block sizes are multiples of 64 and TILE of the block size, so a
     // wavefront lies inside one tile: the tile, the case and its constants
@@ -341,172 +338,210 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         if (A.do_bins) A.P.bin[p] = (uint8_t)bin;
     }
 
-    // ---- shape-weighted node sums of the new state (R-11) and cell sums
-    // (R-23), FP64, into a per-workgroup LDS table keyed by element: the node
-    // sums of the particles of one element are summed in the wavefront first,
-    // the cell sums are added particle by particle. After the barrier the
-    // table is flushed with one FP64 atomic per (element, value). A table
-    // overflow falls back to direct atomics.
+    // ---- shape-weighted sums of the new state at the element's vertices
+    // (R-11) and cell sums (R-23), FP64, deterministic. Every lane stores its
+    // record in LDS. All wavefronts then walk the workgroup's distinct
+    // elements in the same fixed order (first appearance in particle order);
+    // wavefront (rank mod waves) handles an element: it sums, over the
+    // element's particles of the whole workgroup taken in particle order,
+    // the vertex terms w lambda_k Q and, per velocity bin, the cell terms
+    // w and w psi_a, and stores them as the record (workgroup, element).
     const int nq = 12 + 2 * ns;
-    int myslot = -1;   // table slot of this lane's element, found by the node-sum pass
+    const bool cells = A.do_bins && ns > 0;
+    const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     {
-        // Node sums. Every lane stores its particle's record in LDS. Then the
-        // wavefront takes the elements present in it one at a time (a ballot
-        // per element, so the particles of an element form one set however
-        // far the order has frayed since the last sort). For a set, the
-        // wavefront splits into G groups of lanes; lane q of group g sums
-        // term q of all three vertices over the set's g-th, (g+G)-th, ...
-        // particles, the group sums are combined with shuffles, and group 0
-        // adds the totals to the element's slot of the workgroup table. The
-        // terms are the FP64 products w lambda_k Q of R-11, as in the oracle.
-        static_assert(256 * NREC * sizeof(R) + HS * NV * 8 < 64 * 1024, "LDS");
-        const int key = valid ? e : -1;
-        const int lane = __lane_id(), wid = threadIdx.x >> 6;
-        R* my = s_rec + (wid * 64 + lane) * NREC;
+        R* my = s_rec + threadIdx.x * NREC;
         my[0] = lam[0]; my[1] = lam[1]; my[2] = lam[2]; my[3] = wt;
         my[4] = u3[0]; my[5] = u3[1]; my[6] = u3[2]; my[7] = om;
         for (int a = 0; a < ns; ++a) my[8 + a] = psi[a];
-        __syncthreads();
-        // lane roles: 4 groups of 16 lanes when nq <= 16, else 3 groups of 21
-        const int G = nq <= 16 ? 4 : 3, GS = nq <= 16 ? 16 : 21;
-        const int g = lane / GS, q = lane - g * GS;
-        int ia = -1, ib = -1;
-        bool sq = false;
-        if (q >= 1 && q <= 3) ia = 4 + (q - 1);
-        else if (q >= 4 && q <= 6) ia = ib = 4 + (q - 4);
-        else if (q == 7) { ia = 4; ib = 5; }
-        else if (q == 8) { ia = 4; ib = 6; }
-        else if (q == 9) { ia = 5; ib = 6; }
-        else if (q == 10) ia = 7;
-        else if (q >= 11 && q < 11 + ns) ia = 8 + (q - 11);
-        else if (q >= 11 + ns && q < 11 + 2 * ns) ia = ib = 8 + (q - 11 - ns);
-        else if (q == 11 + 2 * ns) sq = true;
-        // term of vertex k: (w lambda_k) * fa_k * fb with fb = rec[ib] or 1
-        // and fa_k = fma(sqm, w lambda_k, fa): fa = rec[ia] or 1 when sqm = 0
-        // (then fa_k = fa exactly), fa = 0 and sqm = 1 for the square term
-        // (then fa_k = w lambda_k exactly), so each term is the same product,
-        // in the same order, as (w lambda_k) [* rec[ia]] [* rec[ib]] or
-        // (w lambda_k)^2
-        const int ia0 = ia >= 0 ? ia : 0, ib0 = ib >= 0 ? ib : 0;
-        const bool has_a = ia >= 0, has_b = ib >= 0;
-        const R ca = sq ? R(0) : R(1);
-        const double sqm = sq ? 1.0 : 0.0;
-        const R* wave_rec = s_rec + wid * 64 * NREC;
-        unsigned long long rem = __ballot(key >= 0);
-        while (rem) {
-            const int ks = __shfl(key, __ffsll((long long)rem) - 1);
-            const unsigned long long set = __ballot(key == ks);
-            rem &= ~set;
+        s_key[threadIdx.x] = valid ? e : -1;
+        s_bin[threadIdx.x] = bin;
+    }
+    __syncthreads();
+    // every wavefront holds the keys and bins of all the workgroup's lanes:
+    // those of wavefront t at (register t, lane)
+    const int kk0 = s_key[lane], kk1 = nw > 1 ? s_key[64 + lane] : -1;
+    const int kk2 = nw > 2 ? s_key[128 + lane] : -1, kk3 = nw > 3 ? s_key[192 + lane] : -1;
+    const int bb0 = s_bin[lane], bb1 = nw > 1 ? s_bin[64 + lane] : 0;
+    const int bb2 = nw > 2 ? s_bin[128 + lane] : 0, bb3 = nw > 3 ? s_bin[192 + lane] : 0;
+    WgSet rem = {__ballot(kk0 >= 0), __ballot(kk1 >= 0), __ballot(kk2 >= 0), __ballot(kk3 >= 0)};
+    // lane roles of the term loop: G groups of GS lanes, lane q of a group
+    // holds term q; vertex terms q < nq, cell terms nq <= q < nq + 1 + ns
+    const int nterm = nq + (cells ? 1 + ns : 0);
+    const int G = nterm <= 16 ? 4 : (nterm <= 21 ? 3 : 2), GS = nterm <= 16 ? 16 : (nterm <= 21 ? 21 : 32);
+    const int g = lane / GS, q = lane - g * GS;
+    // vertex term q: (w lambda_k) * fa_k * fb, fa_k = fma(sqm, w lambda_k, fa),
+    // with fa = rec[ia] (or 1) and fb = rec[ib] (or 1); for the square term
+    // fa = 0 and sqm = 1, so fa_k = w lambda_k exactly, and every term is the
+    // same FP64 product, in the same order, as in the oracle
+    int ia = -1, ib = -1;
+    bool sq = false;
+    if (q >= 1 && q <= 3) ia = 4 + (q - 1);
+    else if (q >= 4 && q <= 6) ia = ib = 4 + (q - 4);
+    else if (q == 7) { ia = 4; ib = 5; }
+    else if (q == 8) { ia = 4; ib = 6; }
+    else if (q == 9) { ia = 5; ib = 6; }
+    else if (q == 10) ia = 7;
+    else if (q >= 11 && q < 11 + ns) ia = 8 + (q - 11);
+    else if (q >= 11 + ns && q < 11 + 2 * ns) ia = ib = 8 + (q - 11 - ns);
+    else if (q == 11 + 2 * ns) sq = true;
+    // cell term: w * (1 or psi_a), as (w * 1) * fa with lambda taken as 1
+    const bool cterm = q >= nq && q < nterm;
+    if (cterm && q > nq) ia = 8 + (q - nq - 1);
+    const int ia0 = ia >= 0 ? ia : 0, ib0 = ib >= 0 ? ib : 0;
+    const bool has_a = ia >= 0, has_b = ib >= 0;
+    const R ca = sq ? R(0) : R(1);
+    const double sqm = sq ? 1.0 : 0.0;
+    const int64_t ltile = gid / TILE - C.poff / TILE;     // the case's tile of this workgroup
+    const int wg_slots = SC_RT * (int)blockDim.x / TILE;
+    const int wg_first = (int)((blockIdx.x * (int64_t)blockDim.x) % TILE) / (int)blockDim.x * wg_slots;
+    // the elements this wavefront handled: lane j holds the j-th (element, handle)
+    int my_el = -1, my_h = 0, nmine = 0;
+    int d = 0;
+    while (rem.any()) {
+        WgSet set;
+        int ks;
+        {
+            WgSet r2 = rem;
+            ks = s_key[r2.pop()];
+            set = {__ballot(kk0 == ks), __ballot(kk1 == ks), __ballot(kk2 == ks), __ballot(kk3 == ks)};
+            rem.m0 &= ~set.m0; rem.m1 &= ~set.m1; rem.m2 &= ~set.m2; rem.m3 &= ~set.m3;
+        }
+        if (d % nw == wid) {
+            // destination: a regular slot of the workgroup, else the pool
+            double* dst = nullptr;
+            int handle = 0;
+            if (d < wg_slots) {
+                handle = (int)(ltile * SC_RT) + wg_first + d;
+                dst = A.srec + C.rec_off + (int64_t)handle * C.rec_stride;
+            } else {
+                int pidx = 0;
+                if (lane == 0) pidx = atomicAdd(A.pool_cnt, 1);
+                pidx = __shfl(pidx, 0);
+                if (pidx < A.pool_cap) {
+                    handle = -1 - pidx;
+                    dst = A.srec + A.pool_off + (int64_t)pidx * A.pool_stride;
+                }
+            }
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            unsigned long long m = set;
-            while (m) {
-                // the set's next G particles, one per group
-                int pk[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    pk[t] = -1;
-                    if (t < G && m) { pk[t] = __ffsll((long long)m) - 1; m &= m - 1; }
+            unsigned long long packed0 = 0ull, packed1 = 0ull;
+            for (int b = 0; b < (cells ? 8 : 1); ++b) {
+                WgSet m = set;
+                if (cells) {
+                    m.m0 &= __ballot(bb0 == b); m.m1 &= __ballot(bb1 == b);
+                    m.m2 &= __ballot(bb2 == b); m.m3 &= __ballot(bb3 == b);
                 }
-                // g <= 3 always, and pk[3] = -1 when G = 3
-                int pp = pk[0];
-                pp = g == 1 ? pk[1] : pp;
-                pp = g == 2 ? pk[2] : pp;
-                pp = g == 3 ? pk[3] : pp;
-                if (pp >= 0) {
-                    const R* rq = wave_rec + pp * NREC;
-                    const R l0 = rq[0], l1 = rq[1], l2 = rq[2], rw = rq[3];
-                    const R xa = rq[ia0], xb = rq[ib0];
-                    const double fa = has_a ? (double)xa : (double)ca;
-                    const double fb = has_b ? (double)xb : 1.0;
-                    const double w = (double)rw;
-                    const double wn0 = w * (double)l0, wn1 = w * (double)l1, wn2 = w * (double)l2;
-                    a0 += (wn0 * __builtin_fma(sqm, wn0, fa)) * fb;
-                    a1 += (wn1 * __builtin_fma(sqm, wn1, fa)) * fb;
-                    a2 += (wn2 * __builtin_fma(sqm, wn2, fa)) * fb;
+                const int cnt = m.count();
+                if (cnt == 0) continue;
+                if (b < 4) packed0 |= (unsigned long long)cnt << (16 * b);
+                else packed1 |= (unsigned long long)cnt << (16 * (b - 4));
+                double c0 = 0.0;
+                while (m.any()) {
+                    // the subset's next G particles, one per group
+                    const int pk0 = m.pop(), pk1 = m.pop();
+                    const int pk2 = G > 2 ? m.pop() : -1, pk3 = G > 3 ? m.pop() : -1;
+                    int pp = pk0;
+                    pp = g == 1 ? pk1 : pp;
+                    pp = g == 2 ? pk2 : pp;
+                    pp = g == 3 ? pk3 : pp;
+                    if (pp >= 0) {
+                        const R* rq = s_rec + pp * NREC;
+                        const R l0 = rq[0], l1 = rq[1], l2 = rq[2], rw = rq[3];
+                        const R xa = rq[ia0], xb = rq[ib0];
+                        const double fa = has_a ? (double)xa : (double)ca;
+                        const double fb = has_b ? (double)xb : 1.0;
+                        const double w = (double)rw;
+                        if (cterm) {
+                            c0 += w * fa;
+                        } else {
+                            const double wn0 = w * (double)l0, wn1 = w * (double)l1, wn2 = w * (double)l2;
+                            a0 += (wn0 * __builtin_fma(sqm, wn0, fa)) * fb;
+                            a1 += (wn1 * __builtin_fma(sqm, wn1, fa)) * fb;
+                            a2 += (wn2 * __builtin_fma(sqm, wn2, fa)) * fb;
+                        }
+                    }
                 }
+                if (cells) {
+                    // the groups' cell sums of bin b, combined in group order
+                    if (G == 4) {
+                        c0 += __shfl_xor(c0, 16);
+                        c0 += __shfl_xor(c0, 32);
+                    } else if (G == 3) {
+                        c0 = (c0 + __shfl(c0, lane + 21)) + __shfl(c0, lane + 42);
+                    } else {
+                        c0 += __shfl_xor(c0, 32);
+                    }
+                    const int v = 3 * nq + b * (1 + ns) + (q - nq);
+                    if (g == 0 && cterm) {
+                        if (dst) dst[SC_HDR + v] = c0;
+                        else unsafeAtomicAdd(A.eo + (int64_t)ks * SC_VMAX + v, c0);
+                    }
+                }
+                if (!dst && lane == 0) atomicAdd(A.eoc + (int64_t)ks * 8 + b, cnt);
             }
             if (G == 4) {
                 a0 += __shfl_xor(a0, 16); a1 += __shfl_xor(a1, 16); a2 += __shfl_xor(a2, 16);
                 a0 += __shfl_xor(a0, 32); a1 += __shfl_xor(a1, 32); a2 += __shfl_xor(a2, 32);
-            } else {
+            } else if (G == 3) {
                 // lanes 0..20 gather groups 1 and 2 (source lanes 21..62)
                 a0 = (a0 + __shfl(a0, lane + 21)) + __shfl(a0, lane + 42);
                 a1 = (a1 + __shfl(a1, lane + 21)) + __shfl(a1, lane + 42);
                 a2 = (a2 + __shfl(a2, lane + 21)) + __shfl(a2, lane + 42);
-            }
-            int slot = 0;
-            if (lane == 0) slot = lds_slot(s_key, ks);
-            slot = __shfl(slot, 0);
-            if ((set >> lane) & 1ull) myslot = slot;
-            if (g == 0 && q < nq) {
-                if (slot >= 0) {
-                    double* sv = &s_val[slot * NV + q];
-                    lds_add(sv, a0);
-                    lds_add(sv + nq, a1);
-                    lds_add(sv + 2 * nq, a2);
-                } else {
-                    const int4 t = A.M.tri_s[ks];
-                    unsafeAtomicAdd(A.nsum + (int64_t)t.x * NQ + q, a0);
-                    unsafeAtomicAdd(A.nsum + (int64_t)t.y * NQ + q, a1);
-                    unsafeAtomicAdd(A.nsum + (int64_t)t.z * NQ + q, a2);
-                }
-            }
-        }
-    }
-    if (A.do_bins && ns > 0 && valid) {
-        // cell sums: every particle adds its count, weight and weighted
-        // scalars to its (element, bin) cell in the element's table slot
-        const int base = 3 * nq + bin * (2 + ns);
-        if (myslot >= 0) {
-            double* sv = &s_val[myslot * NV + base];
-            lds_add(sv, 1.0);
-            lds_add(sv + 1, (double)wt);
-            for (int a = 0; a < ns; ++a) lds_add(sv + 2 + a, (double)wt * (double)psi[a]);
-        } else {
-            double* dst = A.csum + C.csoff + ((int64_t)(e - C.eoff) * 8 + bin) * (1 + ns);
-            atomicAdd(A.ccnt + (int64_t)e * 8 + bin, 1);
-            unsafeAtomicAdd(dst, (double)wt);
-            for (int a = 0; a < ns; ++a) unsafeAtomicAdd(dst + 1 + a, (double)wt * (double)psi[a]);
-        }
-    }
-    __syncthreads();
-    // flush the table: the first wave lists the used slots, then the
-    // workgroup walks (used slot, value) pairs; the pair index is split by a
-    // multiply-shift that equals idx / per for idx < 2^20 / per
-    static_assert(HS <= 64, "one wave lists the slots");
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        const bool used = lane < HS && s_key[lane] >= 0;
-        const unsigned long long um = __ballot(used);
-        if (used) s_used[__popcll(um & ((1ull << lane) - 1))] = lane;
-        if (lane == 0) s_used[HS] = __popcll(um);
-    }
-    __syncthreads();
-    {
-        const int per = 3 * nq + ((A.do_bins && ns > 0) ? 8 * (2 + ns) : 0);
-        const unsigned magic = ((1u << 20) + per - 1) / per;
-        const int npair = s_used[HS] * per;
-        for (int idx = threadIdx.x; idx < npair; idx += blockDim.x) {
-            const int u = (int)(((unsigned)idx * magic) >> 20), v = idx - u * per;
-            const int slot = s_used[u];
-            const int el = s_key[slot];
-            const double x = s_val[slot * NV + v];
-            if (x == 0.0) continue;
-            if (v < 3 * nq) {
-                const int4 t = A.M.tri_s[el];
-                const int k = v / nq, q = v % nq;
-                const int node = k == 0 ? t.x : (k == 1 ? t.y : t.z);
-                unsafeAtomicAdd(A.nsum + (int64_t)node * NQ + q, x);
             } else {
-                const int w8 = v - 3 * nq;
-                const int b = w8 / (2 + ns), j = w8 % (2 + ns);
-                if (j == 0) {
-                    atomicAdd(A.ccnt + (int64_t)el * 8 + b, (int)x);
-                } else {
-                    double* dst = A.csum + C.csoff + ((int64_t)(el - C.eoff) * 8 + b) * (1 + ns);
-                    unsafeAtomicAdd(dst + (j - 1), x);
-                }
+                a0 += __shfl_xor(a0, 32); a1 += __shfl_xor(a1, 32); a2 += __shfl_xor(a2, 32);
             }
+            if (dst) {
+                if (g == 0 && q < nq) {
+                    dst[SC_HDR + q] = a0;
+                    dst[SC_HDR + nq + q] = a1;
+                    dst[SC_HDR + 2 * nq + q] = a2;
+                }
+                if (lane == 0) {
+                    dst[0] = __longlong_as_double((long long)blockIdx.x * 256 + d);
+                    dst[1] = __longlong_as_double((long long)packed0);
+                    dst[2] = __longlong_as_double((long long)packed1);
+                }
+            } else {
+                // no record slot left: the sums go straight into the
+                // element's overflow sums (FP64 atomics, not order-fixed)
+                double* eo = A.eo + (int64_t)ks * SC_VMAX;
+                if (g == 0 && q < nq) {
+                    unsafeAtomicAdd(eo + q, a0);
+                    unsafeAtomicAdd(eo + nq + q, a1);
+                    unsafeAtomicAdd(eo + 2 * nq + q, a2);
+                }
+                handle = INT32_MIN;
+            }
+            if (lane == nmine) { my_el = ks; my_h = handle; }
+            ++nmine;
+        }
+        ++d;
+    }
+    // list the records under their elements (one atomic round trip for all
+    // of this wavefront's elements); an element with more than SC_K records
+    // in a step takes the rest as overflow sums
+    if (lane < nmine) {
+        int slot = SC_K;
+        if (my_h != INT32_MIN) slot = atomicAdd(A.ecnt + my_el, 1);
+        if (slot < SC_K) {
+            A.eslot[(int64_t)my_el * SC_K + slot] = my_h;
+        } else {
+            if (my_h != INT32_MIN) {
+                // the record was written by other lanes of this wavefront:
+                // make those stores visible before reading it back
+                __threadfence();
+                const double* src = my_h >= 0 ? A.srec + C.rec_off + (int64_t)my_h * C.rec_stride
+                                              : A.srec + A.pool_off + (int64_t)(-1 - my_h) * A.pool_stride;
+                double* eo = A.eo + (int64_t)my_el * SC_VMAX;
+                const int nv = sc_nvals(ns, cells);
+                for (int v = 0; v < nv; ++v) unsafeAtomicAdd(eo + v, src[SC_HDR + v]);
+                const unsigned long long p0 = (unsigned long long)__double_as_longlong(src[1]);
+                const unsigned long long p1 = (unsigned long long)__double_as_longlong(src[2]);
+                for (int b = 0; b < 8; ++b)
+                    atomicAdd(A.eoc + (int64_t)my_el * 8 + b, (int)(((b < 4 ? p0 : p1) >> (16 * (b & 3))) & 0xffff));
+            }
+            atomicExch(A.eof + my_el, 1);
+            atomicAdd(A.counters + (int64_t)c * NCNT + C_SCATTER_OVERFLOW, 1ull);
         }
     }
     // ---- counters, one atomic per wavefront

@@ -1,0 +1,178 @@
+// The two passes that turn the particle kernel's scatter records into grid
+// statistics (Sec. I, grid role (i); estimator of reading R-11) and IECM cell
+// means (R-23), in a fixed summation order, so that a step gives the same
+// bits every time it runs on the same input.
+//
+//   k_elem_reduce  one wavefront per element: the element's records of this
+//                  step (listed in any order by the particle kernel) are
+//                  sorted by key and summed in that order, plus the overflow
+//                  sums when the element had any. Out: the element's three
+//                  vertex sums of the node moments and, with cells, its cell
+//                  counts and cell means with the residual rule of R-23.
+//   k_node_reduce  one thread per statistics node: the vertex sums of the
+//                  incident elements, in the order of the node's incidence
+//                  list, give the node sums; then the weighted means,
+//                  central moments and density of R-11, with the thin-node
+//                  rule of R-34.
+#include "pdfmc_dev.h"
+#include "pdfmc_nodes.h"
+
+namespace pdfmc {
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__ cmean, int cells_on)
+{
+    __shared__ double s_cell[4][8 * (1 + MAXS)];
+    __shared__ int s_cnt[4][8];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 4 + wid;
+    if (e >= A.ne) return;            // whole wavefronts leave together
+    const int c = A.elem_case[e];
+    const CaseDev& C = A.cases[c];
+    const int ns = C.ns, nq = 12 + 2 * ns;
+    const bool cells = cells_on && ns > 0;
+    const int nv = sc_nvals(ns, cells);
+    const int n = min(A.ecnt[e], SC_K);
+    // lane j < n: record j as listed, and its key
+    const double* rp = nullptr;
+    long long key = 0x7fffffffffffffffll;
+    if (lane < n) {
+        const int h = A.eslot[e * SC_K + lane];
+        rp = h >= 0 ? A.srec + C.rec_off + (int64_t)h * C.rec_stride
+                    : A.srec + A.pool_off + (int64_t)(-1 - h) * A.pool_stride;
+        key = __double_as_longlong(rp[0]);
+    }
+    // rank of the record among the element's records (keys are distinct)
+    int rank = 0;
+    for (int i = 0; i < n; ++i) rank += __shfl(key, i) < key ? 1 : 0;
+    // the bin of each lane's cell values (-1: a vertex sum); a record holds
+    // the cell values of the bins it has particles in, and nothing for the others
+    const int b0 = cells && lane >= 3 * nq && lane < nv ? (lane - 3 * nq) / (1 + ns) : -1;
+    const int b1 = cells && lane + 64 >= 3 * nq && lane + 64 < nv ? (lane + 64 - 3 * nq) / (1 + ns) : -1;
+    const int bc = lane < 8 ? lane : 0;
+    double acc0 = 0.0, acc1 = 0.0;
+    int cnt = 0;
+    for (int r = 0; r < n; ++r) {
+        const int src = __ffsll((long long)__ballot(lane < n && rank == r)) - 1;
+        const double* q = (const double*)__shfl((long long)rp, src);
+        const unsigned long long w0 = (unsigned long long)__double_as_longlong(q[1]);
+        const unsigned long long w1 = (unsigned long long)__double_as_longlong(q[2]);
+        // particle count of bin b in this record
+        auto count_of = [&](int b) { return (int)((((b < 4) ? w0 : w1) >> (16 * (b & 3))) & 0xffff); };
+        if (lane < nv && (b0 < 0 || count_of(b0) > 0)) acc0 += q[SC_HDR + lane];
+        if (lane + 64 < nv && (b1 < 0 || count_of(b1) > 0)) acc1 += q[SC_HDR + 64 + lane];
+        if (cells && lane < 8) cnt += count_of(bc);
+    }
+    if (A.eof[e]) {
+        // sums that found no record slot (counted as scatter overflow)
+        double* eo = A.eo + e * SC_VMAX;
+        if (lane < nv) { acc0 += eo[lane]; eo[lane] = 0.0; }
+        if (lane + 64 < nv) { acc1 += eo[lane + 64]; eo[lane + 64] = 0.0; }
+        if (lane < 8) {
+            cnt += A.eoc[e * 8 + lane];
+            A.eoc[e * 8 + lane] = 0;
+        }
+        if (lane == 0) A.eof[e] = 0;
+    }
+    if (lane == 0) A.ecnt[e] = 0;
+    // vertex sums: value v = k nq + q -> etot[e][k][q]
+    double* et = A.etot + e * 3 * NQ;
+    if (lane < 3 * nq) et[(lane / nq) * NQ + lane % nq] = acc0;
+    if (lane + 64 < 3 * nq) et[((lane + 64) / nq) * NQ + (lane + 64) % nq] = acc1;
+    if (!cells) return;
+    // cells: value 3 nq + b (1 + ns) + j: j = 0 sum w, j = 1 + a sum w psi_a
+    const int nc = 8 * (1 + ns);
+    const int v0 = lane - 3 * nq, v1 = lane + 64 - 3 * nq;
+    if (v0 >= 0 && v0 < nc) s_cell[wid][v0] = acc0;
+    if (v1 >= 0 && v1 < nc) s_cell[wid][v1] = acc1;
+    if (lane < 8) {
+        s_cnt[wid][lane] = cnt;
+        A.ccnt[e * 8 + lane] = cnt;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lane (b, a): mean of scalar a in bin b; bins with fewer than n_min
+    // particles share one residual cell, pooled in bin order
+    if (lane < 8 * ns) {
+        const int b = lane / ns, a = lane - b * ns;
+        double rw = 0.0, rpa = 0.0;
+        for (int bb = 0; bb < 8; ++bb) {
+            const int cb = s_cnt[wid][bb];
+            if (cb > 0 && cb < C.nmin) {
+                rw += s_cell[wid][bb * (1 + ns)];
+                rpa += s_cell[wid][bb * (1 + ns) + 1 + a];
+            }
+        }
+        const int cb = s_cnt[wid][b];
+        double m = 0.0;
+        if (cb >= C.nmin) m = s_cell[wid][b * (1 + ns) + 1 + a] / s_cell[wid][b * (1 + ns)];
+        else if (rw > 0.0) m = rpa / rw;
+        cmean[C.cmoff + ((int64_t)(e - C.eoff) * 8 + b) * ns + a] = (R)m;
+    }
+}
+template __global__ void k_elem_reduce<double>(NodeArgs, double*, int);
+template __global__ void k_elem_reduce<float>(NodeArgs, float*, int);
+
+__global__ void k_node_reduce(NodeArgs A)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.nn) return;
+    const int c = A.node_case[s];
+    const CaseDev& C = A.cases[c];
+    const int ns = C.ns, nq = 12 + 2 * ns;
+    double r[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) r[q] = 0.0;
+    for (int j = A.inc_ptr[s]; j < A.inc_ptr[s + 1]; ++j) {
+        const int ent = A.inc[j];
+        const double* et = A.etot + (int64_t)(ent / 3) * 3 * NQ + (ent % 3) * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q < nq) r[q] += et[q];
+    }
+    double* ns_out = A.nsum + (int64_t)s * NQ;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (q < nq) ns_out[q] = r[q];
+    double* st = A.stats + (int64_t)s * NST;
+    const double W = r[0];
+    // an empty node, or (once there are previous statistics) one whose
+    // effective sample size W^2 / sum (w N)^2 is below n_eff_min, keeps its
+    // previous moments (R-34)
+    st[0] = W;
+    st[1] = W / A.vol[s];
+    double wsq = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (q == 11 + 2 * ns) wsq = r[q];
+    if (W > 0.0 && (A.first_stats || W * W >= C.neff_min * wsq)) {
+        const double m1 = r[1] / W, m2 = r[2] / W, m3 = r[3] / W;
+        st[2] = m1; st[3] = m2; st[4] = m3;
+        st[5] = r[4] / W - m1 * m1;
+        st[6] = r[5] / W - m2 * m2;
+        st[7] = r[6] / W - m3 * m3;
+        st[8] = r[7] / W - m1 * m2;
+        st[9] = r[8] / W - m1 * m3;
+        st[10] = r[9] / W - m2 * m3;
+        st[11] = r[10] / W;
+#pragma unroll
+        for (int a = 0; a < MAXS; ++a) {
+            if (a < ns) {
+                double ps = 0.0, p2 = 0.0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    if (q == 11 + a) ps = r[q];
+                    if (q == 11 + ns + a) p2 = r[q];
+                }
+                const double m = ps / W;
+                st[12 + a] = m;
+                st[12 + ns + a] = p2 / W - m * m;
+            }
+        }
+    } else {
+        atomicAdd(A.counters + (int64_t)c * NCNT + C_EMPTY_NODE, 1ull);
+    }
+}
+
+}  // namespace pdfmc

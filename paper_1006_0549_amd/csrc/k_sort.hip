@@ -1,15 +1,19 @@
-// Counting sort of the particle arrays by element (periodic re-sort).
+// Counting sort of the particle arrays by element (periodic re-sort), in a
+// fixed order: by element, and inside an element by particle id (R-32), so
+// the order after a sort depends only on which particles each element holds.
 //
 // Keeping each case's particles grouped by element keeps the gathers of
 // element records and nodal fields cache-resident and the elements per
-// wavefront few, which is what the particle kernel's scatter relies on.
-// Order inside an element is not kept (the first lane of an element in a
-// wavefront claims the slots of its element's lanes with an atomic); results
-// do not depend on it beyond the summation order of the FP64 node sums.
+// workgroup few, which is what the particle kernel's scatter relies on.
 //   k_sort_hist     per-element counts (one atomic per element per wavefront)
 //   k_sort_scan_*   exclusive scan of the counts (blocks, block totals), and
-//   k_sort_cursor   the per-case slot cursors
-//   k_sort_scatter  move every particle field to the other buffer set
+//   k_sort_cursor   the per-case segment starts and slot cursors
+//   k_sort_place    each particle's id and index into a slot of its element's
+//                   segment (slots claimed with one atomic per element per
+//                   wavefront, so their order inside a segment is arbitrary)
+//   k_sort_order    one wavefront per segment: the rank of each id inside
+//                   its segment gives the particle's final position
+//   k_sort_gather   move every particle field to the other buffer set
 #include "pdfmc_dev.h"
 #include "pdfmc_sort.h"
 
@@ -115,10 +119,10 @@ __global__ void __launch_bounds__(SCAN_B) k_sort_cursor(SortArgs A)
     const int64_t here = A.scan[e] + A.bsum[e / SCAN_B];
     const int64_t first = A.scan[C.eoff] + A.bsum[C.eoff / SCAN_B];
     A.cursor[e] = here - first + C.poff;
+    A.start[e] = here - first + C.poff;
 }
 
-template <typename R>
-__global__ void k_sort_scatter(SortArgs A, Particles<R> src, Particles<R> dst)
+__global__ void k_sort_place(SortArgs A, const uint32_t* __restrict__ ids)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int tile = wave_tile(gid);
@@ -126,7 +130,7 @@ __global__ void k_sort_scatter(SortArgs A, Particles<R> src, Particles<R> dst)
     const CaseDev& C = A.cases[__builtin_amdgcn_readfirstlane(A.tile_case[tile])];
     const int64_t i = gid - C.poff;
     const bool valid = i >= 0 && i < C.np;
-    const int key = valid ? src.elem[gid] : -1;
+    const int key = valid ? A.elem[gid] : -1;
     bool head; int rank, len, first;
     sort_sets(key, head, rank, len, first);
     unsigned long long base = 0;
@@ -135,14 +139,52 @@ __global__ void k_sort_scatter(SortArgs A, Particles<R> src, Particles<R> dst)
     base = __shfl(base, first);
     if (!valid) return;
     const int64_t q = (int64_t)base + rank;
+    A.tmp_id[q] = ids[gid];
+    A.tmp_src[q] = gid;
+}
+
+// one wavefront per element segment; lane l ranks the slots start + l + 64 j
+// against the whole segment by (id, source index): ids are distinct within a
+// case as uploaded (R-32), and the source index breaks ties should they not
+// be, so the ranks always form a permutation of the segment
+__global__ void __launch_bounds__(256) k_sort_order(SortArgs A)
+{
+    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= A.ne) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t s0 = A.start[e];
+    const int len = A.count[e];
+    for (int j0 = 0; j0 < len; j0 += 64) {
+        const int j = j0 + lane;
+        const uint32_t my = j < len ? A.tmp_id[s0 + j] : 0u;
+        const int64_t ms = j < len ? A.tmp_src[s0 + j] : 0;
+        int r = 0;
+        for (int i = 0; i < len; ++i) {
+            const uint32_t oi = A.tmp_id[s0 + i];
+            r += (oi < my || (oi == my && A.tmp_src[s0 + i] < ms)) ? 1 : 0;
+        }
+        if (j < len) A.perm[s0 + r] = ms;
+    }
+}
+
+template <typename R>
+__global__ void k_sort_gather(SortArgs A, Particles<R> src, Particles<R> dst)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int tile = wave_tile(q);
+    if (tile >= A.ntiles) return;
+    const CaseDev& C = A.cases[__builtin_amdgcn_readfirstlane(A.tile_case[tile])];
     const int64_t j = q - C.poff;
-    dst.x[q] = src.x[gid]; dst.y[q] = src.y[gid];
-    dst.u[q] = src.u[gid]; dst.v[q] = src.v[gid]; dst.w[q] = src.w[gid];
-    dst.om[q] = src.om[gid]; dst.wt[q] = src.wt[gid];
-    dst.elem[q] = key; dst.id[q] = src.id[gid]; dst.bin[q] = src.bin[gid];
+    if (j < 0 || j >= C.np) return;
+    const int64_t p = A.perm[q];
+    const int64_t i = p - C.poff;
+    dst.x[q] = src.x[p]; dst.y[q] = src.y[p];
+    dst.u[q] = src.u[p]; dst.v[q] = src.v[p]; dst.w[q] = src.w[p];
+    dst.om[q] = src.om[p]; dst.wt[q] = src.wt[p];
+    dst.elem[q] = src.elem[p]; dst.id[q] = src.id[p]; dst.bin[q] = src.bin[p];
     for (int a = 0; a < C.ns; ++a) dst.psi[C.psioff + (int64_t)a * C.cap + j] = src.psi[C.psioff + (int64_t)a * C.cap + i];
 }
-template __global__ void k_sort_scatter<double>(SortArgs, Particles<double>, Particles<double>);
-template __global__ void k_sort_scatter<float>(SortArgs, Particles<float>, Particles<float>);
+template __global__ void k_sort_gather<double>(SortArgs, Particles<double>, Particles<double>);
+template __global__ void k_sort_gather<float>(SortArgs, Particles<float>, Particles<float>);
 
 }  // namespace pdfmc

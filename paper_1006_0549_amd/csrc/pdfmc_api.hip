@@ -48,6 +48,8 @@ struct Case {
     int64_t cap = 0, np = 0;
     int64_t poff = 0, psioff = 0, cmoff = 0, csoff = 0, inc_off = 0;
     int eoff = 0, noff = 0, bcoff = 0;
+    int64_t rec_off = 0;          // scatter records (doubles)
+    int rec_stride = 0;
     // Galerkin matrix pattern of the case in ELL form (mode 2)
     EllH ell0;
     int64_t ell_off = 0;
@@ -218,7 +220,14 @@ struct pdfmc_ctx {
             *d_is_wall = nullptr;
     PartBufs part[2]{};
     int cur = 0;
-    double *d_F = nullptr, *d_nsum = nullptr, *d_stats = nullptr, *d_csum = nullptr;
+    double *d_F = nullptr, *d_nsum = nullptr, *d_stats = nullptr;
+    // scatter records: regular slots of every case, then the pool; per-element
+    // record lists, overflow sums, element vertex sums (see pdfmc_dev.h)
+    double* d_srec = nullptr;
+    int64_t SREC = 0, pool_off = 0;
+    int pool_cap = 0;
+    int32_t *d_pool_cnt = nullptr, *d_ecnt = nullptr, *d_eslot = nullptr, *d_eof = nullptr, *d_eoc = nullptr;
+    double *d_eo = nullptr, *d_etot = nullptr;
     float* d_F32 = nullptr;
     char* d_cmean = nullptr;
     int32_t* d_ccnt = nullptr;
@@ -256,7 +265,7 @@ struct pdfmc_ctx {
     unsigned long long* d_counters = nullptr;
     uint32_t* d_step = nullptr;
     int32_t* d_sort_count = nullptr;
-    int64_t *d_sort_scan = nullptr, *d_sort_bsum = nullptr, *d_sort_cursor = nullptr;
+    int64_t *d_sort_scan = nullptr, *d_sort_bsum = nullptr, *d_sort_cursor = nullptr, *d_sort_start = nullptr;
     // options
     int sort_interval = 0, block = 256, use_graph = 0;
     int steps_since_sort = 0;
@@ -366,7 +375,14 @@ void carve(pdfmc_ctx* c, Carver& k)
     if (c->prec == PDFMC_FP32) k.take(c->d_F32, (size_t)c->NN * NF32);
     k.take(c->d_nsum, (size_t)c->NN * NQ);
     k.take(c->d_stats, (size_t)c->NN * NST);
-    k.take(c->d_csum, c->CS);
+    k.take(c->d_srec, c->SREC);
+    k.take(c->d_pool_cnt, 1);
+    k.take(c->d_ecnt, c->NE);
+    k.take(c->d_eslot, (size_t)c->NE * SC_K);
+    k.take(c->d_eof, c->NE);
+    k.take(c->d_eo, (size_t)c->NE * SC_VMAX);
+    k.take(c->d_eoc, 8 * (size_t)c->NE);
+    k.take(c->d_etot, (size_t)c->NE * 3 * NQ);
     k.take(c->d_cmean, c->CM, R);
     k.take(c->d_ccnt, 8 * (size_t)c->NE);
     k.take(c->d_kf, c->NN); k.take(c->d_ef, c->NN); k.take(c->d_L2, c->NN);
@@ -389,6 +405,7 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_sort_scan, c->NE);
     k.take(c->d_sort_bsum, c->NE / SCAN_B + 1);
     k.take(c->d_sort_cursor, c->NE);
+    k.take(c->d_sort_start, c->NE);
     k.take(c->d_amg_i, c->AMG_I);
     k.take(c->d_amg_d, c->AMG_D);
     k.take(c->d_amg, 2 * (size_t)std::max(c->n_amg, 1));
@@ -416,6 +433,21 @@ void compute_offsets(pdfmc_ctx* c)
         cs.ell_off = NELL; NELL += cs.p.mode == 2 ? (int64_t)cs.ell0.w * cs.m.nsn : 0;
         cs.inc_off = 3 * (int64_t)cs.eoff;
     }
+    // scatter records: SC_RT regular slots per particle tile of each case,
+    // each of the case's stride (header + vertex sums + cell sums), then a
+    // pool of two records per tile at the largest stride; the sort's
+    // temporaries (20 bytes per particle) reuse the region between steps
+    int64_t srec = 0;
+    for (auto& cs : c->cases) {
+        cs.rec_stride = SC_HDR + sc_nvals(cs.p.n_scalars, true);
+        cs.rec_off = srec;
+        srec += (cs.cap + TILE - 1) / TILE * SC_RT * (int64_t)cs.rec_stride;
+    }
+    c->pool_off = srec;
+    c->pool_cap = (int)std::min<int64_t>(INT32_MAX / 2, 2 * (NP / TILE) + 64);
+    srec += (int64_t)c->pool_cap * (SC_HDR + SC_VMAX);
+    srec = std::max<int64_t>(srec, (20 * NP + 7) / 8 + 3 * 32);
+    c->SREC = srec;
     int64_t ni = 0, nd = 0, nv = 0, ndv = 0, nt = 0, ntd = 0;
     int na = 0, maxlev = 0;
     for (auto& cs : c->cases) {
@@ -474,6 +506,7 @@ CaseDev make_case_dev(const pdfmc_ctx* c, const Case& cs)
     d.k_floor = p.k_floor; d.eps_floor = p.eps_floor; d.dpdx[0] = p.dpdx[0]; d.dpdx[1] = p.dpdx[1];
     d.cg_rtol = p.cg_rtol; d.cg_maxit = p.cg_maxit; d.neff_min = p.n_eff_min;
     d.reaction = p.reaction;
+    d.rec_off = cs.rec_off; d.rec_stride = cs.rec_stride;
     for (int a = 0; a < MAXS; ++a) { d.kr[a] = p.k_react[a]; d.fkr[a] = (float)p.k_react[a]; }
     (void)c;
     return d;
@@ -497,7 +530,9 @@ NodeArgs node_args(pdfmc_ctx* c)
     A.rec = c->d_rec64; A.area = c->d_area; A.vol = c->d_vol; A.tri_s = c->d_tri_s;
     A.inc_ptr = c->d_inc_ptr; A.inc = c->d_inc; A.incpos = c->d_incpos; A.ell_col = c->d_ell_col; A.ell_len = c->d_ell_len;
     A.is_wall = c->d_is_wall; A.wnx = c->d_wnx; A.wny = c->d_wny;
-    A.nsum = c->d_nsum; A.stats = c->d_stats; A.F = c->d_F; A.csum = c->d_csum; A.ccnt = c->d_ccnt;
+    A.nsum = c->d_nsum; A.stats = c->d_stats; A.F = c->d_F; A.csum = nullptr; A.ccnt = c->d_ccnt;
+    A.srec = c->d_srec; A.pool_off = c->pool_off; A.pool_stride = SC_HDR + SC_VMAX;
+    A.ecnt = c->d_ecnt; A.eslot = c->d_eslot; A.eof = c->d_eof; A.eo = c->d_eo; A.eoc = c->d_eoc; A.etot = c->d_etot;
     A.kf = c->d_kf; A.ef = c->d_ef; A.L2 = c->d_L2; A.er_r = c->d_er_r; A.er_dval = c->d_er_dval; A.er_b = c->d_er_b;
     A.er_x = c->d_er_x; A.er_val = c->d_er_val; A.pk_val = c->d_pk_val; A.pb = c->d_pb; A.phi = c->d_phi; A.P = c->d_P;
     A.counters = c->d_counters;
@@ -516,7 +551,9 @@ StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins)
     if constexpr (sizeof(R) == 8) { A.F = (const R*)c->d_F; A.fstride = NF; }
     else { A.F = (const R*)c->d_F32; A.fstride = NF32; }
     A.cmean = (const R*)c->d_cmean;
-    A.nsum = c->d_nsum; A.csum = c->d_csum; A.ccnt = c->d_ccnt; A.counters = c->d_counters; A.step = c->d_step;
+    A.srec = c->d_srec; A.pool_off = c->pool_off; A.pool_stride = SC_HDR + SC_VMAX; A.pool_cap = c->pool_cap;
+    A.pool_cnt = c->d_pool_cnt; A.ecnt = c->d_ecnt; A.eslot = c->d_eslot; A.eof = c->d_eof; A.eo = c->d_eo;
+    A.eoc = c->d_eoc; A.counters = c->d_counters; A.step = c->d_step;
     A.ntiles = c->ntiles; A.advance = advance; A.do_bins = do_bins;
     return A;
 }
@@ -564,29 +601,25 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins)
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     }
-    return PDFMC_OK;
-}
-
-pdfmc_status enqueue_accum_clear(pdfmc_ctx* c, bool cells)
-{
-    TRY(enqueue_fill(c, c->d_nsum, (int64_t)c->NN * NQ));
-    if (cells && c->any_scalars) {
-        TRY(enqueue_fill(c, c->d_csum, c->CS));
-        TRY(enqueue_fill_i(c, c->d_ccnt, 8 * (int64_t)c->NE));
-    }
-    return PDFMC_OK;
-}
-
-pdfmc_status enqueue_cell_means(pdfmc_ctx* c)
-{
-    if (!c->any_scalars) return PDFMC_OK;
-    NodeArgs A = node_args(c);
+    // the records -> element vertex sums and cell means -> node statistics
+    NodeArgs N = node_args(c);
     if (c->prec == PDFMC_FP64)
-        hipLaunchKernelGGL(k_cell_means<double>, dim3(nblk(8 * (int64_t)c->NE, 256)), dim3(256), 0, c->stream, A, (double*)c->d_cmean);
+        hipLaunchKernelGGL(k_elem_reduce<double>, dim3(nblk(c->NE, 4)), dim3(256), 0, c->stream, N,
+                           (double*)c->d_cmean, do_bins);
     else
-        hipLaunchKernelGGL(k_cell_means<float>, dim3(nblk(8 * (int64_t)c->NE, 256)), dim3(256), 0, c->stream, A, (float*)c->d_cmean);
+        hipLaunchKernelGGL(k_elem_reduce<float>, dim3(nblk(c->NE, 4)), dim3(256), 0, c->stream, N,
+                           (float*)c->d_cmean, do_bins);
+    // a pass that only re-bins (no advance) leaves the node statistics as they are
+    if (advance || !do_bins) hipLaunchKernelGGL(k_node_reduce, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, N);
     LAUNCHCHK(c);
     return PDFMC_OK;
+}
+
+// Before a particle-kernel launch: the record pool starts empty (the element
+// pass leaves the per-element lists and overflow sums cleared).
+pdfmc_status enqueue_accum_clear(pdfmc_ctx* c)
+{
+    return enqueue_fill_i(c, c->d_pool_cnt, 1);
 }
 
 void drop_graphs(pdfmc_ctx* c);
@@ -897,11 +930,8 @@ pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
 
 pdfmc_status enqueue_step_body(pdfmc_ctx* c)
 {
-    TRY(enqueue_accum_clear(c, true));
+    TRY(enqueue_accum_clear(c));
     TRY(enqueue_particles(c, 1, 1));
-    hipLaunchKernelGGL(k_node_stats, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, node_args(c));
-    LAUNCHCHK(c);
-    TRY(enqueue_cell_means(c));
     TRY(enqueue_fields(c, true));
     hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, c->stream, c->d_step);
     LAUNCHCHK(c);
@@ -915,6 +945,11 @@ pdfmc_status enqueue_sort(pdfmc_ctx* c)
     S.cases = c->d_cases; S.tile_case = c->d_tile_case; S.elem_case = c->d_elem_case;
     S.ntiles = c->ntiles; S.ne = c->NE; S.elem = c->part[c->cur].elem;
     S.count = c->d_sort_count; S.scan = c->d_sort_scan; S.bsum = c->d_sort_bsum; S.cursor = c->d_sort_cursor;
+    S.start = c->d_sort_start;
+    // temporaries in the scatter-record region, which holds nothing between steps
+    S.perm = (int64_t*)c->d_srec;
+    S.tmp_src = S.perm + c->NP;
+    S.tmp_id = (uint32_t*)(S.tmp_src + c->NP);
     TRY(enqueue_fill_i(c, c->d_sort_count, c->NE));
     const int64_t threads = (int64_t)c->ntiles * TILE;
     hipLaunchKernelGGL(k_sort_hist, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S);
@@ -922,6 +957,9 @@ pdfmc_status enqueue_sort(pdfmc_ctx* c)
     hipLaunchKernelGGL(k_sort_scan_blocks, dim3(nb), dim3(SCAN_B), 0, c->stream, S);
     hipLaunchKernelGGL(k_sort_scan_totals, dim3(1), dim3(SCAN_B), 0, c->stream, S, nb);
     hipLaunchKernelGGL(k_sort_cursor, dim3(nb), dim3(SCAN_B), 0, c->stream, S);
+    hipLaunchKernelGGL(k_sort_place, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S,
+                       (const uint32_t*)c->part[c->cur].id);
+    hipLaunchKernelGGL(k_sort_order, dim3(nblk(c->NE, 4)), dim3(256), 0, c->stream, S);
     LAUNCHCHK(c);
     PartBufs& A = c->part[c->cur];
     PartBufs& B = c->part[1 - c->cur];
@@ -930,13 +968,13 @@ pdfmc_status enqueue_sort(pdfmc_ctx* c)
                               (double*)A.wt, (double*)A.psi, A.elem, A.id, A.bin};
         Particles<double> dst{(double*)B.x, (double*)B.y, (double*)B.u, (double*)B.v, (double*)B.w, (double*)B.om,
                               (double*)B.wt, (double*)B.psi, B.elem, B.id, B.bin};
-        hipLaunchKernelGGL(k_sort_scatter<double>, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S, src, dst);
+        hipLaunchKernelGGL(k_sort_gather<double>, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S, src, dst);
     } else {
         Particles<float> src{(float*)A.x, (float*)A.y, (float*)A.u, (float*)A.v, (float*)A.w, (float*)A.om,
                              (float*)A.wt, (float*)A.psi, A.elem, A.id, A.bin};
         Particles<float> dst{(float*)B.x, (float*)B.y, (float*)B.u, (float*)B.v, (float*)B.w, (float*)B.om,
                              (float*)B.wt, (float*)B.psi, B.elem, B.id, B.bin};
-        hipLaunchKernelGGL(k_sort_scatter<float>, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S, src, dst);
+        hipLaunchKernelGGL(k_sort_gather<float>, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S, src, dst);
     }
     LAUNCHCHK(c);
     c->cur = 1 - c->cur;
@@ -1336,6 +1374,12 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
             LAUNCHCHK(c);
         }
     }
+    // the scatter's per-element lists and overflow sums start empty (the
+    // element pass clears what it consumes)
+    TRY(enqueue_fill_i(c, c->d_ecnt, c->NE));
+    TRY(enqueue_fill_i(c, c->d_eof, c->NE));
+    TRY(enqueue_fill_i(c, c->d_eoc, 8 * (int64_t)c->NE));
+    TRY(enqueue_fill(c, c->d_eo, (int64_t)c->NE * SC_VMAX));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_stats = false;
     c->bound = true;
@@ -1485,17 +1529,15 @@ pdfmc_status pdfmc_init(pdfmc_ctx* c)
     if (!c) return PDFMC_E_INVALID;
     TRY(check_bound(c));
     // statistics of the uploaded state
-    TRY(enqueue_accum_clear(c, true));
+    TRY(enqueue_accum_clear(c));
     TRY(enqueue_particles(c, 0, 0));
-    hipLaunchKernelGGL(k_node_stats, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, node_args(c));
-    LAUNCHCHK(c);
     c->have_stats = true;
     // Eulerian fields (no projection at initialisation: <P> starts at 0)
     TRY(enqueue_fields(c, false));
-    // bins and cell means against those fields
-    TRY(enqueue_accum_clear(c, true));
+    // bins and cell means against those fields (the statistics pass is
+    // repeated with the same sums, so the node statistics do not change)
+    TRY(enqueue_accum_clear(c));
     TRY(enqueue_particles(c, 0, 1));
-    TRY(enqueue_cell_means(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->initialised = true;
     return PDFMC_OK;
@@ -1510,9 +1552,8 @@ pdfmc_status pdfmc_rebin(pdfmc_ctx* c)
                            (const double*)c->d_F, c->d_F32, c->NN);
         LAUNCHCHK(c);
     }
-    TRY(enqueue_accum_clear(c, true));
+    TRY(enqueue_accum_clear(c));
     TRY(enqueue_particles(c, 0, 1));
-    TRY(enqueue_cell_means(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->initialised = true;
     return PDFMC_OK;

@@ -15,7 +15,7 @@ constexpr int NF32 = 24;       // padded FP32 mirror stride
 constexpr int MAXS = 4;        // scalars per case
 constexpr int NQ = 20;         // node-sum stride: 12 + 2*MAXS
 constexpr int NST = 20;        // statistics stride: 12 + 2*MAXS
-constexpr int NCNT = 12;       // counters per case
+constexpr int NCNT = 13;       // counters per case
 constexpr int TILE = 256;      // particle ranges of cases are padded to this
 constexpr int NER = 5;         // elliptic-relaxation components 11,12,21,22,33
 
@@ -29,8 +29,22 @@ enum Field {
 
 enum Counter {
     C_WALK_FALLBACK = 0, C_REFLECT, C_PERIODIC, C_OMEGA_FLIP, C_EMPTY_NODE, C_NAN,
-    C_WALK_STEPS, C_CG_ER, C_CG_P, C_CG_FAIL, C_K_FLOOR, C_EPS_FLOOR
+    C_WALK_STEPS, C_CG_ER, C_CG_P, C_CG_FAIL, C_K_FLOOR, C_EPS_FLOOR, C_SCATTER_OVERFLOW
 };
+
+// Scatter records (reading R-11 and the cell sums of R-23). Each workgroup of
+// the particle kernel writes one record per distinct element among its
+// particles: the element's three vertex sums of the node moments and its
+// cell sums, summed over the workgroup's particles in a fixed order. Record
+// layout (doubles): [0] key (int64 bits: global workgroup index * 256 + the
+// element's rank among the workgroup's elements), [1] [2] particle counts of
+// bins 0..3 and 4..7 (16 bits each), [3 .. 3 + 3 nq) vertex sums (vertex-major),
+// then, with cells, 8 bins x (1 + ns): sum w, sum w psi_a.
+constexpr int SC_HDR = 3;
+constexpr int SC_RT = 32;       // regular record slots per particle tile
+constexpr int SC_K = 32;        // record handles listed per element per step
+constexpr int SC_VMAX = 3 * NQ + 8 * (1 + MAXS);   // values of a record
+__device__ __host__ inline int sc_nvals(int ns, bool cells) { return 3 * (12 + 2 * ns) + (cells ? 8 * (1 + ns) : 0); }
 
 struct BcDev {
     int32_t type;        // 0 wall, 1 periodic
@@ -66,6 +80,9 @@ struct CaseDev {
     int32_t cg_maxit, reaction;  // reaction: closed scalar source kind (0, 1, 2)
     double kr[MAXS];           // reaction rate constants
     float fkr[MAXS];
+    int64_t rec_off;           // scatter records of the case at srec + rec_off (doubles)
+    int32_t rec_stride;        // doubles per record: SC_HDR + values with cells
+    int32_t pad2;
 };
 
 template <typename R>
@@ -96,9 +113,15 @@ struct StepArgs {
     const R* F;                   // fields: FP64 [NN][22] or FP32 mirror [NN][24]
     int32_t fstride;
     const R* cmean;               // cell means (Real)
-    double* nsum;                 // [NN][NQ] node sums (FP64)
-    double* csum;                 // cell sums (FP64)
-    int32_t* ccnt;                // [NE][8] cell counts
+    double* srec;                 // scatter records (regular slots per case, then the pool)
+    int64_t pool_off;             // pool records at srec + pool_off, pool_stride doubles each
+    int32_t pool_stride, pool_cap;
+    int32_t* pool_cnt;            // records taken from the pool this step
+    int32_t* ecnt;                // [NE] records listed per element
+    int32_t* eslot;               // [NE][SC_K] record handles: >= 0 regular, < 0 pool (-1 - index)
+    int32_t* eof;                 // [NE] 1: the element has values in the overflow sums
+    double* eo;                   // [NE][SC_VMAX] overflow sums (FP64 atomics)
+    int32_t* eoc;                 // [NE][8] overflow counts
     unsigned long long* counters; // [ncase][NCNT]
     const uint32_t* step;         // device step index
     int32_t ntiles;

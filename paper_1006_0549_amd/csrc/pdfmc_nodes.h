@@ -41,6 +41,16 @@ struct NodeArgs {
     double* phi;                     // [nn]
     double* P;                       // [nn] mean pressure
     unsigned long long* counters;    // [ncase][NCNT]
+    // scatter records of the particle kernel (see pdfmc_dev.h)
+    const double* srec;
+    int64_t pool_off;
+    int32_t pool_stride, pad2;
+    int32_t* ecnt;                   // [ne] records listed per element
+    const int32_t* eslot;            // [ne][SC_K] record handles
+    int32_t* eof;                    // [ne] overflow flags
+    double* eo;                      // [ne][SC_VMAX] overflow sums
+    int32_t* eoc;                    // [ne][8] overflow counts
+    double* etot;                    // [ne][3][NQ] vertex sums of each element
 };
 
 constexpr int AMG_MAXL = 8;        // multigrid levels

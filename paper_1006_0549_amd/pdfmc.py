@@ -18,9 +18,10 @@ LIB_PATH = os.path.join(_HERE, "libpdfmc.so")
 
 FP64, FP32 = 0, 1
 NF = 22
-N_COUNTERS = 12
+N_COUNTERS = 13
 COUNTER_NAMES = ["walk_fallback", "reflect", "periodic", "omega_flip", "empty_node", "nan",
-                 "walk_steps", "cg_iters_er", "cg_iters_p", "cg_fail", "k_floor", "eps_floor"]
+                 "walk_steps", "cg_iters_er", "cg_iters_p", "cg_fail", "k_floor", "eps_floor",
+                 "scatter_overflow"]
 STATUS = {0: "OK", 1: "INVALID", 2: "MESH", 3: "NOMEM", 4: "HIP", 5: "STATE", 6: "UNSUPPORTED"}
 
 

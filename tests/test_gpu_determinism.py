@@ -1,0 +1,155 @@
+"""Determinism of the particle path and the sort, through the C ABI.
+
+The scatter of the particle moments (reading R-11) and of the IECM cell sums
+(R-23) sums every statistic in a fixed order (per workgroup in particle
+order, per element in record-key order, per node in incidence order), and the
+periodic sort orders particles by element and then by id. So, while the
+scatter-overflow counter stays at 0:
+  - the same run twice gives the same bits (a race or an order-dependent sum
+    anywhere in the particle path would show here);
+  - cases advanced together in one context give the same bits as each case
+    alone (the record keys keep their relative order);
+  - after a sort the particles are in (element, id) order, and a sorted run
+    follows the oracle as closely as an unsorted one.
+The Eulerian solves of the relaxation and the projection (mode 2) still add
+their FP64 scalars with atomics, so these tests run the simplified model
+(mode 1), where every field comes from the node statistics.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1006_0549_amd as P
+    return P
+
+
+def _cases():
+    """Three mode-1 cases of different shapes, sizes and scalar counts."""
+    cfg = W.config_small()
+    out = [(cfg["mesh"], cfg["params"], cfg["particles"])]
+    mesh = W.channel(n_half=10, nx=24, seed_key=(1, 1, 0))
+    params = W.default_params(mode=1, dt=5e-4, nu=1.0 / 1080.0, n_scalars=2, dpdx=(-1.0, 0.0),
+                              src=[(1.0, 0.5, 0.1, 1.0), (3.0, 1.5, 0.1, 1.0)], stream=1)
+    out.append((mesh, params, W.init_particles(mesh, 37, 2, W.rng_for(1, 1, 1), u_std=1.0)))
+    mesh = W.unit_square(12, 0.2, periodic_x=False, periodic_y=False, lid=(1.0, 0.0, 0.0), seed_key=(3, 5, 0))
+    params = W.default_params(mode=1, dt=5e-4, nu=1.0 / 4000.0, n_scalars=0, dpdx=(0.0, 0.0), stream=2)
+    out.append((mesh, params, W.init_particles(mesh, 61, 0, W.rng_for(3, 5, 1), u_std=0.1)))
+    return out
+
+
+def _context(P, precision, cases, steps, **opt):
+    sim = P.Sim(precision, "cuda:0")
+    ids = [sim.add_case(m, p, len(parts["x"])) for m, p, parts in cases]
+    sim.bind()
+    sim.set_options(**opt)
+    for cs, (m, p, parts) in zip(ids, cases):
+        sim.upload(cs, parts)
+    sim.init()
+    sim.step(steps)
+    return sim, ids
+
+
+def _snapshot(sim, cs, n):
+    d = sim.download(cs, n)
+    mean, cnt = sim.cell_means(cs)
+    return dict(d, stats=sim.stats(cs), sums=sim.node_sums(cs), fields=sim.fields(cs), cmean=mean, ccnt=cnt,
+                counters=sim.counters(cs))
+
+
+def _assert_bitwise(a, b, what):
+    for k, v in a.items():
+        if k == "counters":
+            assert v == b[k], (what, v, b[k])
+        else:
+            assert np.array_equal(np.asarray(v), np.asarray(b[k])), (what, k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_run_twice_bitwise(P, precision):
+    cases = _cases()
+    opt = dict(sort_interval=3, use_graph=True)
+    _flush(f"[run_twice] {precision}: {len(cases)} mode-1 cases, 25 steps, sort every 3, graph")
+    runs = [_context(P, precision, cases, 25, **opt) for _ in range(2)]
+    for i, (m, p, parts) in enumerate(cases):
+        n = len(parts["x"])
+        a = _snapshot(runs[0][0], runs[0][1][i], n)
+        b = _snapshot(runs[1][0], runs[1][1][i], n)
+        assert a["counters"]["scatter_overflow"] == 0
+        assert a["counters"]["reflect"] > 0
+        _assert_bitwise(a, b, f"case {i}")
+
+
+def test_batched_equals_sequential_bitwise(P):
+    cases = _cases()
+    opt = dict(sort_interval=3, use_graph=True)
+    _flush("[batched_bitwise] three mode-1 cases together and one at a time, 12 steps")
+    sim, ids = _context(P, "fp64", cases, 12, **opt)
+    for i, (m, p, parts) in enumerate(cases):
+        n = len(parts["x"])
+        alone, aid = _context(P, "fp64", [cases[i]], 12, **opt)
+        a = _snapshot(sim, ids[i], n)
+        b = _snapshot(alone, aid[0], n)
+        assert a["counters"]["scatter_overflow"] == 0
+        _assert_bitwise(a, b, f"case {i}")
+
+
+def test_sort_orders_by_element_then_id(P):
+    cfg = W.config_small()
+    parts = cfg["particles"]
+    n = len(parts["x"])
+    _flush("[sort_order] small square, 7 steps, then one sort")
+    sim, ids = _context(P, "fp32", [(cfg["mesh"], cfg["params"], parts)], 7)
+    before = sim.download(ids[0], n)
+    sim.sort()
+    after = sim.download(ids[0], n)
+    key = after["elem"].astype(np.int64) * (1 << 32) + after["id"].astype(np.int64)
+    assert np.all(np.diff(key) > 0)
+    # the same particles, moved
+    ob, oa = np.argsort(before["id"]), np.argsort(after["id"])
+    for k in ("x", "y", "u", "v", "w", "omega", "weight", "elem", "bin"):
+        assert np.array_equal(before[k][ob], after[k][oa]), k
+    assert np.array_equal(before["psi"][:, ob], after["psi"][:, oa])
+
+
+def test_sorted_run_follows_the_oracle(P, oracle_mod):
+    """The small square (FP64, mode 1) for 100 steps with a sort every 3 steps
+    against the oracle, which never sorts: the statistics agree to the same
+    1e-9 as the unsorted run; particles are compared by id (R-32)."""
+    cfg = W.config_small()
+    parts = cfg["particles"]
+    n = len(parts["x"])
+    _flush(f"[sorted_vs_oracle] {cfg['name']} particles={n} steps=100 sort every 3")
+    sim, ids = _context(P, "fp64", [(cfg["mesh"], cfg["params"], parts)], 100, sort_interval=3)
+    o = oracle_mod.Oracle()
+    oc = o.add_case(cfg["mesh"], cfg["params"])
+    o.upload(oc, parts)
+    o.init()
+    o.step(100)
+    g = sim.download(ids[0], n)
+    r = o.download(oc, n)
+    order = np.argsort(g["id"])
+    assert np.array_equal(g["id"][order], r["id"])
+    same = g["elem"][order] == r["elem"]
+    assert same.mean() > 0.999, same.mean()
+    gst, rst = sim.stats(ids[0]), o.stats(oc)
+    _, sn = sim.case_info(ids[0])
+    rows = np.unique(sn, return_index=True)[1]
+    sc = np.abs(rst).copy()
+    raw = rst[:, 5:8] + rst[:, 2:5] ** 2
+    for c_, i in ((5, 0), (6, 1), (7, 2)):
+        sc[:, c_] = raw[:, i]
+    for c_, (i, j) in {8: (0, 1), 9: (0, 2), 10: (1, 2)}.items():
+        sc[:, c_] = np.sqrt(raw[:, i] * raw[:, j])
+    sc[:, 13] = rst[:, 13] + rst[:, 12] ** 2
+    d = np.abs(gst - rst)[rows] / np.maximum(sc, 1e-300)[rows]
+    assert d.max() <= 1e-9, (d.max(), np.unravel_index(np.argmax(d), d.shape))

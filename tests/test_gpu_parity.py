@@ -3,7 +3,7 @@ the C ABI (include/pdfmc.h).
 
 Bar (FP64 path): element ids, velocity bins and the full particle state are
 bit-identical after a step from identical state; node sums agree to 1e-13 of
-sum |w N Q| (summation order differs: FP64 atomics on the GPU); statistics to
+sum |w N Q| (the GPU sums in its own fixed order, not the oracle's); statistics to
 1e-12 relative to their scale for one step and 1e-9 over a 100-step run with
 live fields. Cases span several tiles and a ragged last tile, walls, periodic
 edges, sources, 1 and 2 scalars, 8 velocity bins.
@@ -162,9 +162,11 @@ def test_one_step_frozen_bitwise(P, oracle_mod, ns, nb):
 
 def test_frozen_table_overflow(P, oracle_mod):
     """Two particles per element: a workgroup of 256 particles meets about
-    128 elements, more than the 32 slots of its LDS table, so most elements'
-    node and cell sums take the direct-atomic path. The FP64 state, node sums,
-    cell means and statistics still match the oracle after each step."""
+    128 elements, more than its 32 regular record slots, so the rest take
+    records from the pool, and once the pool is exhausted the element sums go
+    to the FP64 overflow sums (counted as scatter overflow). The FP64 state,
+    node sums, cell means and statistics still match the oracle after each
+    step."""
     ns, nb = 2, 8
     mesh, params, parts, F = _frozen_case(ns, nb, ppe=2)
     n = len(parts["x"])
@@ -200,6 +202,7 @@ def test_frozen_table_overflow(P, oracle_mod):
             sc[:, 12 + a] = np.maximum(sc[:, 12 + a], np.sqrt(np.maximum(rst[:, 12 + ns + a] + rst[:, 12 + a] ** 2, 0.0)))
         d = np.abs(gst - rst)[rows] / sc[rows]
         assert d.max() <= 1e-12, (step, d.max(), np.unravel_index(np.argmax(d), d.shape))
+    assert sim.counters(cs)["scatter_overflow"] > 0
 
 
 @pytest.mark.parametrize("reaction,ns,k", [(1, 2, (3.0, 0.7, 0.0, 0.0)), (2, 3, (4.0, 0.0, 0.0, 0.0)),
