@@ -199,7 +199,15 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
 {
     __shared__ __align__(16) R s_rec[256 * NREC];   // per-lane records of the new state
     __shared__ int s_key[256];                       // element of each lane (-1: no particle)
-    __shared__ int s_bin[256];                       // velocity bin of each lane
+    __shared__ double s_stage[4 * SC_SQ * SC_VMAX];  // sums of shared elements, per wavefront
+    __shared__ int s_sel[4 * SC_SQ];                 // their elements
+    __shared__ int s_smask[4 * SC_SQ];               // their bin masks
+    __shared__ int s_nst[4];                         // staged entries per wavefront
+    __shared__ int s_sdst[4 * 64];                   // destination of each set of each wavefront
+    __shared__ unsigned char s_skind[4 * 64];        // its kind: record, staged entry, overflow
+    __shared__ int s_mel[4 * 64], s_mfirst[4 * 64];  // shared elements each wavefront merges
+    __shared__ int s_nmerge[4];
+    __shared__ int s_slot;                           // record slots taken by the workgroup
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // block sizes are multiples of 64 and TILE of the block size, so a
     // wavefront lies inside one tile: the tile, the case and its constants
@@ -339,36 +347,41 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     }
 
     // ---- shape-weighted sums of the new state at the element's vertices
-    // (R-11) and cell sums (R-23), FP64, deterministic. Every lane stores its
-    // record in LDS. All wavefronts then walk the workgroup's distinct
-    // elements in the same fixed order (first appearance in particle order);
-    // wavefront (rank mod waves) handles an element: it sums, over the
-    // element's particles of the whole workgroup taken in particle order,
-    // the vertex terms w lambda_k Q and, per velocity bin, the cell terms
-    // w and w psi_a, and stores them as the record (workgroup, element).
+    // (R-11) and cell sums (R-23), FP64, in a fixed order. Every lane stores
+    // its record in LDS. Each wavefront takes the elements present among its
+    // own lanes one at a time (a ballot per element, in order of first lane)
+    // and sums over that element's lanes, in lane order, the vertex terms
+    // w lambda_k Q. The cell sums (count, w, w psi_a per element and velocity
+    // bin) come from a sort of the wavefront's lanes by (element, bin, lane)
+    // and a segmented scan. An element found in no other wavefront of the
+    // workgroup goes out as a record at once; the sums of an element shared
+    // by several wavefronts are staged in LDS and, after a barrier, added in
+    // wavefront order by the wavefront holding the element's first lane.
+    // Record keys derive from the workgroup and the element's first lane, so
+    // the element pass sums an element's records in an order fixed by the
+    // particle order alone.
     const int nq = 12 + 2 * ns;
     const bool cells = A.do_bins && ns > 0;
+    const int nv = sc_nvals(ns, cells);
+    const int nc = 2 + ns;                       // cell values per bin
     const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int key = valid ? e : -1;
     {
         R* my = s_rec + threadIdx.x * NREC;
         my[0] = lam[0]; my[1] = lam[1]; my[2] = lam[2]; my[3] = wt;
         my[4] = u3[0]; my[5] = u3[1]; my[6] = u3[2]; my[7] = om;
         for (int a = 0; a < ns; ++a) my[8 + a] = psi[a];
-        s_key[threadIdx.x] = valid ? e : -1;
-        s_bin[threadIdx.x] = bin;
+        s_key[threadIdx.x] = key;
+        if (threadIdx.x == 0) s_slot = 0;
+        if (threadIdx.x < 4) s_nmerge[threadIdx.x] = 0;
     }
     __syncthreads();
-    // every wavefront holds the keys and bins of all the workgroup's lanes:
-    // those of wavefront t at (register t, lane)
+    // the keys of all the workgroup's lanes: wavefront t's at (register t, lane)
     const int kk0 = s_key[lane], kk1 = nw > 1 ? s_key[64 + lane] : -1;
     const int kk2 = nw > 2 ? s_key[128 + lane] : -1, kk3 = nw > 3 ? s_key[192 + lane] : -1;
-    const int bb0 = s_bin[lane], bb1 = nw > 1 ? s_bin[64 + lane] : 0;
-    const int bb2 = nw > 2 ? s_bin[128 + lane] : 0, bb3 = nw > 3 ? s_bin[192 + lane] : 0;
-    WgSet rem = {__ballot(kk0 >= 0), __ballot(kk1 >= 0), __ballot(kk2 >= 0), __ballot(kk3 >= 0)};
-    // lane roles of the term loop: G groups of GS lanes, lane q of a group
-    // holds term q; vertex terms q < nq, cell terms nq <= q < nq + 1 + ns
-    const int nterm = nq + (cells ? 1 + ns : 0);
-    const int G = nterm <= 16 ? 4 : (nterm <= 21 ? 3 : 2), GS = nterm <= 16 ? 16 : (nterm <= 21 ? 21 : 32);
+    // lane roles of the vertex-term loop: G groups of GS lanes, lane q of a
+    // group holds term q < nq of the G particles taken per step
+    const int G = nq <= 16 ? 4 : 3, GS = nq <= 16 ? 16 : 21;
     const int g = lane / GS, q = lane - g * GS;
     // vertex term q: (w lambda_k) * fa_k * fb, fa_k = fma(sqm, w lambda_k, fa),
     // with fa = rec[ia] (or 1) and fb = rec[ib] (or 1); for the square term
@@ -385,165 +398,257 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     else if (q >= 11 && q < 11 + ns) ia = 8 + (q - 11);
     else if (q >= 11 + ns && q < 11 + 2 * ns) ia = ib = 8 + (q - 11 - ns);
     else if (q == 11 + 2 * ns) sq = true;
-    // cell term: w * (1 or psi_a), as (w * 1) * fa with lambda taken as 1
-    const bool cterm = q >= nq && q < nterm;
-    if (cterm && q > nq) ia = 8 + (q - nq - 1);
     const int ia0 = ia >= 0 ? ia : 0, ib0 = ib >= 0 ? ib : 0;
     const bool has_a = ia >= 0, has_b = ib >= 0;
     const R ca = sq ? R(0) : R(1);
     const double sqm = sq ? 1.0 : 0.0;
+    const R* wave_rec = s_rec + wid * 64 * NREC;
     const int64_t ltile = gid / TILE - C.poff / TILE;     // the case's tile of this workgroup
     const int wg_slots = SC_RT * (int)blockDim.x / TILE;
     const int wg_first = (int)((blockIdx.x * (int64_t)blockDim.x) % TILE) / (int)blockDim.x * wg_slots;
-    // the elements this wavefront handled: lane j holds the j-th (element, handle)
-    int my_el = -1, my_h = 0, nmine = 0;
-    int d = 0;
-    while (rem.any()) {
-        WgSet set;
-        int ks;
-        {
-            WgSet r2 = rem;
-            ks = s_key[r2.pop()];
-            set = {__ballot(kk0 == ks), __ballot(kk1 == ks), __ballot(kk2 == ks), __ballot(kk3 == ks)};
-            rem.m0 &= ~set.m0; rem.m1 &= ~set.m1; rem.m2 &= ~set.m2; rem.m3 &= ~set.m3;
+    const long long kbase = (long long)blockIdx.x * 512;
+    // a record slot: one of the workgroup's regular slots, else the pool;
+    // null (handle INT32_MIN) when both are used up
+    auto take_slot = [&](int& handle) -> double* {
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(&s_slot, 1);
+        idx = __shfl(idx, 0);
+        if (idx < wg_slots) {
+            handle = (int)(ltile * SC_RT) + wg_first + idx;
+            return A.srec + C.rec_off + (int64_t)handle * C.rec_stride;
         }
-        if (d % nw == wid) {
-            // destination: a regular slot of the workgroup, else the pool
-            double* dst = nullptr;
-            int handle = 0;
-            if (d < wg_slots) {
-                handle = (int)(ltile * SC_RT) + wg_first + d;
-                dst = A.srec + C.rec_off + (int64_t)handle * C.rec_stride;
-            } else {
-                int pidx = 0;
-                if (lane == 0) pidx = atomicAdd(A.pool_cnt, 1);
-                pidx = __shfl(pidx, 0);
-                if (pidx < A.pool_cap) {
-                    handle = -1 - pidx;
-                    dst = A.srec + A.pool_off + (int64_t)pidx * A.pool_stride;
-                }
-            }
+        int pidx = 0;
+        if (lane == 0) pidx = atomicAdd(A.pool_cnt, 1);
+        pidx = __shfl(pidx, 0);
+        if (pidx < A.pool_cap) {
+            handle = -1 - pidx;
+            return A.srec + A.pool_off + (int64_t)pidx * A.pool_stride;
+        }
+        handle = INT32_MIN;
+        return nullptr;
+    };
+    auto rec_ptr = [&](int h) -> double* {
+        return h >= 0 ? A.srec + C.rec_off + (int64_t)h * C.rec_stride : A.srec + A.pool_off + (int64_t)(-1 - h) * A.pool_stride;
+    };
+    // no record slot left anywhere: the element's values go to its overflow
+    // sums with FP64 atomics (not order-fixed; counted)
+    auto overflow = [&](int el) {
+        if (lane == 0) {
+            atomicExch(A.eof + el, 1);
+            atomicAdd(A.counters + (int64_t)c * NCNT + C_SCATTER_OVERFLOW, 1ull);
+        }
+    };
+    int my_set = -1;          // this lane's set among the wavefront's sets
+    {
+        unsigned long long rem = __ballot(key >= 0);
+        int nset = 0, nst = 0;
+        while (rem) {
+            const int ks = __shfl(key, __ffsll((long long)rem) - 1);
+            const unsigned long long set = __ballot(key == ks);
+            rem &= ~set;
+            if ((set >> lane) & 1ull) my_set = nset;
+            const unsigned long long o0 = __ballot(kk0 == ks), o1 = __ballot(kk1 == ks);
+            const unsigned long long o2 = __ballot(kk2 == ks), o3 = __ballot(kk3 == ks);
+            const int ft = o0 ? 0 : o1 ? 1 : o2 ? 2 : 3;
+            const int first = ft * 64 + __ffsll((long long)(ft == 0 ? o0 : ft == 1 ? o1 : ft == 2 ? o2 : o3)) - 1;
+            const bool shared_el = ((wid == 0 ? 0ull : o0) | (wid == 1 ? 0ull : o1) | (wid == 2 ? 0ull : o2) |
+                                    (wid == 3 ? 0ull : o3)) != 0ull;
+            // vertex sums: the set's particles, G per step, one per group
             double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            unsigned long long packed0 = 0ull, packed1 = 0ull;
-            for (int b = 0; b < (cells ? 8 : 1); ++b) {
-                WgSet m = set;
-                if (cells) {
-                    m.m0 &= __ballot(bb0 == b); m.m1 &= __ballot(bb1 == b);
-                    m.m2 &= __ballot(bb2 == b); m.m3 &= __ballot(bb3 == b);
-                }
-                const int cnt = m.count();
-                if (cnt == 0) continue;
-                if (b < 4) packed0 |= (unsigned long long)cnt << (16 * b);
-                else packed1 |= (unsigned long long)cnt << (16 * (b - 4));
-                double c0 = 0.0;
-                while (m.any()) {
-                    // the subset's next G particles, one per group
-                    const int pk0 = m.pop(), pk1 = m.pop();
-                    const int pk2 = G > 2 ? m.pop() : -1, pk3 = G > 3 ? m.pop() : -1;
-                    int pp = pk0;
-                    pp = g == 1 ? pk1 : pp;
-                    pp = g == 2 ? pk2 : pp;
-                    pp = g == 3 ? pk3 : pp;
+            {
+                unsigned long long m = set;
+                while (m) {
+                    int pk[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        pk[t] = -1;
+                        if (t < G && m) { pk[t] = __ffsll((long long)m) - 1; m &= m - 1; }
+                    }
+                    int pp = pk[0];
+                    pp = g == 1 ? pk[1] : pp;
+                    pp = g == 2 ? pk[2] : pp;
+                    pp = g == 3 ? pk[3] : pp;
                     if (pp >= 0) {
-                        const R* rq = s_rec + pp * NREC;
+                        const R* rq = wave_rec + pp * NREC;
                         const R l0 = rq[0], l1 = rq[1], l2 = rq[2], rw = rq[3];
                         const R xa = rq[ia0], xb = rq[ib0];
                         const double fa = has_a ? (double)xa : (double)ca;
                         const double fb = has_b ? (double)xb : 1.0;
                         const double w = (double)rw;
-                        if (cterm) {
-                            c0 += w * fa;
-                        } else {
-                            const double wn0 = w * (double)l0, wn1 = w * (double)l1, wn2 = w * (double)l2;
-                            a0 += (wn0 * __builtin_fma(sqm, wn0, fa)) * fb;
-                            a1 += (wn1 * __builtin_fma(sqm, wn1, fa)) * fb;
-                            a2 += (wn2 * __builtin_fma(sqm, wn2, fa)) * fb;
-                        }
+                        const double wn0 = w * (double)l0, wn1 = w * (double)l1, wn2 = w * (double)l2;
+                        a0 += (wn0 * __builtin_fma(sqm, wn0, fa)) * fb;
+                        a1 += (wn1 * __builtin_fma(sqm, wn1, fa)) * fb;
+                        a2 += (wn2 * __builtin_fma(sqm, wn2, fa)) * fb;
                     }
                 }
-                if (cells) {
-                    // the groups' cell sums of bin b, combined in group order
-                    if (G == 4) {
-                        c0 += __shfl_xor(c0, 16);
-                        c0 += __shfl_xor(c0, 32);
-                    } else if (G == 3) {
-                        c0 = (c0 + __shfl(c0, lane + 21)) + __shfl(c0, lane + 42);
-                    } else {
-                        c0 += __shfl_xor(c0, 32);
-                    }
-                    const int v = 3 * nq + b * (1 + ns) + (q - nq);
-                    if (g == 0 && cterm) {
-                        if (dst) dst[SC_HDR + v] = c0;
-                        else unsafeAtomicAdd(A.eo + (int64_t)ks * SC_VMAX + v, c0);
-                    }
+                if (G == 4) {
+                    a0 += __shfl_xor(a0, 16); a1 += __shfl_xor(a1, 16); a2 += __shfl_xor(a2, 16);
+                    a0 += __shfl_xor(a0, 32); a1 += __shfl_xor(a1, 32); a2 += __shfl_xor(a2, 32);
+                } else {
+                    // lanes 0..20 gather groups 1 and 2 (source lanes 21..62)
+                    a0 = (a0 + __shfl(a0, lane + 21)) + __shfl(a0, lane + 42);
+                    a1 = (a1 + __shfl(a1, lane + 21)) + __shfl(a1, lane + 42);
+                    a2 = (a2 + __shfl(a2, lane + 21)) + __shfl(a2, lane + 42);
                 }
-                if (!dst && lane == 0) atomicAdd(A.eoc + (int64_t)ks * 8 + b, cnt);
             }
-            if (G == 4) {
-                a0 += __shfl_xor(a0, 16); a1 += __shfl_xor(a1, 16); a2 += __shfl_xor(a2, 16);
-                a0 += __shfl_xor(a0, 32); a1 += __shfl_xor(a1, 32); a2 += __shfl_xor(a2, 32);
-            } else if (G == 3) {
-                // lanes 0..20 gather groups 1 and 2 (source lanes 21..62)
-                a0 = (a0 + __shfl(a0, lane + 21)) + __shfl(a0, lane + 42);
-                a1 = (a1 + __shfl(a1, lane + 21)) + __shfl(a1, lane + 42);
-                a2 = (a2 + __shfl(a2, lane + 21)) + __shfl(a2, lane + 42);
-            } else {
-                a0 += __shfl_xor(a0, 32); a1 += __shfl_xor(a1, 32); a2 += __shfl_xor(a2, 32);
-            }
-            if (dst) {
-                if (g == 0 && q < nq) {
-                    dst[SC_HDR + q] = a0;
-                    dst[SC_HDR + nq + q] = a1;
-                    dst[SC_HDR + 2 * nq + q] = a2;
-                }
-                if (lane == 0) {
-                    dst[0] = __longlong_as_double((long long)blockIdx.x * 256 + d);
-                    dst[1] = __longlong_as_double((long long)packed0);
-                    dst[2] = __longlong_as_double((long long)packed1);
-                }
-            } else {
-                // no record slot left: the sums go straight into the
-                // element's overflow sums (FP64 atomics, not order-fixed)
-                double* eo = A.eo + (int64_t)ks * SC_VMAX;
-                if (g == 0 && q < nq) {
-                    unsafeAtomicAdd(eo + q, a0);
-                    unsafeAtomicAdd(eo + nq + q, a1);
-                    unsafeAtomicAdd(eo + 2 * nq + q, a2);
-                }
-                handle = INT32_MIN;
-            }
-            if (lane == nmine) { my_el = ks; my_h = handle; }
-            ++nmine;
-        }
-        ++d;
-    }
-    // list the records under their elements (one atomic round trip for all
-    // of this wavefront's elements); an element with more than SC_K records
-    // in a step takes the rest as overflow sums
-    if (lane < nmine) {
-        int slot = SC_K;
-        if (my_h != INT32_MIN) slot = atomicAdd(A.ecnt + my_el, 1);
-        if (slot < SC_K) {
-            A.eslot[(int64_t)my_el * SC_K + slot] = my_h;
-        } else {
-            if (my_h != INT32_MIN) {
-                // the record was written by other lanes of this wavefront:
-                // make those stores visible before reading it back
-                __threadfence();
-                const double* src = my_h >= 0 ? A.srec + C.rec_off + (int64_t)my_h * C.rec_stride
-                                              : A.srec + A.pool_off + (int64_t)(-1 - my_h) * A.pool_stride;
-                double* eo = A.eo + (int64_t)my_el * SC_VMAX;
-                const int nv = sc_nvals(ns, cells);
-                for (int v = 0; v < nv; ++v) unsafeAtomicAdd(eo + v, src[SC_HDR + v]);
-                const unsigned long long p0 = (unsigned long long)__double_as_longlong(src[1]);
-                const unsigned long long p1 = (unsigned long long)__double_as_longlong(src[2]);
+            long long mask = 0;
+            if (cells) {
+#pragma unroll
                 for (int b = 0; b < 8; ++b)
-                    atomicAdd(A.eoc + (int64_t)my_el * 8 + b, (int)(((b < 4 ? p0 : p1) >> (16 * (b & 3))) & 0xffff));
+                    if (set & __ballot(bin == b)) mask |= 1ll << b;
             }
-            atomicExch(A.eof + my_el, 1);
-            atomicAdd(A.counters + (int64_t)c * NCNT + C_SCATTER_OVERFLOW, 1ull);
+            int kind, dcode;              // destination: 0 record (handle), 1 staged entry, 2 none
+            if (shared_el && nst < SC_SQ) {
+                const int ent = wid * SC_SQ + nst++;
+                double* sv = s_stage + ent * SC_VMAX;
+                if (g == 0 && q < nq) { sv[q] = a0; sv[nq + q] = a1; sv[2 * nq + q] = a2; }
+                if (lane == 0) { s_sel[ent] = ks; s_smask[ent] = (int)mask; }
+                kind = 1; dcode = ent;
+            } else {
+                int h;
+                double* dst = take_slot(h);
+                if (dst) {
+                    if (g == 0 && q < nq) { dst[SC_HDR + q] = a0; dst[SC_HDR + nq + q] = a1; dst[SC_HDR + 2 * nq + q] = a2; }
+                    if (lane == 0) {
+                        // the element's only sums here are keyed by its first
+                        // lane; a share of a shared element by this
+                        // wavefront's first lane of it
+                        const long long k = kbase + (shared_el ? 256 + wid * 64 + __ffsll((long long)set) - 1 : first);
+                        dst[0] = __longlong_as_double(k);
+                        dst[1] = __longlong_as_double((long long)ks);
+                        dst[2] = __longlong_as_double(mask);
+                    }
+                    kind = 0; dcode = h;
+                } else {
+                    double* eo = A.eo + (int64_t)ks * SC_VMAX;
+                    if (g == 0 && q < nq) {
+                        unsafeAtomicAdd(eo + q, a0); unsafeAtomicAdd(eo + nq + q, a1); unsafeAtomicAdd(eo + 2 * nq + q, a2);
+                    }
+                    overflow(ks);
+                    kind = 2; dcode = ks;
+                }
+            }
+            // a shared element whose first lane is here is merged by this wavefront
+            if (shared_el && ft == wid && lane == 0) {
+                const int mi = s_nmerge[wid]++;
+                s_mel[wid * 64 + mi] = ks;
+                s_mfirst[wid * 64 + mi] = first;
+            }
+            if (lane == 0) { s_skind[wid * 64 + nset] = (unsigned char)kind; s_sdst[wid * 64 + nset] = dcode; }
+            ++nset;
+        }
+        if (lane == 0) s_nst[wid] = nst;
+    }
+    if (cells) {
+        // cell sums: sort the lanes by (element, bin, lane) (bitonic, across
+        // the wavefront), then a segmented inclusive scan of (1, w, w psi_a);
+        // the last lane of each (element, bin) run holds the run's sums
+        unsigned long long sk = key >= 0 ? ((unsigned long long)key << 9) | ((unsigned long long)bin << 6) | (unsigned)lane
+                                         : ~0ull;
+#pragma unroll
+        for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                const unsigned long long o = (unsigned long long)__shfl_xor((long long)sk, jj);
+                const bool keep_min = ((lane & jj) == 0) == ((lane & kk) == 0);
+                sk = keep_min ? (o < sk ? o : sk) : (o > sk ? o : sk);
+            }
+        }
+        const bool cvalid = sk != ~0ull;
+        const int src = (int)(sk & 63);
+        const unsigned long long ck = sk >> 6;
+        const unsigned long long ckp = (unsigned long long)__shfl_up((long long)ck, 1);
+        const unsigned long long ckn = (unsigned long long)__shfl_down((long long)ck, 1);
+        const bool head = lane == 0 || ckp != ck;
+        const bool tail = lane == 63 || ckn != ck;
+        int st = head ? lane : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(st, d);
+            if (lane >= d && o > st) st = o;
+        }
+        const R* rq = wave_rec + src * NREC;
+        const double w = cvalid ? (double)rq[3] : 0.0;
+        double x[2 + MAXS];
+        x[0] = 1.0;
+        x[1] = w;
+#pragma unroll
+        for (int a = 0; a < MAXS; ++a) x[2 + a] = a < ns ? w * (double)rq[8 + a] : 0.0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+            for (int j2 = 0; j2 < 2 + MAXS; ++j2) {
+                if (j2 < nc) {
+                    const double y = __shfl_up(x[j2], d);
+                    if (lane - d >= st) x[j2] += y;
+                }
+            }
+        }
+        const int sset = __shfl(my_set, src);
+        if (cvalid && tail) {
+            const int b = (int)(ck & 7);
+            const int kind = s_skind[wid * 64 + sset], dcode = s_sdst[wid * 64 + sset];
+            const int off = 3 * nq + b * nc;
+            if (kind == 1) {
+                double* sv = s_stage + dcode * SC_VMAX + off;
+#pragma unroll
+                for (int j2 = 0; j2 < 2 + MAXS; ++j2) if (j2 < nc) sv[j2] = x[j2];
+            } else if (kind == 0) {
+                double* dst = rec_ptr(dcode) + SC_HDR + off;
+#pragma unroll
+                for (int j2 = 0; j2 < 2 + MAXS; ++j2) if (j2 < nc) dst[j2] = x[j2];
+            } else {
+                double* eo = A.eo + (int64_t)dcode * SC_VMAX + off;
+#pragma unroll
+                for (int j2 = 0; j2 < 2 + MAXS; ++j2) if (j2 < nc) unsafeAtomicAdd(eo + j2, x[j2]);
+            }
         }
     }
+    __syncthreads();
+    // merge the staged sums of the shared elements whose first lane is in this
+    // wavefront, in wavefront order (entry index = t SC_SQ + s)
+    {
+        const int ne_w = nw * SC_SQ;
+        int el_j = -1;
+        if (lane < ne_w && lane - (lane / SC_SQ) * SC_SQ < s_nst[lane / SC_SQ]) el_j = s_sel[lane];
+        const int nmerge = s_nmerge[wid];
+        for (int r = 0; r < nmerge; ++r) {
+            const int el = s_mel[wid * 64 + r], first = s_mfirst[wid * 64 + r];
+            const unsigned long long ents = __ballot(el_j == el);
+            if (!ents) continue;          // every share of it went out as a record of its own
+            double x0 = 0.0, x1 = 0.0;
+            long long mask = 0;
+            unsigned long long m = ents;
+            while (m) {
+                const int jx = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                const int em = s_smask[jx];
+                mask |= em;
+                const double* sv = s_stage + jx * SC_VMAX;
+                if (lane < nv && (lane < 3 * nq || ((em >> ((lane - 3 * nq) / nc)) & 1))) x0 += sv[lane];
+                if (lane + 64 < nv && (lane + 64 < 3 * nq || ((em >> ((lane + 64 - 3 * nq) / nc)) & 1)))
+                    x1 += sv[lane + 64];
+            }
+            int h;
+            double* dst = take_slot(h);
+            if (dst) {
+                if (lane < nv) dst[SC_HDR + lane] = x0;
+                if (lane + 64 < nv) dst[SC_HDR + 64 + lane] = x1;
+                if (lane == 0) {
+                    dst[0] = __longlong_as_double(kbase + first);
+                    dst[1] = __longlong_as_double((long long)el);
+                    dst[2] = __longlong_as_double(mask);
+                }
+            } else {
+                double* eo = A.eo + (int64_t)el * SC_VMAX;
+                if (lane < nv && x0 != 0.0) unsafeAtomicAdd(eo + lane, x0);
+                if (lane + 64 < nv && x1 != 0.0) unsafeAtomicAdd(eo + 64 + lane, x1);
+                overflow(el);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) A.wgcnt[blockIdx.x] = s_slot < wg_slots ? s_slot : wg_slots;
     // ---- counters, one atomic per wavefront
     {
         int v0 = wave_sum_int(wc.fallback), v1 = wave_sum_int(wc.refl), v2 = wave_sum_int(wc.per);

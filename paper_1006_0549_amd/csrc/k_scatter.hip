@@ -1,14 +1,17 @@
-// The two passes that turn the particle kernel's scatter records into grid
+// The passes that turn the particle kernel's scatter records into grid
 // statistics (Sec. I, grid role (i); estimator of reading R-11) and IECM cell
 // means (R-23), in a fixed summation order, so that a step gives the same
 // bits every time it runs on the same input.
 //
-//   k_elem_reduce  one wavefront per element: the element's records of this
-//                  step (listed in any order by the particle kernel) are
-//                  sorted by key and summed in that order, plus the overflow
-//                  sums when the element had any. Out: the element's three
-//                  vertex sums of the node moments and, with cells, its cell
-//                  counts and cell means with the residual rule of R-23.
+//   k_scatter_register  one thread per record slot: lists each record written
+//                  this step under its element (an element with more than
+//                  SC_K records takes the rest as overflow sums, counted)
+//   k_elem_reduce  one wavefront per element: the element's records (listed
+//                  in any order) are sorted by key and summed in that order,
+//                  plus the overflow sums when the element had any. Out: the
+//                  element's three vertex sums of the node moments and, with
+//                  cells, its cell counts and cell means with the residual
+//                  rule of R-23.
 //   k_node_reduce  one thread per statistics node: the vertex sums of the
 //                  incident elements, in the order of the node's incidence
 //                  list, give the node sums; then the weighted means,
@@ -19,17 +22,61 @@
 
 namespace pdfmc {
 
+__global__ void k_scatter_register(NodeArgs A, int ntiles, int block, const int32_t* tile_case, const int32_t* pool_cnt,
+                                   int pool_cap, unsigned long long* counters, int cells_on)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nreg = (int64_t)ntiles * SC_RT;
+    const double* rp = nullptr;
+    int handle = 0;
+    int c = 0;
+    if (t < nreg) {
+        // regular slot: tile, workgroup inside the tile, slot inside the workgroup
+        const int tile = (int)(t / SC_RT), it = (int)(t % SC_RT);
+        const int wg_slots = SC_RT * block / TILE;
+        const int wg = tile * (TILE / block) + it / wg_slots, sl = it % wg_slots;
+        if (sl >= A.wgcnt[wg]) return;
+        c = tile_case[tile];
+        const CaseDev& C = A.cases[c];
+        handle = (int)((tile - C.poff / TILE) * SC_RT + it);
+        rp = A.srec + C.rec_off + (int64_t)handle * C.rec_stride;
+    } else {
+        const int64_t pi = t - nreg;
+        const int np = min(*pool_cnt, pool_cap);
+        if (pi >= np) return;
+        handle = -1 - (int)pi;
+        rp = A.srec + A.pool_off + pi * A.pool_stride;
+    }
+    const int el = (int)__double_as_longlong(rp[1]);
+    if (t >= nreg) c = A.elem_case[el];
+    const int slot = atomicAdd(A.ecnt + el, 1);
+    if (slot < SC_K) {
+        A.eslot[(int64_t)el * SC_K + slot] = handle;
+        return;
+    }
+    // list full: the record's values go to the element's overflow sums
+    const CaseDev& C = A.cases[c];
+    const int ns = C.ns, nq = 12 + 2 * ns, nc = 2 + ns;
+    const bool cells = cells_on && ns > 0;
+    const int nv = sc_nvals(ns, cells);
+    const long long mask = __double_as_longlong(rp[2]);
+    double* eo = A.eo + (int64_t)el * SC_VMAX;
+    for (int v = 0; v < nv; ++v)
+        if (v < 3 * nq || ((mask >> ((v - 3 * nq) / nc)) & 1)) unsafeAtomicAdd(eo + v, rp[SC_HDR + v]);
+    atomicExch(A.eof + el, 1);
+    atomicAdd(counters + (int64_t)c * NCNT + C_SCATTER_OVERFLOW, 1ull);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__ cmean, int cells_on)
 {
-    __shared__ double s_cell[4][8 * (1 + MAXS)];
-    __shared__ int s_cnt[4][8];
+    __shared__ double s_cell[4][8 * (2 + MAXS)];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t e = (int64_t)blockIdx.x * 4 + wid;
     if (e >= A.ne) return;            // whole wavefronts leave together
     const int c = A.elem_case[e];
     const CaseDev& C = A.cases[c];
-    const int ns = C.ns, nq = 12 + 2 * ns;
+    const int ns = C.ns, nq = 12 + 2 * ns, nc = 2 + ns;
     const bool cells = cells_on && ns > 0;
     const int nv = sc_nvals(ns, cells);
     const int n = min(A.ecnt[e], SC_K);
@@ -45,33 +92,39 @@ __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__
     // rank of the record among the element's records (keys are distinct)
     int rank = 0;
     for (int i = 0; i < n; ++i) rank += __shfl(key, i) < key ? 1 : 0;
-    // the bin of each lane's cell values (-1: a vertex sum); a record holds
-    // the cell values of the bins it has particles in, and nothing for the others
-    const int b0 = cells && lane >= 3 * nq && lane < nv ? (lane - 3 * nq) / (1 + ns) : -1;
-    const int b1 = cells && lane + 64 >= 3 * nq && lane + 64 < nv ? (lane + 64 - 3 * nq) / (1 + ns) : -1;
-    const int bc = lane < 8 ? lane : 0;
+    // the bin of each lane's cell values (-1: a vertex sum); a record's cell
+    // values are valid for the bins in its mask only
+    const int b0 = cells && lane >= 3 * nq && lane < nv ? (lane - 3 * nq) / nc : -1;
+    const int b1 = cells && lane + 64 >= 3 * nq && lane + 64 < nv ? (lane + 64 - 3 * nq) / nc : -1;
     double acc0 = 0.0, acc1 = 0.0;
-    int cnt = 0;
-    for (int r = 0; r < n; ++r) {
-        const int src = __ffsll((long long)__ballot(lane < n && rank == r)) - 1;
-        const double* q = (const double*)__shfl((long long)rp, src);
-        const unsigned long long w0 = (unsigned long long)__double_as_longlong(q[1]);
-        const unsigned long long w1 = (unsigned long long)__double_as_longlong(q[2]);
-        // particle count of bin b in this record
-        auto count_of = [&](int b) { return (int)((((b < 4) ? w0 : w1) >> (16 * (b & 3))) & 0xffff); };
-        if (lane < nv && (b0 < 0 || count_of(b0) > 0)) acc0 += q[SC_HDR + lane];
-        if (lane + 64 < nv && (b1 < 0 || count_of(b1) > 0)) acc1 += q[SC_HDR + 64 + lane];
-        if (cells && lane < 8) cnt += count_of(bc);
+    // four records at a time: their loads first, then the sums in rank order
+    for (int r0 = 0; r0 < n; r0 += 4) {
+        long long mk[4];
+        double x0[4], x1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            mk[u] = 0; x0[u] = 0.0; x1[u] = 0.0;
+            if (r0 + u < n) {
+                const int src = __ffsll((long long)__ballot(lane < n && rank == r0 + u)) - 1;
+                const double* q = (const double*)__shfl((long long)rp, src);
+                mk[u] = __double_as_longlong(q[2]);
+                if (lane < nv) x0[u] = q[SC_HDR + lane];
+                if (lane + 64 < nv) x1[u] = q[SC_HDR + 64 + lane];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (r0 + u < n) {
+                if (lane < nv && (b0 < 0 || ((mk[u] >> b0) & 1))) acc0 += x0[u];
+                if (lane + 64 < nv && (b1 < 0 || ((mk[u] >> b1) & 1))) acc1 += x1[u];
+            }
+        }
     }
     if (A.eof[e]) {
-        // sums that found no record slot (counted as scatter overflow)
+        // sums that found no record slot or list entry (counted as scatter overflow)
         double* eo = A.eo + e * SC_VMAX;
         if (lane < nv) { acc0 += eo[lane]; eo[lane] = 0.0; }
         if (lane + 64 < nv) { acc1 += eo[lane + 64]; eo[lane + 64] = 0.0; }
-        if (lane < 8) {
-            cnt += A.eoc[e * 8 + lane];
-            A.eoc[e * 8 + lane] = 0;
-        }
         if (lane == 0) A.eof[e] = 0;
     }
     if (lane == 0) A.ecnt[e] = 0;
@@ -80,33 +133,29 @@ __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__
     if (lane < 3 * nq) et[(lane / nq) * NQ + lane % nq] = acc0;
     if (lane + 64 < 3 * nq) et[((lane + 64) / nq) * NQ + (lane + 64) % nq] = acc1;
     if (!cells) return;
-    // cells: value 3 nq + b (1 + ns) + j: j = 0 sum w, j = 1 + a sum w psi_a
-    const int nc = 8 * (1 + ns);
+    // cells: value 3 nq + b nc + j: j = 0 particle count, 1 sum w, 2 + a sum w psi_a
     const int v0 = lane - 3 * nq, v1 = lane + 64 - 3 * nq;
-    if (v0 >= 0 && v0 < nc) s_cell[wid][v0] = acc0;
-    if (v1 >= 0 && v1 < nc) s_cell[wid][v1] = acc1;
-    if (lane < 8) {
-        s_cnt[wid][lane] = cnt;
-        A.ccnt[e * 8 + lane] = cnt;
-    }
+    if (v0 >= 0 && v0 < 8 * nc) s_cell[wid][v0] = acc0;
+    if (v1 >= 0 && v1 < 8 * nc) s_cell[wid][v1] = acc1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 8) A.ccnt[e * 8 + lane] = (int32_t)s_cell[wid][lane * nc];
     // lane (b, a): mean of scalar a in bin b; bins with fewer than n_min
     // particles share one residual cell, pooled in bin order
     if (lane < 8 * ns) {
         const int b = lane / ns, a = lane - b * ns;
         double rw = 0.0, rpa = 0.0;
         for (int bb = 0; bb < 8; ++bb) {
-            const int cb = s_cnt[wid][bb];
+            const int cb = (int)s_cell[wid][bb * nc];
             if (cb > 0 && cb < C.nmin) {
-                rw += s_cell[wid][bb * (1 + ns)];
-                rpa += s_cell[wid][bb * (1 + ns) + 1 + a];
+                rw += s_cell[wid][bb * nc + 1];
+                rpa += s_cell[wid][bb * nc + 2 + a];
             }
         }
-        const int cb = s_cnt[wid][b];
+        const int cb = (int)s_cell[wid][b * nc];
         double m = 0.0;
-        if (cb >= C.nmin) m = s_cell[wid][b * (1 + ns) + 1 + a] / s_cell[wid][b * (1 + ns)];
+        if (cb >= C.nmin) m = s_cell[wid][b * nc + 2 + a] / s_cell[wid][b * nc + 1];
         else if (rw > 0.0) m = rpa / rw;
         cmean[C.cmoff + ((int64_t)(e - C.eoff) * 8 + b) * ns + a] = (R)m;
     }

@@ -143,27 +143,96 @@ __global__ void k_sort_place(SortArgs A, const uint32_t* __restrict__ ids)
     A.tmp_src[q] = gid;
 }
 
-// one wavefront per element segment; lane l ranks the slots start + l + 64 j
-// against the whole segment by (id, source index): ids are distinct within a
-// case as uploaded (R-32), and the source index breaks ties should they not
-// be, so the ranks always form a permutation of the segment
+// (id, source index) of slot j of a segment as one 64-bit key: source
+// indices are below 2^32 (particle arrays of fewer than 4 G entries)
+__device__ inline unsigned long long sort_key(const SortArgs& A, int64_t s0, int j)
+{
+    return ((unsigned long long)A.tmp_id[s0 + j] << 32) | (unsigned long long)A.tmp_src[s0 + j];
+}
+
+// one wavefront per element segment: the segment's (id, source index) pairs
+// are sorted in LDS by a bitonic network, and the sorted source indices are
+// the final order. ids are distinct within a case as uploaded (R-32); the
+// source index breaks ties should they not be. Segments longer than SORT_SEG
+// are listed for k_sort_order_big.
+constexpr int SORT_SEG = 512;
 __global__ void __launch_bounds__(256) k_sort_order(SortArgs A)
 {
-    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ unsigned long long s_keys[4][SORT_SEG];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 4 + wid;
     if (e >= A.ne) return;
-    const int lane = threadIdx.x & 63;
     const int64_t s0 = A.start[e];
     const int len = A.count[e];
-    for (int j0 = 0; j0 < len; j0 += 64) {
-        const int j = j0 + lane;
-        const uint32_t my = j < len ? A.tmp_id[s0 + j] : 0u;
-        const int64_t ms = j < len ? A.tmp_src[s0 + j] : 0;
-        int r = 0;
-        for (int i = 0; i < len; ++i) {
-            const uint32_t oi = A.tmp_id[s0 + i];
-            r += (oi < my || (oi == my && A.tmp_src[s0 + i] < ms)) ? 1 : 0;
+    if (len > SORT_SEG) {
+        if (lane == 0) A.big[atomicAdd(A.nbig, 1)] = (int32_t)e;
+        return;
+    }
+    int P = 1;
+    while (P < len) P <<= 1;
+    unsigned long long* k = s_keys[wid];
+    for (int i = lane; i < P; i += 64) k[i] = i < len ? sort_key(A, s0, i) : ~0ull;
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = lane; i < P; i += 64) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long a = k[i], b = k[ixj];
+                    const bool up = (i & kk) == 0;
+                    if ((a > b) == up) { k[i] = b; k[ixj] = a; }
+                }
+            }
         }
-        if (j < len) A.perm[s0 + r] = ms;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = lane; i < len; i += 64) A.perm[s0 + i] = (int64_t)(k[i] & 0xffffffffull);
+}
+
+// The listed long segments, one 1024-thread workgroup at a time (the grid is
+// fixed; workgroup w takes list entries w, w + gridDim, ...): a bitonic sort
+// in LDS for up to SORT_BIG particles, else ranks from memory.
+constexpr int SORT_BIG = 8192;
+__global__ void __launch_bounds__(1024) k_sort_order_big(SortArgs A)
+{
+    __shared__ unsigned long long k[SORT_BIG];
+    const int nb = *A.nbig;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int e = A.big[b];
+        const int64_t s0 = A.start[e];
+        const int len = A.count[e];
+        if (len <= SORT_BIG) {
+            int P = 1;
+            while (P < len) P <<= 1;
+            for (int i = threadIdx.x; i < P; i += blockDim.x) k[i] = i < len ? sort_key(A, s0, i) : ~0ull;
+            for (int kk = 2; kk <= P; kk <<= 1) {
+                for (int j = kk >> 1; j > 0; j >>= 1) {
+                    __syncthreads();
+                    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                        const int ixj = i ^ j;
+                        if (ixj > i) {
+                            const unsigned long long a = k[i], c2 = k[ixj];
+                            const bool up = (i & kk) == 0;
+                            if ((a > c2) == up) { k[i] = c2; k[ixj] = a; }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < len; i += blockDim.x) A.perm[s0 + i] = (int64_t)(k[i] & 0xffffffffull);
+            __syncthreads();
+        } else {
+            for (int j = threadIdx.x; j < len; j += blockDim.x) {
+                const unsigned long long my = sort_key(A, s0, j);
+                int r = 0;
+                for (int i = 0; i < len; ++i) r += sort_key(A, s0, i) < my ? 1 : 0;
+                A.perm[s0 + r] = (int64_t)(my & 0xffffffffull);
+            }
+        }
     }
 }
 

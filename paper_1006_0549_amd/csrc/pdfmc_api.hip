@@ -226,7 +226,7 @@ struct pdfmc_ctx {
     double* d_srec = nullptr;
     int64_t SREC = 0, pool_off = 0;
     int pool_cap = 0;
-    int32_t *d_pool_cnt = nullptr, *d_ecnt = nullptr, *d_eslot = nullptr, *d_eof = nullptr, *d_eoc = nullptr;
+    int32_t *d_pool_cnt = nullptr, *d_ecnt = nullptr, *d_eslot = nullptr, *d_eof = nullptr, *d_wgcnt = nullptr;
     double *d_eo = nullptr, *d_etot = nullptr;
     float* d_F32 = nullptr;
     char* d_cmean = nullptr;
@@ -266,6 +266,7 @@ struct pdfmc_ctx {
     uint32_t* d_step = nullptr;
     int32_t* d_sort_count = nullptr;
     int64_t *d_sort_scan = nullptr, *d_sort_bsum = nullptr, *d_sort_cursor = nullptr, *d_sort_start = nullptr;
+    int32_t *d_sort_big = nullptr, *d_sort_nbig = nullptr;
     // options
     int sort_interval = 0, block = 256, use_graph = 0;
     int steps_since_sort = 0;
@@ -381,7 +382,7 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_eslot, (size_t)c->NE * SC_K);
     k.take(c->d_eof, c->NE);
     k.take(c->d_eo, (size_t)c->NE * SC_VMAX);
-    k.take(c->d_eoc, 8 * (size_t)c->NE);
+    k.take(c->d_wgcnt, 4 * (size_t)c->ntiles);
     k.take(c->d_etot, (size_t)c->NE * 3 * NQ);
     k.take(c->d_cmean, c->CM, R);
     k.take(c->d_ccnt, 8 * (size_t)c->NE);
@@ -406,6 +407,8 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_sort_bsum, c->NE / SCAN_B + 1);
     k.take(c->d_sort_cursor, c->NE);
     k.take(c->d_sort_start, c->NE);
+    k.take(c->d_sort_big, c->NE);
+    k.take(c->d_sort_nbig, 1);
     k.take(c->d_amg_i, c->AMG_I);
     k.take(c->d_amg_d, c->AMG_D);
     k.take(c->d_amg, 2 * (size_t)std::max(c->n_amg, 1));
@@ -435,7 +438,7 @@ void compute_offsets(pdfmc_ctx* c)
     }
     // scatter records: SC_RT regular slots per particle tile of each case,
     // each of the case's stride (header + vertex sums + cell sums), then a
-    // pool of two records per tile at the largest stride; the sort's
+    // pool of eight records per tile at the largest stride; the sort's
     // temporaries (20 bytes per particle) reuse the region between steps
     int64_t srec = 0;
     for (auto& cs : c->cases) {
@@ -444,7 +447,7 @@ void compute_offsets(pdfmc_ctx* c)
         srec += (cs.cap + TILE - 1) / TILE * SC_RT * (int64_t)cs.rec_stride;
     }
     c->pool_off = srec;
-    c->pool_cap = (int)std::min<int64_t>(INT32_MAX / 2, 2 * (NP / TILE) + 64);
+    c->pool_cap = (int)std::min<int64_t>(INT32_MAX / 2, 8 * (NP / TILE) + 64);
     srec += (int64_t)c->pool_cap * (SC_HDR + SC_VMAX);
     srec = std::max<int64_t>(srec, (20 * NP + 7) / 8 + 3 * 32);
     c->SREC = srec;
@@ -532,7 +535,7 @@ NodeArgs node_args(pdfmc_ctx* c)
     A.is_wall = c->d_is_wall; A.wnx = c->d_wnx; A.wny = c->d_wny;
     A.nsum = c->d_nsum; A.stats = c->d_stats; A.F = c->d_F; A.csum = nullptr; A.ccnt = c->d_ccnt;
     A.srec = c->d_srec; A.pool_off = c->pool_off; A.pool_stride = SC_HDR + SC_VMAX;
-    A.ecnt = c->d_ecnt; A.eslot = c->d_eslot; A.eof = c->d_eof; A.eo = c->d_eo; A.eoc = c->d_eoc; A.etot = c->d_etot;
+    A.ecnt = c->d_ecnt; A.eslot = c->d_eslot; A.eof = c->d_eof; A.eo = c->d_eo; A.wgcnt = c->d_wgcnt; A.etot = c->d_etot;
     A.kf = c->d_kf; A.ef = c->d_ef; A.L2 = c->d_L2; A.er_r = c->d_er_r; A.er_dval = c->d_er_dval; A.er_b = c->d_er_b;
     A.er_x = c->d_er_x; A.er_val = c->d_er_val; A.pk_val = c->d_pk_val; A.pb = c->d_pb; A.phi = c->d_phi; A.P = c->d_P;
     A.counters = c->d_counters;
@@ -552,8 +555,8 @@ StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins)
     else { A.F = (const R*)c->d_F32; A.fstride = NF32; }
     A.cmean = (const R*)c->d_cmean;
     A.srec = c->d_srec; A.pool_off = c->pool_off; A.pool_stride = SC_HDR + SC_VMAX; A.pool_cap = c->pool_cap;
-    A.pool_cnt = c->d_pool_cnt; A.ecnt = c->d_ecnt; A.eslot = c->d_eslot; A.eof = c->d_eof; A.eo = c->d_eo;
-    A.eoc = c->d_eoc; A.counters = c->d_counters; A.step = c->d_step;
+    A.pool_cnt = c->d_pool_cnt; A.wgcnt = c->d_wgcnt; A.eof = c->d_eof; A.eo = c->d_eo;
+    A.counters = c->d_counters; A.step = c->d_step;
     A.ntiles = c->ntiles; A.advance = advance; A.do_bins = do_bins;
     return A;
 }
@@ -601,8 +604,12 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins)
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     }
-    // the records -> element vertex sums and cell means -> node statistics
+    // the records -> element lists -> element vertex sums and cell means ->
+    // node statistics
     NodeArgs N = node_args(c);
+    hipLaunchKernelGGL(k_scatter_register, dim3(nblk((int64_t)c->ntiles * SC_RT + c->pool_cap, 256)), dim3(256), 0,
+                       c->stream, N, c->ntiles, b, (const int32_t*)c->d_tile_case, (const int32_t*)c->d_pool_cnt,
+                       c->pool_cap, c->d_counters, do_bins);
     if (c->prec == PDFMC_FP64)
         hipLaunchKernelGGL(k_elem_reduce<double>, dim3(nblk(c->NE, 4)), dim3(256), 0, c->stream, N,
                            (double*)c->d_cmean, do_bins);
@@ -945,12 +952,13 @@ pdfmc_status enqueue_sort(pdfmc_ctx* c)
     S.cases = c->d_cases; S.tile_case = c->d_tile_case; S.elem_case = c->d_elem_case;
     S.ntiles = c->ntiles; S.ne = c->NE; S.elem = c->part[c->cur].elem;
     S.count = c->d_sort_count; S.scan = c->d_sort_scan; S.bsum = c->d_sort_bsum; S.cursor = c->d_sort_cursor;
-    S.start = c->d_sort_start;
+    S.start = c->d_sort_start; S.big = c->d_sort_big; S.nbig = c->d_sort_nbig;
     // temporaries in the scatter-record region, which holds nothing between steps
     S.perm = (int64_t*)c->d_srec;
     S.tmp_src = S.perm + c->NP;
     S.tmp_id = (uint32_t*)(S.tmp_src + c->NP);
     TRY(enqueue_fill_i(c, c->d_sort_count, c->NE));
+    TRY(enqueue_fill_i(c, c->d_sort_nbig, 1));
     const int64_t threads = (int64_t)c->ntiles * TILE;
     hipLaunchKernelGGL(k_sort_hist, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S);
     const int nb = (int)nblk(c->NE, SCAN_B);
@@ -960,6 +968,7 @@ pdfmc_status enqueue_sort(pdfmc_ctx* c)
     hipLaunchKernelGGL(k_sort_place, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S,
                        (const uint32_t*)c->part[c->cur].id);
     hipLaunchKernelGGL(k_sort_order, dim3(nblk(c->NE, 4)), dim3(256), 0, c->stream, S);
+    hipLaunchKernelGGL(k_sort_order_big, dim3(64), dim3(1024), 0, c->stream, S);
     LAUNCHCHK(c);
     PartBufs& A = c->part[c->cur];
     PartBufs& B = c->part[1 - c->cur];
@@ -1378,7 +1387,6 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     // element pass clears what it consumes)
     TRY(enqueue_fill_i(c, c->d_ecnt, c->NE));
     TRY(enqueue_fill_i(c, c->d_eof, c->NE));
-    TRY(enqueue_fill_i(c, c->d_eoc, 8 * (int64_t)c->NE));
     TRY(enqueue_fill(c, c->d_eo, (int64_t)c->NE * SC_VMAX));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_stats = false;

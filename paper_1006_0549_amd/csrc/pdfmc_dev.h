@@ -34,17 +34,21 @@ enum Counter {
 
 // Scatter records (reading R-11 and the cell sums of R-23). Each workgroup of
 // the particle kernel writes one record per distinct element among its
-// particles: the element's three vertex sums of the node moments and its
-// cell sums, summed over the workgroup's particles in a fixed order. Record
-// layout (doubles): [0] key (int64 bits: global workgroup index * 256 + the
-// element's rank among the workgroup's elements), [1] [2] particle counts of
-// bins 0..3 and 4..7 (16 bits each), [3 .. 3 + 3 nq) vertex sums (vertex-major),
-// then, with cells, 8 bins x (1 + ns): sum w, sum w psi_a.
+// particles (more when the element's sums could not all be merged): the
+// element's three vertex sums of the node moments and its cell sums, summed
+// over the workgroup's particles in a fixed order. Record layout (doubles):
+// [0] key (int64 bits: global workgroup index * 512 + the element's first
+// lane in the workgroup, or 256 + a wavefront's first lane of it for a share
+// that went out alone), [1] element (int64 bits), [2] mask of the bins with
+// particles (int64 bits), [3 .. 3 + 3 nq) vertex sums (vertex-major), then,
+// with cells, 8 bins x (2 + ns): particle count, sum w, sum w psi_a (valid
+// for the bins in the mask only).
 constexpr int SC_HDR = 3;
-constexpr int SC_RT = 32;       // regular record slots per particle tile
-constexpr int SC_K = 32;        // record handles listed per element per step
-constexpr int SC_VMAX = 3 * NQ + 8 * (1 + MAXS);   // values of a record
-__device__ __host__ inline int sc_nvals(int ns, bool cells) { return 3 * (12 + 2 * ns) + (cells ? 8 * (1 + ns) : 0); }
+constexpr int SC_RT = 40;       // regular record slots per particle tile
+constexpr int SC_SQ = 6;        // sums of shared elements a wavefront stages in LDS for the merge
+constexpr int SC_K = 64;        // record handles listed per element per step (one per lane of the element pass)
+constexpr int SC_VMAX = 3 * NQ + 8 * (2 + MAXS);   // values of a record
+__device__ __host__ inline int sc_nvals(int ns, bool cells) { return 3 * (12 + 2 * ns) + (cells ? 8 * (2 + ns) : 0); }
 
 struct BcDev {
     int32_t type;        // 0 wall, 1 periodic
@@ -117,11 +121,9 @@ struct StepArgs {
     int64_t pool_off;             // pool records at srec + pool_off, pool_stride doubles each
     int32_t pool_stride, pool_cap;
     int32_t* pool_cnt;            // records taken from the pool this step
-    int32_t* ecnt;                // [NE] records listed per element
-    int32_t* eslot;               // [NE][SC_K] record handles: >= 0 regular, < 0 pool (-1 - index)
+    int32_t* wgcnt;               // [workgroups] regular record slots used by each workgroup
     int32_t* eof;                 // [NE] 1: the element has values in the overflow sums
     double* eo;                   // [NE][SC_VMAX] overflow sums (FP64 atomics)
-    int32_t* eoc;                 // [NE][8] overflow counts
     unsigned long long* counters; // [ncase][NCNT]
     const uint32_t* step;         // device step index
     int32_t ntiles;

@@ -12,6 +12,8 @@ template <typename R> __global__ void k_draw_gaussians(uint32_t slo, uint32_t sh
 __global__ void k_fill_f64(double* a, int64_t n, double v);
 __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v);
 __global__ void k_step_increment(uint32_t* step);
+__global__ void k_scatter_register(NodeArgs A, int ntiles, int block, const int32_t* tile_case, const int32_t* pool_cnt,
+                                   int pool_cap, unsigned long long* counters, int cells_on);
 template <typename R> __global__ void k_elem_reduce(NodeArgs A, R* cmean, int cells_on);
 __global__ void k_node_reduce(NodeArgs A);
 __global__ void k_fields_grad(NodeArgs A);
@@ -50,6 +52,7 @@ __global__ void k_sort_scan_totals(SortArgs A, int nb);
 __global__ void k_sort_cursor(SortArgs A);
 __global__ void k_sort_place(SortArgs A, const uint32_t* ids);
 __global__ void k_sort_order(SortArgs A);
+__global__ void k_sort_order_big(SortArgs A);
 template <typename R> __global__ void k_sort_gather(SortArgs A, Particles<R> src, Particles<R> dst);
 
 }  // namespace pdfmc

@@ -46,10 +46,10 @@ struct NodeArgs {
     int64_t pool_off;
     int32_t pool_stride, pad2;
     int32_t* ecnt;                   // [ne] records listed per element
-    const int32_t* eslot;            // [ne][SC_K] record handles
+    int32_t* eslot;                  // [ne][SC_K] record handles: >= 0 regular, < 0 pool (-1 - index)
     int32_t* eof;                    // [ne] overflow flags
     double* eo;                      // [ne][SC_VMAX] overflow sums
-    int32_t* eoc;                    // [ne][8] overflow counts
+    const int32_t* wgcnt;            // [workgroups] regular record slots used by each workgroup
     double* etot;                    // [ne][3][NQ] vertex sums of each element
 };
 

@@ -18,6 +18,8 @@ struct SortArgs {
     uint32_t* tmp_id;        // [NP] ids placed in their segments (arbitrary order inside)
     int64_t* tmp_src;        // [NP] source index of each placed id
     int64_t* perm;           // [NP] source index of the particle at each final position
+    int32_t* big;            // [ne] elements whose segments are sorted by k_sort_order_big
+    int32_t* nbig;           // their count
 };
 
 constexpr int SCAN_B = 1024;     // elements per block of the count scan

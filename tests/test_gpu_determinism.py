@@ -103,12 +103,17 @@ def test_batched_equals_sequential_bitwise(P):
         _assert_bitwise(a, b, f"case {i}")
 
 
-def test_sort_orders_by_element_then_id(P):
-    cfg = W.config_small()
-    parts = cfg["particles"]
+@pytest.mark.parametrize("nodes,ppe", [(16, 50), (4, 700), (3, 9500)],
+                         ids=["short-segments", "long-segments", "longest-segments"])
+def test_sort_orders_by_element_then_id(P, nodes, ppe):
+    """Element segments of up to 512 particles are sorted by one wavefront,
+    longer ones by a workgroup, and those beyond 8192 by ranks from memory."""
+    mesh = W.unit_square(nodes, 0.2, periodic_x=True, seed_key=(0, 0, 0))
+    params = W.default_params(mode=1, n_scalars=1, dt=1e-3, nu=1e-3)
+    parts = W.init_particles(mesh, ppe, 1, W.rng_for(0, 0, 5), u_std=0.1, psi_disks=[(0.5, 0.5, 0.3, 1.0)])
     n = len(parts["x"])
-    _flush("[sort_order] small square, 7 steps, then one sort")
-    sim, ids = _context(P, "fp32", [(cfg["mesh"], cfg["params"], parts)], 7)
+    _flush(f"[sort_order] square {mesh.n_elems} triangles, {n} particles, 7 steps, then one sort")
+    sim, ids = _context(P, "fp32", [(mesh, params, parts)], 7)
     before = sim.download(ids[0], n)
     sim.sort()
     after = sim.download(ids[0], n)
