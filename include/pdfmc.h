@@ -130,29 +130,101 @@ pdfmc_status pdfmc_case_info(pdfmc_ctx* ctx, int32_t case_id, int32_t* n_stat_no
 pdfmc_status pdfmc_workspace_query(pdfmc_ctx* ctx, uint64_t* bytes);
 pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* ctx, void* dev_ptr, uint64_t bytes);
 
-/* Particle init: upload an ensemble (n <= capacity). Rejects an element id
- * outside the case. Particles keep their id across sorts. */
+/* Particle ensemble (Sec. II, closing paragraph: the flow is represented by
+ * a large number of particles carrying position, velocity, frequency and
+ * compositions). Upload copies an ensemble from the host (n <= capacity);
+ * the whole ensemble is checked before any device work, and an element id
+ * outside the case, a non-finite x, y, U, omega, weight or scalar, or a
+ * weight that is not positive gives PDFMC_E_INVALID (these checks need no
+ * bound workspace; the copy itself then needs one, PDFMC_E_STATE before).
+ * The particle counters restart at 0. Particles keep their id (the RNG
+ * identity of R-32) across sorts. */
 pdfmc_status pdfmc_particles_upload(pdfmc_ctx* ctx, int32_t case_id, const pdfmc_particles_host* p);
+
+/* Initial ensemble drawn on the device (readings R-29..R-32 of the paper's
+ * unstated initial conditions): ppe particles per element, particle i in
+ * element i / ppe with id i, its draws from the case's Philox generator with
+ * purpose 1 (counter (id, 0, stream, 256 + block), blocks 0..4, uniforms
+ * u_0..u_9 formed as for the Wiener increments):
+ *   position uniform in the element: s = sqrt(u_0), lambda = (1 - s,
+ *     s (1 - u_1), s u_1), X = (lambda_0 x_0 + lambda_1 x_1) + lambda_2 x_2;
+ *   velocity U_i = u_std g_i, Box-Muller Gaussians g_0, g_1 from (u_2, u_3)
+ *     and g_2 from (u_4, u_5);
+ *   frequency Gamma(4, omega_scale): -omega_scale (sum of ln u_6..u_9);
+ *   scalar a = disk[a][3] inside its disk (centre disk[a][0..1], radius
+ *     disk[a][2] > 0), else 0; mass weight A_e / ppe (R-31); bin 0.
+ * Computed in FP64 in either precision (an FP32 context stores the rounded
+ * values). Errors: PDFMC_E_INVALID for ppe < 1, ne * ppe above the case's
+ * capacity, u_std < 0, omega_scale <= 0 or non-finite values; PDFMC_E_STATE
+ * before a workspace is bound. Synchronises the stream; counters restart. */
+typedef struct {
+    double u_std;                       /* velocity standard deviation per component */
+    double omega_scale;                 /* scale of the Gamma(4, scale) frequency     */
+    double disk[PDFMC_MAX_SCALARS][4];  /* cx, cy, r, value; r <= 0: no disk          */
+} pdfmc_init_params;
+pdfmc_status pdfmc_particles_init(pdfmc_ctx* ctx, int32_t case_id, int32_t ppe, const pdfmc_init_params* p);
 pdfmc_status pdfmc_particles_download(pdfmc_ctx* ctx, int32_t case_id, pdfmc_particles_host* p);
 
-/* Eulerian fields per raw node, [n_nodes*PDFMC_NF] node-major, slots:
+/* The Eulerian fields evaluated at the particles (Sec. II, after Eq.(3):
+ * the mean fields on the right-hand sides of Eqs.(4), (5) and (9) are
+ * evaluated at the particle positions; reading R-06 lists them), per raw
+ * node, [n_nodes*PDFMC_NF] node-major, slots:
  * 0-2 <U_i>; 3-4 d<P>/dx_j; 5-10 d<U_i>/dx_j (i-major); 11-13 lap <U_i>;
- * 14-18 G11,G12,G21,G22,G33; 19 <omega>; 20 C0 eps; 21 S_omega. */
-pdfmc_status pdfmc_fields_upload(pdfmc_ctx* ctx, int32_t case_id, const double* F);
+ * 14-18 G11,G12,G21,G22,G33; 19 <omega>; 20 C0 eps; 21 S_omega.
+ * Upload copies them in (periodic images take the value of the image with
+ * the lowest raw index); every value must be finite (PDFMC_E_INVALID). Bit q
+ * of freeze_mask keeps slot q of this case at the uploaded value in the
+ * fields the particles see, also in modes 1 and 2 where the step derives
+ * the fields from the statistics (the other fields of the same step are
+ * derived from the computed values); mode 0 freezes every slot anyway.
+ * Bits above slot 21: PDFMC_E_INVALID. Synchronises the stream. */
+pdfmc_status pdfmc_fields_upload(pdfmc_ctx* ctx, int32_t case_id, const double* F, uint32_t freeze_mask);
+/* The fields in force, same layout as the upload; synchronises the stream. */
 pdfmc_status pdfmc_fields_download(pdfmc_ctx* ctx, int32_t case_id, double* F);
+/* The mean pressure <P> per raw node (Sec. II, closing paragraph: the mean
+ * pressure of Eq.(4) from the projection on the grid, reading R-27; 0 in
+ * modes 0 and 1, and before the first step). Synchronises the stream. */
 pdfmc_status pdfmc_pressure_download(pdfmc_ctx* ctx, int32_t case_id, double* P);
 
-/* Initialisation pass over every case: statistics of the uploaded state,
- * the Eulerian fields (not in mode 0), velocity bins and cell means. */
+/* Initialisation pass over every case (the state the first forward-Euler
+ * step of Sec. II starts from): grid statistics of the uploaded or drawn
+ * ensemble (Sec. I, grid role (i)), the Eulerian fields derived from them
+ * (not in mode 0), velocity bins and cell means of IECM (Eq.(9), R-23).
+ * PDFMC_E_STATE before a workspace is bound. Synchronises the stream. */
 pdfmc_status pdfmc_init(pdfmc_ctx* ctx);
-/* Only recompute bins and cell means against the current fields. */
+/* Only recompute the velocity bins and cell means of Eq.(9) (R-23) against
+ * the fields in force (after a fields upload). Synchronises the stream. */
 pdfmc_status pdfmc_rebin(pdfmc_ctx* ctx);
-/* Advance every case by n_steps time steps (asynchronous). */
-pdfmc_status pdfmc_step(pdfmc_ctx* ctx, int32_t n_steps);
-/* Time-step index that enters the RNG counter (R-09); for restarts. */
+/* Advance every case by n_steps time steps (asynchronous on the stream).
+ * One step is the forward-Euler step of Sec. II, closing paragraph: the
+ * particle SDEs Eqs.(2), (4), (5), (9) with tracking and boundary
+ * conditions, then the grid statistics of the new state (Sec. I, role (i)),
+ * then the Eulerian fields, relaxation and projection (role (ii)); the
+ * order is reading R-08. stage_mask selects stages (tests isolate kernels
+ * with it; PDFMC_STAGE_ALL is the method's step):
+ *   PDFMC_STAGE_ADVANCE  the particle increments, walk and sources; without
+ *                        it the particles stay where they are
+ *   PDFMC_STAGE_STATS    node statistics and cell means of the new state;
+ *                        without it they keep their values
+ *   PDFMC_STAGE_FIELDS   the Eulerian fields from the statistics; without it
+ *                        they keep their values
+ * The step index (R-09) advances in every case. Reports launch failures
+ * only; anomalies inside a step are counted (pdfmc_counters). Errors:
+ * PDFMC_E_INVALID for n_steps < 0 or unknown stage bits, PDFMC_E_STATE
+ * before init. */
+#define PDFMC_STAGE_ADVANCE 1u
+#define PDFMC_STAGE_STATS 2u
+#define PDFMC_STAGE_FIELDS 4u
+#define PDFMC_STAGE_ALL 7u
+pdfmc_status pdfmc_step(pdfmc_ctx* ctx, int32_t n_steps, uint32_t stage_mask);
+/* Time-step index that enters the RNG counter (R-09): a restart that sets
+ * the index and uploads particles and fields continues the same sample
+ * path. Synchronises the stream. */
 pdfmc_status pdfmc_set_step_index(pdfmc_ctx* ctx, uint32_t n);
 
-/* Statistics readback per raw node: [n_nodes*(12+2*n_scalars)]:
+/* Statistics readback (Sec. I, grid role (i): Eulerian statistics extracted
+ * at the gridpoints; estimator of reading R-11, thin-node rule R-34), per
+ * raw node: [n_nodes*(12+2*n_scalars)]:
  * W, rho, <U_1..3>, <u1u1>,<u2u2>,<u3u3>,<u1u2>,<u1u3>,<u2u3>, <omega>,
  * <psi_a> (n_scalars), <psi_a'^2> (n_scalars). Synchronises the stream. */
 pdfmc_status pdfmc_stats_readback(pdfmc_ctx* ctx, int32_t case_id, double* out);
@@ -164,7 +236,10 @@ pdfmc_status pdfmc_node_sums(pdfmc_ctx* ctx, int32_t case_id, double* out);
 /* Cell means of the IECM conditional mean, [n_elems*8*n_s], and cell
  * particle counts [n_elems*8] (either pointer may be NULL). */
 pdfmc_status pdfmc_cell_means(pdfmc_ctx* ctx, int32_t case_id, double* mean, int32_t* count);
-/* Counters since upload, [PDFMC_N_COUNTERS]: walk fallbacks, reflections,
+/* Counters since upload or initial draw (the failure detection around the
+ * readings the paper leaves open: R-13 walk fallback, R-14 reflections,
+ * R-15 periodic crossings, R-21 frequency sign flips, R-34 thin nodes,
+ * R-18 floors, R-28 solver iterations), [PDFMC_N_COUNTERS]: walk fallbacks, reflections,
  * periodic crossings, omega sign flips, empty nodes, non-finite particles,
  * walk steps, ER CG iterations, projection CG iterations, CG failures,
  * k floor hits, eps floor hits, scatter overflows (a workgroup's element sums

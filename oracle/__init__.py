@@ -67,6 +67,21 @@ class _Params(C.Structure):
                 ("reaction", C.c_int32), ("k_react", C.c_double * 4)]
 
 
+class _InitParams(C.Structure):
+    _fields_ = [("u_std", C.c_double), ("omega_scale", C.c_double), ("disk", (C.c_double * 4) * 4)]
+
+
+def init_params_struct(u_std, omega_scale, disks=()):
+    ip = _InitParams()
+    ip.u_std, ip.omega_scale = float(u_std), float(omega_scale)
+    for a, dk in enumerate(disks):
+        if dk is None:
+            continue
+        for j in range(4):
+            ip.disk[a][j] = float(dk[j])
+    return ip
+
+
 class _Particles(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.POINTER(C.c_double)) for k in
                                      ("x", "y", "u", "v", "w", "omega", "weight", "psi")] + \
@@ -105,7 +120,8 @@ def lib():
         for name in ("orc_add_case", "orc_mesh_info", "orc_particles_upload", "orc_particles_download",
                      "orc_fields_upload", "orc_fields_download", "orc_pressure_download", "orc_init",
                      "orc_rebin", "orc_step", "orc_stats", "orc_node_sums", "orc_cell_means",
-                     "orc_counters", "orc_bary", "orc_recover", "orc_set_stats", "orc_derive"):
+                     "orc_counters", "orc_bary", "orc_recover", "orc_set_stats", "orc_derive",
+                     "orc_particles_init"):
             getattr(L, name).restype = C.c_int
         L.orc_relax_source.restype = C.c_int
         L.orc_relax_source.argtypes = [C.c_void_p] + [C.POINTER(C.c_double)] * 2 + [C.c_double, C.c_double] + \
@@ -262,6 +278,13 @@ class Oracle:
                         b.ctypes.data_as(C.POINTER(C.c_uint8)))
         self._check(self._L.orc_particles_upload(self._c, cs, C.byref(st)), "upload")
 
+    def particles_init(self, cs, ppe, u_std=0.1, omega_scale=0.25, disks=()):
+        """Initial ensemble of R-29/R-30 (ppe particles per element, drawn from
+        the case's generator with purpose 1); returns the particle count."""
+        ip = init_params_struct(u_std, omega_scale, disks)
+        self._check(self._L.orc_particles_init(self._c, cs, int(ppe), C.byref(ip)), "particles_init")
+        return self._cases[cs][0].n_elems * int(ppe)
+
     def download(self, cs, n):
         ns = self._cases[cs][1]["n_scalars"]
         out = {k: np.zeros(n) for k in ("x", "y", "u", "v", "w", "omega", "weight")}
@@ -277,9 +300,9 @@ class Oracle:
         out["elem"], out["id"], out["bin"] = elem, pid, b
         return out
 
-    def fields_upload(self, cs, F):
+    def fields_upload(self, cs, F, freeze_mask=0):
         F = np.ascontiguousarray(F, dtype=np.float64)
-        self._check(self._L.orc_fields_upload(self._c, cs, _dp(F)), "fields_upload")
+        self._check(self._L.orc_fields_upload(self._c, cs, _dp(F), C.c_uint32(int(freeze_mask))), "fields_upload")
 
     def fields(self, cs):
         mesh = self._cases[cs][0]

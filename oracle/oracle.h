@@ -109,9 +109,29 @@ int orc_mesh_info(orc_ctx* c, int32_t cs, int32_t* n_stat_nodes, int32_t* stat_n
                   int32_t* nbr /*[3*ne] or NULL*/, double* rec /*[8*ne] or NULL*/,
                   double* vol /*[n_nodes] or NULL*/);
 int orc_particles_upload(orc_ctx* c, int32_t cs, const orc_particles* p);
+/* Initial ensemble of a case (R-29, R-30, R-31, R-32): ppe particles per
+ * element, particle i in element i / ppe with id i, drawn from the case's
+ * generator with purpose 1 (counter (id, 0, stream, 256 + block), blocks
+ * 0..4, uniforms u_0..u_9):
+ *   position uniform in the element: s = sqrt(u_0), lambda = (1 - s,
+ *     s (1 - u_1), s u_1), X = (lambda_0 x_0 + lambda_1 x_1) + lambda_2 x_2;
+ *   velocity U_i = u_std g_i with Box-Muller Gaussians g_0, g_1 from
+ *     (u_2, u_3) and g_2 from (u_4, u_5);
+ *   frequency Gamma(4, omega_scale): omega = -omega_scale (((ln u_6 +
+ *     ln u_7) + ln u_8) + ln u_9);
+ *   scalar a = disk[a][3] inside its disk (centre disk[a][0..1], radius
+ *     disk[a][2] > 0), else 0; mass weight A_e / ppe; bin 0. */
+typedef struct {
+    double u_std, omega_scale;
+    double disk[ORC_MAXS][4];
+} orc_init_params;
+int orc_particles_init(orc_ctx* c, int32_t cs, int32_t ppe, const orc_init_params* ip);
 int orc_particles_download(orc_ctx* c, int32_t cs, orc_particles* p);
-/* F: [n_nodes*ORC_NF], node-major, per raw node (periodic images must agree) */
-int orc_fields_upload(orc_ctx* c, int32_t cs, const double* F);
+/* F: [n_nodes*ORC_NF], node-major, per raw node (periodic images must agree).
+ * Bit q of freeze_mask keeps slot q at the uploaded value whenever the
+ * fields are derived from the statistics (applied after the whole
+ * derivation, so the other slots see the derived values). */
+int orc_fields_upload(orc_ctx* c, int32_t cs, const double* F, uint32_t freeze_mask);
 int orc_fields_download(orc_ctx* c, int32_t cs, double* F);
 int orc_pressure_download(orc_ctx* c, int32_t cs, double* P /*[n_nodes]*/);
 /* initialisation pass: statistics of the uploaded state, Eulerian fields

@@ -15,7 +15,7 @@ static void case_free(ocase* cs)
     omesh_free(&cs->m);
     free(cs->x); free(cs->y); free(cs->u); free(cs->v); free(cs->w); free(cs->om); free(cs->wt);
     free(cs->psi); free(cs->elem); free(cs->id); free(cs->bin);
-    free(cs->F); free(cs->stats); free(cs->sums); free(cs->cmean); free(cs->ccount); free(cs->P);
+    free(cs->F); free(cs->Ffrz); free(cs->stats); free(cs->sums); free(cs->cmean); free(cs->ccount); free(cs->P);
     free(cs);
 }
 
@@ -56,6 +56,7 @@ int orc_add_case(orc_ctx* c, const orc_mesh_desc* m, const orc_params* p, int32_
     if (rc) { case_free(cs); return rc; }
     int nsn = cs->m.nsn, ne = cs->m.ne, ns = p->n_scalars;
     cs->F = orc_alloc(sizeof(double) * (size_t)nsn * ORC_NF);
+    cs->Ffrz = orc_alloc(sizeof(double) * (size_t)nsn * ORC_NF);
     cs->stats = orc_alloc(sizeof(double) * (size_t)nsn * (12 + 2 * ns));
     cs->sums = orc_alloc(sizeof(double) * (size_t)nsn * (12 + 2 * ns));
     cs->cmean = orc_alloc(sizeof(double) * (size_t)ne * 8 * (ns > 0 ? ns : 1));
@@ -124,12 +125,14 @@ int orc_particles_download(orc_ctx* c, int32_t ci, orc_particles* p)
     return ORC_OK;
 }
 
-int orc_fields_upload(orc_ctx* c, int32_t ci, const double* F)
+int orc_fields_upload(orc_ctx* c, int32_t ci, const double* F, uint32_t freeze_mask)
 {
     ocase* cs = get_case(c, ci);
-    if (!cs || !F) return orc_err(c, ORC_E_INVALID, "fields_upload: bad argument");
+    if (!cs || !F || (freeze_mask >> ORC_NF)) return orc_err(c, ORC_E_INVALID, "fields_upload: bad argument");
     for (int s = 0; s < cs->m.nsn; ++s)
         memcpy(cs->F + (size_t)s * ORC_NF, F + (size_t)cs->m.rep[s] * ORC_NF, sizeof(double) * ORC_NF);
+    memcpy(cs->Ffrz, cs->F, sizeof(double) * (size_t)cs->m.nsn * ORC_NF);
+    cs->freeze = freeze_mask;
     return ORC_OK;
 }
 
@@ -343,5 +346,60 @@ int orc_relax_source(const orc_params* p, const double stress[6], const double g
                       {stress[4], stress[5], stress[2]}};
     double dU[3][3] = {{grad[0], grad[1], 0.0}, {grad[2], grad[3], 0.0}, {grad[4], grad[5], 0.0}};
     orc_relax_node(p, R, dU, k, eps, n[0], n[1], r, dval, L2, Av);
+    return ORC_OK;
+}
+
+int orc_particles_init(orc_ctx* c, int32_t ci, int32_t ppe, const orc_init_params* ip)
+{
+    ocase* cs = get_case(c, ci);
+    if (!cs || !ip || ppe < 1) return orc_err(c, ORC_E_INVALID, "particles_init: bad argument");
+    const omesh* m = &cs->m;
+    const int ns = cs->p.n_scalars;
+    const int64_t n = (int64_t)m->ne * ppe;
+    free(cs->x); free(cs->y); free(cs->u); free(cs->v); free(cs->w); free(cs->om); free(cs->wt);
+    free(cs->psi); free(cs->elem); free(cs->id); free(cs->bin);
+    size_t d = sizeof(double) * (size_t)n;
+    cs->np = n;
+    cs->x = orc_alloc(d); cs->y = orc_alloc(d); cs->u = orc_alloc(d); cs->v = orc_alloc(d);
+    cs->w = orc_alloc(d); cs->om = orc_alloc(d); cs->wt = orc_alloc(d);
+    cs->psi = orc_alloc(d * (ns > 0 ? ns : 1));
+    cs->elem = orc_alloc(sizeof(int32_t) * (size_t)n);
+    cs->id = orc_alloc(sizeof(uint32_t) * (size_t)n);
+    cs->bin = orc_alloc((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int e = (int)(i / ppe);
+        double u[10];
+        orc_init_uniforms(cs->p.seed, (uint32_t)i, cs->p.stream, u);
+        /* R-29: uniform in the element */
+        const int* t = m->tri + 3 * e;
+        double s = sqrt(u[0]);
+        double l0 = 1.0 - s, l1 = s * (1.0 - u[1]), l2 = s * u[1];
+        double x = (l0 * m->x[t[0]] + l1 * m->x[t[1]]) + l2 * m->x[t[2]];
+        double y = (l0 * m->y[t[0]] + l1 * m->y[t[1]]) + l2 * m->y[t[2]];
+        /* R-30: Gaussian velocity components, Gamma(4, scale) frequency */
+        double r0 = sqrt(-2.0 * orc_ln(u[2])), s0, c0;
+        orc_sincos2pi(u[3], &s0, &c0);
+        double r1 = sqrt(-2.0 * orc_ln(u[4])), s1, c1;
+        orc_sincos2pi(u[5], &s1, &c1);
+        cs->x[i] = x; cs->y[i] = y;
+        cs->u[i] = ip->u_std * (r0 * c0);
+        cs->v[i] = ip->u_std * (r0 * s0);
+        cs->w[i] = ip->u_std * (r1 * c1);
+        cs->om[i] = -ip->omega_scale * (((orc_ln(u[6]) + orc_ln(u[7])) + orc_ln(u[8])) + orc_ln(u[9]));
+        /* R-31 mass weight, R-32 identity */
+        cs->wt[i] = m->area[e] / (double)ppe;
+        cs->elem[i] = e;
+        cs->id[i] = (uint32_t)i;
+        cs->bin[i] = 0;
+        for (int a = 0; a < ns; ++a) {
+            double val = 0.0;
+            if (ip->disk[a][2] > 0.0) {
+                double dx = x - ip->disk[a][0], dy = y - ip->disk[a][1];
+                if (dx * dx + dy * dy < ip->disk[a][2] * ip->disk[a][2]) val = ip->disk[a][3];
+            }
+            cs->psi[(size_t)a * n + i] = val;
+        }
+    }
+    memset(cs->cnt, 0, sizeof cs->cnt);
     return ORC_OK;
 }

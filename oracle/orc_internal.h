@@ -47,6 +47,8 @@ typedef struct {
     double *x, *y, *u, *v, *w, *om, *wt, *psi;
     int32_t* elem; uint32_t* id; uint8_t* bin;
     double *F;       /* [nsn*ORC_NF] */
+    double *Ffrz;    /* [nsn*ORC_NF] uploaded fields, for the frozen slots */
+    uint32_t freeze; /* bit q: slot q keeps its uploaded value */
     double *stats;   /* [nsn*(12+2ns)] */
     double *sums;    /* [nsn*(11+2ns)] raw sums of the last statistics pass */
     double *cmean;   /* [ne*8*ns] */
@@ -74,6 +76,7 @@ void omesh_bary(const omesh* m, int e, double x, double y, double lam[3]);
 
 /* rng */
 void orc_uniforms(uint64_t seed, uint32_t id, uint32_t step, uint32_t stream, double u[6]);
+void orc_init_uniforms(uint64_t seed, uint32_t id, uint32_t stream, double u[10]);
 
 /* locate */
 int  orc_walk_case(ocase* cs, int e0, double* x, double* y, double u3[3]);

@@ -450,6 +450,10 @@ int orc_derive_fields(orc_ctx* c, ocase* cs, int project)
         }
     }
     free(kf); free(ef); free(tmp);
+    /* slots the caller froze keep their uploaded values */
+    for (int s = 0; s < nsn; ++s)
+        for (int q = 0; q < ORC_NF; ++q)
+            if ((cs->freeze >> q) & 1u) cs->F[(size_t)s * ORC_NF + q] = cs->Ffrz[(size_t)s * ORC_NF + q];
     return rc;
 }
 

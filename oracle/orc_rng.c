@@ -146,3 +146,21 @@ void orc_gauss6(uint64_t seed, uint32_t id, uint32_t step, uint32_t stream, doub
         xi[2 * j + 1] = r * s;
     }
 }
+
+/* Initial-state draws (R-29, R-30): the same generator with purpose 1 in the
+ * counter, counter = (id, 0, stream, (1 << 8) | block), blocks 0..4 ->
+ * 20 words; uniform m = 0..9 from words 2m (high) and 2m+1 (low),
+ * u_m = (2*((w_{2m} << 20) | (w_{2m+1} >> 12)) + 1) * 2^-53. */
+void orc_init_uniforms(uint64_t seed, uint32_t id, uint32_t stream, double u[10])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[20];
+    for (uint32_t b = 0; b < 5; ++b) {
+        uint32_t ctr[4] = {id, 0u, stream, (1u << 8) | b};
+        orc_philox4x32_10(ctr, key, w + 4 * b);
+    }
+    for (int m = 0; m < 10; ++m) {
+        uint64_t K = ((uint64_t)w[2 * m] << 20) | (uint64_t)(w[2 * m + 1] >> 12);
+        u[m] = (double)(2 * K + 1) * 0x1p-53;
+    }
+}

@@ -13,7 +13,7 @@
 //                  solves themselves are in k_mg.hip (R-28)
 //   k_er_finish    G_ij and C0 eps from the relaxed tensor (R-19)
 //   k_proj_rhs / k_proj_finish  pressure projection (R-27)
-//   k_mirror_f32   FP32 copy of the fields for the FP32 particle kernel
+//   k_fields_elem  element-major copy of the fields in the particle precision
 #include "pdfmc_dev.h"
 #include "pdfmc_nodes.h"
 
@@ -310,14 +310,37 @@ __global__ void k_proj_grad(NodeArgs A)
     A.F[(int64_t)s * NF + F_DPY] = C.dpdx[1] + gy;
 }
 
-__global__ void k_mirror_f32(const double* __restrict__ F, float* __restrict__ F32, int nn)
+// Field slots a case keeps frozen go back to their uploaded values after the
+// fields have been derived from the statistics (the particles then see the
+// uploaded values; fields derived within the step used the computed ones).
+__global__ void k_fields_freeze(const CaseDev* __restrict__ cases, const int32_t* __restrict__ node_case,
+                                const double* __restrict__ Ffrz, double* __restrict__ F, int nn)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)nn * NF32) return;
-    const int64_t s = i / NF32;
-    const int q = (int)(i % NF32);
-    F32[i] = q < NF ? (float)F[s * NF + q] : 0.0f;
+    if (i >= (int64_t)nn * NF) return;
+    const int64_t s = i / NF;
+    const int q = (int)(i - s * NF);
+    if ((cases[node_case[s]].freeze >> q) & 1u) F[i] = Ffrz[i];
 }
+
+// Element-major copy of the nodal fields in the particle precision: row k of
+// element e holds the fields of its vertex k, so that a particle reads its
+// element's three rows from one place right after its element id.
+template <typename R>
+__global__ void k_fields_elem(const double* __restrict__ F, const int4* __restrict__ tri_s, R* __restrict__ Fel, int ne)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)ne * 3 * NFE) return;
+    const int64_t r = i / NFE;
+    const int q = (int)(i - r * NFE);
+    const int64_t e = r / 3;
+    const int k = (int)(r - e * 3);
+    const int4 t = tri_s[e];
+    const int s = k == 0 ? t.x : (k == 1 ? t.y : t.z);
+    Fel[i] = q < NF ? (R)F[(int64_t)s * NF + q] : R(0);
+}
+template __global__ void k_fields_elem<double>(const double*, const int4*, double*, int);
+template __global__ void k_fields_elem<float>(const double*, const int4*, float*, int);
 
 // ---------------------------------------------------------------- multigrid
 

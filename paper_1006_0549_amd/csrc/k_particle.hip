@@ -195,7 +195,7 @@ __device__ inline void load_field_row(const R* __restrict__ F, int stride, int s
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_particle_step(StepArgs<R> A)
 {
     __shared__ __align__(16) R s_rec[256 * NREC];   // per-lane records of the new state
     __shared__ int s_key[256];                       // element of each lane (-1: no particle)
@@ -227,7 +227,6 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     R u3[3] = {R(0), R(0), R(0)};
     R psi[MAXS] = {R(0), R(0), R(0), R(0)};
     R lam[3] = {R(0), R(0), R(0)};
-    int4 sn = make_int4(0, 0, 0, 0);
     int bin = 0;
     WalkCount wc = {0, 0, 0, 0};
     int flips = 0, nans = 0;
@@ -239,16 +238,21 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         om = A.P.om[p]; wt = A.P.wt[p];
         for (int a = 0; a < ns; ++a) psi[a] = A.P.psi[C.psioff + (int64_t)a * C.cap + i];
         bary<R>(A.M.rec, e, x, y, lam);
-        sn = A.M.tri_s[e];
         if (A.advance) {
             const int4 nbe = A.M.nbr[e];
+            // Wiener increments first: they need only the particle's id, so
+            // their arithmetic overlaps the loads of the element's tables
+            R xi[6];
+            if constexpr (sizeof(R) == 8) gauss6_f64(C.seed_lo, C.seed_hi, A.P.id[p], step, C.stream, xi);
+            else gauss6_f32(C.seed_lo, C.seed_hi, A.P.id[p], step, C.stream, xi);
             R f[NF];
             {
                 // R-06, row by row: f = fma(l2, F2, fma(l1, F1, l0 F0)), so
-                // only one gathered node row is live at a time
-                const R* F0 = A.F + (int64_t)sn.x * A.fstride;
-                const R* F1 = A.F + (int64_t)sn.y * A.fstride;
-                const R* F2 = A.F + (int64_t)sn.z * A.fstride;
+                // only one vertex row is live at a time; the element's three
+                // vertex rows lie together (element-major copy of the fields)
+                const R* F0 = A.Fel + (int64_t)e * 3 * NFE;
+                const R* F1 = F0 + NFE;
+                const R* F2 = F1 + NFE;
                 R om_n[3];
 #pragma unroll
                 for (int q = 0; q < NF; ++q) f[q] = lam[0] * F0[q];
@@ -282,9 +286,6 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
                     for (int a = 0; a < ns; ++a) psi[a] = (psi[a] - fm * (psi[a] - cm[a])) + dt * s[a];
                 }
             }
-            R xi[6];
-            if constexpr (sizeof(R) == 8) gauss6_f64(C.seed_lo, C.seed_hi, A.P.id[p], step, C.stream, xi);
-            else gauss6_f32(C.seed_lo, C.seed_hi, A.P.id[p], step, C.stream, xi);
             R dt, tnu, sq_nu, C3, c34;
             if constexpr (sizeof(R) == 8) { dt = C.dt; tnu = C.tnu; sq_nu = C.sq_nu; C3 = C.C3; c34 = C.c34; }
             else { dt = C.fdt; tnu = C.ftnu; sq_nu = C.fsq_nu; C3 = C.fC3; c34 = C.fc34; }
@@ -331,13 +332,12 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
             A.P.u[p] = u3[0]; A.P.v[p] = u3[1]; A.P.w[p] = u3[2];
             A.P.om[p] = om; A.P.elem[p] = e;
             for (int a = 0; a < ns; ++a) A.P.psi[C.psioff + (int64_t)a * C.cap + i] = psi[a];
-            sn = A.M.tri_s[e];
         }
         // R-23 bin: octant of U - <U>(X) with <U> from the fields of this step
         if (A.do_bins && C.nbins == 8) {
-            const R* F0 = A.F + (int64_t)sn.x * A.fstride;
-            const R* F1 = A.F + (int64_t)sn.y * A.fstride;
-            const R* F2 = A.F + (int64_t)sn.z * A.fstride;
+            const R* F0 = A.Fel + (int64_t)e * 3 * NFE;
+            const R* F1 = F0 + NFE;
+            const R* F2 = F1 + NFE;
             for (int q = 0; q < 3; ++q) {
                 R m = rfma<R>(lam[2], F2[q], rfma<R>(lam[1], F1[q], lam[0] * F0[q]));
                 if (u3[q] - m >= R(0)) bin += (1 << q);
@@ -346,6 +346,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
         if (A.do_bins) A.P.bin[p] = (uint8_t)bin;
     }
 
+    if (A.scatter) {
     // ---- shape-weighted sums of the new state at the element's vertices
     // (R-11) and cell sums (R-23), FP64, in a fixed order. Every lane stores
     // its record in LDS. Each wavefront takes the elements present among its
@@ -649,6 +650,7 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
     }
     __syncthreads();
     if (threadIdx.x == 0) A.wgcnt[blockIdx.x] = s_slot < wg_slots ? s_slot : wg_slots;
+    }
     // ---- counters, one atomic per wavefront
     {
         int v0 = wave_sum_int(wc.fallback), v1 = wave_sum_int(wc.refl), v2 = wave_sum_int(wc.per);
@@ -667,6 +669,56 @@ __global__ void __launch_bounds__(256) k_particle_step(StepArgs<R> A)
 
 template __global__ void k_particle_step<double>(StepArgs<double>);
 template __global__ void k_particle_step<float>(StepArgs<float>);
+
+// Initial ensemble of a case (R-29..R-32): particle i of the case lies in its
+// element i / ppe, has id i, and draws its state from the generator with
+// purpose 1 (init_uniforms): position uniform in the element, Gaussian
+// velocity, Gamma(4, scale) frequency, scalars set inside their initial
+// disks, mass weight A_e / ppe. FP64 arithmetic in either precision (the
+// FP32 context stores the rounded values); the operation order is the one of
+// the written recipe, so the FP64 ensemble is the same bit for bit wherever
+// the recipe is followed.
+template <typename R>
+__global__ void k_particles_init(InitArgs<R> A)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const CaseDev& C = A.cases[A.cs];
+    const int e = C.eoff + (int)(i / A.ppe);
+    double u[10];
+    init_uniforms(C.seed_lo, C.seed_hi, (uint32_t)i, C.stream, u);
+    const double* v = A.exy + 6 * (int64_t)e;
+    const double s = __builtin_sqrt(u[0]);
+    const double l0 = 1.0 - s, l1 = s * (1.0 - u[1]), l2 = s * u[1];
+    const double x = (l0 * v[0] + l1 * v[2]) + l2 * v[4];
+    const double y = (l0 * v[1] + l1 * v[3]) + l2 * v[5];
+    const double r0 = __builtin_sqrt(-2.0 * ln_series(u[2]));
+    const double r1 = __builtin_sqrt(-2.0 * ln_series(u[4]));
+    double s0, c0, s1, c1;
+    sincos2pi_series(u[3], s0, c0);
+    sincos2pi_series(u[5], s1, c1);
+    const double om = -A.omega_scale * (((ln_series(u[6]) + ln_series(u[7])) + ln_series(u[8])) + ln_series(u[9]));
+    const int64_t p = C.poff + i;
+    A.P.x[p] = (R)x; A.P.y[p] = (R)y;
+    A.P.u[p] = (R)(A.u_std * (r0 * c0));
+    A.P.v[p] = (R)(A.u_std * (r0 * s0));
+    A.P.w[p] = (R)(A.u_std * (r1 * c1));
+    A.P.om[p] = (R)om;
+    A.P.wt[p] = (R)(A.area[e] / (double)A.ppe);
+    A.P.elem[p] = e;
+    A.P.id[p] = (uint32_t)i;
+    A.P.bin[p] = 0;
+    for (int a = 0; a < C.ns; ++a) {
+        double val = 0.0;
+        if (A.disk[a][2] > 0.0) {
+            const double dx = x - A.disk[a][0], dy = y - A.disk[a][1];
+            if (dx * dx + dy * dy < A.disk[a][2] * A.disk[a][2]) val = A.disk[a][3];
+        }
+        A.P.psi[C.psioff + (int64_t)a * C.cap + i] = (R)val;
+    }
+}
+template __global__ void k_particles_init<double>(InitArgs<double>);
+template __global__ void k_particles_init<float>(InitArgs<float>);
 
 // Device draws of the Wiener increments (test hook of R-09/R-10).
 template <typename R>

@@ -50,6 +50,7 @@ struct Case {
     int eoff = 0, noff = 0, bcoff = 0;
     int64_t rec_off = 0;          // scatter records (doubles)
     int rec_stride = 0;
+    uint32_t freeze = 0;          // field slots kept at their uploaded values
     // Galerkin matrix pattern of the case in ELL form (mode 2)
     EllH ell0;
     int64_t ell_off = 0;
@@ -213,6 +214,7 @@ struct pdfmc_ctx {
     char* d_rec = nullptr;          // Real records for the particle kernel
     double* d_rec64 = nullptr;      // FP64 records for the node kernels
     char* d_exy = nullptr;
+    double* d_exy64 = nullptr;      // FP64 vertex coordinates (initial ensemble)
     int4 *d_tri_s = nullptr, *d_nbr = nullptr, *d_partner = nullptr;
     BcDev* d_bc = nullptr;
     double *d_area = nullptr, *d_vol = nullptr, *d_wnx = nullptr, *d_wny = nullptr;
@@ -228,7 +230,8 @@ struct pdfmc_ctx {
     int pool_cap = 0;
     int32_t *d_pool_cnt = nullptr, *d_ecnt = nullptr, *d_eslot = nullptr, *d_eof = nullptr, *d_wgcnt = nullptr;
     double *d_eo = nullptr, *d_etot = nullptr;
-    float* d_F32 = nullptr;
+    char* d_Fel = nullptr;          // element-major fields in the particle precision
+    double* d_Ffrz = nullptr;       // uploaded fields, for the slots a case keeps frozen
     char* d_cmean = nullptr;
     int32_t* d_ccnt = nullptr;
     double *d_kf = nullptr, *d_ef = nullptr, *d_L2 = nullptr, *d_er_r = nullptr, *d_er_dval = nullptr, *d_er_b = nullptr,
@@ -271,7 +274,9 @@ struct pdfmc_ctx {
     int sort_interval = 0, block = 256, use_graph = 0;
     int steps_since_sort = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    uint32_t graph_stages = PDFMC_STAGE_ALL;   // stages of the captured graphs
     bool any_er = false, any_eul = false, any_scalars = false;
+    bool any_freeze = false;        // some case keeps field slots frozen
     // multigrid data: flat int/double regions, hierarchy descriptors,
     // Galerkin jobs of the relaxation hierarchies per level, per-job vectors
     int64_t AMG_I = 0, AMG_D = 0;
@@ -351,6 +356,7 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_rec, 8 * (size_t)c->NE, R);
     k.take(c->d_rec64, 8 * (size_t)c->NE);
     k.take(c->d_exy, 6 * (size_t)c->NE, R);
+    k.take(c->d_exy64, 6 * (size_t)c->NE);
     k.take(c->d_tri_s, c->NE);
     k.take(c->d_nbr, c->NE);
     k.take(c->d_partner, c->NE);
@@ -373,7 +379,8 @@ void carve(pdfmc_ctx* c, Carver& k)
         k.take(P.elem, NP); k.take(P.id, NP); k.take(P.bin, NP);
     }
     k.take(c->d_F, (size_t)c->NN * NF);
-    if (c->prec == PDFMC_FP32) k.take(c->d_F32, (size_t)c->NN * NF32);
+    k.take(c->d_Fel, (size_t)c->NE * 3 * NFE, R);
+    k.take(c->d_Ffrz, (size_t)c->NN * NF);
     k.take(c->d_nsum, (size_t)c->NN * NQ);
     k.take(c->d_stats, (size_t)c->NN * NST);
     k.take(c->d_srec, c->SREC);
@@ -509,7 +516,7 @@ CaseDev make_case_dev(const pdfmc_ctx* c, const Case& cs)
     d.k_floor = p.k_floor; d.eps_floor = p.eps_floor; d.dpdx[0] = p.dpdx[0]; d.dpdx[1] = p.dpdx[1];
     d.cg_rtol = p.cg_rtol; d.cg_maxit = p.cg_maxit; d.neff_min = p.n_eff_min;
     d.reaction = p.reaction;
-    d.rec_off = cs.rec_off; d.rec_stride = cs.rec_stride;
+    d.rec_off = cs.rec_off; d.rec_stride = cs.rec_stride; d.freeze = cs.freeze;
     for (int a = 0; a < MAXS; ++a) { d.kr[a] = p.k_react[a]; d.fkr[a] = (float)p.k_react[a]; }
     (void)c;
     return d;
@@ -543,7 +550,7 @@ NodeArgs node_args(pdfmc_ctx* c)
 }
 
 template <typename R>
-StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins)
+StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins, int scatter)
 {
     StepArgs<R> A{};
     PartBufs& B = c->part[c->cur];
@@ -551,13 +558,12 @@ StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins)
     A.M = MeshDev<R>{(const R*)c->d_rec, c->d_tri_s, c->d_nbr, c->d_partner, (const R*)c->d_exy, c->d_bc};
     A.cases = c->d_cases;
     A.tile_case = c->d_tile_case;
-    if constexpr (sizeof(R) == 8) { A.F = (const R*)c->d_F; A.fstride = NF; }
-    else { A.F = (const R*)c->d_F32; A.fstride = NF32; }
+    A.Fel = (const R*)c->d_Fel;
     A.cmean = (const R*)c->d_cmean;
     A.srec = c->d_srec; A.pool_off = c->pool_off; A.pool_stride = SC_HDR + SC_VMAX; A.pool_cap = c->pool_cap;
     A.pool_cnt = c->d_pool_cnt; A.wgcnt = c->d_wgcnt; A.eof = c->d_eof; A.eo = c->d_eo;
     A.counters = c->d_counters; A.step = c->d_step;
-    A.ntiles = c->ntiles; A.advance = advance; A.do_bins = do_bins;
+    A.ntiles = c->ntiles; A.advance = advance; A.do_bins = do_bins; A.scatter = scatter;
     return A;
 }
 
@@ -579,7 +585,10 @@ pdfmc_status enqueue_fill_i(pdfmc_ctx* c, int32_t* p, int64_t n)
     return PDFMC_OK;
 }
 
-pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins)
+// advance: move the particles; do_bins: velocity bins and cell means;
+// scatter: the records and their sums; node_stats: the node statistics from
+// those sums (a re-binning pass leaves them as they are).
+pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins, int scatter, bool node_stats)
 {
     if (c->ntiles == 0) return PDFMC_OK;
     const int64_t threads = (int64_t)c->ntiles * TILE;
@@ -595,15 +604,16 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins)
     }
     if (c->prec == PDFMC_FP64)
         hipLaunchKernelGGL(k_particle_step<double>, dim3(nblk(threads, b)), dim3(b), 0, c->stream,
-                           step_args<double>(c, advance, do_bins));
+                           step_args<double>(c, advance, do_bins, scatter));
     else
         hipLaunchKernelGGL(k_particle_step<float>, dim3(nblk(threads, b)), dim3(b), 0, c->stream,
-                           step_args<float>(c, advance, do_bins));
+                           step_args<float>(c, advance, do_bins, scatter));
     LAUNCHCHK(c);
     if (timed) {
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     }
+    if (!scatter) return PDFMC_OK;
     // the records -> element lists -> element vertex sums and cell means ->
     // node statistics
     NodeArgs N = node_args(c);
@@ -616,8 +626,7 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins)
     else
         hipLaunchKernelGGL(k_elem_reduce<float>, dim3(nblk(c->NE, 4)), dim3(256), 0, c->stream, N,
                            (float*)c->d_cmean, do_bins);
-    // a pass that only re-bins (no advance) leaves the node statistics as they are
-    if (advance || !do_bins) hipLaunchKernelGGL(k_node_reduce, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, N);
+    if (node_stats) hipLaunchKernelGGL(k_node_reduce, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, N);
     LAUNCHCHK(c);
     return PDFMC_OK;
 }
@@ -900,6 +909,20 @@ pdfmc_status enqueue_galerkin(pdfmc_ctx* c, const GalJob* jobs, int n, int64_t m
     return PDFMC_OK;
 }
 
+// The element-major copy of the fields that the particle kernel reads.
+pdfmc_status enqueue_fields_elem(pdfmc_ctx* c)
+{
+    const dim3 g(nblk((int64_t)c->NE * 3 * NFE, 256)), b(256);
+    if (c->prec == PDFMC_FP64)
+        hipLaunchKernelGGL(k_fields_elem<double>, g, b, 0, c->stream, (const double*)c->d_F, (const int4*)c->d_tri_s,
+                           (double*)c->d_Fel, c->NE);
+    else
+        hipLaunchKernelGGL(k_fields_elem<float>, g, b, 0, c->stream, (const double*)c->d_F, (const int4*)c->d_tri_s,
+                           (float*)c->d_Fel, c->NE);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
+}
+
 pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
 {
     NodeArgs A = node_args(c);
@@ -927,19 +950,28 @@ pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
         hipLaunchKernelGGL(k_proj_grad, g, b, 0, c->stream, A);
         LAUNCHCHK(c);
     }
-    if (c->prec == PDFMC_FP32) {
-        hipLaunchKernelGGL(k_mirror_f32, dim3(nblk((int64_t)c->NN * NF32, 256)), dim3(256), 0, c->stream,
-                           (const double*)c->d_F, c->d_F32, c->NN);
+    if (c->any_freeze) {
+        hipLaunchKernelGGL(k_fields_freeze, dim3(nblk((int64_t)c->NN * NF, 256)), dim3(256), 0, c->stream,
+                           (const CaseDev*)c->d_cases, (const int32_t*)c->d_node_case, (const double*)c->d_Ffrz,
+                           c->d_F, c->NN);
         LAUNCHCHK(c);
     }
+    TRY(enqueue_fields_elem(c));
     return PDFMC_OK;
 }
 
-pdfmc_status enqueue_step_body(pdfmc_ctx* c)
+// One step restricted to the stages in `stages` (PDFMC_STAGE_*): without
+// ADVANCE the particles stay where they are (the statistics of the current
+// state are formed), without STATS the node statistics and cell means keep
+// their values, without FIELDS the Eulerian fields keep theirs.
+pdfmc_status enqueue_step_body(pdfmc_ctx* c, uint32_t stages)
 {
-    TRY(enqueue_accum_clear(c));
-    TRY(enqueue_particles(c, 1, 1));
-    TRY(enqueue_fields(c, true));
+    const bool adv = stages & PDFMC_STAGE_ADVANCE, st = stages & PDFMC_STAGE_STATS;
+    if (adv || st) {
+        TRY(enqueue_accum_clear(c));
+        TRY(enqueue_particles(c, adv ? 1 : 0, 1, st ? 1 : 0, st));
+    }
+    if (stages & PDFMC_STAGE_FIELDS) TRY(enqueue_fields(c, true));
     hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, c->stream, c->d_step);
     LAUNCHCHK(c);
     return PDFMC_OK;
@@ -1195,6 +1227,7 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     TRY(h2d(c, c->d_node_case, node_case));
     TRY(h2d(c, c->d_elem_case, elem_case));
     TRY(h2d(c, c->d_rec64, rec64));
+    TRY(h2d(c, c->d_exy64, exy64));
     TRY(h2d(c, c->d_tri_s, tri_s));
     TRY(h2d(c, c->d_nbr, nbr));
     TRY(h2d(c, c->d_partner, partner));
@@ -1398,8 +1431,8 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
 pdfmc_status pdfmc_particles_upload(pdfmc_ctx* c, int32_t ci, const pdfmc_particles_host* p)
 {
     TRY(check_case(c, ci));
-    TRY(check_bound(c));
     Case& cs = c->cases[ci];
+    // the whole ensemble is checked on the host before any device work
     if (!p || p->n < 0 || p->n > cs.cap) return fail(c, PDFMC_E_INVALID, "particles_upload: n must be 0..capacity");
     if (!p->x || !p->y || !p->u || !p->v || !p->w || !p->omega || !p->weight || !p->elem || !p->id ||
         (cs.p.n_scalars > 0 && !p->psi))
@@ -1414,6 +1447,22 @@ pdfmc_status pdfmc_particles_upload(pdfmc_ctx* c, int32_t ci, const pdfmc_partic
             if (p->bin[i] >= (cs.p.n_bins == 8 ? 8 : 1))
                 return fail(c, PDFMC_E_INVALID, "particles_upload: particle " + std::to_string(i) + " has bin " +
                                                     std::to_string(p->bin[i]));
+    for (int64_t i = 0; i < n; ++i) {
+        const double vals[7] = {p->x[i], p->y[i], p->u[i], p->v[i], p->w[i], p->omega[i], p->weight[i]};
+        static const char* names[7] = {"x", "y", "u", "v", "w", "omega", "weight"};
+        for (int k = 0; k < 7; ++k)
+            if (!std::isfinite(vals[k]))
+                return fail(c, PDFMC_E_INVALID, std::string("particles_upload: particle ") + std::to_string(i) +
+                                                    " has a non-finite " + names[k]);
+        if (!(p->weight[i] > 0.0))
+            return fail(c, PDFMC_E_INVALID, "particles_upload: particle " + std::to_string(i) +
+                                                " has a mass weight that is not positive");
+        for (int a = 0; a < cs.p.n_scalars; ++a)
+            if (!std::isfinite(p->psi[(size_t)a * n + i]))
+                return fail(c, PDFMC_E_INVALID, "particles_upload: particle " + std::to_string(i) +
+                                                    " has a non-finite scalar " + std::to_string(a));
+    }
+    TRY(check_bound(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     PartBufs& B = c->part[c->cur];
     const size_t R = rsz(c);
@@ -1445,6 +1494,50 @@ pdfmc_status pdfmc_particles_upload(pdfmc_ctx* c, int32_t ci, const pdfmc_partic
     CaseDev d = make_case_dev(c, cs);
     HIPCHK(c, hipMemcpy(c->d_cases + ci, &d, sizeof d, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemset(c->d_counters + (int64_t)ci * NCNT, 0, NCNT * sizeof(unsigned long long)));
+    return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_particles_init(pdfmc_ctx* c, int32_t ci, int32_t ppe, const pdfmc_init_params* ip)
+{
+    TRY(check_case(c, ci));
+    Case& cs = c->cases[ci];
+    if (!ip) return fail(c, PDFMC_E_INVALID, "particles_init: null parameters");
+    if (ppe < 1) return fail(c, PDFMC_E_INVALID, "particles_init: ppe must be >= 1");
+    const int64_t n = (int64_t)cs.m.ne * ppe;
+    if (n > cs.cap)
+        return fail(c, PDFMC_E_INVALID, "particles_init: " + std::to_string(n) + " particles exceed the capacity " +
+                                            std::to_string(cs.cap));
+    if (!(std::isfinite(ip->u_std) && ip->u_std >= 0.0))
+        return fail(c, PDFMC_E_INVALID, "particles_init: u_std must be finite and >= 0");
+    if (!(std::isfinite(ip->omega_scale) && ip->omega_scale > 0.0))
+        return fail(c, PDFMC_E_INVALID, "particles_init: omega_scale must be finite and > 0");
+    for (int a = 0; a < PDFMC_MAX_SCALARS; ++a)
+        for (int j = 0; j < 4; ++j)
+            if (!std::isfinite(ip->disk[a][j])) return fail(c, PDFMC_E_INVALID, "particles_init: non-finite disk");
+    TRY(check_bound(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    cs.np = n;
+    CaseDev d = make_case_dev(c, cs);
+    HIPCHK(c, hipMemcpy(c->d_cases + ci, &d, sizeof d, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(c->d_counters + (int64_t)ci * NCNT, 0, NCNT * sizeof(unsigned long long)));
+    if (n > 0) {
+        PartBufs& B = c->part[c->cur];
+        auto launch = [&](auto tag) -> pdfmc_status {
+            using R = decltype(tag);
+            InitArgs<R> A{};
+            A.P = Particles<R>{(R*)B.x, (R*)B.y, (R*)B.u, (R*)B.v, (R*)B.w, (R*)B.om, (R*)B.wt, (R*)B.psi, B.elem, B.id, B.bin};
+            A.cases = c->d_cases; A.exy = c->d_exy64; A.area = c->d_area;
+            A.n = n; A.cs = ci; A.ppe = ppe; A.u_std = ip->u_std; A.omega_scale = ip->omega_scale;
+            for (int a = 0; a < MAXS; ++a)
+                for (int j = 0; j < 4; ++j) A.disk[a][j] = a < cs.p.n_scalars ? ip->disk[a][j] : 0.0;
+            hipLaunchKernelGGL(k_particles_init<R>, dim3(nblk(n, 256)), dim3(256), 0, c->stream, A);
+            LAUNCHCHK(c);
+            return PDFMC_OK;
+        };
+        if (c->prec == PDFMC_FP64) TRY(launch(double{}));
+        else TRY(launch(float{}));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PDFMC_OK;
 }
 
@@ -1486,22 +1579,30 @@ pdfmc_status pdfmc_particles_download(pdfmc_ctx* c, int32_t ci, pdfmc_particles_
     return PDFMC_OK;
 }
 
-pdfmc_status pdfmc_fields_upload(pdfmc_ctx* c, int32_t ci, const double* F)
+pdfmc_status pdfmc_fields_upload(pdfmc_ctx* c, int32_t ci, const double* F, uint32_t freeze_mask)
 {
     TRY(check_case(c, ci));
-    TRY(check_bound(c));
     if (!F) return fail(c, PDFMC_E_INVALID, "fields_upload: null");
-    const Case& cs = c->cases[ci];
+    if (freeze_mask >> NF) return fail(c, PDFMC_E_INVALID, "fields_upload: freeze_mask has bits above slot 21");
+    Case& cs = c->cases[ci];
+    for (int64_t i = 0; i < (int64_t)cs.m.nn * NF; ++i)
+        if (!std::isfinite(F[i])) return fail(c, PDFMC_E_INVALID, "fields_upload: non-finite field value");
+    TRY(check_bound(c));
     std::vector<double> tmp((size_t)cs.m.nsn * NF);
     for (int s = 0; s < cs.m.nsn; ++s) std::copy(F + (size_t)cs.m.rep[s] * NF, F + (size_t)cs.m.rep[s] * NF + NF, &tmp[(size_t)s * NF]);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->d_F + (size_t)cs.noff * NF, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
-    if (c->prec == PDFMC_FP32) {
-        hipLaunchKernelGGL(k_mirror_f32, dim3(nblk((int64_t)c->NN * NF32, 256)), dim3(256), 0, c->stream,
-                           (const double*)c->d_F, c->d_F32, c->NN);
-        LAUNCHCHK(c);
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->d_Ffrz + (size_t)cs.noff * NF, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
+    if (cs.freeze != freeze_mask) {
+        cs.freeze = freeze_mask;
+        CaseDev d = make_case_dev(c, cs);
+        HIPCHK(c, hipMemcpy(c->d_cases + ci, &d, sizeof d, hipMemcpyHostToDevice));
+        c->any_freeze = false;
+        for (auto& k : c->cases) c->any_freeze |= k.freeze != 0;
+        drop_graphs(c);
     }
+    TRY(enqueue_fields_elem(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PDFMC_OK;
 }
 
@@ -1538,14 +1639,14 @@ pdfmc_status pdfmc_init(pdfmc_ctx* c)
     TRY(check_bound(c));
     // statistics of the uploaded state
     TRY(enqueue_accum_clear(c));
-    TRY(enqueue_particles(c, 0, 0));
+    TRY(enqueue_particles(c, 0, 0, 1, true));
     c->have_stats = true;
     // Eulerian fields (no projection at initialisation: <P> starts at 0)
     TRY(enqueue_fields(c, false));
     // bins and cell means against those fields (the statistics pass is
     // repeated with the same sums, so the node statistics do not change)
     TRY(enqueue_accum_clear(c));
-    TRY(enqueue_particles(c, 0, 1));
+    TRY(enqueue_particles(c, 0, 1, 1, false));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->initialised = true;
     return PDFMC_OK;
@@ -1555,24 +1656,25 @@ pdfmc_status pdfmc_rebin(pdfmc_ctx* c)
 {
     if (!c) return PDFMC_E_INVALID;
     TRY(check_bound(c));
-    if (c->prec == PDFMC_FP32) {
-        hipLaunchKernelGGL(k_mirror_f32, dim3(nblk((int64_t)c->NN * NF32, 256)), dim3(256), 0, c->stream,
-                           (const double*)c->d_F, c->d_F32, c->NN);
-        LAUNCHCHK(c);
-    }
+    TRY(enqueue_fields_elem(c));
     TRY(enqueue_accum_clear(c));
-    TRY(enqueue_particles(c, 0, 1));
+    TRY(enqueue_particles(c, 0, 1, 1, false));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->initialised = true;
     return PDFMC_OK;
 }
 
-pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps)
+pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps, uint32_t stage_mask)
 {
     if (!c) return PDFMC_E_INVALID;
+    if (n_steps < 0) return fail(c, PDFMC_E_INVALID, "step: n_steps < 0");
+    if (stage_mask & ~(uint32_t)PDFMC_STAGE_ALL) return fail(c, PDFMC_E_INVALID, "step: unknown stage bits");
     TRY(check_bound(c));
     if (!c->initialised) return fail(c, PDFMC_E_STATE, "step: call pdfmc_init (or pdfmc_rebin) first");
-    if (n_steps < 0) return fail(c, PDFMC_E_INVALID, "step: n_steps < 0");
+    if (stage_mask != c->graph_stages) {
+        drop_graphs(c);
+        c->graph_stages = stage_mask;
+    }
     for (int s = 0; s < n_steps; ++s) {
         mg_adapt(c);
         if (c->sort_interval > 0 && c->steps_since_sort >= c->sort_interval) TRY(enqueue_sort(c));
@@ -1581,7 +1683,7 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps)
             if (!g) {
                 hipGraph_t graph = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                pdfmc_status st = enqueue_step_body(c);
+                pdfmc_status st = enqueue_step_body(c, stage_mask);
                 hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
                 if (st != PDFMC_OK) { if (graph) (void)hipGraphDestroy(graph); return st; }
                 if (e2 != hipSuccess) return fail(c, PDFMC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e2));
@@ -1591,7 +1693,7 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps)
             }
             HIPCHK(c, hipGraphLaunch(g, c->stream));
         } else {
-            TRY(enqueue_step_body(c));
+            TRY(enqueue_step_body(c, stage_mask));
         }
         TRY(mg_after_step(c));
         c->steps_since_sort++;
@@ -1787,14 +1889,14 @@ pdfmc_status pdfmc_timing_read(pdfmc_ctx* c, double* total_ms, int64_t* launches
 // which also captures a new graph when graphs are enabled).
 static pdfmc_status tune_time(pdfmc_ctx* c, int n, double* ms)
 {
-    TRY(pdfmc_step(c, 1));
+    TRY(pdfmc_step(c, 1, PDFMC_STAGE_ALL));
     hipEvent_t a = nullptr, b = nullptr;
     HIPCHK(c, hipEventCreate(&a));
     HIPCHK(c, hipEventCreate(&b));
     pdfmc_status st = PDFMC_OK;
     float f = 0.0f;
     if (hipEventRecord(a, c->stream) != hipSuccess) st = fail(c, PDFMC_E_HIP, "autotune: event record");
-    if (st == PDFMC_OK) st = pdfmc_step(c, n);
+    if (st == PDFMC_OK) st = pdfmc_step(c, n, PDFMC_STAGE_ALL);
     if (st == PDFMC_OK && hipEventRecord(b, c->stream) != hipSuccess) st = fail(c, PDFMC_E_HIP, "autotune: event record");
     if (st == PDFMC_OK && hipEventSynchronize(b) != hipSuccess) st = fail(c, PDFMC_E_HIP, "autotune: event sync");
     if (st == PDFMC_OK && hipEventElapsedTime(&f, a, b) != hipSuccess) st = fail(c, PDFMC_E_HIP, "autotune: elapsed");

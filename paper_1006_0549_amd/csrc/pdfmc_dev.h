@@ -11,7 +11,7 @@
 namespace pdfmc {
 
 constexpr int NF = 22;         // Eulerian field slots per node
-constexpr int NF32 = 24;       // padded FP32 mirror stride
+constexpr int NFE = 24;        // padded row of the element-major field copy (3 rows per element)
 constexpr int MAXS = 4;        // scalars per case
 constexpr int NQ = 20;         // node-sum stride: 12 + 2*MAXS
 constexpr int NST = 20;        // statistics stride: 12 + 2*MAXS
@@ -86,7 +86,7 @@ struct CaseDev {
     float fkr[MAXS];
     int64_t rec_off;           // scatter records of the case at srec + rec_off (doubles)
     int32_t rec_stride;        // doubles per record: SC_HDR + values with cells
-    int32_t pad2;
+    uint32_t freeze;           // field slots kept at their uploaded values (bit q: slot q)
 };
 
 template <typename R>
@@ -114,8 +114,7 @@ struct StepArgs {
     MeshDev<R> M;
     const CaseDev* cases;
     const int32_t* tile_case;     // particle tile -> case
-    const R* F;                   // fields: FP64 [NN][22] or FP32 mirror [NN][24]
-    int32_t fstride;
+    const R* Fel;                 // fields at the element's vertices, [NE][3][NFE] (Real)
     const R* cmean;               // cell means (Real)
     double* srec;                 // scatter records (regular slots per case, then the pool)
     int64_t pool_off;             // pool records at srec + pool_off, pool_stride doubles each
@@ -129,7 +128,20 @@ struct StepArgs {
     int32_t ntiles;
     int32_t advance;              // 1: advance then statistics; 0: statistics only
     int32_t do_bins;              // 1: bins + cell sums
-    int32_t pad;
+    int32_t scatter;              // 1: statistics records of the new state; 0: none
+};
+
+// Arguments of the initial-ensemble kernel (R-29..R-32).
+template <typename R>
+struct InitArgs {
+    Particles<R> P;
+    const CaseDev* cases;
+    const double* exy;         // [6*NE] FP64 vertex coordinates
+    const double* area;        // [NE] element areas
+    int64_t n;                 // particles: ne * ppe
+    int32_t cs, ppe;
+    double u_std, omega_scale;
+    double disk[MAXS][4];
 };
 
 }  // namespace pdfmc

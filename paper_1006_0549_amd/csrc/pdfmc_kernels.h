@@ -7,6 +7,7 @@
 namespace pdfmc {
 
 template <typename R> __global__ void k_particle_step(StepArgs<R> A);
+template <typename R> __global__ void k_particles_init(InitArgs<R> A);
 template <typename R> __global__ void k_draw_gaussians(uint32_t slo, uint32_t shi, uint32_t step, uint32_t stream,
                                                        const uint32_t* ids, int64_t n, R* out);
 __global__ void k_fill_f64(double* a, int64_t n, double v);
@@ -24,7 +25,8 @@ __global__ void k_er_finish(NodeArgs A);
 __global__ void k_proj_rhs(NodeArgs A);
 __global__ void k_proj_update(NodeArgs A);
 __global__ void k_proj_grad(NodeArgs A);
-__global__ void k_mirror_f32(const double* F, float* F32, int nn);
+__global__ void k_fields_freeze(const CaseDev* cases, const int32_t* node_case, const double* Ffrz, double* F, int nn);
+template <typename R> __global__ void k_fields_elem(const double* F, const int4* tri_s, R* Fel, int ne);
 __global__ void k_mg_dinv(const AmgDev* hs, const int4* tab);
 __global__ void k_mg_coarse(const AmgDev* hs);
 __global__ void k_mg_setup1(const MgJob* jobs, const int4* tab, const int32_t* st);

@@ -27,8 +27,10 @@ __device__ inline void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, u
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        uint32_t h0 = __umulhi(m0, c0), l0 = m0 * c0;
-        uint32_t h1 = __umulhi(m1, c2), l1 = m1 * c2;
+        // each 32 x 32 -> 64-bit product in one multiply (high and low word together)
+        const uint64_t p0 = (uint64_t)m0 * c0, p1 = (uint64_t)m1 * c2;
+        const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+        const uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
         uint32_t n0 = h1 ^ c1 ^ k0;
         uint32_t n2 = h0 ^ c3 ^ k1;
         c0 = n0; c1 = l1; c2 = n2; c3 = l0;
@@ -149,6 +151,26 @@ __device__ inline void gauss6_f32(uint32_t k0, uint32_t k1, uint32_t id, uint32_
         float c = __builtin_amdgcn_cosf(u1);
         xi[2 * j] = r * c;
         xi[2 * j + 1] = r * s;
+    }
+}
+
+// Initial-state draws (R-29, R-30): the same generator with purpose 1 in the
+// counter, counter = (id, 0, stream, (1 << 8) | block), blocks 0..4 ->
+// 20 words; uniform m = 0..9 from words 2m (high) and 2m+1 (low),
+// u_m = (2 ((w_2m << 20) | (w_2m+1 >> 12)) + 1) 2^-53.
+__device__ inline void init_uniforms(uint32_t k0, uint32_t k1, uint32_t id, uint32_t stream, double u[10])
+{
+    uint32_t w[20];
+#pragma unroll
+    for (uint32_t b = 0; b < 5; ++b) {
+        uint32_t c0 = id, c1 = 0u, c2 = stream, c3 = (1u << 8) | b;
+        philox4x32_10(c0, c1, c2, c3, k0, k1);
+        w[4 * b] = c0; w[4 * b + 1] = c1; w[4 * b + 2] = c2; w[4 * b + 3] = c3;
+    }
+#pragma unroll
+    for (int m = 0; m < 10; ++m) {
+        const uint64_t K = ((uint64_t)w[2 * m] << 20) | (uint64_t)(w[2 * m + 1] >> 12);
+        u[m] = (double)(2 * K + 1) * 0x1p-53;
     }
 }
 

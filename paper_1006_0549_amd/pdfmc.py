@@ -57,6 +57,10 @@ class _TuneResult(C.Structure):
                 ("trials", C.c_int32), ("steps", C.c_int32), ("ms_per_step", C.c_double)]
 
 
+class _InitParams(C.Structure):
+    _fields_ = [("u_std", C.c_double), ("omega_scale", C.c_double), ("disk", (C.c_double * 4) * 4)]
+
+
 class _Particles(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, C.c_void_p) for k in
                                      ("x", "y", "u", "v", "w", "omega", "weight", "psi", "elem", "id", "bin")]
@@ -64,7 +68,7 @@ class _Particles(C.Structure):
 
 _lib = None
 EXPORTS = ["pdfmc_create", "pdfmc_destroy", "pdfmc_last_error", "pdfmc_add_case", "pdfmc_case_info",
-           "pdfmc_workspace_query", "pdfmc_workspace_bind", "pdfmc_particles_upload",
+           "pdfmc_workspace_query", "pdfmc_workspace_bind", "pdfmc_particles_upload", "pdfmc_particles_init",
            "pdfmc_particles_download", "pdfmc_fields_upload", "pdfmc_fields_download",
            "pdfmc_pressure_download", "pdfmc_init", "pdfmc_rebin", "pdfmc_step", "pdfmc_set_step_index",
            "pdfmc_stats_readback", "pdfmc_node_sums", "pdfmc_cell_means", "pdfmc_counters",
@@ -93,14 +97,16 @@ def lib():
         L.pdfmc_workspace_query.argtypes = [vp, C.POINTER(C.c_uint64)]
         L.pdfmc_workspace_bind.argtypes = [vp, vp, C.c_uint64]
         L.pdfmc_particles_upload.argtypes = [vp, C.c_int32, C.POINTER(_Particles)]
+        L.pdfmc_particles_init.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(_InitParams)]
         L.pdfmc_particles_download.argtypes = [vp, C.c_int32, C.POINTER(_Particles)]
-        for f in ("pdfmc_fields_upload", "pdfmc_fields_download", "pdfmc_pressure_download",
+        L.pdfmc_fields_upload.argtypes = [vp, C.c_int32, vp, C.c_uint32]
+        for f in ("pdfmc_fields_download", "pdfmc_pressure_download",
                   "pdfmc_stats_readback", "pdfmc_node_sums", "pdfmc_counters"):
             getattr(L, f).argtypes = [vp, C.c_int32, vp]
         L.pdfmc_cell_means.argtypes = [vp, C.c_int32, vp, vp]
         for f in ("pdfmc_init", "pdfmc_rebin", "pdfmc_sort", "pdfmc_synchronize"):
             getattr(L, f).argtypes = [vp]
-        L.pdfmc_step.argtypes = [vp, C.c_int32]
+        L.pdfmc_step.argtypes = [vp, C.c_int32, C.c_uint32]
         L.pdfmc_set_step_index.argtypes = [vp, C.c_uint32]
         L.pdfmc_set_options.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
         L.pdfmc_timing.argtypes = [vp, C.c_int32]
@@ -262,6 +268,18 @@ class Sim:
                                                      "elem", "id", "bin")])
         self._check(self._L.pdfmc_particles_upload(self._h, cs, C.byref(st)), "particles_upload")
 
+    def init_particles(self, cs, ppe, u_std=0.1, omega_scale=0.25, disks=()):
+        """Draw the initial ensemble on the device (ppe particles per element;
+        disks[a] = (cx, cy, r, value) for scalar a); returns the particle count."""
+        ip = _InitParams()
+        ip.u_std, ip.omega_scale = float(u_std), float(omega_scale)
+        for a, dk in enumerate(disks):
+            if dk is not None:
+                for j in range(4):
+                    ip.disk[a][j] = float(dk[j])
+        self._check(self._L.pdfmc_particles_init(self._h, cs, int(ppe), C.byref(ip)), "particles_init")
+        return self._cases[cs][0].n_elems * int(ppe)
+
     def download(self, cs, n):
         ns = self._cases[cs][1]["n_scalars"]
         out = {k: np.zeros(n) for k in ("x", "y", "u", "v", "w", "omega", "weight")}
@@ -274,9 +292,11 @@ class Sim:
         self._check(self._L.pdfmc_particles_download(self._h, cs, C.byref(st)), "particles_download")
         return out
 
-    def fields_upload(self, cs, F):
+    def fields_upload(self, cs, F, freeze_mask=0):
+        """Fields per raw node; bit q of freeze_mask keeps slot q at these
+        values in every later step."""
         F = np.ascontiguousarray(F, np.float64)
-        self._check(self._L.pdfmc_fields_upload(self._h, cs, F.ctypes.data), "fields_upload")
+        self._check(self._L.pdfmc_fields_upload(self._h, cs, F.ctypes.data, int(freeze_mask)), "fields_upload")
 
     def fields(self, cs):
         F = np.zeros((self._cases[cs][0].n_nodes, NF))
@@ -295,8 +315,10 @@ class Sim:
     def rebin(self):
         self._check(self._L.pdfmc_rebin(self._h), "rebin")
 
-    def step(self, n=1):
-        self._check(self._L.pdfmc_step(self._h, int(n)), "step")
+    STAGE_ADVANCE, STAGE_STATS, STAGE_FIELDS, STAGE_ALL = 1, 2, 4, 7
+
+    def step(self, n=1, stages=7):
+        self._check(self._L.pdfmc_step(self._h, int(n), int(stages)), "step")
 
     def set_step_index(self, n):
         self._check(self._L.pdfmc_set_step_index(self._h, int(n)), "set_step_index")

@@ -134,3 +134,71 @@ def test_projection_factor_host(pkg):
         s.set_projection_solver("lu")
     with pytest.raises(pkg.PdfmcError, match="INVALID.*method"):
         s._check(s._L.pdfmc_set_projection_solver(s._h, 7), "set_projection_solver")
+
+
+def test_upload_rejections_before_device_work(pkg):
+    """The particle upload checks the whole ensemble on the host: an element
+    outside the case, a bin beyond the case's bins, a non-finite value or a
+    mass weight that is not positive is PDFMC_E_INVALID; a valid ensemble
+    passes the checks and then meets the missing workspace (PDFMC_E_STATE)."""
+    mesh = W.unit_square(6, 0.2, periodic_x=True)
+    s = _sim(pkg)
+    cs = s.add_case(mesh, W.default_params(n_scalars=1), 1000)
+    good = W.init_particles(mesh, 3, 1, W.rng_for(0, 0, 1))
+    n = len(good["x"])
+
+    def bad(**kw):
+        p = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in good.items()}
+        for k, (i, v) in kw.items():
+            if k == "psi":
+                p[k][0, i] = v
+            else:
+                p[k][i] = v
+        return p
+
+    cases = [(dict(elem=(5, mesh.n_elems)), "element"), (dict(elem=(0, -1)), "element"),
+             (dict(x=(7, np.nan)), "non-finite x"), (dict(omega=(n - 1, np.inf)), "non-finite omega"),
+             (dict(weight=(3, 0.0)), "mass weight"), (dict(weight=(4, -1e-3)), "mass weight"),
+             (dict(psi=(2, np.nan)), "non-finite scalar")]
+    for kw, msg in cases:
+        with pytest.raises(pkg.PdfmcError, match="INVALID.*" + msg):
+            s.upload(cs, bad(**kw))
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*bin"):
+        s.upload(cs, dict(good, bin=np.full(n, 8, np.uint8)))      # bins are 0..7
+    with pytest.raises(pkg.PdfmcError, match="STATE"):
+        s.upload(cs, good)
+
+
+def test_init_fields_and_stage_rejections(pkg):
+    """Argument checks of the device initial draw, the fields upload (freeze
+    bits, finiteness) and the step's stage mask."""
+    mesh = W.unit_square(6, 0.2, periodic_x=True)
+    s = _sim(pkg)
+    cs = s.add_case(mesh, W.default_params(n_scalars=1), 10 * mesh.n_elems)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*ppe"):
+        s.init_particles(cs, 0)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*capacity"):
+        s.init_particles(cs, 11)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*u_std"):
+        s.init_particles(cs, 2, u_std=-1.0)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*omega_scale"):
+        s.init_particles(cs, 2, omega_scale=0.0)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*disk"):
+        s.init_particles(cs, 2, disks=[(0.5, 0.5, np.nan, 1.0)])
+    with pytest.raises(pkg.PdfmcError, match="STATE"):
+        s.init_particles(cs, 10)
+    F = np.zeros((mesh.n_nodes, pkg.NF))
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*freeze_mask"):
+        s.fields_upload(cs, F, freeze_mask=1 << pkg.NF)
+    F[3, 7] = np.nan
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*non-finite"):
+        s.fields_upload(cs, F)
+    F[3, 7] = 0.0
+    with pytest.raises(pkg.PdfmcError, match="STATE"):
+        s.fields_upload(cs, F, freeze_mask=(1 << pkg.NF) - 1)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*stage"):
+        s.step(1, stages=8)
+    with pytest.raises(pkg.PdfmcError, match="INVALID.*n_steps"):
+        s.step(-1)
+    with pytest.raises(pkg.PdfmcError, match="STATE"):
+        s.step(1, stages=s.STAGE_ADVANCE)

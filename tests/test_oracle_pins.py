@@ -408,3 +408,81 @@ def test_oracle_reproduces_its_regression_record(oracle_mod):
     spec.loader.exec_module(mg)
     want = np.loadtxt(mg.OUT)
     np.testing.assert_array_equal(mg.run(), want)
+
+
+# ------------------------------------------------------------ R-29 / R-30 initial state
+
+def test_initial_ensemble_distributions(oracle_mod):
+    """The initial ensemble (R-29/R-30): every particle inside its element,
+    its first barycentric coordinate distributed as Beta(1, 2) (the law of a
+    barycentric coordinate of a point uniform in a triangle), velocity
+    components N(0, u_std^2), frequency Gamma(4, scale), scalar = value
+    exactly inside the disk and 0 outside, weights A_e / ppe summing to the
+    domain area, ids 0..n-1 in element order."""
+    from scipy import stats
+    mesh = W.unit_square(6, 0.2, periodic_x=True, seed_key=(98, 0, 0))
+    params = W.default_params(n_scalars=2, seed=12345, stream=3)
+    o = oracle_mod.Oracle()
+    cs = o.add_case(mesh, params)
+    ppe, u_std, scale = 1500, 0.37, 0.21
+    disk = (0.45, 0.55, 0.22, 2.5)
+    n = o.particles_init(cs, ppe, u_std, scale, [disk, None])
+    r = o.download(cs, n)
+    assert np.array_equal(r["id"], np.arange(n, dtype=np.uint32))
+    assert np.array_equal(r["elem"], np.repeat(np.arange(mesh.n_elems), ppe))
+    lam = np.array([o.bary(cs, int(e), x, y) for e, x, y in zip(r["elem"][::37], r["x"][::37], r["y"][::37])])
+    assert lam.min() >= -1e-15
+    assert stats.kstest(lam[:, 0], lambda t: 1 - (1 - t) ** 2).pvalue > 1e-3
+    assert stats.kstest(lam[:, 2], lambda t: 1 - (1 - t) ** 2).pvalue > 1e-3
+    for k in ("u", "v", "w"):
+        assert stats.kstest(r[k] / u_std, "norm").pvalue > 1e-3, k
+    assert stats.kstest(r["omega"], stats.gamma(4, scale=scale).cdf).pvalue > 1e-3
+    assert abs(np.corrcoef(r["u"], r["omega"])[0, 1]) < 4 / np.sqrt(n)
+    d1, d2 = mesh.xy[mesh.tri[:, 1]] - mesh.xy[mesh.tri[:, 0]], mesh.xy[mesh.tri[:, 2]] - mesh.xy[mesh.tri[:, 0]]
+    area = 0.5 * np.abs(d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0])
+    np.testing.assert_allclose(r["weight"], (area / ppe)[r["elem"]], rtol=1e-14)
+    assert r["weight"].sum() == pytest.approx(1.0, rel=1e-13)
+    inside = (r["x"] - disk[0]) ** 2 + (r["y"] - disk[1]) ** 2 < disk[2] ** 2
+    assert np.all(r["psi"][0][inside] == disk[3]) and np.all(r["psi"][0][~inside] == 0.0)
+    assert np.all(r["psi"][1] == 0.0)
+    # ppe particles per element: the mass-weighted (not the counted) share of
+    # the particles inside the disk is its area
+    assert r["weight"][inside].sum() == pytest.approx(np.pi * disk[2] ** 2, abs=4 * np.sqrt(0.15 / n))
+    # another stream gives other draws, the same stream the same ones
+    o2 = oracle_mod.Oracle()
+    c2 = o2.add_case(mesh, dict(params, stream=4))
+    o2.particles_init(c2, ppe, u_std, scale, [disk, None])
+    assert not np.array_equal(o2.download(c2, n)["u"], r["u"])
+    o3 = oracle_mod.Oracle()
+    c3 = o3.add_case(mesh, params)
+    o3.particles_init(c3, ppe, u_std, scale, [disk, None])
+    assert np.array_equal(o3.download(c3, n)["omega"], r["omega"])
+
+
+def test_freezing_every_slot_is_the_frozen_field_mode(oracle_mod):
+    """Mode 1 derives the fields from the statistics; with every slot frozen
+    at the uploaded values it must step exactly like mode 0, which keeps the
+    uploaded fields throughout. With only <omega> frozen, that slot keeps its
+    value while the mean velocity slots follow the statistics."""
+    mesh = W.unit_square(8, 0.2, periodic_x=True, seed_key=(6, 0, 0))
+    parts = W.init_particles(mesh, 20, 1, W.rng_for(6, 0, 1), u_std=0.1, psi_disks=[(0.5, 0.5, 0.2, 1.0)])
+    n = len(parts["x"])
+    F = W.frozen_fields(mesh, C0=2.1, omega=1.5, k=0.01)
+    runs = []
+    for mode, mask in ((0, 0), (1, (1 << 22) - 1), (1, 1 << 19)):
+        o = oracle_mod.Oracle()
+        cs = o.add_case(mesh, W.default_params(mode=mode, n_scalars=1, dt=1e-3, nu=1e-3))
+        o.fields_upload(cs, F, freeze_mask=mask)
+        o.upload(cs, parts)
+        o.init()
+        o.step(15)
+        runs.append((o.download(cs, n), o.stats(cs), o.fields(cs)))
+    for k in ("x", "y", "u", "v", "w", "omega", "psi", "elem"):
+        assert np.array_equal(runs[0][0][k], runs[1][0][k]), k
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[1][2], F)
+    f = runs[2][2]
+    assert np.array_equal(f[:, 19], F[:, 19])
+    assert not np.array_equal(f[:, 0], F[:, 0])
+    with pytest.raises(RuntimeError, match="fields_upload"):
+        o.fields_upload(cs, F, freeze_mask=1 << 22)
