@@ -310,8 +310,29 @@ typedef struct {
     double ms_per_step;
 } pdfmc_tune_result;
 pdfmc_status pdfmc_autotune(pdfmc_ctx* ctx, int32_t steps_per_trial, pdfmc_tune_result* out);
-/* Sort the particles of every case by element now (stable counting sort). */
+/* Sort the particles of every case by element, and inside an element by id,
+ * now. The order is a layout choice only: the particles keep their ids, which
+ * fix their random draws (R-32), so a sorted run takes the same path as an
+ * unsorted one. The temporaries live in the workspace. Synchronises the
+ * stream. PDFMC_E_STATE before a workspace is bound. */
 pdfmc_status pdfmc_sort(pdfmc_ctx* ctx);
+/* pdfmc_sort without allocating and without synchronising: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, hosts that forbid hipMalloc). The same kernels with the same result
+ * as pdfmc_sort, asynchronous on the context's stream; the temporaries live
+ * in a static device array of PDFMC_SORT_NOALLOC_BYTES, one per device, held
+ * until the process ends. Its address is looked up when a workspace is bound,
+ * for the device current at pdfmc_workspace_bind. The sort needs
+ * 32 NE + 20 NP + 8 (NE / 1024 + 1) bytes plus at most 2.5 KiB of alignment
+ * (NE elements, NP particle slots: every case's capacity rounded up to 256);
+ * beyond PDFMC_SORT_NOALLOC_BYTES: PDFMC_E_INVALID (use pdfmc_sort).
+ * Every call on one device shares the array and finds the last call's
+ * contents (the counts are cleared by the call itself): calls that overlap
+ * on one device (two streams, contexts or threads) race and give wrong
+ * orders, so serialise them. PDFMC_E_STATE before a workspace is bound;
+ * PDFMC_E_HIP if the array's address could not be looked up. */
+#define PDFMC_SORT_NOALLOC_BYTES (32u << 20)
+pdfmc_status pdfmc_sort_noalloc(pdfmc_ctx* ctx);
 pdfmc_status pdfmc_synchronize(pdfmc_ctx* ctx);
 
 /* Live timing of the particle kernel: while enabled, every time-step launch

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,7 +26,42 @@
 
 using namespace pdfmc;
 
+// The sort's temporaries for pdfmc_sort_noalloc, which allocates nothing.
+// Each device holds its own copy for the life of the process. In host code
+// this name is only a stand-in for the symbol: kernels and fills get the
+// device address looked up by static_scratch_address.
+static __device__ __align__(256) unsigned char scratch[PDFMC_SORT_NOALLOC_BYTES];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;      // by device ordinal; nullptr until looked up
+
+// The device address of `scratch` on device `dev`, looked up once per
+// device with that device current (the caller's current device is restored).
+hipError_t static_scratch_address(int dev, void** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0) return hipErrorInvalidDevice;
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        int prev = -1;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (prev != dev) {
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 // ELL forms of one hierarchy: A on levels >= 1, P and R on every level but
 // the coarsest, and the Galerkin lists with ELL source/destination positions.
@@ -208,6 +244,9 @@ struct pdfmc_ctx {
     bool have_stats = false;        // node statistics have been formed once
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
+    int device = -1;                // device current at workspace bind
+    void* d_static_scratch = nullptr;   // that device's address of the static sort scratch
+    std::string static_scratch_err;     // why the address lookup failed, if it did
     // device arrays
     CaseDev* d_cases = nullptr;
     int32_t *d_tile_case = nullptr, *d_node_case = nullptr, *d_elem_case = nullptr;
@@ -977,20 +1016,54 @@ pdfmc_status enqueue_step_body(pdfmc_ctx* c, uint32_t stages)
     return PDFMC_OK;
 }
 
-pdfmc_status enqueue_sort(pdfmc_ctx* c)
+// The temporaries of one sort: per-element counts, scans, cursors, segment
+// starts and the list of long segments, and per-particle placed ids, their
+// sources and the final permutation.
+struct SortScratch {
+    int32_t* count; int64_t *scan, *bsum, *cursor, *start; int32_t *big, *nbig;
+    int64_t *perm, *tmp_src; uint32_t* tmp_id;
+};
+
+// The temporaries carved from one contiguous region (256-byte aligned
+// pieces); with base == nullptr only the size is computed.
+uint64_t sort_scratch_carve(char* base, int64_t ne, int64_t np, SortScratch* sc)
+{
+    Carver k{base, 0, base != nullptr};
+    SortScratch t{};
+    k.take(t.count, ne); k.take(t.scan, ne); k.take(t.bsum, ne / SCAN_B + 1); k.take(t.cursor, ne);
+    k.take(t.start, ne); k.take(t.big, ne); k.take(t.nbig, 1);
+    k.take(t.perm, np); k.take(t.tmp_src, np); k.take(t.tmp_id, np);
+    if (sc) *sc = t;
+    return k.off;
+}
+
+// The sort's temporaries in the bound workspace: per-element arrays of their
+// own, per-particle ones in the scatter-record region, which holds nothing
+// between steps.
+SortScratch sort_scratch_ws(pdfmc_ctx* c)
+{
+    SortScratch t{};
+    t.count = c->d_sort_count; t.scan = c->d_sort_scan; t.bsum = c->d_sort_bsum; t.cursor = c->d_sort_cursor;
+    t.start = c->d_sort_start; t.big = c->d_sort_big; t.nbig = c->d_sort_nbig;
+    t.perm = (int64_t*)c->d_srec;
+    t.tmp_src = t.perm + c->NP;
+    t.tmp_id = (uint32_t*)(t.tmp_src + c->NP);
+    return t;
+}
+
+pdfmc_status enqueue_sort(pdfmc_ctx* c, const SortScratch& T)
 {
     if (c->ntiles == 0) return PDFMC_OK;
     SortArgs S{};
     S.cases = c->d_cases; S.tile_case = c->d_tile_case; S.elem_case = c->d_elem_case;
     S.ntiles = c->ntiles; S.ne = c->NE; S.elem = c->part[c->cur].elem;
-    S.count = c->d_sort_count; S.scan = c->d_sort_scan; S.bsum = c->d_sort_bsum; S.cursor = c->d_sort_cursor;
-    S.start = c->d_sort_start; S.big = c->d_sort_big; S.nbig = c->d_sort_nbig;
-    // temporaries in the scatter-record region, which holds nothing between steps
-    S.perm = (int64_t*)c->d_srec;
-    S.tmp_src = S.perm + c->NP;
-    S.tmp_id = (uint32_t*)(S.tmp_src + c->NP);
-    TRY(enqueue_fill_i(c, c->d_sort_count, c->NE));
-    TRY(enqueue_fill_i(c, c->d_sort_nbig, 1));
+    S.count = T.count; S.scan = T.scan; S.bsum = T.bsum; S.cursor = T.cursor;
+    S.start = T.start; S.big = T.big; S.nbig = T.nbig;
+    S.perm = T.perm; S.tmp_src = T.tmp_src; S.tmp_id = T.tmp_id;
+    // counts and the long-segment count start at zero (fill kernels, so the
+    // sequence can be captured)
+    TRY(enqueue_fill_i(c, T.count, c->NE));
+    TRY(enqueue_fill_i(c, T.nbig, 1));
     const int64_t threads = (int64_t)c->ntiles * TILE;
     hipLaunchKernelGGL(k_sort_hist, dim3(nblk(threads, 256)), dim3(256), 0, c->stream, S);
     const int nb = (int)nblk(c->NE, SCAN_B);
@@ -1423,6 +1496,17 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     TRY(enqueue_fill(c, c->d_eo, (int64_t)c->NE * SC_VMAX));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->have_stats = false;
+    // the static scratch of pdfmc_sort_noalloc on this device (set-up only;
+    // a failed lookup fails that entry point, not the bind)
+    c->d_static_scratch = nullptr;
+    c->static_scratch_err.clear();
+    hipError_t se = hipGetDevice(&c->device);
+    if (se == hipSuccess) se = static_scratch_address(c->device, &c->d_static_scratch);
+    if (se != hipSuccess) {
+        c->d_static_scratch = nullptr;
+        c->static_scratch_err = hipGetErrorString(se);
+        (void)hipGetLastError();
+    }
     c->bound = true;
     c->initialised = false;
     return PDFMC_OK;
@@ -1677,7 +1761,7 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps, uint32_t stage_mask)
     }
     for (int s = 0; s < n_steps; ++s) {
         mg_adapt(c);
-        if (c->sort_interval > 0 && c->steps_since_sort >= c->sort_interval) TRY(enqueue_sort(c));
+        if (c->sort_interval > 0 && c->steps_since_sort >= c->sort_interval) TRY(enqueue_sort(c, sort_scratch_ws(c)));
         if (c->use_graph && !c->timing) {
             hipGraphExec_t& g = c->graph[c->cur];
             if (!g) {
@@ -1849,9 +1933,25 @@ pdfmc_status pdfmc_sort(pdfmc_ctx* c)
 {
     if (!c) return PDFMC_E_INVALID;
     TRY(check_bound(c));
-    TRY(enqueue_sort(c));
+    TRY(enqueue_sort(c, sort_scratch_ws(c)));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return PDFMC_OK;
+}
+
+pdfmc_status pdfmc_sort_noalloc(pdfmc_ctx* c)
+{
+    if (!c) return PDFMC_E_INVALID;
+    TRY(check_bound(c));
+    const uint64_t need = sort_scratch_carve(nullptr, c->NE, c->NP, nullptr);
+    if (need > (uint64_t)PDFMC_SORT_NOALLOC_BYTES)
+        return fail(c, PDFMC_E_INVALID, "sort_noalloc: the sort needs " + std::to_string(need) +
+                                            " bytes of scratch, the static scratch holds " +
+                                            std::to_string((uint64_t)PDFMC_SORT_NOALLOC_BYTES) + " (use pdfmc_sort)");
+    if (!c->d_static_scratch)
+        return fail(c, PDFMC_E_HIP, "sort_noalloc: no device address for the static scratch: " + c->static_scratch_err);
+    SortScratch T{};
+    sort_scratch_carve((char*)c->d_static_scratch, c->NE, c->NP, &T);
+    return enqueue_sort(c, T);
 }
 
 pdfmc_status pdfmc_synchronize(pdfmc_ctx* c)

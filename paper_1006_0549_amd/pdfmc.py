@@ -72,7 +72,7 @@ EXPORTS = ["pdfmc_create", "pdfmc_destroy", "pdfmc_last_error", "pdfmc_add_case"
            "pdfmc_particles_download", "pdfmc_fields_upload", "pdfmc_fields_download",
            "pdfmc_pressure_download", "pdfmc_init", "pdfmc_rebin", "pdfmc_step", "pdfmc_set_step_index",
            "pdfmc_stats_readback", "pdfmc_node_sums", "pdfmc_cell_means", "pdfmc_counters",
-           "pdfmc_set_options", "pdfmc_sort", "pdfmc_synchronize", "pdfmc_timing", "pdfmc_timing_read",
+           "pdfmc_set_options", "pdfmc_sort", "pdfmc_sort_noalloc", "pdfmc_synchronize", "pdfmc_timing", "pdfmc_timing_read",
            "pdfmc_draw_gaussians", "pdfmc_set_solver", "pdfmc_solver_info", "pdfmc_autotune",
            "pdfmc_set_projection_solver", "pdfmc_projection_info"]
 
@@ -104,7 +104,7 @@ def lib():
                   "pdfmc_stats_readback", "pdfmc_node_sums", "pdfmc_counters"):
             getattr(L, f).argtypes = [vp, C.c_int32, vp]
         L.pdfmc_cell_means.argtypes = [vp, C.c_int32, vp, vp]
-        for f in ("pdfmc_init", "pdfmc_rebin", "pdfmc_sort", "pdfmc_synchronize"):
+        for f in ("pdfmc_init", "pdfmc_rebin", "pdfmc_sort", "pdfmc_sort_noalloc", "pdfmc_synchronize"):
             getattr(L, f).argtypes = [vp]
         L.pdfmc_step.argtypes = [vp, C.c_int32, C.c_uint32]
         L.pdfmc_set_step_index.argtypes = [vp, C.c_uint32]
@@ -325,6 +325,10 @@ class Sim:
 
     def sort(self):
         self._check(self._L.pdfmc_sort(self._h), "sort")
+
+    def sort_noalloc(self):
+        """The sort with static device scratch (asynchronous, allocates nothing)."""
+        self._check(self._L.pdfmc_sort_noalloc(self._h), "sort_noalloc")
 
     def synchronize(self):
         self._check(self._L.pdfmc_synchronize(self._h), "synchronize")
