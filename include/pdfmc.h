@@ -69,7 +69,8 @@ typedef struct {
 
 typedef struct {
     int32_t n_nodes;  const double* xy;        /* [2*n_nodes] interleaved x,y      */
-    int32_t n_elems;  const int32_t* tri;      /* [3*n_elems] counter-clockwise    */
+    int32_t n_elems;  const int32_t* tri;      /* [3*n_elems] counter-clockwise;
+                                                  n_elems < 2^23 per case        */
     const int32_t* edge_tag;  /* [3*n_elems]; edge k is opposite vertex k;
                                  -1 interior, else an index into bc[]           */
     int32_t n_bc;     const pdfmc_bc* bc;

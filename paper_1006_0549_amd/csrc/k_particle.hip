@@ -13,17 +13,17 @@
 //
 // Layout: structure of arrays, one lane per particle, tiles of 256 particles
 // that never straddle two cases. The scatter is deterministic and uses no
-// floating-point atomics: the workgroup lists the distinct elements of its
-// particles in a fixed order (first appearance in particle order), one
-// wavefront per element sums that element's particles from the whole
-// workgroup in particle order, and the sums go out as one record per
-// (workgroup, element) with plain stores. The records of an element are
-// summed in key order by the element pass, and the vertex sums of the
-// elements around a node by the node pass (k_scatter.hip). Arithmetic of the
-// FP64 instantiation follows the operation order of the readings exactly (no
-// contraction; explicit fma only where the readings put one), so that it
-// reproduces the CPU oracle bit for bit; only the summation order of the node
-// and cell sums differs.
+// floating-point atomics: each wavefront sorts its particles by (element,
+// bin, lane), lane groups walk the sorted positions and sum each element's
+// run in sorted order, and each element's sums go out as one record per
+// (workgroup, element) with plain stores (the runs of an element that
+// several wavefronts hold are first added in LDS, in wavefront order). The
+// records of an element are summed in key order by the element pass, and the
+// vertex sums of the elements around a node by the node pass (k_scatter.hip).
+// Arithmetic of the FP64 instantiation follows the operation order of the
+// readings exactly (no contraction; explicit fma only where the readings put
+// one), so that it reproduces the CPU oracle bit for bit; only the summation
+// order of the node and cell sums differs.
 #include "pdfmc_dev.h"
 #include "pdfmc_math.h"
 
@@ -165,24 +165,11 @@ __device__ inline int wave_sum_int(int v)
 
 // ---------------------------------------------------------------- scatter helpers
 
-constexpr int NREC = 8 + MAXS;                  // per-lane record: lambda_0..2, w, U_1..3, omega, psi_a
-
-// A set of the workgroup's particles: one 64-bit lane mask per wavefront
-// (at most four), kept in separate scalars so that they stay in registers.
-struct WgSet {
-    unsigned long long m0, m1, m2, m3;
-    __device__ bool any() const { return (m0 | m1 | m2 | m3) != 0ull; }
-    __device__ int count() const { return __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3); }
-    // the lowest particle of the set, removed from it; -1 when empty
-    __device__ int pop()
-    {
-        if (m0) { const int l = __ffsll((long long)m0) - 1; m0 &= m0 - 1; return l; }
-        if (m1) { const int l = __ffsll((long long)m1) - 1; m1 &= m1 - 1; return 64 + l; }
-        if (m2) { const int l = __ffsll((long long)m2) - 1; m2 &= m2 - 1; return 128 + l; }
-        if (m3) { const int l = __ffsll((long long)m3) - 1; m3 &= m3 - 1; return 192 + l; }
-        return -1;
-    }
-};
+// per-lane record in LDS: lambda_0..2, w | U_1..3, omega | psi_0..3 | 1, 0
+// (the constants stand in for absent factors of a vertex term), 16 slots so
+// that the first four load as one vector
+constexpr int NREC = 16;
+constexpr int RI_ONE = 12, RI_ZERO = 13;
 
 // ---------------------------------------------------------------- the kernel
 
@@ -198,14 +185,12 @@ template <typename R>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_particle_step(StepArgs<R> A)
 {
     __shared__ __align__(16) R s_rec[256 * NREC];   // per-lane records of the new state
-    __shared__ int s_key[256];                       // element of each lane (-1: no particle)
+    __shared__ int s_sorted[256];                    // each wavefront's elements, sorted
     __shared__ double s_stage[4 * SC_SQ * SC_VMAX];  // sums of shared elements, per wavefront
     __shared__ int s_sel[4 * SC_SQ];                 // their elements
     __shared__ int s_smask[4 * SC_SQ];               // their bin masks
     __shared__ int s_nst[4];                         // staged entries per wavefront
-    __shared__ int s_sdst[4 * 64];                   // destination of each set of each wavefront
-    __shared__ unsigned char s_skind[4 * 64];        // its kind: record, staged entry, overflow
-    __shared__ int s_mel[4 * 64], s_mfirst[4 * 64];  // shared elements each wavefront merges
+    __shared__ int s_mel[4 * 64], s_mfirst[4 * 64];  // shared elements each wavefront merges, first positions
     __shared__ int s_nmerge[4];
     __shared__ int s_slot;                           // record slots taken by the workgroup
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,267 +333,325 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
     if (A.scatter) {
     // ---- shape-weighted sums of the new state at the element's vertices
-    // (R-11) and cell sums (R-23), FP64, in a fixed order. Every lane stores
-    // its record in LDS. Each wavefront takes the elements present among its
-    // own lanes one at a time (a ballot per element, in order of first lane)
-    // and sums over that element's lanes, in lane order, the vertex terms
-    // w lambda_k Q. The cell sums (count, w, w psi_a per element and velocity
-    // bin) come from a sort of the wavefront's lanes by (element, bin, lane)
-    // and a segmented scan. An element found in no other wavefront of the
-    // workgroup goes out as a record at once; the sums of an element shared
-    // by several wavefronts are staged in LDS and, after a barrier, added in
-    // wavefront order by the wavefront holding the element's first lane.
-    // Record keys derive from the workgroup and the element's first lane, so
-    // the element pass sums an element's records in an order fixed by the
-    // particle order alone.
+    // (R-11) and cell sums (R-23), FP64, in an order fixed by the particle
+    // order alone, with no floating-point atomics.
+    //  1. Each wavefront sorts its lanes by (element, bin, lane); the
+    //     particles of one element then form a run of sorted positions.
+    //  2. Lane groups walk the sorted positions, a contiguous range per
+    //     group, adding the vertex terms w lambda_k Q of one particle per
+    //     step (lane q of a group holds term q); a run that crosses a range
+    //     boundary is completed by a carry from group to group.
+    //  3. Cell sums (count, w, w psi_a per element and bin) come from a
+    //     segmented scan over the same sorted order.
+    //  4. A run whose element no other wavefront of the workgroup holds goes
+    //     out as a record; the runs of an element that several wavefronts
+    //     hold are staged in LDS and, after a barrier, added in wavefront
+    //     order by the lowest of those wavefronts.
+    // Record keys derive from the workgroup, the wavefront and the run's
+    // first sorted position, so the element pass sums an element's records
+    // in an order that depends on the particle order only.
     const int nq = 12 + 2 * ns;
     const bool cells = A.do_bins && ns > 0;
     const int nv = sc_nvals(ns, cells);
     const int nc = 2 + ns;                       // cell values per bin
     const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int key = valid ? e : -1;
+    // (1) sort key: case-local element << 9 | bin << 6 | lane (a case has
+    // fewer than 2^23 elements); lanes without a particle last
+    unsigned sk = valid ? ((unsigned)(e - C.eoff) << 9) | ((unsigned)(cells ? bin : 0) << 6) | (unsigned)lane : ~0u;
+#pragma unroll
+    for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            const unsigned o = (unsigned)__shfl_xor((int)sk, jj);
+            const bool keep_min = ((lane & jj) == 0) == ((lane & kk) == 0);
+            sk = keep_min ? min(o, sk) : max(o, sk);
+        }
+    }
+    // sorted position = lane: its particle's lane, element and bin
+    const bool pv = sk != ~0u;
+    const int src = (int)(sk & 63);
+    const int E = pv ? C.eoff + (int)(sk >> 9) : -1;
+    const int sbin = (int)((sk >> 6) & 7);
     {
         R* my = s_rec + threadIdx.x * NREC;
         my[0] = lam[0]; my[1] = lam[1]; my[2] = lam[2]; my[3] = wt;
         my[4] = u3[0]; my[5] = u3[1]; my[6] = u3[2]; my[7] = om;
-        for (int a = 0; a < ns; ++a) my[8 + a] = psi[a];
-        s_key[threadIdx.x] = key;
+#pragma unroll
+        for (int a = 0; a < MAXS; ++a) my[8 + a] = psi[a];
+        my[RI_ONE] = R(1);
+        my[RI_ZERO] = R(0);
+        s_sorted[threadIdx.x] = pv ? E : 0x7fffffff;
         if (threadIdx.x == 0) s_slot = 0;
         if (threadIdx.x < 4) s_nmerge[threadIdx.x] = 0;
     }
     __syncthreads();
-    // the keys of all the workgroup's lanes: wavefront t's at (register t, lane)
-    const int kk0 = s_key[lane], kk1 = nw > 1 ? s_key[64 + lane] : -1;
-    const int kk2 = nw > 2 ? s_key[128 + lane] : -1, kk3 = nw > 3 ? s_key[192 + lane] : -1;
-    // lane roles of the vertex-term loop: G groups of GS lanes, lane q of a
-    // group holds term q < nq of the G particles taken per step
-    const int G = nq <= 16 ? 4 : 3, GS = nq <= 16 ? 16 : 21;
-    const int g = lane / GS, q = lane - g * GS;
-    // vertex term q: (w lambda_k) * fa_k * fb, fa_k = fma(sqm, w lambda_k, fa),
-    // with fa = rec[ia] (or 1) and fb = rec[ib] (or 1); for the square term
-    // fa = 0 and sqm = 1, so fa_k = w lambda_k exactly, and every term is the
-    // same FP64 product, in the same order, as in the oracle
-    int ia = -1, ib = -1;
-    bool sq = false;
-    if (q >= 1 && q <= 3) ia = 4 + (q - 1);
-    else if (q >= 4 && q <= 6) ia = ib = 4 + (q - 4);
-    else if (q == 7) { ia = 4; ib = 5; }
-    else if (q == 8) { ia = 4; ib = 6; }
-    else if (q == 9) { ia = 5; ib = 6; }
-    else if (q == 10) ia = 7;
-    else if (q >= 11 && q < 11 + ns) ia = 8 + (q - 11);
-    else if (q >= 11 + ns && q < 11 + 2 * ns) ia = ib = 8 + (q - 11 - ns);
-    else if (q == 11 + 2 * ns) sq = true;
-    const int ia0 = ia >= 0 ? ia : 0, ib0 = ib >= 0 ? ib : 0;
-    const bool has_a = ia >= 0, has_b = ib >= 0;
-    const R ca = sq ? R(0) : R(1);
-    const double sqm = sq ? 1.0 : 0.0;
-    const R* wave_rec = s_rec + wid * 64 * NREC;
+    // (2) runs of equal element among the sorted positions
+    const int Ep = __shfl_up(E, 1), En = __shfl_down(E, 1);
+    const bool head = pv && (lane == 0 || Ep != E);
+    const bool tail = pv && (lane == 63 || En != E);
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long before = (1ull << lane) - 1;          // positions < lane
+    const unsigned long long upto = before | (1ull << lane);        // positions <= lane
+    const int hpos = 63 - __clzll(hm & upto | 1ull);      // first position of this position's run
+    // wavefronts of the workgroup that hold this position's element (binary
+    // search in each one's sorted elements)
+    int inw = 1 << wid;
+    for (int t = 0; t < nw; ++t) {
+        if (t == wid) continue;
+        const int* L = s_sorted + t * 64;
+        int lo = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1)
+            if (L[lo + st - 1] < E) lo += st;
+        if (pv && L[lo] == E) inw |= 1 << t;
+    }
+    const bool shared_el = inw != (1 << wid);
+    // destination of the run starting at each head: a stage entry (element
+    // shared with another wavefront, while entries are left), else a record
+    // slot (the workgroup's regular slots, then the pool), else the
+    // element's overflow sums (FP64 atomics, counted)
+    const unsigned long long shm = __ballot(head && shared_el);
+    const int sidx = __popcll(shm & before);
+    const bool staged = head && shared_el && sidx < SC_SQ;
+    const bool needrec = head && !staged;
+    const unsigned long long rm = __ballot(needrec);
+    const int nrec = __popcll(rm), ridx = __popcll(rm & before);
     const int64_t ltile = gid / TILE - C.poff / TILE;     // the case's tile of this workgroup
     const int wg_slots = SC_RT * (int)blockDim.x / TILE;
     const int wg_first = (int)((blockIdx.x * (int64_t)blockDim.x) % TILE) / (int)blockDim.x * wg_slots;
     const long long kbase = (long long)blockIdx.x * 512;
-    // a record slot: one of the workgroup's regular slots, else the pool;
-    // null (handle INT32_MIN) when both are used up
-    auto take_slot = [&](int& handle) -> double* {
-        int idx = 0;
-        if (lane == 0) idx = atomicAdd(&s_slot, 1);
-        idx = __shfl(idx, 0);
-        if (idx < wg_slots) {
-            handle = (int)(ltile * SC_RT) + wg_first + idx;
-            return A.srec + C.rec_off + (int64_t)handle * C.rec_stride;
+    int base = 0;
+    if (lane == 0 && nrec > 0) base = atomicAdd(&s_slot, nrec);
+    base = __shfl(base, 0);
+    const int nreg = max(0, min(nrec, wg_slots - base));
+    int pbase = 0;
+    if (lane == 0 && nrec > nreg) pbase = atomicAdd(A.pool_cnt, nrec - nreg);
+    pbase = __shfl(pbase, 0);
+    int kind = 2, dcode = E;             // 0 record (handle), 1 stage entry, 2 overflow (element)
+    if (staged) {
+        kind = 1;
+        dcode = wid * SC_SQ + sidx;
+    } else if (needrec) {
+        if (ridx < nreg) {
+            kind = 0;
+            dcode = (int)(ltile * SC_RT) + wg_first + base + ridx;
+        } else if (pbase + (ridx - nreg) < A.pool_cap) {
+            kind = 0;
+            dcode = -1 - (pbase + (ridx - nreg));
         }
-        int pidx = 0;
-        if (lane == 0) pidx = atomicAdd(A.pool_cnt, 1);
-        pidx = __shfl(pidx, 0);
-        if (pidx < A.pool_cap) {
-            handle = -1 - pidx;
-            return A.srec + A.pool_off + (int64_t)pidx * A.pool_stride;
-        }
-        handle = INT32_MIN;
-        return nullptr;
-    };
+    }
+    double* const rec_base = A.srec + C.rec_off;
+    double* const pool_base = A.srec + A.pool_off;
+    const int64_t rec_stride = C.rec_stride, pool_stride = A.pool_stride;
     auto rec_ptr = [&](int h) -> double* {
-        return h >= 0 ? A.srec + C.rec_off + (int64_t)h * C.rec_stride : A.srec + A.pool_off + (int64_t)(-1 - h) * A.pool_stride;
+        return h >= 0 ? rec_base + (int64_t)h * rec_stride : pool_base + (int64_t)(-1 - h) * pool_stride;
     };
-    // no record slot left anywhere: the element's values go to its overflow
-    // sums with FP64 atomics (not order-fixed; counted)
-    auto overflow = [&](int el) {
-        if (lane == 0) {
-            atomicExch(A.eof + el, 1);
+    // bins present in the run starting at each head (cells only)
+    long long mask = 0;
+    if (cells) {
+        const unsigned long long later = hm & ~upto;
+        const unsigned long long vm = __ballot(pv);
+        // last position of the run starting here: before the next head, else the last particle
+        const int tpos = later ? __ffsll((long long)later) - 2 : 63 - __clzll(vm | 1ull);
+        const unsigned long long runm = (tpos >= 63 ? ~0ull : ((1ull << (tpos + 1)) - 1)) & ~before;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            if (__ballot(pv && sbin == b) & runm) mask |= 1ll << b;
+    }
+    // headers, stage entries and the merge list, from the head lanes
+    if (head) {
+        if (kind == 0) {
+            double* dst = rec_ptr(dcode);
+            dst[0] = __longlong_as_double(kbase + (shared_el ? 256 : 0) + wid * 64 + lane);
+            dst[1] = __longlong_as_double((long long)E);
+            dst[2] = __longlong_as_double(mask);
+        } else if (kind == 1) {
+            s_sel[dcode] = E;
+            s_smask[dcode] = (int)mask;
+        } else {
+            atomicExch(A.eof + E, 1);
             atomicAdd(A.counters + (int64_t)c * NCNT + C_SCATTER_OVERFLOW, 1ull);
         }
-    };
-    int my_set = -1;          // this lane's set among the wavefront's sets
+    }
     {
-        unsigned long long rem = __ballot(key >= 0);
-        int nset = 0, nst = 0;
-        while (rem) {
-            const int ks = __shfl(key, __ffsll((long long)rem) - 1);
-            const unsigned long long set = __ballot(key == ks);
-            rem &= ~set;
-            if ((set >> lane) & 1ull) my_set = nset;
-            const unsigned long long o0 = __ballot(kk0 == ks), o1 = __ballot(kk1 == ks);
-            const unsigned long long o2 = __ballot(kk2 == ks), o3 = __ballot(kk3 == ks);
-            const int ft = o0 ? 0 : o1 ? 1 : o2 ? 2 : 3;
-            const int first = ft * 64 + __ffsll((long long)(ft == 0 ? o0 : ft == 1 ? o1 : ft == 2 ? o2 : o3)) - 1;
-            const bool shared_el = ((wid == 0 ? 0ull : o0) | (wid == 1 ? 0ull : o1) | (wid == 2 ? 0ull : o2) |
-                                    (wid == 3 ? 0ull : o3)) != 0ull;
-            // vertex sums: the set's particles, G per step, one per group
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-            {
-                unsigned long long m = set;
-                while (m) {
-                    int pk[4];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        pk[t] = -1;
-                        if (t < G && m) { pk[t] = __ffsll((long long)m) - 1; m &= m - 1; }
-                    }
-                    int pp = pk[0];
-                    pp = g == 1 ? pk[1] : pp;
-                    pp = g == 2 ? pk[2] : pp;
-                    pp = g == 3 ? pk[3] : pp;
-                    if (pp >= 0) {
-                        const R* rq = wave_rec + pp * NREC;
-                        const R l0 = rq[0], l1 = rq[1], l2 = rq[2], rw = rq[3];
-                        const R xa = rq[ia0], xb = rq[ib0];
-                        const double fa = has_a ? (double)xa : (double)ca;
-                        const double fb = has_b ? (double)xb : 1.0;
-                        const double w = (double)rw;
-                        const double wn0 = w * (double)l0, wn1 = w * (double)l1, wn2 = w * (double)l2;
-                        a0 += (wn0 * __builtin_fma(sqm, wn0, fa)) * fb;
-                        a1 += (wn1 * __builtin_fma(sqm, wn1, fa)) * fb;
-                        a2 += (wn2 * __builtin_fma(sqm, wn2, fa)) * fb;
-                    }
-                }
-                if (G == 4) {
-                    a0 += __shfl_xor(a0, 16); a1 += __shfl_xor(a1, 16); a2 += __shfl_xor(a2, 16);
-                    a0 += __shfl_xor(a0, 32); a1 += __shfl_xor(a1, 32); a2 += __shfl_xor(a2, 32);
-                } else {
-                    // lanes 0..20 gather groups 1 and 2 (source lanes 21..62)
-                    a0 = (a0 + __shfl(a0, lane + 21)) + __shfl(a0, lane + 42);
-                    a1 = (a1 + __shfl(a1, lane + 21)) + __shfl(a1, lane + 42);
-                    a2 = (a2 + __shfl(a2, lane + 21)) + __shfl(a2, lane + 42);
-                }
-            }
-            long long mask = 0;
-            if (cells) {
-#pragma unroll
-                for (int b = 0; b < 8; ++b)
-                    if (set & __ballot(bin == b)) mask |= 1ll << b;
-            }
-            int kind, dcode;              // destination: 0 record (handle), 1 staged entry, 2 none
-            if (shared_el && nst < SC_SQ) {
-                const int ent = wid * SC_SQ + nst++;
-                double* sv = s_stage + ent * SC_VMAX;
-                if (g == 0 && q < nq) { sv[q] = a0; sv[nq + q] = a1; sv[2 * nq + q] = a2; }
-                if (lane == 0) { s_sel[ent] = ks; s_smask[ent] = (int)mask; }
-                kind = 1; dcode = ent;
-            } else {
-                int h;
-                double* dst = take_slot(h);
-                if (dst) {
-                    if (g == 0 && q < nq) { dst[SC_HDR + q] = a0; dst[SC_HDR + nq + q] = a1; dst[SC_HDR + 2 * nq + q] = a2; }
-                    if (lane == 0) {
-                        // the element's only sums here are keyed by its first
-                        // lane; a share of a shared element by this
-                        // wavefront's first lane of it
-                        const long long k = kbase + (shared_el ? 256 + wid * 64 + __ffsll((long long)set) - 1 : first);
-                        dst[0] = __longlong_as_double(k);
-                        dst[1] = __longlong_as_double((long long)ks);
-                        dst[2] = __longlong_as_double(mask);
-                    }
-                    kind = 0; dcode = h;
-                } else {
-                    double* eo = A.eo + (int64_t)ks * SC_VMAX;
-                    if (g == 0 && q < nq) {
-                        unsafeAtomicAdd(eo + q, a0); unsafeAtomicAdd(eo + nq + q, a1); unsafeAtomicAdd(eo + 2 * nq + q, a2);
-                    }
-                    overflow(ks);
-                    kind = 2; dcode = ks;
-                }
-            }
-            // a shared element whose first lane is here is merged by this wavefront
-            if (shared_el && ft == wid && lane == 0) {
-                const int mi = s_nmerge[wid]++;
-                s_mel[wid * 64 + mi] = ks;
-                s_mfirst[wid * 64 + mi] = first;
-            }
-            if (lane == 0) { s_skind[wid * 64 + nset] = (unsigned char)kind; s_sdst[wid * 64 + nset] = dcode; }
-            ++nset;
+        const bool merger = head && shared_el && (__ffs(inw) - 1) == wid;
+        const unsigned long long mm = __ballot(merger);
+        if (merger) {
+            const int mi = __popcll(mm & before);
+            s_mel[wid * 64 + mi] = E;
+            s_mfirst[wid * 64 + mi] = lane;
         }
-        if (lane == 0) s_nst[wid] = nst;
+        if (lane == 0) {
+            s_nmerge[wid] = __popcll(mm);
+            s_nst[wid] = min(__popcll(shm), SC_SQ);
+        }
+    }
+    // per position: its run's destination
+    const int rkind = __shfl(kind, hpos), rdcode = __shfl(dcode, hpos);
+    const R* wave_rec = s_rec + wid * 64 * NREC;
+    // (3) vertex sums: G groups of GS lanes, group g walks sorted positions
+    // [g P, g P + P); lane q of a group holds term q < nq:
+    //   (w lambda_k) * fma(sqm, w lambda_k, fa fb),
+    // fa, fb record values (or 1), and for the square term fa fb = 0, sqm = 1
+    {
+        const int G = nq <= 16 ? 4 : 3, GS = nq <= 16 ? 16 : 21, P = nq <= 16 ? 16 : 22;
+        const int g = nq <= 16 ? lane >> 4 : (lane * 49) >> 10;      // lane / GS for lane < 64
+        const int q = lane - g * GS;
+        const bool glane = g < G;
+        // factors of term q: record slots ia, ib (1 when absent, 0 for the square term)
+        const int qs = q - 11;                     // scalar terms
+        int ia, ib;
+        if (q == 0) { ia = RI_ONE; ib = RI_ONE; }
+        else if (q <= 3) { ia = 3 + q; ib = RI_ONE; }
+        else if (q <= 6) { ia = q; ib = q; }
+        else if (q <= 9) { ia = q == 9 ? 5 : 4; ib = q == 7 ? 5 : 6; }
+        else if (q == 10) { ia = 7; ib = RI_ONE; }
+        else if (qs < ns) { ia = 8 + qs; ib = RI_ONE; }
+        else if (qs < 2 * ns) { ia = 8 + qs - ns; ib = ia; }
+        else { ia = RI_ZERO; ib = RI_ZERO; }
+        const double sqm = q == 11 + 2 * ns ? 1.0 : 0.0;
+        const bool wq = glane && q < nq;      // lanes that write sums
+        // per sorted position, packed: particle lane, tail, valid, run head, run destination kind
+        const int pk = src | ((int)tail << 6) | ((int)pv << 7) | (hpos << 8) | (rkind << 14);
+        auto emit = [&](int k_, int d_, double v0, double v1, double v2) {
+            if (!wq) return;
+            if (k_ == 0) {
+                double* dst = rec_ptr(d_) + SC_HDR;
+                dst[q] = v0; dst[nq + q] = v1; dst[2 * nq + q] = v2;
+            } else if (k_ == 1) {
+                double* sv = s_stage + d_ * SC_VMAX;
+                sv[q] = v0; sv[nq + q] = v1; sv[2 * nq + q] = v2;
+            } else {
+                double* eo = A.eo + (int64_t)d_ * SC_VMAX;
+                unsafeAtomicAdd(eo + q, v0); unsafeAtomicAdd(eo + nq + q, v1); unsafeAtomicAdd(eo + 2 * nq + q, v2);
+            }
+        };
+        const int p0 = glane ? g * P : 64;
+        // the group's range [p0, p0 + P) among the sorted positions:
+        //   hp   its first run began before the range
+        //   hpe  ... and ends inside it (else the range is that run's middle)
+        //   tp   its last run began inside the range and continues past it
+        const unsigned long long tm = __ballot(tail);
+        const unsigned long long rmask = p0 >= 64 ? 0ull : (~0ull << p0) & (p0 + P >= 64 ? ~0ull : ((1ull << (p0 + P)) - 1));
+        const int w0 = __shfl(pk, p0 & 63);
+        const int dc0 = __shfl(rdcode, p0 & 63);
+        const int plast = min(p0 + P, 64) - 1;
+        const int wl = __shfl(pk, plast & 63);
+        const bool hp = p0 < 64 && ((w0 >> 7) & 1) && ((w0 >> 8) & 63) < p0;
+        const bool hpe = hp && (tm & rmask) != 0ull;
+        const bool tp = p0 < 64 && ((wl >> 7) & 1) && !((wl >> 6) & 1) && (hm & rmask) != 0ull;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;     // the run in progress
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0;     // the range's first run, when it began before the range
+        for (int it = 0; it < P; ++it) {
+            const int pos = p0 + it;
+            const int w_ = __shfl(pk, pos & 63);
+            const int dc = __shfl(rdcode, pos & 63);
+            if (pos < 64 && ((w_ >> 7) & 1)) {
+                const R* rq = wave_rec + (w_ & 63) * NREC;
+                const R l0 = rq[0], l1 = rq[1], l2 = rq[2], rw = rq[3];
+                const double gq = (double)rq[ia] * (double)rq[ib];
+                const double w = (double)rw;
+                const double wn0 = w * (double)l0, wn1 = w * (double)l1, wn2 = w * (double)l2;
+                a0 = __builtin_fma(wn0, __builtin_fma(sqm, wn0, gq), a0);
+                a1 = __builtin_fma(wn1, __builtin_fma(sqm, wn1, gq), a1);
+                a2 = __builtin_fma(wn2, __builtin_fma(sqm, wn2, gq), a2);
+                if ((w_ >> 6) & 1) {
+                    // a run ends here: complete if it began in the range,
+                    // else the first run's piece, completed after the carry
+                    if (((w_ >> 8) & 63) >= p0) emit((w_ >> 14) & 3, dc, a0, a1, a2);
+                    else { h0 = a0; h1 = a1; h2 = a2; }
+                    a0 = 0.0; a1 = 0.0; a2 = 0.0;
+                }
+            }
+        }
+        if (hp && !hpe) { h0 = a0; h1 = a1; h2 = a2; }     // the whole range is the middle of one run
+        // carry from group to group, in group order: what group g passes on
+        // is its last run when that began in its range (a), else the
+        // continued run when it spans the whole range (carry + h)
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+        for (int gg = 1; gg < G; ++gg) {
+            const double o0 = tp ? a0 : (hp && !hpe ? c0 + h0 : 0.0);
+            const double o1 = tp ? a1 : (hp && !hpe ? c1 + h1 : 0.0);
+            const double o2 = tp ? a2 : (hp && !hpe ? c2 + h2 : 0.0);
+            const int from = lane >= GS ? lane - GS : lane;
+            const double r0 = __shfl(o0, from), r1 = __shfl(o1, from), r2 = __shfl(o2, from);
+            if (g == gg) { c0 = r0; c1 = r1; c2 = r2; }
+        }
+        // a continued run that ends in this group's range: carry + h
+        if (glane && hpe) emit((w0 >> 14) & 3, dc0, c0 + h0, c1 + h1, c2 + h2);
     }
     if (cells) {
-        // cell sums: sort the lanes by (element, bin, lane) (bitonic, across
-        // the wavefront), then a segmented inclusive scan of (1, w, w psi_a);
-        // the last lane of each (element, bin) run holds the run's sums
-        unsigned long long sk = key >= 0 ? ((unsigned long long)key << 9) | ((unsigned long long)bin << 6) | (unsigned)lane
-                                         : ~0ull;
-#pragma unroll
-        for (int kk = 2; kk <= 64; kk <<= 1) {
-#pragma unroll
-            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-                const unsigned long long o = (unsigned long long)__shfl_xor((long long)sk, jj);
-                const bool keep_min = ((lane & jj) == 0) == ((lane & kk) == 0);
-                sk = keep_min ? (o < sk ? o : sk) : (o > sk ? o : sk);
-            }
-        }
-        const bool cvalid = sk != ~0ull;
-        const int src = (int)(sk & 63);
-        const unsigned long long ck = sk >> 6;
-        const unsigned long long ckp = (unsigned long long)__shfl_up((long long)ck, 1);
-        const unsigned long long ckn = (unsigned long long)__shfl_down((long long)ck, 1);
-        const bool head = lane == 0 || ckp != ck;
-        const bool tail = lane == 63 || ckn != ck;
-        int st = head ? lane : 0;
+        // (4) cell sums: a segmented inclusive scan of (1, w, w psi_a) over
+        // the sorted positions; the last position of each (element, bin)
+        // run holds the run's sums
+        const unsigned ck = sk >> 6;
+        const unsigned ckp = (unsigned)__shfl_up((int)ck, 1);
+        const unsigned ckn = (unsigned)__shfl_down((int)ck, 1);
+        const bool chead = lane == 0 || ckp != ck;
+        const bool ctail = lane == 63 || ckn != ck;
+        int st = chead ? lane : 0;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int o = __shfl_up(st, d);
             if (lane >= d && o > st) st = o;
         }
         const R* rq = wave_rec + src * NREC;
-        const double w = cvalid ? (double)rq[3] : 0.0;
+        const double w = pv ? (double)rq[3] : 0.0;
         double x[2 + MAXS];
         x[0] = 1.0;
         x[1] = w;
 #pragma unroll
         for (int a = 0; a < MAXS; ++a) x[2 + a] = a < ns ? w * (double)rq[8 + a] : 0.0;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
+        for (int j2 = 0; j2 < 2 + MAXS; ++j2) {
+            if (j2 < nc) {
 #pragma unroll
-            for (int j2 = 0; j2 < 2 + MAXS; ++j2) {
-                if (j2 < nc) {
+                for (int d = 1; d < 64; d <<= 1) {
                     const double y = __shfl_up(x[j2], d);
                     if (lane - d >= st) x[j2] += y;
                 }
             }
         }
-        const int sset = __shfl(my_set, src);
-        if (cvalid && tail) {
-            const int b = (int)(ck & 7);
-            const int kind = s_skind[wid * 64 + sset], dcode = s_sdst[wid * 64 + sset];
-            const int off = 3 * nq + b * nc;
-            if (kind == 1) {
-                double* sv = s_stage + dcode * SC_VMAX + off;
+        if (pv && ctail) {
+            const int off = 3 * nq + sbin * nc;
+            if (rkind == 1) {
+                double* sv = s_stage + rdcode * SC_VMAX + off;
 #pragma unroll
                 for (int j2 = 0; j2 < 2 + MAXS; ++j2) if (j2 < nc) sv[j2] = x[j2];
-            } else if (kind == 0) {
-                double* dst = rec_ptr(dcode) + SC_HDR + off;
+            } else if (rkind == 0) {
+                double* dst = rec_ptr(rdcode) + SC_HDR + off;
 #pragma unroll
                 for (int j2 = 0; j2 < 2 + MAXS; ++j2) if (j2 < nc) dst[j2] = x[j2];
             } else {
-                double* eo = A.eo + (int64_t)dcode * SC_VMAX + off;
+                double* eo = A.eo + (int64_t)rdcode * SC_VMAX + off;
 #pragma unroll
                 for (int j2 = 0; j2 < 2 + MAXS; ++j2) if (j2 < nc) unsafeAtomicAdd(eo + j2, x[j2]);
             }
         }
     }
     __syncthreads();
-    // merge the staged sums of the shared elements whose first lane is in this
-    // wavefront, in wavefront order (entry index = t SC_SQ + s)
+    // (5) the wavefront's merges: the staged sums of each shared element
+    // whose lowest wavefront is this one, in wavefront order (entry index
+    // t SC_SQ + s), go out as one record
     {
+        auto take_slot = [&](int& handle) -> double* {
+            int idx = 0;
+            if (lane == 0) idx = atomicAdd(&s_slot, 1);
+            idx = __shfl(idx, 0);
+            if (idx < wg_slots) {
+                handle = (int)(ltile * SC_RT) + wg_first + idx;
+                return A.srec + C.rec_off + (int64_t)handle * C.rec_stride;
+            }
+            int pidx = 0;
+            if (lane == 0) pidx = atomicAdd(A.pool_cnt, 1);
+            pidx = __shfl(pidx, 0);
+            if (pidx < A.pool_cap) {
+                handle = -1 - pidx;
+                return A.srec + A.pool_off + (int64_t)pidx * A.pool_stride;
+            }
+            handle = INT32_MIN;
+            return nullptr;
+        };
         const int ne_w = nw * SC_SQ;
         int el_j = -1;
         if (lane < ne_w && lane - (lane / SC_SQ) * SC_SQ < s_nst[lane / SC_SQ]) el_j = s_sel[lane];
@@ -618,13 +661,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
             const unsigned long long ents = __ballot(el_j == el);
             if (!ents) continue;          // every share of it went out as a record of its own
             double x0 = 0.0, x1 = 0.0;
-            long long mask = 0;
+            long long mk = 0;
             unsigned long long m = ents;
             while (m) {
                 const int jx = __ffsll((long long)m) - 1;
                 m &= m - 1;
                 const int em = s_smask[jx];
-                mask |= em;
+                mk |= em;
                 const double* sv = s_stage + jx * SC_VMAX;
                 if (lane < nv && (lane < 3 * nq || ((em >> ((lane - 3 * nq) / nc)) & 1))) x0 += sv[lane];
                 if (lane + 64 < nv && (lane + 64 < 3 * nq || ((em >> ((lane + 64 - 3 * nq) / nc)) & 1)))
@@ -636,15 +679,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                 if (lane < nv) dst[SC_HDR + lane] = x0;
                 if (lane + 64 < nv) dst[SC_HDR + 64 + lane] = x1;
                 if (lane == 0) {
-                    dst[0] = __longlong_as_double(kbase + first);
+                    dst[0] = __longlong_as_double(kbase + wid * 64 + first);
                     dst[1] = __longlong_as_double((long long)el);
-                    dst[2] = __longlong_as_double(mask);
+                    dst[2] = __longlong_as_double(mk);
                 }
             } else {
                 double* eo = A.eo + (int64_t)el * SC_VMAX;
                 if (lane < nv && x0 != 0.0) unsafeAtomicAdd(eo + lane, x0);
                 if (lane + 64 < nv && x1 != 0.0) unsafeAtomicAdd(eo + 64 + lane, x1);
-                overflow(el);
+                if (lane == 0) {
+                    atomicExch(A.eof + el, 1);
+                    atomicAdd(A.counters + (int64_t)c * NCNT + C_SCATTER_OVERFLOW, 1ull);
+                }
             }
         }
     }

@@ -31,6 +31,11 @@ int derive_mesh(const pdfmc_mesh_desc& d, MeshHost& m, std::string& err)
         err = "mesh: missing arrays or empty mesh";
         return PDFMC_E_INVALID;
     }
+    if (d.n_elems >= (1 << 23)) {
+        // the scatter sorts a wavefront's particles on (element << 9 | bin << 6 | lane) in 32 bits
+        err = "mesh: a case holds at most 2^23 - 1 elements";
+        return PDFMC_E_INVALID;
+    }
     const int nn = d.n_nodes, ne = d.n_elems;
     m.nn = nn; m.ne = ne;
     m.x.resize(nn); m.y.resize(nn);
