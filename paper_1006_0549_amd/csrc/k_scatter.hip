@@ -47,11 +47,14 @@ __global__ void k_scatter_register(NodeArgs A, int ntiles, int block, const int3
         handle = -1 - (int)pi;
         rp = A.srec + A.pool_off + pi * A.pool_stride;
     }
+    const long long key = __double_as_longlong(rp[0]);
     const int el = (int)__double_as_longlong(rp[1]);
     if (t >= nreg) c = A.elem_case[el];
     const int slot = atomicAdd(A.ecnt + el, 1);
     if (slot < SC_K) {
-        A.eslot[(int64_t)el * SC_K + slot] = handle;
+        // the key travels with the handle, so the element pass ranks its
+        // records without reading their headers
+        A.eslot[(int64_t)el * SC_K + slot] = (int64_t)((unsigned long long)key << 32 | (uint32_t)handle);
         return;
     }
     // list full: the record's values go to the element's overflow sums
@@ -79,15 +82,17 @@ __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__
     const int ns = C.ns, nq = 12 + 2 * ns, nc = 2 + ns;
     const bool cells = cells_on && ns > 0;
     const int nv = sc_nvals(ns, cells);
+    // the list entries are read together with the count (entries past the
+    // count are stale and unused); lane j < n: record j as listed, and its key
+    const int64_t ent = A.eslot[e * SC_K + lane];
     const int n = min(A.ecnt[e], SC_K);
-    // lane j < n: record j as listed, and its key
     const double* rp = nullptr;
     long long key = 0x7fffffffffffffffll;
     if (lane < n) {
-        const int h = A.eslot[e * SC_K + lane];
+        const int h = (int)(uint32_t)ent;
         rp = h >= 0 ? A.srec + C.rec_off + (int64_t)h * C.rec_stride
                     : A.srec + A.pool_off + (int64_t)(-1 - h) * A.pool_stride;
-        key = __double_as_longlong(rp[0]);
+        key = (long long)((unsigned long long)ent >> 32);
     }
     // rank of the record among the element's records (keys are distinct)
     int rank = 0;

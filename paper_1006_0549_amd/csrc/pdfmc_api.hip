@@ -267,7 +267,8 @@ struct pdfmc_ctx {
     double* d_srec = nullptr;
     int64_t SREC = 0, pool_off = 0;
     int pool_cap = 0;
-    int32_t *d_pool_cnt = nullptr, *d_ecnt = nullptr, *d_eslot = nullptr, *d_eof = nullptr, *d_wgcnt = nullptr;
+    int32_t *d_pool_cnt = nullptr, *d_ecnt = nullptr, *d_eof = nullptr, *d_wgcnt = nullptr;
+    int64_t* d_eslot = nullptr;
     double *d_eo = nullptr, *d_etot = nullptr;
     char* d_Fel = nullptr;          // element-major fields in the particle precision
     double* d_Ffrz = nullptr;       // uploaded fields, for the slots a case keeps frozen
@@ -312,7 +313,9 @@ struct pdfmc_ctx {
     // options
     int sort_interval = 0, block = 256, use_graph = 0;
     int steps_since_sort = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [buffer set][sort at the end]
+    hipStream_t side = nullptr;                  // the sort's stream, beside the fields phase
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint32_t graph_stages = PDFMC_STAGE_ALL;   // stages of the captured graphs
     bool any_er = false, any_eul = false, any_scalars = false;
     bool any_freeze = false;        // some case keeps field slots frozen
@@ -999,23 +1002,6 @@ pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
     return PDFMC_OK;
 }
 
-// One step restricted to the stages in `stages` (PDFMC_STAGE_*): without
-// ADVANCE the particles stay where they are (the statistics of the current
-// state are formed), without STATS the node statistics and cell means keep
-// their values, without FIELDS the Eulerian fields keep theirs.
-pdfmc_status enqueue_step_body(pdfmc_ctx* c, uint32_t stages)
-{
-    const bool adv = stages & PDFMC_STAGE_ADVANCE, st = stages & PDFMC_STAGE_STATS;
-    if (adv || st) {
-        TRY(enqueue_accum_clear(c));
-        TRY(enqueue_particles(c, adv ? 1 : 0, 1, st ? 1 : 0, st));
-    }
-    if (stages & PDFMC_STAGE_FIELDS) TRY(enqueue_fields(c, true));
-    hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, c->stream, c->d_step);
-    LAUNCHCHK(c);
-    return PDFMC_OK;
-}
-
 // The temporaries of one sort: per-element counts, scans, cursors, segment
 // starts and the list of long segments, and per-particle placed ids, their
 // sources and the final permutation.
@@ -1049,6 +1035,39 @@ SortScratch sort_scratch_ws(pdfmc_ctx* c)
     t.tmp_src = t.perm + c->NP;
     t.tmp_id = (uint32_t*)(t.tmp_src + c->NP);
     return t;
+}
+
+pdfmc_status enqueue_sort(pdfmc_ctx* c, const SortScratch& T);
+
+// One step restricted to the stages in `stages` (PDFMC_STAGE_*): without
+// ADVANCE the particles stay where they are (the statistics of the current
+// state are formed), without STATS the node statistics and cell means keep
+// their values, without FIELDS the Eulerian fields keep theirs.
+pdfmc_status enqueue_step_body(pdfmc_ctx* c, uint32_t stages, bool sort_after)
+{
+    const bool adv = stages & PDFMC_STAGE_ADVANCE, st = stages & PDFMC_STAGE_STATS;
+    if (adv || st) {
+        TRY(enqueue_accum_clear(c));
+        TRY(enqueue_particles(c, adv ? 1 : 0, 1, st ? 1 : 0, st));
+    }
+    // a sort due before the next step runs on the side stream while the
+    // fields are formed: it reads and writes only the particle arrays and its
+    // temporaries in the record region, which the fields phase does not touch
+    if (sort_after) {
+        HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        hipStream_t main_stream = c->stream;
+        c->stream = c->side;
+        const pdfmc_status ss = enqueue_sort(c, sort_scratch_ws(c));
+        c->stream = main_stream;
+        TRY(ss);
+        HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+    }
+    if (stages & PDFMC_STAGE_FIELDS) TRY(enqueue_fields(c, true));
+    if (sort_after) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, c->stream, c->d_step);
+    LAUNCHCHK(c);
+    return PDFMC_OK;
 }
 
 pdfmc_status enqueue_sort(pdfmc_ctx* c, const SortScratch& T)
@@ -1111,8 +1130,9 @@ pdfmc_status check_bound(pdfmc_ctx* c)
 
 void drop_graphs(pdfmc_ctx* c)
 {
-    for (auto& g : c->graph)
-        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+    for (auto& gs : c->graph)
+        for (auto& g : gs)
+            if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
 }  // namespace
@@ -1139,6 +1159,10 @@ void pdfmc_destroy(pdfmc_ctx* c)
     if (!c) return;
     if (c->bound) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side) (void)hipStreamDestroy(c->side);
     for (auto e : c->ev) (void)hipEventDestroy(e);
     if (c->need_ev) (void)hipEventDestroy(c->need_ev);
     if (c->h_need) (void)hipHostFree(c->h_need);
@@ -1226,6 +1250,9 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     uint64_t need = 0;
     TRY(pdfmc_workspace_query(c, &need));
     if (bytes < need) return fail(c, PDFMC_E_NOMEM, "workspace_bind: need " + std::to_string(need) + " bytes");
+    // record keys (workgroup index * 512 + position) stay below 2^32 at the smallest block size
+    if (c->NP > ((int64_t)1 << 29))
+        return fail(c, PDFMC_E_INVALID, "workspace_bind: at most 2^29 particle slots in one context");
     char* base = (char*)(((uintptr_t)dev + 255) & ~(uintptr_t)255);
     Carver k{base, 0, true};
     carve(c, k);
@@ -1748,6 +1775,17 @@ pdfmc_status pdfmc_rebin(pdfmc_ctx* c)
     return PDFMC_OK;
 }
 
+// The side stream and the events that fork the sort off the main stream and
+// join it back (default priority, like the main stream).
+static pdfmc_status ensure_side_stream(pdfmc_ctx* c)
+{
+    if (c->side) return PDFMC_OK;
+    HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    return PDFMC_OK;
+}
+
 pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps, uint32_t stage_mask)
 {
     if (!c) return PDFMC_E_INVALID;
@@ -1759,16 +1797,21 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps, uint32_t stage_mask)
         drop_graphs(c);
         c->graph_stages = stage_mask;
     }
+    TRY(ensure_side_stream(c));
     for (int s = 0; s < n_steps; ++s) {
         mg_adapt(c);
-        if (c->sort_interval > 0 && c->steps_since_sort >= c->sort_interval) TRY(enqueue_sort(c, sort_scratch_ws(c)));
+        // the periodic sort comes at the end of the step after which it is
+        // due, so that it overlaps the fields phase
+        const bool sort_after = c->sort_interval > 0 && c->ntiles > 0 && c->steps_since_sort + 1 >= c->sort_interval;
+        const int cur0 = c->cur;
         if (c->use_graph && !c->timing) {
-            hipGraphExec_t& g = c->graph[c->cur];
+            hipGraphExec_t& g = c->graph[cur0][sort_after ? 1 : 0];
             if (!g) {
                 hipGraph_t graph = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                pdfmc_status st = enqueue_step_body(c, stage_mask);
+                pdfmc_status st = enqueue_step_body(c, stage_mask, sort_after);
                 hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+                c->cur = cur0;           // the replay below performs the step
                 if (st != PDFMC_OK) { if (graph) (void)hipGraphDestroy(graph); return st; }
                 if (e2 != hipSuccess) return fail(c, PDFMC_E_HIP, std::string("graph capture: ") + hipGetErrorString(e2));
                 hipError_t e3 = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
@@ -1776,11 +1819,12 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps, uint32_t stage_mask)
                 if (e3 != hipSuccess) { g = nullptr; return fail(c, PDFMC_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e3)); }
             }
             HIPCHK(c, hipGraphLaunch(g, c->stream));
+            if (sort_after) c->cur = 1 - cur0;    // the graph's sort wrote the other buffer set
         } else {
-            TRY(enqueue_step_body(c, stage_mask));
+            TRY(enqueue_step_body(c, stage_mask, sort_after));
         }
         TRY(mg_after_step(c));
-        c->steps_since_sort++;
+        c->steps_since_sort = sort_after ? 0 : c->steps_since_sort + 1;
     }
     return PDFMC_OK;
 }

@@ -46,7 +46,7 @@ struct NodeArgs {
     int64_t pool_off;
     int32_t pool_stride, pad2;
     int32_t* ecnt;                   // [ne] records listed per element
-    int32_t* eslot;                  // [ne][SC_K] record handles: >= 0 regular, < 0 pool (-1 - index)
+    int64_t* eslot;                  // [ne][SC_K] record key << 32 | handle (>= 0 regular, < 0 pool: -1 - index)
     int32_t* eof;                    // [ne] overflow flags
     double* eo;                      // [ne][SC_VMAX] overflow sums
     const int32_t* wgcnt;            // [workgroups] regular record slots used by each workgroup
