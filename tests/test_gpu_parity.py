@@ -78,7 +78,7 @@ def _assert_state_equal(g, r, keys=("x", "y", "u", "v", "w", "omega")):
         bad = np.nonzero(g[k] != r[k])[0]
         assert bad.size == 0, (k, bad[:5], g[k][bad[:5]], r[k][bad[:5]])
     if r["psi"].size:
-        # mixing uses cell means, i.e. FP64 sums whose order differs (atomics):
+        # mixing uses cell means, i.e. FP64 sums in another order than the oracle's:
         # |delta psi| <= (dt/t_m) |delta mean| ~ a few ulp of the scalar scale
         d = np.abs(g["psi"] - r["psi"])
         assert d.max() <= 1e-14 * max(1.0, np.abs(r["psi"]).max()), d.max()
@@ -158,6 +158,42 @@ def test_one_step_frozen_bitwise(P, oracle_mod, ns, nb):
     for k in ("walk_fallback", "reflect", "periodic", "omega_flip", "nan", "walk_steps"):
         assert gc_[k] == rc_[k], (k, gc_[k], rc_[k])
     assert rc_["reflect"] > 0 and rc_["periodic"] > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_walk_caps_follow_the_oracle(P, oracle_mod, precision):
+    """Particles set from the host so that both caps of the walk are reached
+    in one step, on a coarse mesh (three element rows): five with a
+    wall-normal velocity that crosses the unit square twelve times (the
+    eighth reflection ends the walk, R-14), five with a streamwise velocity
+    that crosses about 180 elements through the periodic edges (the 64-step
+    cap, R-13); both end in the fallback. In FP64 the
+    state and the counters equal the oracle's bit for bit; in FP32 (best
+    visited element as the fallback) the counters show both caps and every
+    particle keeps a valid element."""
+    mesh = W.unit_square(4, 0.2, periodic_x=True, periodic_y=False, seed_key=(9, 0, 0))
+    params = W.default_params(mode=0, dt=1e-3, nu=1e-4, n_scalars=0)
+    parts = W.init_particles(mesh, 12, 0, W.rng_for(9, 0, 1), u_std=0.1)
+    parts["v"][:5] = 12000.0
+    parts["u"][5:10] = 30000.0
+    n = len(parts["x"])
+    F = W.frozen_fields(mesh, C0=2.1, omega=1.0, k=0.01)
+    _flush(f"[walk_caps] {precision}: {n} particles, ten at extreme velocities, one step")
+    sim, cs, o, oc = _pair(P, oracle_mod, mesh, params, parts, precision=precision, fields=F)
+    sim.init(); o.init()
+    sim.step(1); o.step(1)
+    gc_, rc_ = sim.counters(cs), o.counters(oc)
+    assert rc_["walk_fallback"] >= 10 and rc_["reflect"] >= 5 * 8, rc_
+    assert gc_["walk_fallback"] >= 10 and gc_["reflect"] >= 5 * 8, gc_
+    g, r = sim.download(cs, n), o.download(oc, n)
+    assert g["elem"].min() >= 0 and g["elem"].max() < mesh.n_elems
+    if precision == "fp64":
+        _assert_state_equal(g, r)
+        for k in ("walk_fallback", "reflect", "periodic", "walk_steps"):
+            assert gc_[k] == rc_[k], (k, gc_[k], rc_[k])
+    else:
+        # the other particles take the same elements as in FP64 (up to rounding on an edge)
+        assert (g["elem"][10:] == r["elem"][10:]).mean() > 0.97
 
 
 def test_frozen_table_overflow(P, oracle_mod):
@@ -331,32 +367,46 @@ def test_elliptic_relaxation_and_projection(P, oracle_mod, solver):
     assert (gc_["cg_iters_p"] == 0) if direct else (gc_["cg_iters_p"] > 0)
 
 
-def _band_fraction(gst, rst, parts_r, col, ns):
-    """fraction of nodes where |FP32 - FP64| <= 3 sigma_n, sigma_n^2 = var / N_eff"""
-    W_ = rst[:, 0]
-    var = {2: rst[:, 5], 3: rst[:, 6], 4: rst[:, 7], 12: rst[:, 12 + ns] if ns else None}[col]
-    neff = 20.0  # conservative lower bound of the effective sample size per node
-    sig = np.sqrt(np.maximum(var, 1e-30) / neff)
-    return np.mean(np.abs(gst[:, col] - rst[:, col]) <= 3 * sig)
-
-
-def test_fp32_within_statistical_band(P, oracle_mod):
+def _fp32_cases():
     cfg = W.config_small()
-    parts = cfg["particles"]
+    ch = W.channel(n_half=8, nx=20, seed_key=(1, 3, 0))
+    chp = W.default_params(mode=2, dt=5e-4, nu=1.0 / 1080.0, n_scalars=1, dpdx=(-1.0, 0.0),
+                           src=[(3.0, 1.0, 0.2, 1.0)], stream=5)
+    chparts = W.init_particles(ch, 60, 1, W.rng_for(1, 3, 1), u_std=1.0)
+    return [("square-mode1", cfg["mesh"], cfg["params"], cfg["particles"], 100),
+            ("channel-mode2", ch, chp, chparts, 60)]
+
+
+@pytest.mark.parametrize("case", range(2), ids=[c[0] for c in _fp32_cases()])
+def test_fp32_statistical_band(P, oracle_mod, case):
+    """The FP32 path against the FP64 oracle over a run: at every statistics
+    node, every statistic (<U_i>, <u_i u_j>, <omega>, <psi>, <psi'^2>) within
+    three standard errors of the oracle's, the standard error taken from the
+    node's effective sample size W^2 / sum (w lambda)^2 (oracle/band.py), at
+    99% of the (node, statistic) pairs or more; mode 1 on the small square and
+    the full model (relaxation and projection) on a small channel."""
+    from oracle import band
+    name, mesh, params, parts, steps = _fp32_cases()[case]
     n = len(parts["x"])
-    _flush(f"[fp32] {cfg['name']} FP32 against the FP64 oracle, 100 steps")
-    sim, cs, o, oc = _pair(P, oracle_mod, cfg["mesh"], cfg["params"], parts, precision="fp32")
+    ns = params["n_scalars"]
+    _flush(f"[fp32-band] {name}: {n} particles, {steps} steps, FP32 against the FP64 oracle")
+    sim, cs, o, oc = _pair(P, oracle_mod, mesh, params, parts, precision="fp32")
     sim.init(); o.init()
-    sim.step(100); o.step(100)
+    sim.step(steps); o.step(steps)
     rows = _stat_rows(sim, cs)
-    gst, rst = sim.stats(cs)[rows], o.stats(oc)[rows]
-    for col in (2, 3, 4, 12):
-        assert _band_fraction(gst, rst, parts, col, 1) >= 0.99, col
-    # the same Wiener path: FP32 particles stay close to the FP64 ones
+    gst, rst, sums = sim.stats(cs), o.stats(oc), o.node_sums(oc)
+    fr = band.fractions(gst, rst, sums, ns, rows=rows)
+    _flush(f"[fp32-band] {name}: " + ", ".join(f"{k} {v['fraction']:.4f} (median {v['median_sigma']:.2g} sigma)"
+                                              for k, v in fr.items()))
+    for k, v in fr.items():
+        assert v["fraction"] >= 0.99, (k, v)
+        # the same Wiener path: typically far inside the band
+        assert v["median_sigma"] < 0.5, (k, v)
+    # the particles themselves stay close to the FP64 ones
     g, r = sim.download(cs, n), o.download(oc, n)
     assert (g["elem"] == r["elem"]).mean() > 0.99
-    du = np.abs(g["u"] - r["u"])
-    assert np.median(du) < 1e-4, np.median(du)
+    du = np.abs(g["u"] - r["u"]) / np.std(r["u"])
+    assert np.median(du) < 1e-3, np.median(du)
 
 
 def _run(P, mesh, params, parts, steps, precision="fp64", **opt):
