@@ -171,38 +171,94 @@ def one_by_one(cases, prec, steps, warmup, opts):
     return dict(value=total_n / (total_ms * 1e-3), ms_per_step=total_ms / steps)
 
 
-def cpu_baseline(cases, budget_s=20.0):
-    """The oracle, single-threaded, on a bounded sample: the smallest case of
-    the workload, as many full steps as fit in the budget."""
+def gpu_stats(cases, prec, steps, opts):
+    """Node statistics of the cases after exactly `steps` steps from their
+    initial state (one context, the benchmark's launch settings)."""
+    import torch
+    from paper_1006_0549_amd import Sim
+    sim = Sim(prec, "cuda:0")
+    ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in cases]
+    sim.bind()
+    sim.set_options(sort_interval=opts.get("sort_interval", 0), block_size=opts.get("block_size", 256),
+                    use_graph=opts.get("graph", False))
+    sim.set_solver(iterations=opts.get("cg_iters", 0), tail_rows=opts.get("tail_rows", 64))
+    sim.set_projection_solver(opts.get("projection", "direct"))
+    for cs, c in zip(ids, cases):
+        sim.upload(cs, c["particles"])
+    sim.init()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    out = [(sim.stats(cs), np.unique(sim.case_info(cs)[1], return_index=True)[1]) for cs in ids]
+    del sim
+    return out
+
+
+def host_cpu():
+    info = {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if ":" in line:
+                k, v = (t.strip() for t in line.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v
+    except OSError:
+        pass
+    name = info.get("model name", "unknown")
+    return f"{name} (family {info.get('cpu family', '?')}, model {info.get('model', '?')}, " \
+           f"stepping {info.get('stepping', '?')})"
+
+
+def cpu_baseline(cases, opts, budget_s=30.0, max_steps=20):
+    """The oracle leg. The oracle (single-threaded FP64 C, untuned) advances a
+    bounded sample of the workload: the three smallest cases of a batch (the
+    whole workload otherwise) for as many steps as fit in the budget, at most
+    max_steps; that gives the CPU rate. The FP32 and FP64 GPU paths then
+    advance the same sample for the same number of steps from the same
+    initial state, and their node statistics are compared with the oracle's:
+    relative L2 error per group of statistics and the fraction of (node,
+    statistic) pairs inside three standard errors (oracle/band.py)."""
     import oracle
-    c = min(cases, key=lambda c: len(c["particles"]["x"]))
-    n = len(c["particles"]["x"])
+    from oracle import band
+    sample = sorted(cases, key=lambda c: len(c["particles"]["x"]))[:3]
+    n = sum(len(c["particles"]["x"]) for c in sample)
     o = oracle.Oracle()
-    oc = o.add_case(c["mesh"], c["params"])
-    o.upload(oc, c["particles"])
+    ocs = [o.add_case(c["mesh"], c["params"]) for c in sample]
+    for oc, c in zip(ocs, sample):
+        o.upload(oc, c["particles"])
     t0 = time.perf_counter()
     o.init()
     log(f"oracle init {time.perf_counter() - t0:.1f} s")
     done, t = 0, 0.0
-    while t < budget_s and done < 50:
+    while t < budget_s and done < max_steps:
         t1 = time.perf_counter()
         o.step(1)
         t += time.perf_counter() - t1
         done += 1
         log(f"oracle step {done}: {t:.1f} s")
-    what = "the smallest case of the batch" if len(cases) > 1 else "the same workload"
-    cpu = "unknown"
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return dict(value=n * done / t, unit="particle-updates/s", cores=1, kind="oracle",
-                host_cpu=cpu, host_threads=os.cpu_count(),
-                sample=f"{done} full steps of {what} ({c['mesh'].name}, {n} particles, "
-                       f"{c['params']['n_scalars']} scalars), single-threaded FP64 C, timed after initialisation")
+    ref = [(o.stats(oc), o.node_sums(oc)) for oc in ocs]
+    what = "the three smallest cases of the batch" if len(cases) > 1 else "the workload"
+    names = ", ".join(f"{c['mesh'].name} ({len(c['particles']['x'])} particles, {c['params']['n_scalars']} scalars)"
+                      for c in sample)
+    cpu = dict(value=n * done / t, unit="particle-updates/s", cores=1, kind="oracle", host_cpu=host_cpu(),
+               host_threads=os.cpu_count(),
+               sample=f"{done} full steps of {what}: {names}; single-threaded FP64 C, timed after initialisation")
+    prec = {}
+    for p_ in ("fp32", "fp64"):
+        g = gpu_stats(sample, p_, done, dict(opts, autotune=False))
+        groups, fr = {}, {}
+        for c, (gst, rows), (rst, sums) in zip(sample, g, ref):
+            ns = c["params"]["n_scalars"]
+            for k, cols in band.columns(ns).items():
+                if cols:
+                    groups.setdefault(k, []).append((gst[rows][:, cols].ravel(), rst[rows][:, cols].ravel()))
+            for k, v in band.fractions(gst, rst, sums, ns, rows=rows).items():
+                fr.setdefault(k, []).append((v["fraction"], len(rows) * len(band.columns(ns)[k])))
+        prec[p_] = dict(
+            rel_l2={k: rel_l2(np.concatenate([a for a, _ in v]), np.concatenate([b for _, b in v]))
+                    for k, v in groups.items()},
+            in_3_sigma={k: float(sum(f * w for f, w in v) / sum(w for _, w in v)) for k, v in fr.items()})
+        log(f"{p_} against the oracle after {done} steps: {prec[p_]}")
+    return cpu, dict(steps=done, sample=names, **prec)
 
 
 def rel_l2(a, b):
@@ -312,7 +368,9 @@ def main():
         extra["one_by_one"] = dict(value=s["value"], ms_per_step=s["ms_per_step"],
                                    batched_speedup=value / s["value"], steps=5)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(cases)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, extra["precision_vs_oracle"] = cpu_baseline(cases, opts)
 
     out = {
         "metric": METRIC,
