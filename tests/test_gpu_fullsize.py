@@ -33,8 +33,9 @@ def _sample_ids(n, k, seed):
     return np.sort(rng.choice(n, size=min(k, n), replace=False))
 
 
-def _check_sampled(oracle_mod, mesh, params, parts, F, after, ids):
-    """Oracle: frozen fields F, the sampled particles, one step; compare."""
+def _check_sampled(oracle_mod, mesh, params, parts, F, after, ids, step_index=0):
+    """Oracle: frozen fields F, the sampled particles, one step (with the
+    given step index in the random-number counter); compare."""
     sub = {k: (v[..., ids] if isinstance(v, np.ndarray) and v.shape[-1] == len(parts["x"]) else v)
            for k, v in parts.items()}
     p0 = dict(params)
@@ -44,6 +45,7 @@ def _check_sampled(oracle_mod, mesh, params, parts, F, after, ids):
     o.fields_upload(oc, F)
     o.upload(oc, sub)
     o.init()
+    o.set_step_index(step_index)
     o.step(1)
     r = o.download(oc, len(ids))
     g = {k: after[k][np.searchsorted(after["id"], r["id"])] for k in ("x", "y", "u", "v", "w", "omega", "elem", "bin", "id")}
@@ -82,6 +84,42 @@ def test_channel_full_size_sampled_fp64(P, oracle_mod):
     assert cnt["nan"] == 0 and cnt["cg_fail"] == 0
     _flush("[fullsize] channel: oracle on 4096 sampled particles")
     _check_sampled(oracle_mod, mesh, params, parts, F, after, _sample_ids(n, 4096, 1))
+
+
+def test_cavity_full_size_sampled_fp64(P, oracle_mod):
+    """The lid-driven cavity at its full size (about 100k triangles refined at
+    the walls, 100 particles per element, two scalars, sort every 10 steps,
+    graph replay), FP64, after a sort and a step: a sample of particles
+    against the oracle with the GPU's fields frozen, bit for bit, and the
+    node weights adding up to the particle weight."""
+    cfg = W.config_cavity()
+    mesh, params, parts = cfg["mesh"], cfg["params"], cfg["particles"]
+    n = len(parts["x"])
+    _flush(f"[fullsize] cavity {mesh.n_elems} triangles, {n} particles, FP64, graph replay")
+    sim = P.Sim("fp64", "cuda:0")
+    cs = sim.add_case(mesh, params, n)
+    sim.bind()
+    sim.set_options(sort_interval=10, block_size=256, use_graph=True)
+    sim.upload(cs, parts)
+    sim.init()
+    sim.step(9)                  # the tenth step ends with a sort
+    sim.synchronize()
+    F = sim.fields(cs)
+    before = _by_id(sim.download(cs, n))
+    sim.step(1)
+    after = _by_id(sim.download(cs, n))
+    S = sim.node_sums(cs)
+    rows = np.unique(sim.case_info(cs)[1], return_index=True)[1]
+    wsum = float(after["weight"].sum())
+    assert abs(S[rows, 0].sum() - wsum) <= 1e-12 * wsum
+    cnt = sim.counters(cs)
+    assert cnt["nan"] == 0 and cnt["cg_fail"] == 0, cnt
+    # the sort at the end of the tenth step left the particles in (element, id) order
+    d = sim.download(cs, n)
+    key = d["elem"].astype(np.int64) * (1 << 32) + d["id"].astype(np.int64)
+    assert np.all(np.diff(key) > 0)
+    _flush("[fullsize] cavity: oracle on 4096 sampled particles")
+    _check_sampled(oracle_mod, mesh, params, before, F, after, _sample_ids(n, 4096, 3), step_index=9)
 
 
 def test_batch32_full_size_sampled_fp64(P, oracle_mod):
