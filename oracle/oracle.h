@@ -18,7 +18,8 @@
  * listed in the design notes of the repository and restated where used.
  *
  * Pins (CPU tests, each tied to something other than this code): the
- * generator (rocRAND's Philox, libm, distributions), location against brute
+ * generator (rocRAND's Philox, libm, distributions), the initial ensemble
+ * against the distributions it draws from, location against brute
  * force, the boundary conditions against their closed forms, the SDEs against
  * Ornstein-Uhlenbeck, Gamma and SLM-decay recurrences, interpolation through
  * a frozen linear mean velocity, mixing invariants and its clamp, the
@@ -27,7 +28,7 @@
  * S_omega under homogeneous shear, and the elliptic-relaxation source (its
  * production part under simple shear, A_v and length-scale limits,
  * isotropic part, wall values, G_ij and C0 eps) against hand-derived closed
- * forms.
+ * forms, and the freeze mask against the frozen-field mode.
  *
  * Parity unpinned: the fully coupled model over many steps (relaxation and
  * projection feeding back into the particles). The paper prints no numbers
