@@ -183,8 +183,11 @@ pdfmc_status pdfmc_fields_upload(pdfmc_ctx* ctx, int32_t case_id, const double* 
 /* The fields in force, same layout as the upload; synchronises the stream. */
 pdfmc_status pdfmc_fields_download(pdfmc_ctx* ctx, int32_t case_id, double* F);
 /* The mean pressure <P> per raw node (Sec. II, closing paragraph: the mean
- * pressure of Eq.(4) from the projection on the grid, reading R-27; 0 in
- * modes 0 and 1, and before the first step). Synchronises the stream. */
+ * pressure of Eq.(4) from the projection on the grid, reading R-27: the
+ * potential phi of the last projection, whose recovered gradient corrects
+ * the particle velocities at the start of the next step; in mode 2 the
+ * field slots d<P>/dx_j then hold the driving gradient alone). 0 in modes 0
+ * and 1, and before the first step. Synchronises the stream. */
 pdfmc_status pdfmc_pressure_download(pdfmc_ctx* ctx, int32_t case_id, double* P);
 
 /* Initialisation pass over every case (the state the first forward-Euler

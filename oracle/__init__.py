@@ -118,7 +118,7 @@ def lib():
         L.orc_fem_projection.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
                                          C.c_double, C.c_void_p]
         for name in ("orc_add_case", "orc_mesh_info", "orc_particles_upload", "orc_particles_download",
-                     "orc_fields_upload", "orc_fields_download", "orc_pressure_download", "orc_init",
+                     "orc_fields_upload", "orc_fields_download", "orc_pressure_download", "orc_pressure_upload", "orc_init",
                      "orc_rebin", "orc_step", "orc_stats", "orc_node_sums", "orc_cell_means",
                      "orc_counters", "orc_bary", "orc_recover", "orc_set_stats", "orc_derive",
                      "orc_particles_init"):
@@ -303,6 +303,10 @@ class Oracle:
     def fields_upload(self, cs, F, freeze_mask=0):
         F = np.ascontiguousarray(F, dtype=np.float64)
         self._check(self._L.orc_fields_upload(self._c, cs, _dp(F), C.c_uint32(int(freeze_mask))), "fields_upload")
+
+    def pressure_upload(self, cs, P):
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        self._check(self._L.orc_pressure_upload(self._c, cs, _dp(P)), "pressure_upload")
 
     def fields(self, cs):
         mesh = self._cases[cs][0]

@@ -134,6 +134,9 @@ int orc_particles_download(orc_ctx* c, int32_t cs, orc_particles* p);
  * derivation, so the other slots see the derived values). */
 int orc_fields_upload(orc_ctx* c, int32_t cs, const double* F, uint32_t freeze_mask);
 int orc_fields_download(orc_ctx* c, int32_t cs, double* F);
+/* P: [n_nodes] mean pressure per raw node; sets <P> and the velocity
+ * correction -dt grad <P> that the next step applies (R-27) */
+int orc_pressure_upload(orc_ctx* c, int32_t cs, const double* P);
 int orc_pressure_download(orc_ctx* c, int32_t cs, double* P /*[n_nodes]*/);
 /* initialisation pass: statistics of the uploaded state, Eulerian fields
  * (except in mode 0), velocity bins and cell means */

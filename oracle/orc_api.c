@@ -15,7 +15,7 @@ static void case_free(ocase* cs)
     omesh_free(&cs->m);
     free(cs->x); free(cs->y); free(cs->u); free(cs->v); free(cs->w); free(cs->om); free(cs->wt);
     free(cs->psi); free(cs->elem); free(cs->id); free(cs->bin);
-    free(cs->F); free(cs->Ffrz); free(cs->stats); free(cs->sums); free(cs->cmean); free(cs->ccount); free(cs->P);
+    free(cs->F); free(cs->Ffrz); free(cs->stats); free(cs->sums); free(cs->cmean); free(cs->ccount); free(cs->P); free(cs->gphi);
     free(cs);
 }
 
@@ -62,6 +62,7 @@ int orc_add_case(orc_ctx* c, const orc_mesh_desc* m, const orc_params* p, int32_
     cs->cmean = orc_alloc(sizeof(double) * (size_t)ne * 8 * (ns > 0 ? ns : 1));
     cs->ccount = orc_alloc(sizeof(int32_t) * (size_t)ne * 8);
     cs->P = orc_alloc(sizeof(double) * nsn);
+    cs->gphi = orc_alloc(sizeof(double) * (size_t)nsn * 2);
     c->cases = realloc(c->cases, sizeof(ocase*) * (c->ncase + 1));
     c->cases[c->ncase] = cs;
     *case_id = c->ncase++;
@@ -133,6 +134,20 @@ int orc_fields_upload(orc_ctx* c, int32_t ci, const double* F, uint32_t freeze_m
         memcpy(cs->F + (size_t)s * ORC_NF, F + (size_t)cs->m.rep[s] * ORC_NF, sizeof(double) * ORC_NF);
     memcpy(cs->Ffrz, cs->F, sizeof(double) * (size_t)cs->m.nsn * ORC_NF);
     cs->freeze = freeze_mask;
+    return ORC_OK;
+}
+
+int orc_pressure_upload(orc_ctx* c, int32_t ci, const double* P)
+{
+    ocase* cs = get_case(c, ci);
+    if (!cs || !P) return orc_err(c, ORC_E_INVALID, "pressure_upload: bad argument");
+    const int nsn = cs->m.nsn;
+    for (int s = 0; s < nsn; ++s) cs->P[s] = P[cs->m.rep[s]];
+    double* gx = orc_alloc(sizeof(double) * nsn);
+    double* gy = orc_alloc(sizeof(double) * nsn);
+    orc_recover_grad(&cs->m, cs->P, gx, gy);
+    for (int s = 0; s < nsn; ++s) { cs->gphi[2 * (size_t)s] = gx[s]; cs->gphi[2 * (size_t)s + 1] = gy[s]; }
+    free(gx); free(gy);
     return ORC_OK;
 }
 

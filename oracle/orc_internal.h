@@ -54,6 +54,7 @@ typedef struct {
     double *cmean;   /* [ne*8*ns] */
     int32_t *ccount; /* [ne*8] */
     double *P;       /* mean pressure, per statistics node */
+    double *gphi;    /* [nsn*2] its recovered gradient: the velocity correction of the next step (R-27) */
     int have_stats;
     int64_t cnt[ORC_NCOUNT];
 } ocase;

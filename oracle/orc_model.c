@@ -74,9 +74,23 @@ static void advance_particle(ocase* cs, int64_t p, uint32_t n)
         }
     }
 
+    /* R-27: the projection of the last step corrects the velocity,
+     * U <- U - dt grad <P>(X), before the step uses it */
+    double u = cs->u[p], v = cs->v[p], w = cs->w[p];
+    {
+        /* zero unless a projection ran (mode 2) or a pressure was uploaded */
+        const int* sg = m->tri_s + 3 * e;
+        const double* g0 = cs->gphi + 2 * (size_t)sg[0];
+        const double* g1 = cs->gphi + 2 * (size_t)sg[1];
+        const double* g2 = cs->gphi + 2 * (size_t)sg[2];
+        double gx = fma(lam[2], g2[0], fma(lam[1], g1[0], lam[0] * g0[0]));
+        double gy = fma(lam[2], g2[1], fma(lam[1], g1[1], lam[0] * g0[1]));
+        u = u - dt * gx;
+        v = v - dt * gy;
+    }
+
     /* Eq.(4) with the generalized Langevin model; the dW_j of the viscous
      * term is the same increment as in Eq.(2) (R-01) */
-    double u = cs->u[p], v = cs->v[p], w = cs->w[p];
     double d1 = u - f[F_U1], d2 = v - f[F_U2], d3 = w - f[F_U3];
     double tnu = 2.0 * P->nu;
     double sq_nu = sqrt(tnu * dt);
@@ -430,7 +444,9 @@ int orc_derive_fields(orc_ctx* c, ocase* cs, int project)
         }
         free(wp); free(L2); free(r); free(dv); free(dm);
 
-        /* R-27: incremental pressure projection on the grid */
+        /* R-27: pressure projection on the grid (Chorin's, not incremental):
+         * <P> = phi with grad^2 phi = div <U> / dt; the particles take the
+         * correction -dt grad <P> at the start of the next step */
         if (rc == ORC_OK && project) {
             double* U1 = orc_alloc(sizeof(double) * nsn);
             double* U2 = orc_alloc(sizeof(double) * nsn);
@@ -440,13 +456,17 @@ int orc_derive_fields(orc_ctx* c, ocase* cs, int project)
             rc = orc_projection(m, U1, U2, P->dt, 1e-13, 100000, phi, &it);
             cs->cnt[CNT_CG_P] += it;
             if (rc) orc_err(c, rc, "pressure projection solve did not converge");
-            for (int s = 0; s < nsn; ++s) cs->P[s] += phi[s];
+            for (int s = 0; s < nsn; ++s) cs->P[s] = phi[s];
             free(U1); free(U2); free(phi);
         }
+        /* the predictor sees the driving gradient alone; the projection's
+         * gradient acts through the correction */
         orc_recover_grad(m, cs->P, gx, gy);
         for (int s = 0; s < nsn; ++s) {
-            cs->F[(size_t)s * ORC_NF + F_DPX] = P->dpdx[0] + gx[s];
-            cs->F[(size_t)s * ORC_NF + F_DPY] = P->dpdx[1] + gy[s];
+            cs->F[(size_t)s * ORC_NF + F_DPX] = P->dpdx[0];
+            cs->F[(size_t)s * ORC_NF + F_DPY] = P->dpdx[1];
+            cs->gphi[2 * (size_t)s] = gx[s];
+            cs->gphi[2 * (size_t)s + 1] = gy[s];
         }
     }
     free(kf); free(ef); free(tmp);

@@ -295,7 +295,7 @@ __global__ void k_proj_update(NodeArgs A)
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;
-    A.P[s] += A.phi[s];
+    A.P[s] = A.phi[s];     // R-27: the projection is not incremental
 }
 
 __global__ void k_proj_grad(NodeArgs A)
@@ -304,10 +304,14 @@ __global__ void k_proj_grad(NodeArgs A)
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;
+    // the predictor sees the driving gradient alone; the gradient of <P>
+    // corrects the particle velocities at the start of the next step
     double gx, gy;
     recover_grad(A, A.P, 1, s, gx, gy);
-    A.F[(int64_t)s * NF + F_DPX] = C.dpdx[0] + gx;
-    A.F[(int64_t)s * NF + F_DPY] = C.dpdx[1] + gy;
+    A.F[(int64_t)s * NF + F_DPX] = C.dpdx[0];
+    A.F[(int64_t)s * NF + F_DPY] = C.dpdx[1];
+    A.gphi[2 * (int64_t)s] = gx;
+    A.gphi[2 * (int64_t)s + 1] = gy;
 }
 
 // Field slots a case keeps frozen go back to their uploaded values after the
@@ -327,7 +331,8 @@ __global__ void k_fields_freeze(const CaseDev* __restrict__ cases, const int32_t
 // element e holds the fields of its vertex k, so that a particle reads its
 // element's three rows from one place right after its element id.
 template <typename R>
-__global__ void k_fields_elem(const double* __restrict__ F, const int4* __restrict__ tri_s, R* __restrict__ Fel, int ne)
+__global__ void k_fields_elem(const double* __restrict__ F, const double* __restrict__ gphi, const int4* __restrict__ tri_s,
+                              R* __restrict__ Fel, int ne)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)ne * 3 * NFE) return;
@@ -337,10 +342,10 @@ __global__ void k_fields_elem(const double* __restrict__ F, const int4* __restri
     const int k = (int)(r - e * 3);
     const int4 t = tri_s[e];
     const int s = k == 0 ? t.x : (k == 1 ? t.y : t.z);
-    Fel[i] = q < NF ? (R)F[(int64_t)s * NF + q] : R(0);
+    Fel[i] = q < NF ? (R)F[(int64_t)s * NF + q] : (R)gphi[2 * (int64_t)s + (q - FE_GPX)];
 }
-template __global__ void k_fields_elem<double>(const double*, const int4*, double*, int);
-template __global__ void k_fields_elem<float>(const double*, const int4*, float*, int);
+template __global__ void k_fields_elem<double>(const double*, const double*, const int4*, double*, int);
+template __global__ void k_fields_elem<float>(const double*, const double*, const int4*, float*, int);
 
 // ---------------------------------------------------------------- multigrid
 

@@ -275,7 +275,7 @@ struct pdfmc_ctx {
     char* d_cmean = nullptr;
     int32_t* d_ccnt = nullptr;
     double *d_kf = nullptr, *d_ef = nullptr, *d_L2 = nullptr, *d_er_r = nullptr, *d_er_dval = nullptr, *d_er_b = nullptr,
-           *d_er_x = nullptr, *d_er_val = nullptr, *d_pk_val = nullptr, *d_pb = nullptr, *d_phi = nullptr, *d_P = nullptr;
+           *d_er_x = nullptr, *d_er_val = nullptr, *d_pk_val = nullptr, *d_pb = nullptr, *d_phi = nullptr, *d_P = nullptr, *d_gphi = nullptr;
     // Eulerian solves: systems (relaxation first, then projection), their
     // vectors, accumulators and state; row-block tables of the phase kernels
     MgJob* d_mg_jobs = nullptr;
@@ -439,7 +439,7 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_er_r, (size_t)NER * c->NN); k.take(c->d_er_dval, (size_t)NER * c->NN);
     k.take(c->d_er_b, (size_t)NER * c->NN); k.take(c->d_er_x, (size_t)NER * c->NN);
     k.take(c->d_er_val, c->NELL); k.take(c->d_pk_val, c->NELL);
-    k.take(c->d_pb, c->NN); k.take(c->d_phi, c->NN); k.take(c->d_P, c->NN);
+    k.take(c->d_pb, c->NN); k.take(c->d_phi, c->NN); k.take(c->d_P, c->NN); k.take(c->d_gphi, 2 * (size_t)c->NN);
     k.take(c->d_mg_jobs, (NER + 1) * c->cases.size());
     k.take(c->d_mg_vec, c->MGV);
     k.take(c->d_mg_acc, (size_t)(NER + 1) * c->cases.size() * MG_NSLOT * MG_SLOT);
@@ -586,7 +586,7 @@ NodeArgs node_args(pdfmc_ctx* c)
     A.srec = c->d_srec; A.pool_off = c->pool_off; A.pool_stride = SC_HDR + SC_VMAX;
     A.ecnt = c->d_ecnt; A.eslot = c->d_eslot; A.eof = c->d_eof; A.eo = c->d_eo; A.wgcnt = c->d_wgcnt; A.etot = c->d_etot;
     A.kf = c->d_kf; A.ef = c->d_ef; A.L2 = c->d_L2; A.er_r = c->d_er_r; A.er_dval = c->d_er_dval; A.er_b = c->d_er_b;
-    A.er_x = c->d_er_x; A.er_val = c->d_er_val; A.pk_val = c->d_pk_val; A.pb = c->d_pb; A.phi = c->d_phi; A.P = c->d_P;
+    A.er_x = c->d_er_x; A.er_val = c->d_er_val; A.pk_val = c->d_pk_val; A.pb = c->d_pb; A.phi = c->d_phi; A.P = c->d_P; A.gphi = c->d_gphi;
     A.counters = c->d_counters;
     return A;
 }
@@ -956,10 +956,12 @@ pdfmc_status enqueue_fields_elem(pdfmc_ctx* c)
 {
     const dim3 g(nblk((int64_t)c->NE * 3 * NFE, 256)), b(256);
     if (c->prec == PDFMC_FP64)
-        hipLaunchKernelGGL(k_fields_elem<double>, g, b, 0, c->stream, (const double*)c->d_F, (const int4*)c->d_tri_s,
+        hipLaunchKernelGGL(k_fields_elem<double>, g, b, 0, c->stream, (const double*)c->d_F, (const double*)c->d_gphi,
+                           (const int4*)c->d_tri_s,
                            (double*)c->d_Fel, c->NE);
     else
-        hipLaunchKernelGGL(k_fields_elem<float>, g, b, 0, c->stream, (const double*)c->d_F, (const int4*)c->d_tri_s,
+        hipLaunchKernelGGL(k_fields_elem<float>, g, b, 0, c->stream, (const double*)c->d_F, (const double*)c->d_gphi,
+                           (const int4*)c->d_tri_s,
                            (float*)c->d_Fel, c->NE);
     LAUNCHCHK(c);
     return PDFMC_OK;
@@ -1499,6 +1501,7 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     TRY(enqueue_fill(c, c->d_er_x, (int64_t)NER * NN));
     TRY(enqueue_fill(c, c->d_phi, NN));
     TRY(enqueue_fill(c, c->d_P, NN));
+    TRY(enqueue_fill(c, c->d_gphi, 2 * (int64_t)NN));
     TRY(enqueue_fill(c, c->d_pb, NN));
     TRY(enqueue_fill(c, c->d_mg_vec, c->MGV));
     TRY(enqueue_fill(c, c->d_mg_acc, (int64_t)(NER + 1) * c->cases.size() * MG_NSLOT * MG_SLOT));

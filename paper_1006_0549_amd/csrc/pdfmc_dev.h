@@ -26,6 +26,9 @@ enum Field {
     F_G11, F_G12, F_G21, F_G22, F_G33,
     F_OMEGA, F_C0EPS, F_SOMEGA
 };
+// slots of the element-major copy past the fields: the recovered gradient of
+// the mean pressure, i.e. the velocity correction of the next step (R-27)
+constexpr int FE_GPX = 22, FE_GPY = 23;
 
 enum Counter {
     C_WALK_FALLBACK = 0, C_REFLECT, C_PERIODIC, C_OMEGA_FLIP, C_EMPTY_NODE, C_NAN,

@@ -39,7 +39,8 @@ struct NodeArgs {
     double* pk_val;                  // stiffness of the projection (ELL)
     double* pb;                      // [nn]
     double* phi;                     // [nn]
-    double* P;                       // [nn] mean pressure
+    double* P;                       // [nn] mean pressure (the last projection's phi)
+    double* gphi;                    // [nn][2] its recovered gradient (the next step's velocity correction)
     unsigned long long* counters;    // [ncase][NCNT]
     // scatter records of the particle kernel (see pdfmc_dev.h)
     const double* srec;
