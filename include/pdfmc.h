@@ -97,6 +97,11 @@ typedef struct {
                             2 A + B -> P on scalars 0, 1, 2 at the rate
                               k_0 psi_0 psi_1 (needs n_scalars >= 3)        */
     double k_react[PDFMC_MAX_SCALARS];  /* rate constants, finite and >= 0    */
+    int32_t rebin;       /* velocity bins of IECM, Eq.(9) (variant R-36 of R-23):
+                            0 formed against the fields of the step that moved
+                            the particle; 1 formed again, with the cell means,
+                            against the new fields at the end of the step (one
+                            more particle pass per step)                    */
 } pdfmc_case_params;
 
 /* Particle ensemble on the host, structure of arrays, always FP64 here (the

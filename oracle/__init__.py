@@ -64,7 +64,7 @@ class _Params(C.Structure):
                 ("k_floor", C.c_double), ("eps_floor", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
                 ("seed", C.c_uint64), ("stream", C.c_uint32), ("n_eff_min", C.c_double),
-                ("reaction", C.c_int32), ("k_react", C.c_double * 4)]
+                ("reaction", C.c_int32), ("k_react", C.c_double * 4), ("rebin", C.c_int32)]
 
 
 class _InitParams(C.Structure):
@@ -207,11 +207,12 @@ def _mesh_struct(mesh):
 def _params_struct(p):
     s = _Params()
     for name, _ in _Params._fields_:
-        if name in ("dpdx", "src", "reaction", "k_react"):
+        if name in ("dpdx", "src", "reaction", "k_react", "rebin"):
             continue
         setattr(s, name, p[name])
     s.dpdx[0], s.dpdx[1] = p["dpdx"]
     s.reaction = int(p.get("reaction", 0))
+    s.rebin = int(p.get("rebin", 0))
     kr = list(p.get("k_react", ()))
     for a in range(4):
         s.k_react[a] = float(kr[a]) if a < len(kr) else 0.0

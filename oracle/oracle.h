@@ -88,6 +88,8 @@ typedef struct {
                             2 A + B -> P on scalars 0, 1, 2 at the rate
                               k_0 psi_0 psi_1 (further scalars inert) */
     double k_react[ORC_MAXS];   /* rate constants, >= 0 */
+    int32_t rebin;       /* R-36: 1 = the velocity bins and cell means are formed
+                            again against the new fields at the end of a step */
 } orc_params;
 
 typedef struct {

@@ -45,6 +45,7 @@ int orc_add_case(orc_ctx* c, const orc_mesh_desc* m, const orc_params* p, int32_
     if (!(p->dt > 0.0) || !(p->nu >= 0.0)) return orc_err(c, ORC_E_INVALID, "add_case: dt must be > 0, nu >= 0");
     if (!(p->n_eff_min >= 0.0)) return orc_err(c, ORC_E_INVALID, "add_case: n_eff_min must be >= 0");
     if (p->reaction < 0 || p->reaction > 2) return orc_err(c, ORC_E_INVALID, "add_case: reaction must be 0, 1 or 2");
+    if (p->rebin < 0 || p->rebin > 1) return orc_err(c, ORC_E_INVALID, "add_case: rebin must be 0 or 1");
     if (p->reaction == 2 && p->n_scalars < 3)
         return orc_err(c, ORC_E_INVALID, "add_case: reaction 2 (A + B -> P) needs at least 3 scalars");
     for (int a = 0; a < ORC_MAXS; ++a)

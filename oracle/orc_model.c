@@ -490,5 +490,8 @@ int orc_case_step(orc_ctx* c, ocase* cs, uint32_t n)
     for (int64_t p = 0; p < cs->np; ++p) advance_particle(cs, p, n);
     orc_node_moments(cs);
     orc_case_rebin(cs);              /* bins against F^n, the fields of this step */
-    return orc_derive_fields(c, cs, 1);
+    int rc = orc_derive_fields(c, cs, 1);
+    /* R-36: bins and cell means against F^{n+1}, the fields the next step uses */
+    if (rc == ORC_OK && cs->p.rebin) orc_case_rebin(cs);
+    return rc;
 }

@@ -201,6 +201,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int tile = __builtin_amdgcn_readfirstlane((int)(gid / TILE));
     const int c = __builtin_amdgcn_readfirstlane(A.tile_case[tile < A.ntiles ? tile : A.ntiles - 1]);
     const CaseDev& C = A.cases[c];
+    // a rebinning pass skips the cases that keep the bins of their step: the
+    // whole workgroup leaves (one case per workgroup), with no records
+    if (A.rebin_only && !C.rebin) {
+        if (threadIdx.x == 0) A.wgcnt[blockIdx.x] = 0;
+        return;
+    }
     const int64_t i = gid - C.poff;
     const bool valid = tile < A.ntiles && (i >= 0) && (i < C.np);
     const int64_t p = gid;

@@ -71,7 +71,7 @@ __global__ void k_scatter_register(NodeArgs A, int ntiles, int block, const int3
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__ cmean, int cells_on)
+__global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__ cmean, int cells_on, int rebin_only)
 {
     __shared__ double s_cell[4][8 * (2 + MAXS)];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -79,6 +79,7 @@ __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__
     if (e >= A.ne) return;            // whole wavefronts leave together
     const int c = A.elem_case[e];
     const CaseDev& C = A.cases[c];
+    if (rebin_only && !C.rebin) return;   // a case that keeps the bins of its step (no records this pass)
     const int ns = C.ns, nq = 12 + 2 * ns, nc = 2 + ns;
     const bool cells = cells_on && ns > 0;
     const int nv = sc_nvals(ns, cells);
@@ -165,8 +166,8 @@ __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__
         cmean[C.cmoff + ((int64_t)(e - C.eoff) * 8 + b) * ns + a] = (R)m;
     }
 }
-template __global__ void k_elem_reduce<double>(NodeArgs, double*, int);
-template __global__ void k_elem_reduce<float>(NodeArgs, float*, int);
+template __global__ void k_elem_reduce<double>(NodeArgs, double*, int, int);
+template __global__ void k_elem_reduce<float>(NodeArgs, float*, int, int);
 
 __global__ void k_node_reduce(NodeArgs A)
 {

@@ -317,7 +317,7 @@ struct pdfmc_ctx {
     hipStream_t side = nullptr;                  // the sort's stream, beside the fields phase
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint32_t graph_stages = PDFMC_STAGE_ALL;   // stages of the captured graphs
-    bool any_er = false, any_eul = false, any_scalars = false;
+    bool any_er = false, any_eul = false, any_scalars = false, any_rebin = false;
     bool any_freeze = false;        // some case keeps field slots frozen
     // multigrid data: flat int/double regions, hierarchy descriptors,
     // Galerkin jobs of the relaxation hierarchies per level, per-job vectors
@@ -558,6 +558,7 @@ CaseDev make_case_dev(const pdfmc_ctx* c, const Case& cs)
     d.k_floor = p.k_floor; d.eps_floor = p.eps_floor; d.dpdx[0] = p.dpdx[0]; d.dpdx[1] = p.dpdx[1];
     d.cg_rtol = p.cg_rtol; d.cg_maxit = p.cg_maxit; d.neff_min = p.n_eff_min;
     d.reaction = p.reaction;
+    d.rebin = p.rebin;
     d.rec_off = cs.rec_off; d.rec_stride = cs.rec_stride; d.freeze = cs.freeze;
     for (int a = 0; a < MAXS; ++a) { d.kr[a] = p.k_react[a]; d.fkr[a] = (float)p.k_react[a]; }
     (void)c;
@@ -592,7 +593,7 @@ NodeArgs node_args(pdfmc_ctx* c)
 }
 
 template <typename R>
-StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins, int scatter)
+StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins, int scatter, int rebin_only)
 {
     StepArgs<R> A{};
     PartBufs& B = c->part[c->cur];
@@ -605,7 +606,7 @@ StepArgs<R> step_args(pdfmc_ctx* c, int advance, int do_bins, int scatter)
     A.srec = c->d_srec; A.pool_off = c->pool_off; A.pool_stride = SC_HDR + SC_VMAX; A.pool_cap = c->pool_cap;
     A.pool_cnt = c->d_pool_cnt; A.wgcnt = c->d_wgcnt; A.eof = c->d_eof; A.eo = c->d_eo;
     A.counters = c->d_counters; A.step = c->d_step;
-    A.ntiles = c->ntiles; A.advance = advance; A.do_bins = do_bins; A.scatter = scatter;
+    A.ntiles = c->ntiles; A.advance = advance; A.do_bins = do_bins; A.scatter = scatter; A.rebin_only = rebin_only;
     return A;
 }
 
@@ -630,7 +631,8 @@ pdfmc_status enqueue_fill_i(pdfmc_ctx* c, int32_t* p, int64_t n)
 // advance: move the particles; do_bins: velocity bins and cell means;
 // scatter: the records and their sums; node_stats: the node statistics from
 // those sums (a re-binning pass leaves them as they are).
-pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins, int scatter, bool node_stats)
+pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins, int scatter, bool node_stats,
+                               int rebin_only = 0)
 {
     if (c->ntiles == 0) return PDFMC_OK;
     const int64_t threads = (int64_t)c->ntiles * TILE;
@@ -646,10 +648,10 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins, int scatt
     }
     if (c->prec == PDFMC_FP64)
         hipLaunchKernelGGL(k_particle_step<double>, dim3(nblk(threads, b)), dim3(b), 0, c->stream,
-                           step_args<double>(c, advance, do_bins, scatter));
+                           step_args<double>(c, advance, do_bins, scatter, rebin_only));
     else
         hipLaunchKernelGGL(k_particle_step<float>, dim3(nblk(threads, b)), dim3(b), 0, c->stream,
-                           step_args<float>(c, advance, do_bins, scatter));
+                           step_args<float>(c, advance, do_bins, scatter, rebin_only));
     LAUNCHCHK(c);
     if (timed) {
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
@@ -664,10 +666,10 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins, int scatt
                        c->pool_cap, c->d_counters, do_bins);
     if (c->prec == PDFMC_FP64)
         hipLaunchKernelGGL(k_elem_reduce<double>, dim3(nblk(c->NE, 4)), dim3(256), 0, c->stream, N,
-                           (double*)c->d_cmean, do_bins);
+                           (double*)c->d_cmean, do_bins, rebin_only);
     else
         hipLaunchKernelGGL(k_elem_reduce<float>, dim3(nblk(c->NE, 4)), dim3(256), 0, c->stream, N,
-                           (float*)c->d_cmean, do_bins);
+                           (float*)c->d_cmean, do_bins, rebin_only);
     if (node_stats) hipLaunchKernelGGL(k_node_reduce, dim3(nblk(c->NN, 256)), dim3(256), 0, c->stream, N);
     LAUNCHCHK(c);
     return PDFMC_OK;
@@ -1067,6 +1069,13 @@ pdfmc_status enqueue_step_body(pdfmc_ctx* c, uint32_t stages, bool sort_after)
     }
     if (stages & PDFMC_STAGE_FIELDS) TRY(enqueue_fields(c, true));
     if (sort_after) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    // R-36: the cases that form their bins and cell means again against the
+    // new fields (a statistics-free particle pass over their tiles); after the
+    // sort has joined, since both use the particle arrays and the record region
+    if ((stages & PDFMC_STAGE_FIELDS) && c->any_rebin) {
+        TRY(enqueue_accum_clear(c));
+        TRY(enqueue_particles(c, 0, 1, 1, false, 1));
+    }
     hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, c->stream, c->d_step);
     LAUNCHCHK(c);
     return PDFMC_OK;
@@ -1185,6 +1194,7 @@ pdfmc_status pdfmc_add_case(pdfmc_ctx* c, const pdfmc_mesh_desc* mesh, const pdf
     if (!(p->dt > 0.0) || !(p->nu >= 0.0)) return fail(c, PDFMC_E_INVALID, "add_case: need dt > 0 and nu >= 0");
     if (!(p->n_eff_min >= 0.0)) return fail(c, PDFMC_E_INVALID, "add_case: n_eff_min must be >= 0");
     if (p->reaction < 0 || p->reaction > 2) return fail(c, PDFMC_E_INVALID, "add_case: reaction must be 0, 1 or 2");
+    if (p->rebin < 0 || p->rebin > 1) return fail(c, PDFMC_E_INVALID, "add_case: rebin must be 0 or 1");
     if (p->reaction == 2 && p->n_scalars < 3)
         return fail(c, PDFMC_E_INVALID, "add_case: reaction 2 (A + B -> P) needs at least 3 scalars");
     for (int a = 0; a < PDFMC_MAX_SCALARS; ++a)
@@ -1260,8 +1270,9 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     carve(c, k);
     drop_graphs(c);
     c->ws = (char*)dev; c->ws_bytes = bytes; c->cur = 0;
-    c->any_er = c->any_eul = c->any_scalars = false;
+    c->any_er = c->any_eul = c->any_scalars = c->any_rebin = false;
     for (auto& cs : c->cases) {
+        c->any_rebin |= cs.p.rebin != 0;
         c->any_er |= cs.p.mode == 2;
         c->any_eul |= cs.p.mode >= 1;
         c->any_scalars |= cs.p.n_scalars > 0;

@@ -85,6 +85,7 @@ struct CaseDev {
     double cg_rtol;
     double neff_min;           // least effective sample size of a node estimate
     int32_t cg_maxit, reaction;  // reaction: closed scalar source kind (0, 1, 2)
+    int32_t rebin;             // bins and cell means formed again at the end of a step (R-36)
     double kr[MAXS];           // reaction rate constants
     float fkr[MAXS];
     int64_t rec_off;           // scatter records of the case at srec + rec_off (doubles)
@@ -131,6 +132,7 @@ struct StepArgs {
     int32_t ntiles;
     int32_t advance;              // 1: advance then statistics; 0: statistics only
     int32_t do_bins;              // 1: bins + cell sums
+    int32_t rebin_only;           // 1: only the cases with the end-of-step rebinning take part
     int32_t scatter;              // 1: statistics records of the new state; 0: none
 };
 

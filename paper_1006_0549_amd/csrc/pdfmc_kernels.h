@@ -15,7 +15,7 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v);
 __global__ void k_step_increment(uint32_t* step);
 __global__ void k_scatter_register(NodeArgs A, int ntiles, int block, const int32_t* tile_case, const int32_t* pool_cnt,
                                    int pool_cap, unsigned long long* counters, int cells_on);
-template <typename R> __global__ void k_elem_reduce(NodeArgs A, R* cmean, int cells_on);
+template <typename R> __global__ void k_elem_reduce(NodeArgs A, R* cmean, int cells_on, int rebin_only);
 __global__ void k_node_reduce(NodeArgs A);
 __global__ void k_fields_grad(NodeArgs A);
 __global__ void k_fields_derived(NodeArgs A);

@@ -49,7 +49,7 @@ class _CaseParams(C.Structure):
                 ("n_min", C.c_int32), ("src", (C.c_double * 4) * 4), ("k_floor", C.c_double),
                 ("eps_floor", C.c_double), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
                 ("seed", C.c_uint64), ("stream", C.c_uint32), ("n_eff_min", C.c_double),
-                ("reaction", C.c_int32), ("k_react", C.c_double * 4)]
+                ("reaction", C.c_int32), ("k_react", C.c_double * 4), ("rebin", C.c_int32)]
 
 
 class _TuneResult(C.Structure):
@@ -184,10 +184,11 @@ class Sim:
                        len(mesh.bcs), bcs)
         p = _CaseParams()
         for name, _ in _CaseParams._fields_:
-            if name not in ("dpdx", "src", "reaction", "k_react"):
+            if name not in ("dpdx", "src", "reaction", "k_react", "rebin"):
                 setattr(p, name, params[name])
         p.dpdx[0], p.dpdx[1] = params["dpdx"]
         p.reaction = int(params.get("reaction", 0))
+        p.rebin = int(params.get("rebin", 0))
         kr = list(params.get("k_react", ()))
         for a in range(4):
             p.k_react[a] = float(kr[a]) if a < len(kr) else 0.0

@@ -538,3 +538,58 @@ def test_row_parallel_phases_match_one_workgroup_completion(P):
     assert abs(ca["cg_iters_er"] - cb["cg_iters_er"]) <= 5 * 4, (ca["cg_iters_er"], cb["cg_iters_er"])
     sc = np.maximum(np.abs(Fb).max(0), 1e-12)
     assert np.max(np.abs(Fa - Fb) / sc) <= 1e-8
+
+
+def test_rebin_variant_follows_the_oracle(P, oracle_mod):
+    """R-36 (bins and cell means formed again against the new fields at the
+    end of each step), mode 1 on the small square with its scalar. The fields
+    come from the statistics, whose summation order differs from the
+    oracle's, so the comparison is to the bars of the other mode-1 runs:
+    after one step the state to 1e-12 and the bins and cell counts equal
+    (a bin flips only for |U - <U>| at rounding level), after 50 steps the
+    statistics to 1e-9. In one context with a case that keeps the bins of its
+    step, each case gives the same bits as alone (the rebinning pass skips
+    the other case's tiles and elements)."""
+    cfg = W.config_small()
+    params = dict(cfg["params"], rebin=1)
+    parts = cfg["particles"]
+    n = len(parts["x"])
+    _flush(f"[rebin] small square, {n} particles, bins formed again at the end of each step")
+    sim, cs, o, oc = _pair(P, oracle_mod, cfg["mesh"], params, parts)
+    sim.init(); o.init()
+    sim.step(1); o.step(1)
+    g, r = sim.download(cs, n), o.download(oc, n)
+    assert np.array_equal(g["elem"], r["elem"])
+    for k in ("x", "y", "u", "v", "w", "omega"):
+        assert np.abs(g[k] - r[k]).max() <= 1e-12 * np.abs(r[k]).max(), k
+    assert np.array_equal(g["bin"], r["bin"])
+    gm, gc = sim.cell_means(cs)
+    rm, rc = o.cell_means(oc)
+    assert np.array_equal(gc, rc)
+    np.testing.assert_allclose(gm, rm, rtol=1e-10, atol=1e-12)
+    # the variant's bins are those of the new fields: they differ from the bins formed in the step
+    sim.step(49); o.step(49)
+    rows = _stat_rows(sim, cs)
+    gst, rst = sim.stats(cs), o.stats(oc)
+    d = np.abs(gst - rst)[rows] / _scale(rst, 1)[rows]
+    assert d.max() <= 1e-9, (d.max(), np.unravel_index(np.argmax(d), d.shape))
+    # mixed with a case that keeps the bins of its step
+    other = W.unit_square(10, 0.2, periodic_x=True, seed_key=(8, 0, 0))
+    op = W.default_params(mode=1, n_scalars=2, dt=1e-3, nu=1e-3, stream=4, src=[(0.3, 0.3, 0.1, 1.0), (0.7, 0.6, 0.1, 1.0)])
+    oparts = W.init_particles(other, 40, 2, W.rng_for(8, 0, 1), u_std=0.1)
+    runs = []
+    for group in ([(cfg["mesh"], params, parts), (other, op, oparts)], [(cfg["mesh"], params, parts)], [(other, op, oparts)]):
+        s2 = P.Sim("fp64", "cuda:0")
+        ids = [s2.add_case(m, p_, len(q["x"])) for m, p_, q in group]
+        s2.bind()
+        s2.set_options(sort_interval=3, use_graph=True)
+        for i_, (m, p_, q) in zip(ids, group):
+            s2.upload(i_, q)
+        s2.init()
+        s2.step(8)
+        runs.append([(s2.download(i_, len(q["x"])), s2.cell_means(i_), s2.stats(i_)) for i_, (m, p_, q) in zip(ids, group)])
+    for both, alone in ((runs[0][0], runs[1][0]), (runs[0][1], runs[2][0])):
+        for k in both[0]:
+            assert np.array_equal(both[0][k], alone[0][k]), k
+        assert np.array_equal(both[1][0], alone[1][0]) and np.array_equal(both[1][1], alone[1][1])
+        assert np.array_equal(both[2], alone[2])

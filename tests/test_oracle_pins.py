@@ -486,3 +486,41 @@ def test_freezing_every_slot_is_the_frozen_field_mode(oracle_mod):
     assert not np.array_equal(f[:, 0], F[:, 0])
     with pytest.raises(RuntimeError, match="fields_upload"):
         o.fields_upload(cs, F, freeze_mask=1 << 22)
+
+
+def test_rebin_variant_is_one_more_rebinning(oracle_mod):
+    """R-36 (a variant of R-23): forming the bins and cell means again
+    against the new fields at the end of each step. With frozen fields
+    (mode 0) the new fields are the old ones, so the variant changes
+    nothing, bit for bit; with fields from the statistics (mode 1) one
+    variant step equals a plain step followed by an explicit rebinning."""
+    mesh = W.unit_square(8, 0.2, periodic_x=True, seed_key=(6, 1, 0))
+    parts = W.init_particles(mesh, 20, 1, W.rng_for(6, 1, 1), u_std=0.1, psi_disks=[(0.5, 0.5, 0.2, 1.0)])
+    n = len(parts["x"])
+    F = W.frozen_fields(mesh, C0=2.1, omega=1.5, k=0.01)
+
+    def run(mode, rebin, steps, extra_rebin=False):
+        o = oracle_mod.Oracle()
+        cs = o.add_case(mesh, W.default_params(mode=mode, n_scalars=1, dt=1e-3, nu=1e-3, rebin=rebin))
+        o.fields_upload(cs, F)
+        o.upload(cs, parts)
+        o.init()
+        for _ in range(steps):
+            o.step(1)
+            if extra_rebin:
+                o.rebin()
+        m, cnt = o.cell_means(cs)
+        return o.download(cs, n), m, cnt, o.stats(cs)
+
+    a, b = run(0, 0, 10), run(0, 1, 10)
+    for x, y in zip(a, b):
+        if isinstance(x, dict):
+            for k in x:
+                assert np.array_equal(x[k], y[k]), k
+        else:
+            assert np.array_equal(x, y)
+    plain, variant, explicit = run(1, 0, 3), run(1, 1, 3), run(1, 0, 3, extra_rebin=True)
+    assert not np.array_equal(plain[0]["bin"], variant[0]["bin"])
+    for k in ("x", "y", "u", "v", "w", "omega", "psi", "elem", "bin"):
+        assert np.array_equal(variant[0][k], explicit[0][k]), k
+    assert np.array_equal(variant[1], explicit[1]) and np.array_equal(variant[2], explicit[2])

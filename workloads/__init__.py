@@ -305,7 +305,8 @@ def default_params(**over) -> dict:
              C1=1.85, C2=0.63, gamma5=0.1, Cv=1.4, CL=0.134, Ceta=72.0,
              dpdx=(-1.0, 0.0), n_scalars=1, n_bins=8, n_min=4, src=[],
              k_floor=1e-12, eps_floor=1e-12, cg_rtol=1e-10, cg_maxit=2000,
-             seed=PROJECT_SEED, stream=0, n_eff_min=8.0, reaction=0, k_react=(0.0, 0.0, 0.0, 0.0))
+             seed=PROJECT_SEED, stream=0, n_eff_min=8.0, reaction=0, k_react=(0.0, 0.0, 0.0, 0.0),
+             rebin=0)
     p.update(over)
     return p
 
