@@ -86,7 +86,8 @@ def measured_traffic(workload_name, prec):
 
 def algorithmic_bytes(prec, cases, nsn):
     """Bytes the particle kernel must move per launch: every particle's state
-    read and written once, the node fields read and node sums written once,
+    read and written once, the node fields (with the projection's gradient)
+    read and node sums written once,
     element records and cell tables read/written once."""
     R = 4 if prec == "fp32" else 8
     total, npart = 0, 0
@@ -95,7 +96,7 @@ def algorithmic_bytes(prec, cases, nsn):
         n = len(c["particles"]["x"])
         ne = c["mesh"].n_elems
         per_particle = (7 * R + ns * R + 4 + 4 + 1) + (6 * R + ns * R + 4 + 1)
-        per_node = 22 * R + 8 * (11 + 2 * ns)
+        per_node = 24 * R + 8 * (11 + 2 * ns)      # 22 fields + the velocity correction's 2
         per_elem = 8 * R + 12 + (8 * ns * R + 8 * (1 + ns) * 8 + 8 * 4 if ns else 0)
         total += n * per_particle + nn * per_node + ne * per_elem
         npart += n

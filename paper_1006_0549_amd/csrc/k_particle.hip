@@ -230,6 +230,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int a = 0; a < ns; ++a) psi[a] = A.P.psi[C.psioff + (int64_t)a * C.cap + i];
         bary<R>(A.M.rec, e, x, y, lam);
         if (A.advance) {
+            {
+                // R-27: the last projection corrects the velocity, U <- U - dt grad <P>(X),
+                // before the step uses it (zero without a projection)
+                const R* G0 = A.Fel + (int64_t)e * 3 * NFE;
+                const R gpx = rfma<R>(lam[2], G0[2 * NFE + FE_GPX], rfma<R>(lam[1], G0[NFE + FE_GPX], lam[0] * G0[FE_GPX]));
+                const R gpy = rfma<R>(lam[2], G0[2 * NFE + FE_GPY], rfma<R>(lam[1], G0[NFE + FE_GPY], lam[0] * G0[FE_GPY]));
+                R dtc;
+                if constexpr (sizeof(R) == 8) dtc = C.dt; else dtc = C.fdt;
+                u3[0] = u3[0] - dtc * gpx;
+                u3[1] = u3[1] - dtc * gpy;
+            }
+            // the element's field rows are not loaded above this point: loaded
+            // together with the correction's, the FP32 kernel's registers
+            // spilled (no spill, about 1% faster)
+            __builtin_amdgcn_sched_barrier(0);
             const int4 nbe = A.M.nbr[e];
             // Wiener increments first: they need only the particle's id, so
             // their arithmetic overlaps the loads of the element's tables
@@ -254,16 +269,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
                 for (int q = 0; q < NF; ++q) f[q] = rfma<R>(lam[2], F2[q], f[q]);
                 om_n[2] = F2[F_OMEGA];
-                // R-27: the last projection corrects the velocity, U <- U - dt grad <P>(X),
-                // before the step uses it (zero without a projection)
-                {
-                    const R gpx = rfma<R>(lam[2], F2[FE_GPX], rfma<R>(lam[1], F1[FE_GPX], lam[0] * F0[FE_GPX]));
-                    const R gpy = rfma<R>(lam[2], F2[FE_GPY], rfma<R>(lam[1], F1[FE_GPY], lam[0] * F0[FE_GPY]));
-                    R dtc;
-                    if constexpr (sizeof(R) == 8) dtc = C.dt; else dtc = C.fdt;
-                    u3[0] = u3[0] - dtc * gpx;
-                    u3[1] = u3[1] - dtc * gpy;
-                }
                 // Eq.(9) IECM with the cell means of this state (R-23, R-24),
                 // plus the closed reaction source on the composition before
                 // the step (R-35)
