@@ -623,7 +623,6 @@ __global__ void __launch_bounds__(MGB) k_mg_setup1(const MgJob* __restrict__ job
 {
     const int4 e = tab[blockIdx.x];
     const MgJob& J = jobs[e.x];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *J.need = 0u;
 #define SETUP1(NV) setup1_body<NV>(J, e.y)
     MG_DISPATCH(J, SETUP1);
 #undef SETUP1

@@ -910,8 +910,11 @@ pdfmc_status mg_after_step(pdfmc_ctx* c)
     // k_mg_finish)
     if (++c->need_tick < NEED_EVERY) return PDFMC_OK;
     c->need_tick = 0;
+    // the counter holds the largest count of the steps since the last
+    // readback (the solves only raise it); it restarts after the copy
     HIPCHK(c, hipMemcpyAsync(c->h_need, c->d_mg_need, sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipEventRecord(c->need_ev, c->stream));
+    TRY(enqueue_fill_i(c, (int32_t*)c->d_mg_need, 1));
     c->need_pending = true;
     return PDFMC_OK;
 }
@@ -921,16 +924,16 @@ void mg_adapt(pdfmc_ctx* c)
     if (!c->mg_auto || !c->need_pending) return;
     if (hipEventQuery(c->need_ev) != hipSuccess) return;
     c->need_pending = false;
-    const int need = (int)*c->h_need;
+    const int need = (int)*c->h_need;     // the largest of the last NEED_EVERY steps
     // the one-workgroup completion is many times slower per iteration than
-    // the phases, so keep a margin above what was needed
-    const int margin = std::max(4, need / 6);
+    // the phases, so keep a margin above what the window needed
+    const int margin = std::max(2, need / 8);
     int want = c->mg_iters;
     if (need + 1 > c->mg_iters) {
         want = need + margin;
         c->need_low = 0;
     } else if (need + 2 * margin < c->mg_iters) {
-        // two low readings in a row (16 steps) before unrolling fewer
+        // two low readings in a row (two windows) before unrolling fewer
         if (++c->need_low >= 2) { want = need + margin; c->need_low = 0; }
     } else {
         c->need_low = 0;

@@ -100,7 +100,8 @@ struct GalJob {
 // One linear system on the rows of one case; every pointer is offset to the
 // case's first row (local indices). Preconditioned CG whose iterations are
 // split into phases; scalars are accumulated per iteration in rotating slots.
-constexpr int MG_SLOT = 8;         // doubles per accumulator slot
+constexpr int MG_SLOT = 32;        // doubles per accumulator slot: 256 B, so that the atomic adds of
+                                   // many workgroups to different columns meet on different lines
 constexpr int MG_NSLOT = 5;        // 4 iteration slots + 1 set-up slot
 struct MgJob {
     int32_t hier;                  // index of the hierarchy
@@ -123,7 +124,7 @@ struct MgJob {
     int32_t* state;                // [0] converged, [1] iteration count
     unsigned long long* iters;
     unsigned long long* fails;
-    unsigned int* need;            // largest iteration count of the step (all systems)
+    unsigned int* need;            // largest iteration count since the host last read it (all systems)
 };
 
 // One supernode of a case's projection factor (nested-dissection Cholesky of
