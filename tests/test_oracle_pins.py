@@ -524,3 +524,57 @@ def test_rebin_variant_is_one_more_rebinning(oracle_mod):
     for k in ("x", "y", "u", "v", "w", "omega", "psi", "elem", "bin"):
         assert np.array_equal(variant[0][k], explicit[0][k]), k
     assert np.array_equal(variant[1], explicit[1]) and np.array_equal(variant[2], explicit[2])
+
+
+# ------------------------------------------------------------ Taylor's dispersion (Sec. III.A)
+
+def test_taylor_absolute_dispersion(oracle_mod):
+    """Homogeneous frozen fields on a periodic box (SLM drift G_ii =
+    -(1/2 + 3/4 C0) omega, C0 eps set for a stationary velocity variance
+    sig2, uniform <U_1> = 1): every particle's cross-stream displacement
+    follows the discrete Ornstein-Uhlenbeck form of Taylor's absolute
+    dispersion (tests/taylor_dispersion.py), and its streamwise displacement
+    has the mean <U_1> t. A wrong sign or factor in the drift, the diffusion
+    C0 eps dt, the position's (2 nu dt)^{1/2} or the velocity used in Eq.(2)
+    shifts the variance by more than the band; the band is three standard
+    errors of a variance estimate, (2/N)^{1/2}."""
+    from taylor_dispersion import discrete_variance, stationary_c0eps, taylor_variance
+    mesh = W.unit_square(24, 0.2, periodic_x=True, periodic_y=True, seed_key=(5, 0, 0))
+    omega, C0, dt, nu, sig2, U0 = 4.0, 2.1, 1e-3, 1e-3, 0.25, 1.0
+    G = -(0.5 + 0.75 * C0) * omega
+    params = W.default_params(mode=0, dt=dt, nu=nu, n_scalars=0, dpdx=(0.0, 0.0), stream=11)
+    F = W.frozen_fields(mesh, C0=C0, omega=omega, dpdx=(0.0, 0.0))
+    F[:, F_U1] = U0
+    F[:, F_C0EPS] = stationary_c0eps(G, dt, sig2)
+    parts = W.init_particles(mesh, 10, 0, W.rng_for(5, 0, 1), u_std=math.sqrt(sig2))
+    parts["u"] = parts["u"] + U0
+    n = len(parts["x"])
+    o = oracle_mod.Oracle()
+    cs = o.add_case(mesh, params)
+    o.fields_upload(cs, F)
+    o.upload(cs, parts)
+    o.init()
+    prev = o.download(cs, n)
+    X = np.zeros(n)
+    Y = np.zeros(n)
+    done = 0
+    tol = 3.0 * math.sqrt(2.0 / n)
+    for check in (60, 120, 240, 360):
+        while done < check:
+            o.step(30)
+            done += 30
+            cur = o.download(cs, n)
+            a, b = np.argsort(cur["id"]), np.argsort(prev["id"])
+            dx = cur["x"][a] - prev["x"][b]
+            dy = cur["y"][a] - prev["y"][b]
+            X += dx - np.round(dx)          # unwrap the periodic shifts (box of side 1)
+            Y += dy - np.round(dy)
+            prev = cur
+        want = discrete_variance(done, dt, G, sig2, nu)
+        got = float(np.mean(Y * Y) - np.mean(Y) ** 2)
+        assert abs(got / want - 1.0) < tol, (done, got, want)
+        # the continuous formula is the dt -> 0 limit: O(|G| dt) apart
+        t = done * dt
+        assert abs(taylor_variance(t, -1.0 / G, sig2, nu) / want - 1.0) < 2.0 * abs(G) * dt
+        sx = math.sqrt(float(np.var(X)) / n)
+        assert abs(float(np.mean(X)) - U0 * t) < 4.0 * sx + 1e-12, (done, np.mean(X), U0 * t)
