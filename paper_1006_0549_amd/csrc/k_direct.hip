@@ -6,7 +6,10 @@
 // root down give the solution, which is finally made mean-free.
 //
 // Forward, supernode S: y_S = L11^-1 b_S; b_R -= L21 y_S for the later
-// unknowns R it reaches (FP64 atomics: siblings reach common ancestors).
+// unknowns R it reaches. Siblings reach common ancestors, so S stores its
+// updates L21 y_S in a slot of its own, and an ancestor subtracts the updates
+// of its unknowns, in supernode order, when it loads b: the same bits on
+// every run and in any batch.
 // Backward: x_S = L11^-T (y_S - L21^T x_R), the x_R final from higher sweeps.
 #include "pdfmc_kernels.h"
 
@@ -65,7 +68,7 @@ __global__ void __launch_bounds__(1024) k_ds_post(const DsCase* __restrict__ cs,
 template <int DSB, int CAP>
 __global__ void __launch_bounds__(DSB) k_ds_forward(const DsNode* __restrict__ nodes, const int32_t* __restrict__ list,
                                                     const int32_t* __restrict__ idx, const double* __restrict__ val,
-                                                    double* __restrict__ x)
+                                                    double* __restrict__ x, DsUpd U)
 {
     const DsNode N = nodes[list[blockIdx.x]];
     const int s = N.s, m = N.m;
@@ -73,7 +76,12 @@ __global__ void __launch_bounds__(DSB) k_ds_forward(const DsNode* __restrict__ n
     const double* Li = val + N.val;
     const double* L21 = Li + (int64_t)s * s;
     __shared__ double bs[CAP], ys[CAP];
-    for (int t = threadIdx.x; t < s; t += DSB) bs[t] = x[vi[t]];
+    for (int t = threadIdx.x; t < s; t += DSB) {
+        const int u = vi[t];
+        double b = x[u];
+        for (int q = U.cptr[u]; q < U.cptr[u + 1]; ++q) b -= U.contrib[U.clist[q]];
+        bs[t] = b;
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     constexpr int NWV = DSB / 64;
@@ -93,7 +101,7 @@ __global__ void __launch_bounds__(DSB) k_ds_forward(const DsNode* __restrict__ n
         double a = 0.0;
         for (int j = lane; j < s; j += 64) a += row[j] * ys[j];
         a = wave_sum(a);
-        if (lane == 0) unsafeAtomicAdd(x + vi[s + r], -a);
+        if (lane == 0) U.contrib[N.cof + r] = a;
     }
 }
 
@@ -144,7 +152,8 @@ __global__ void __launch_bounds__(DSB) k_ds_backward(const DsNode* __restrict__ 
 }
 
 #define DS_INST(B, C)                                                                                           \
-    template __global__ void k_ds_forward<B, C>(const DsNode*, const int32_t*, const int32_t*, const double*, double*); \
+    template __global__ void k_ds_forward<B, C>(const DsNode*, const int32_t*, const int32_t*, const double*, double*, \
+                                                DsUpd);                                                                 \
     template __global__ void k_ds_backward<B, C>(const DsNode*, const int32_t*, const int32_t*, const double*, double*);
 DS_INST(256, DS_SMALL)
 DS_INST(1024, DS_SMALL)

@@ -81,9 +81,13 @@ __device__ inline double rz_w(const MgJob& J, const double* s)
 }
 
 // Sum M per-lane values over the workgroup, separately for each column
-// (lane t holds column t % NV), and add the sums to dst(v, m).
+// (lane t holds column t % NV), in a fixed order. With part, the workgroup's
+// sums go to part[v M + m] with plain stores (a row-parallel phase: one of
+// many workgroups of the system; k_mg_reduce adds them in block order);
+// without, they are added to dst(v, m) (the one workgroup of a system in
+// k_mg_tail and k_mg_finish: a single addition onto a cleared word).
 template <int NV, int M, typename D>
-__device__ inline void block_accumulate(const double (&val)[M], D dst)
+__device__ inline void block_accumulate(const double (&val)[M], D dst, double* part)
 {
     const int t = threadIdx.x, nt = blockDim.x;
     if constexpr (NV == 1) {
@@ -99,7 +103,8 @@ __device__ inline void block_accumulate(const double (&val)[M], D dst)
         if (t < M) {
             double s = 0.0;
             for (int w = 0; w < nw; ++w) s += sh[w * M + t];
-            unsafeAtomicAdd(dst(0, t), s);
+            if (part) part[t] = s;
+            else unsafeAtomicAdd(dst(0, t), s);
         }
     } else {
         // lanes t and t + 64 NV hold the same column: fold each wave group of
@@ -112,7 +117,8 @@ __device__ inline void block_accumulate(const double (&val)[M], D dst)
             const int v = t % NV, m = t / NV;
             double s = 0.0;
             for (int u = v; u < nt; u += NV) s += sh[m * nt + u];
-            unsafeAtomicAdd(dst(v, m), s);
+            if (part) part[v * M + m] = s;
+            else unsafeAtomicAdd(dst(v, m), s);
         }
     }
     // workgroup-scope release: the atomics above have completed before any
@@ -216,7 +222,7 @@ __device__ inline const double* level_rhs(const MgJob& J, int l, int k)
 
 template <int NV>
 __device__ __forceinline__ void pa_body(const MgJob& J, const AmgDev& H, int k, const Scal& sc, int v, int t0,
-                                        int t1, int st)
+                                        int t1, int st, double* part)
 {
     const double* z = J.ly[0];
     const double* pold = J.p[(k - 1) & 1];
@@ -241,12 +247,12 @@ __device__ __forceinline__ void pa_body(const MgJob& J, const AmgDev& H, int k, 
             pnew[t] = 0.0;
             J.q[t] = 0.0;
         }
-    block_accumulate<NV, 1>({pq}, [&](int u, int) { return slot(J, k, u); });
+    block_accumulate<NV, 1>({pq}, [&](int u, int) { return slot(J, k, u); }, part);
 }
 
 template <int NV>
 __device__ __forceinline__ void pb_body(const MgJob& J, const AmgDev& H, int k, bool first, const Scal& sc,
-                                        bool leader, int v, int t0, int t1, int st)
+                                        bool leader, int v, int t0, int t1, int st, double* part)
 {
     if (leader)
         for (int u = 0; u < NV * MG_SLOT; ++u) slot(J, k + 1, 0)[u] = 0.0;
@@ -270,7 +276,7 @@ __device__ __forceinline__ void pb_body(const MgJob& J, const AmgDev& H, int k, 
         sr += rn;
         if (smooth) J.ly[0][t] = pre_row(H, 0, bget, i);
     }
-    block_accumulate<NV, 2>({rr, sr}, [&](int u, int m) { return slot(J, k, u) + 1 + m; });
+    block_accumulate<NV, 2>({rr, sr}, [&](int u, int m) { return slot(J, k, u) + 1 + m; }, part);
 }
 
 template <int NV>
@@ -335,9 +341,9 @@ __device__ inline void post2_pairs(const MgJob& J, const AmgDev& H, int l, int k
 }
 
 template <int NV>
-__device__ inline void accumulate_rz(const MgJob& J, int k, double rz, double sz)
+__device__ inline void accumulate_rz(const MgJob& J, int k, double rz, double sz, double* part)
 {
-    block_accumulate<NV, 2>({rz, sz}, [&](int u, int m) { return slot(J, k, u) + 3 + m; });
+    block_accumulate<NV, 2>({rz, sz}, [&](int u, int m) { return slot(J, k, u) + 3 + m; }, part);
 }
 
 // No pair: the start of the pair loops for lanes beyond the multiple of NV.
@@ -398,7 +404,7 @@ __device__ __forceinline__ void tail_body(const MgJob& J, const AmgDev& H, int k
             rz += r[t] * J.ly[0][t];
             sz += J.ly[0][t];
         }
-        accumulate_rz<NV>(J, k, rz, sz);
+        accumulate_rz<NV>(J, k, rz, sz, nullptr);
     }
 }
 
@@ -421,6 +427,13 @@ __device__ inline Pairs<NV> block_pairs(int row0, int rows)
     return p;
 }
 
+// the partial sums of the row-parallel workgroup whose first row is row0
+template <int NV>
+__device__ inline double* block_part(const MgJob& J, int row0)
+{
+    return J.part + (int64_t)(row0 / (MGB / NV)) * MG_PART;
+}
+
 // ---------------------------------------------------------------- kernel bodies
 
 template <int NV>
@@ -428,7 +441,7 @@ __device__ void setup1_body(const MgJob& J, int row0)
 {
     const Pairs<NV> q = block_pairs<NV>(row0, J.n);
     const double x = q.live ? J.b[q.t0] : 0.0;
-    block_accumulate<NV, 2>({x, x * x}, [&](int u, int m) { return setup_slot(J, u) + m; });
+    block_accumulate<NV, 2>({x, x * x}, [&](int u, int m) { return setup_slot(J, u) + m; }, block_part<NV>(J, row0));
 }
 
 template <int NV>
@@ -449,7 +462,7 @@ __device__ void setup2_body(const MgJob& J, const AmgDev& H, int row0)
         }
         bb = b * b;
     }
-    block_accumulate<NV, 1>({bb}, [&](int u, int) { return setup_slot(J, u) + 2; });
+    block_accumulate<NV, 1>({bb}, [&](int u, int) { return setup_slot(J, u) + 2; }, block_part<NV>(J, row0));
 }
 
 template <int NV>
@@ -461,7 +474,7 @@ __device__ void pa_kernel_body(const MgJob& J, const AmgDev& H, int row0, int k)
         if (row0 == 0 && threadIdx.x == 0) { J.state[0] = 1; J.state[1] = k; }
         return;
     }
-    pa_body<NV>(J, H, k, sc, q.v, q.t0, q.t1, 1);
+    pa_body<NV>(J, H, k, sc, q.v, q.t0, q.t1, 1, block_part<NV>(J, row0));
 }
 
 template <int NV>
@@ -469,7 +482,7 @@ __device__ void pb_kernel_body(const MgJob& J, const AmgDev& H, int row0, int k,
 {
     const Pairs<NV> q = block_pairs<NV>(row0, J.n);
     const Scal sc = pb_scalars<NV, false>(J, k, first, q.v);
-    pb_body<NV>(J, H, k, first, sc, row0 == 0 && threadIdx.x == 0, q.v, q.t0, q.t1, 1);
+    pb_body<NV>(J, H, k, first, sc, row0 == 0 && threadIdx.x == 0, q.v, q.t0, q.t1, 1, block_part<NV>(J, row0));
 }
 
 template <int NV>
@@ -491,9 +504,9 @@ __device__ void finish_body(const MgJob& J, const AmgDev& H, int k0)
         const Scal sa = pa_scalars<NV, true>(J, k, v);
         if (sa.all) { done = true; it = k; break; }
         if (k >= J.maxit) { it = k; break; }
-        pa_body<NV>(J, H, k, sa, v, t0, NV * n, nt);
+        pa_body<NV>(J, H, k, sa, v, t0, NV * n, nt, nullptr);
         const Scal sb = pb_scalars<NV, true>(J, k, false, v);
-        pb_body<NV>(J, H, k, false, sb, tid == 0, v, t0, NV * n, nt);
+        pb_body<NV>(J, H, k, false, sb, tid == 0, v, t0, NV * n, nt, nullptr);
         if (H.nbig >= 1) {
             res_pairs<NV>(J, H, 0, k, t0, NV * n, nt);
             __syncthreads();
@@ -515,7 +528,7 @@ __device__ void finish_body(const MgJob& J, const AmgDev& H, int k0)
             __syncthreads();
             double rz = 0.0, sz = 0.0;
             post2_pairs<NV>(J, H, l, k, t0, NV * H.n[l], nt, rz, sz);
-            if (l == 0) accumulate_rz<NV>(J, k, rz, sz);
+            if (l == 0) accumulate_rz<NV>(J, k, rz, sz, nullptr);
             else __syncthreads();
         }
     }
@@ -776,10 +789,43 @@ __global__ void __launch_bounds__(MGB) k_mg_post2(const MgJob* __restrict__ jobs
         const Pairs<NV> q = block_pairs<NV>(e.y, H.n[l]);        \
         double rz = 0.0, sz = 0.0;                               \
         post2_pairs<NV>(J, H, l, k, q.t0, q.t1, 1, rz, sz);      \
-        if (l == 0) accumulate_rz<NV>(J, k, rz, sz);             \
+        if (l == 0) accumulate_rz<NV>(J, k, rz, sz, block_part<NV>(J, e.y)); \
     }
     MG_DISPATCH(J, PS2);
 #undef PS2
+}
+
+// The sums of a row-parallel phase: for each system that ran the phase, the
+// partials of its workgroups (row-block order) are added in a fixed order
+// (16 lanes per word, each over every 16th block in turn, then the 16 lanes
+// in order) and stored into the phase's accumulator words, slot k words
+// word0 .. word0 + M - 1 (setup: the set-up slot). The same skips as the
+// phase: a converged system or one past its cap (not for the set-up); with
+// big_only, a system whose level 0 the tail handles (its k_mg_tail adds its
+// own sums). So a system's sums depend on its rows alone, in any batch.
+__global__ void __launch_bounds__(256) k_mg_reduce(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
+                                                   const int32_t* __restrict__ st, int k, int word0, int M, int setup,
+                                                   int big_only)
+{
+    const MgJob& J = jobs[blockIdx.x];
+    if (J.n <= 0) return;
+    if (!setup && (st[2 * blockIdx.x] != 0 || k >= J.maxit)) return;
+    if (big_only && hs[J.hier].nbig < 1) return;
+    __shared__ double sh[MG_PART * 16];
+    const int nw = J.nv * M, nb = J.nblk0;
+    const int t = threadIdx.x, w = t >> 4, j = t & 15;
+    if (w < nw) {
+        double s = 0.0;
+        for (int b = j; b < nb; b += 16) s += J.part[(int64_t)b * MG_PART + w];
+        sh[t] = s;
+    }
+    __syncthreads();
+    if (t < nw) {
+        double s = 0.0;
+        for (int q = 0; q < 16; ++q) s += sh[t * 16 + q];
+        const int v = t / M, m = t - v * M;
+        (setup ? setup_slot(J, v) : slot(J, k, v))[word0 + m] = s;
+    }
 }
 
 // Completes, in one workgroup per system, every system that has not

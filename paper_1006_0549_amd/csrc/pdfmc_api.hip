@@ -287,8 +287,9 @@ struct pdfmc_ctx {
     double* d_mg_dinv = nullptr;
     double* d_mg_ainv = nullptr;
     int4* d_mg_tab = nullptr;      // (system, first row, hierarchy, 0)
+    double* d_mg_part = nullptr;   // the row blocks' partial sums of a phase, per system
     int4* d_mg_tab_dinv = nullptr;
-    int64_t MGV = 0, MGD = 0, MGT = 0, MGTD = 0;
+    int64_t MGV = 0, MGD = 0, MGT = 0, MGTD = 0, MGP = 0;
     struct TabRange { int64_t off = 0; int n_er = 0, n_all = 0; };
     TabRange tab0;                  // level-0 rows of every system
     TabRange tabl[AMG_MAXL];        // level-l rows of the systems with more than l large levels
@@ -338,7 +339,10 @@ struct pdfmc_ctx {
     double* d_ds_val = nullptr;
     DsCase* d_ds_cases = nullptr;
     int32_t* d_ds_list = nullptr;
-    int64_t DSN = 0, DSI = 0, DSV = 0;
+    int32_t* d_ds_cptr = nullptr;      // [NN + 1] per unknown, its contributors in d_ds_clist
+    int32_t* d_ds_clist = nullptr;     // contributor slots, per unknown in supernode order
+    double* d_ds_contrib = nullptr;    // the forward sweep's updates of later unknowns
+    int64_t DSN = 0, DSI = 0, DSV = 0, DSR = 0;
     int DSC = 0, ds_height = -1;
     std::vector<int64_t> ds_hoff;      // list offsets per height
     std::vector<int> ds_hwide;         // per height: sweep variant (small, 256 threads, 1024 threads)
@@ -448,6 +452,7 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_mg_dinv, c->MGD);
     k.take(c->d_mg_ainv, 2 * (size_t)std::max(c->n_amg, 1) * AMG_MAXC * AMG_MAXC);
     k.take(c->d_mg_tab, c->MGT);
+    k.take(c->d_mg_part, (size_t)std::max<int64_t>(c->MGP, 1) * MG_PART);
     k.take(c->d_mg_tab_dinv, c->MGTD);
     k.take(c->d_counters, NCNT * c->cases.size());
     k.take(c->d_step, 1);
@@ -467,6 +472,9 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_ds_val, c->DSV);
     k.take(c->d_ds_cases, c->DSC);
     k.take(c->d_ds_list, c->DSN);
+    k.take(c->d_ds_cptr, c->DSC > 0 ? (size_t)c->NN + 1 : 1);
+    k.take(c->d_ds_clist, (size_t)std::max<int64_t>(c->DSR, 1));
+    k.take(c->d_ds_contrib, (size_t)std::max<int64_t>(c->DSR, 1));
 }
 
 void compute_offsets(pdfmc_ctx* c)
@@ -500,7 +508,7 @@ void compute_offsets(pdfmc_ctx* c)
     srec += (int64_t)c->pool_cap * (SC_HDR + SC_VMAX);
     srec = std::max<int64_t>(srec, (20 * NP + 7) / 8 + 3 * 32);
     c->SREC = srec;
-    int64_t ni = 0, nd = 0, nv = 0, ndv = 0, nt = 0, ntd = 0;
+    int64_t ni = 0, nd = 0, nv = 0, ndv = 0, nt = 0, ntd = 0, np0 = 0;
     int na = 0, maxlev = 0;
     for (auto& cs : c->cases) {
         if (!cs.has_amg) { cs.amg_index = -1; continue; }
@@ -518,10 +526,11 @@ void compute_offsets(pdfmc_ctx* c)
                 nt += mg_blocks_nv(lv.A.n, ncol);
             }
             nt += mg_blocks_nv(cs.amg[h].lv[0].A.n, ncol);
+            np0 += mg_blocks_nv(cs.amg[h].lv[0].A.n, ncol);
         }
     }
     c->AMG_I = ni; c->AMG_D = nd; c->n_amg = na; c->amg_levels = maxlev;
-    int64_t dsn = 0, dsi = 0, dsv = 0;
+    int64_t dsn = 0, dsi = 0, dsv = 0, dsr = 0;
     int dsc = 0, dsh = -1;
     for (auto& cs : c->cases) {
         if (!cs.has_chol) { cs.ds_case_index = -1; continue; }
@@ -529,10 +538,11 @@ void compute_offsets(pdfmc_ctx* c)
         dsn += (int64_t)cs.chol.nodes.size();
         dsi += cs.chol.n_idx;
         dsv += cs.chol.n_val;
+        for (const CholNode& S : cs.chol.nodes) dsr += (int64_t)S.str.size();
         dsh = std::max(dsh, cs.chol.height);
     }
-    c->DSN = dsn; c->DSI = dsi; c->DSV = dsv; c->DSC = dsc; c->ds_height = dsh;
-    c->MGV = nv; c->MGD = ndv; c->MGT = nt; c->MGTD = ntd;
+    c->DSN = dsn; c->DSI = dsi; c->DSV = dsv; c->DSC = dsc; c->ds_height = dsh; c->DSR = dsr;
+    c->MGV = nv; c->MGD = ndv; c->MGT = nt; c->MGTD = ntd; c->MGP = np0;
     c->NP = NP; c->PSI = PSI; c->CM = CM; c->CS = CS; c->NE = NE; c->NN = NN; c->NBC = NBC; c->NELL = NELL;
     c->ntiles = (int)(NP / TILE);
 }
@@ -739,12 +749,16 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
     c->n_jobs_er = (int)jer.size();
     c->n_jobs_p = (int)jp.size();
     jer.insert(jer.end(), jp.begin(), jp.end());
-    int64_t aoff = 0;
+    int64_t aoff = 0, poff = 0;
     for (size_t j = 0; j < jer.size(); ++j) {
         jer[j].acc = c->d_mg_acc + aoff;
         aoff += (int64_t)jer[j].nv * MG_NSLOT * MG_SLOT;
         jer[j].state = c->d_mg_state + 2 * j;
+        jer[j].nblk0 = (int32_t)mg_blocks_nv(jer[j].n, jer[j].nv);
+        jer[j].part = c->d_mg_part + poff * MG_PART;
+        poff += jer[j].nblk0;
     }
+    if (poff > c->MGP) return fail(c, PDFMC_E_STATE, "solver partial sums exceed their reservation");
     c->h_jobs = jer;
     TRY(h2d(c, c->d_mg_jobs, c->h_jobs));
     const int nj = (int)jer.size();
@@ -806,12 +820,13 @@ pdfmc_status enqueue_direct_projection(pdfmc_ctx* c)
         const DsNode* nd = c->d_ds_nodes;
         const int32_t* ix = c->d_ds_idx;
         const double* vl = c->d_ds_val;
+        const DsUpd U{c->d_ds_cptr, c->d_ds_clist, c->d_ds_contrib};
         if (c->ds_hwide[h] == 2)
-            hipLaunchKernelGGL((k_ds_forward<1024, DS_MAXS>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi);
+            hipLaunchKernelGGL((k_ds_forward<1024, DS_MAXS>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi, U);
         else if (c->ds_hwide[h] == 1)
-            hipLaunchKernelGGL((k_ds_forward<1024, DS_SMALL>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi);
+            hipLaunchKernelGGL((k_ds_forward<1024, DS_SMALL>), dim3((unsigned)n), dim3(1024), 0, st, nd, lst, ix, vl, c->d_phi, U);
         else
-            hipLaunchKernelGGL((k_ds_forward<256, DS_SMALL>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi);
+            hipLaunchKernelGGL((k_ds_forward<256, DS_SMALL>), dim3((unsigned)n), dim3(256), 0, st, nd, lst, ix, vl, c->d_phi, U);
     }
     for (int h = c->ds_height; h >= 0; --h) {
         const int64_t n = c->ds_hoff[h + 1] - c->ds_hoff[h];
@@ -849,8 +864,15 @@ pdfmc_status enqueue_mg(pdfmc_ctx* c, bool project)
     hipStream_t st = c->stream;
     hipLaunchKernelGGL(k_mg_dinv, dim3(c->n_tab_dinv), dim3(256), 0, st, H, (const int4*)c->d_mg_tab_dinv);
     hipLaunchKernelGGL(k_mg_coarse, dim3(2 * c->n_amg), dim3(1024), 0, st, H);
+    // every phase whose workgroups each hold a share of a system's sums is
+    // followed by k_mg_reduce, which adds the shares in block order
+    auto reduce = [&](int k, int word0, int M, int setup, int big_only) {
+        hipLaunchKernelGGL(k_mg_reduce, dim3(nj), dim3(256), 0, st, J, H, S, k, word0, M, setup, big_only);
+    };
     hipLaunchKernelGGL(k_mg_setup1, dim3(g0), dim3(256), 0, st, J, T0, S);
+    reduce(0, 0, 2, 1, 0);
     hipLaunchKernelGGL(k_mg_setup2, dim3(g0), dim3(256), 0, st, J, H, T0, S);
+    reduce(0, 2, 1, 1, 0);
     LAUNCHCHK(c);
     auto vcycle = [&](int k) -> pdfmc_status {
         if (maxbig >= 1)
@@ -870,15 +892,19 @@ pdfmc_status enqueue_mg(pdfmc_ctx* c, bool project)
             hipLaunchKernelGGL(k_mg_prolong, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
             hipLaunchKernelGGL(k_mg_post1, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
             hipLaunchKernelGGL(k_mg_post2, gl, dim3(256), 0, st, J, H, Tl, S, l, k);
+            if (l == 0) reduce(k, 3, 2, 0, 1);
         }
         LAUNCHCHK(c);
         return PDFMC_OK;
     };
     hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, S, -1, 1);
+    reduce(-1, 1, 2, 0, 0);
     TRY(vcycle(-1));
     for (int k = 0; k < c->mg_iters; ++k) {
         hipLaunchKernelGGL(k_mg_pa, dim3(g0), dim3(256), 0, st, J, H, T0, S, k);
+        reduce(k, 0, 1, 0, 0);
         hipLaunchKernelGGL(k_mg_pb, dim3(g0), dim3(256), 0, st, J, H, T0, S, k, 0);
+        reduce(k, 1, 2, 0, 0);
         TRY(vcycle(k));
     }
     hipLaunchKernelGGL(k_mg_finish, dim3(nj), dim3(512), 0, st, J, H, c->mg_iters);
@@ -1464,6 +1490,10 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         idx.reserve(c->DSI);
         val.reserve(c->DSV);
         std::vector<std::vector<int32_t>> byh(c->ds_height + 1);
+        // contributors of each unknown, in supernode order (children before parents)
+        std::vector<int32_t> ccnt((size_t)c->NN + 1, 0);
+        std::vector<std::pair<int32_t, int32_t>> cpairs;     // (unknown, slot)
+        int64_t cof = 0;
         for (auto& cs : c->cases) {
             if (!cs.has_chol) continue;
             dcs.push_back(DsCase{cs.noff, cs.m.nsn, cs.chol.pin, 0});
@@ -1473,6 +1503,13 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                 d.m = (int32_t)S.str.size();
                 d.idx = (int64_t)idx.size();
                 d.val = (int64_t)val.size();
+                d.cof = cof;
+                for (int r = 0; r < d.m; ++r) {
+                    const int32_t u = cs.noff + S.str[r];
+                    cpairs.emplace_back(u, (int32_t)(cof + r));
+                    ++ccnt[(size_t)u + 1];
+                }
+                cof += d.m;
                 for (int v : S.vars) idx.push_back(cs.noff + v);
                 for (int u : S.str) idx.push_back(cs.noff + u);
                 val.insert(val.end(), S.linv.begin(), S.linv.end());
@@ -1503,6 +1540,12 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         TRY(h2d(c, c->d_ds_val, val));
         TRY(h2d(c, c->d_ds_cases, dcs));
         TRY(h2d(c, c->d_ds_list, list));
+        if (cof != c->DSR) return fail(c, PDFMC_E_STATE, "projection factor updates differ from their reservation");
+        for (size_t u = 1; u < ccnt.size(); ++u) ccnt[u] += ccnt[u - 1];
+        std::vector<int32_t> clist((size_t)std::max<int64_t>(cof, 1), 0), pos(ccnt.begin(), ccnt.end() - 1);
+        for (const auto& pr : cpairs) clist[(size_t)pos[pr.first]++] = pr.second;   // stable: supernode order
+        TRY(h2d(c, c->d_ds_cptr, ccnt));
+        TRY(h2d(c, c->d_ds_clist, clist));
     }
     c->proj_direct = c->proj_method == PDFMC_PROJ_DIRECT && c->n_amg > 0 && c->DSC == c->n_amg;
     // solver systems: one five-column relaxation system per mode-2 case,

@@ -103,6 +103,7 @@ struct GalJob {
 constexpr int MG_SLOT = 32;        // doubles per accumulator slot: 256 B, so that the atomic adds of
                                    // many workgroups to different columns meet on different lines
 constexpr int MG_NSLOT = 5;        // 4 iteration slots + 1 set-up slot
+constexpr int MG_PART = 16;        // doubles per row block's partial sums (nv M <= 10)
 struct MgJob {
     int32_t hier;                  // index of the hierarchy
     int32_t mean_free;             // singular system: solution and residual kept mean-free
@@ -125,6 +126,8 @@ struct MgJob {
     unsigned long long* iters;
     unsigned long long* fails;
     unsigned int* need;            // largest iteration count since the host last read it (all systems)
+    double* part;                  // [nblk0][MG_PART] the row-parallel workgroups' sums of a phase
+    int32_t nblk0;                 // row blocks of level 0
 };
 
 // One supernode of a case's projection factor (nested-dissection Cholesky of
@@ -135,6 +138,15 @@ struct DsNode {
     int32_t s, m;                  // own unknowns, later unknowns reached
     int64_t idx;                   // own unknowns at idx[idx .. idx+s), later ones at [idx+s .. idx+s+m)
     int64_t val;                   // L11^-1 (s x s, row-major, lower) at val, then L21 (m x s, row-major)
+    int64_t cof;                   // its updates of the m later unknowns at contrib[cof .. cof+m)
+};
+// The forward sweep's updates of later unknowns, for a fixed summation order:
+// unknown u (global index) subtracts contrib[clist[q]] for q in
+// [cptr[u], cptr[u+1]), its contributors in supernode order.
+struct DsUpd {
+    const int32_t* cptr;
+    const int32_t* clist;
+    double* contrib;
 };
 struct DsCase {
     int32_t noff, n, pin, pad;     // first statistics node, unknowns, decoupled unknown (case-local)

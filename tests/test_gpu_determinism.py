@@ -11,9 +11,11 @@ scatter-overflow counter stays at 0:
     alone (the record keys keep their relative order);
   - after a sort the particles are in (element, id) order, and a sorted run
     follows the oracle as closely as an unsorted one.
-The Eulerian solves of the relaxation and the projection (mode 2) still add
-their FP64 scalars with atomics, so these tests run the simplified model
-(mode 1), where every field comes from the node statistics.
+The Eulerian solves of the full model (mode 2) sum in fixed orders too: the
+multigrid PCG adds its workgroups' shares of each dot product in block order,
+and the forward sweep over the projection's Cholesky factor applies the
+updates of an unknown in supernode order. So the full model is checked the
+same way, with the projection on the factor and on the multigrid PCG.
 """
 import numpy as np
 import pytest
@@ -158,3 +160,71 @@ def test_sorted_run_follows_the_oracle(P, oracle_mod):
     sc[:, 13] = rst[:, 13] + rst[:, 12] ** 2
     d = np.abs(gst - rst)[rows] / np.maximum(sc, 1e-300)[rows]
     assert d.max() <= 1e-9, (d.max(), np.unravel_index(np.argmax(d), d.shape))
+
+
+def _full_cases():
+    """Two mode-2 cases (elliptic relaxation and projection): a channel with
+    two scalars and a lid-driven square without scalars."""
+    mesh = W.channel(n_half=10, nx=24, seed_key=(1, 1, 0))
+    params = W.default_params(mode=2, dt=5e-4, nu=1.0 / 1080.0, n_scalars=2, dpdx=(-1.0, 0.0),
+                              src=[(1.0, 0.5, 0.1, 1.0), (3.0, 1.5, 0.1, 1.0)], stream=1)
+    out = [(mesh, params, W.init_particles(mesh, 20, 2, W.rng_for(1, 1, 1), u_std=1.0))]
+    mesh = W.unit_square(14, 0.2, periodic_x=False, periodic_y=False, lid=(1.0, 0.0, 0.0), seed_key=(3, 7, 0))
+    params = W.default_params(mode=2, dt=2e-4, nu=1.0 / 4000.0, n_scalars=0, dpdx=(0.0, 0.0), stream=2)
+    out.append((mesh, params, W.init_particles(mesh, 40, 0, W.rng_for(3, 7, 1), u_std=0.1)))
+    return out
+
+
+def _full_context(P, precision, cases, steps, projection):
+    sim = P.Sim(precision, "cuda:0")
+    ids = [sim.add_case(m, p, len(parts["x"])) for m, p, parts in cases]
+    sim.bind()
+    sim.set_options(sort_interval=3, use_graph=True)
+    # a fixed unrolled PCG length, well above what the systems need: every
+    # solve completes in the row-parallel phases in every context (the
+    # one-workgroup completion sums in another order)
+    sim.set_solver(iterations=40, tail_rows=64)
+    sim.set_projection_solver(projection)
+    for cs, (m, p, parts) in zip(ids, cases):
+        sim.upload(cs, parts)
+    sim.init()
+    sim.step(steps)
+    return sim, ids
+
+
+def _full_snapshot(sim, cs, n):
+    d = _snapshot(sim, cs, n)
+    d["pressure"] = sim.pressure(cs)
+    return d
+
+
+@pytest.mark.parametrize("projection", ["direct", "pcg"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_model_run_twice_bitwise(P, precision, projection):
+    cases = _full_cases()
+    _flush(f"[full_twice] {precision}, projection {projection}: {len(cases)} mode-2 cases, 20 steps, "
+           f"sort every 3, graph")
+    runs = [_full_context(P, precision, cases, 20, projection) for _ in range(2)]
+    for i, (m, p, parts) in enumerate(cases):
+        n = len(parts["x"])
+        a = _full_snapshot(runs[0][0], runs[0][1][i], n)
+        b = _full_snapshot(runs[1][0], runs[1][1][i], n)
+        assert a["counters"]["scatter_overflow"] == 0
+        assert a["counters"]["cg_iters_er"] > 0 and a["counters"]["cg_fail"] == 0
+        _assert_bitwise(a, b, f"case {i}")
+
+
+@pytest.mark.parametrize("projection", ["direct", "pcg"])
+def test_full_model_batched_equals_sequential_bitwise(P, projection):
+    cases = _full_cases()
+    _flush(f"[full_batched] projection {projection}: two mode-2 cases together and one at a time, 12 steps")
+    sim, ids = _full_context(P, "fp64", cases, 12, projection)
+    for i, (m, p, parts) in enumerate(cases):
+        n = len(parts["x"])
+        alone, aid = _full_context(P, "fp64", [cases[i]], 12, projection)
+        a = _full_snapshot(sim, ids[i], n)
+        b = _full_snapshot(alone, aid[0], n)
+        assert a["counters"]["scatter_overflow"] == 0
+        # iteration counts are per case; the unrolled count of the context may differ
+        _assert_bitwise({k: v for k, v in a.items() if k != "counters"},
+                        {k: v for k, v in b.items() if k != "counters"}, f"case {i}")
