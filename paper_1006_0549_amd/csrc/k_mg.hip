@@ -574,7 +574,7 @@ __device__ void finish_body(const MgJob& J, const AmgDev& H, int k0)
 // Inverse diagonals of every level; tab entries: (hierarchy, level, first row)
 __global__ void k_mg_dinv(const AmgDev* __restrict__ hs, const int4* __restrict__ tab)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const AmgDev& H = hs[e.x];
     const EllDev& A = H.A[e.y];
     const int i = e.z + threadIdx.x;
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(1024) k_mg_coarse(const AmgDev* __restrict__ h
 __global__ void __launch_bounds__(MGB) k_mg_setup1(const MgJob* __restrict__ jobs, const int4* __restrict__ tab,
                                                    const int32_t* __restrict__ st)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
 #define SETUP1(NV) setup1_body<NV>(J, e.y)
     MG_DISPATCH(J, SETUP1);
@@ -646,7 +646,7 @@ __global__ void __launch_bounds__(MGB) k_mg_setup1(const MgJob* __restrict__ job
 __global__ void __launch_bounds__(MGB) k_mg_setup2(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
                                                    const int4* __restrict__ tab, const int32_t* __restrict__ st)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
 #define SETUP2(NV) setup2_body<NV>(J, hs[e.z], e.y)
     MG_DISPATCH(J, SETUP2);
@@ -656,7 +656,7 @@ __global__ void __launch_bounds__(MGB) k_mg_setup2(const MgJob* __restrict__ job
 __global__ void __launch_bounds__(MGB) k_mg_pa(const MgJob* __restrict__ jobs, const AmgDev* __restrict__ hs,
                                                const int4* __restrict__ tab, const int32_t* __restrict__ st, int k)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
     if (st[2 * e.x] != 0 || k >= J.maxit) return;
 #define PA(NV) pa_kernel_body<NV>(J, hs[e.z], e.y, k)
@@ -668,7 +668,7 @@ __global__ void __launch_bounds__(MGB) k_mg_pb(const MgJob* __restrict__ jobs, c
                                                const int4* __restrict__ tab, const int32_t* __restrict__ st, int k,
                                                int first)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
     if (st[2 * e.x] != 0 || k >= J.maxit) return;
 #define PB(NV) pb_kernel_body<NV>(J, hs[e.z], e.y, k, first != 0)
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(MGB) k_mg_res(const MgJob* __restrict__ jobs, 
                                                 const int4* __restrict__ tab, const int32_t* __restrict__ st, int l,
                                                 int k)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
     if (st[2 * e.x] != 0 || k >= J.maxit) return;
     const AmgDev& H = hs[e.z];
@@ -700,7 +700,7 @@ __global__ void __launch_bounds__(MGB) k_mg_restrict(const MgJob* __restrict__ j
                                                      const int4* __restrict__ tab, const int32_t* __restrict__ st,
                                                      int l, int k)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
     if (st[2 * e.x] != 0 || k >= J.maxit) return;
     const AmgDev& H = hs[e.z];
@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(MGB) k_mg_pre(const MgJob* __restrict__ jobs, 
                                                 const int4* __restrict__ tab, const int32_t* __restrict__ st, int l,
                                                 int k)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
     if (st[2 * e.x] != 0 || k >= J.maxit) return;
     const AmgDev& H = hs[e.z];
@@ -746,7 +746,7 @@ __global__ void __launch_bounds__(MGB) k_mg_prolong(const MgJob* __restrict__ jo
                                                     const int4* __restrict__ tab, const int32_t* __restrict__ st,
                                                     int l, int k)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
     if (st[2 * e.x] != 0 || k >= J.maxit) return;
     const AmgDev& H = hs[e.z];
@@ -763,7 +763,7 @@ __global__ void __launch_bounds__(MGB) k_mg_post1(const MgJob* __restrict__ jobs
                                                   const int4* __restrict__ tab, const int32_t* __restrict__ st, int l,
                                                   int k)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
     if (st[2 * e.x] != 0 || k >= J.maxit) return;
     const AmgDev& H = hs[e.z];
@@ -780,7 +780,7 @@ __global__ void __launch_bounds__(MGB) k_mg_post2(const MgJob* __restrict__ jobs
                                                   const int4* __restrict__ tab, const int32_t* __restrict__ st, int l,
                                                   int k)
 {
-    const int4 e = tab[blockIdx.x];
+    const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
     if (st[2 * e.x] != 0 || k >= J.maxit) return;
     const AmgDev& H = hs[e.z];

@@ -2,6 +2,8 @@
 // side of the method: Sec. I grid roles (i) statistics and (ii) Eulerian
 // solves). Each kernel covers every case of the context in one launch:
 // threads map to global statistics nodes or elements and look up their case.
+// The node kernels take their blocks in XCD order (xcd_block): neighbouring
+// nodes, which read each other's values, then share an L2.
 //
 //   (node statistics and cell means come from the scatter passes, k_scatter.hip)
 //   k_fields_grad  <U>, <omega>, recovered gradients of <U> (R-16)
@@ -77,7 +79,7 @@ __device__ inline void recover_grad3(const NodeArgs& A, const double* f, int fst
 
 __global__ void k_fields_grad(NodeArgs A)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode == 0) return;
@@ -102,7 +104,7 @@ __device__ inline double det3(const double R[3][3])
 
 __global__ void k_fields_derived(NodeArgs A)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const int c = A.node_case[s];
     const CaseDev& C = A.cases[c];
@@ -185,7 +187,7 @@ __global__ void k_fields_derived(NodeArgs A)
 // The matrix is stored per case in ELL form (column-major, local columns).
 __global__ void k_er_assemble(NodeArgs A)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;
@@ -228,7 +230,7 @@ __global__ void k_er_assemble(NodeArgs A)
 // Stiffness matrix of the projection (constant; assembled once).
 __global__ void k_stiffness_assemble(NodeArgs A)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;
@@ -246,7 +248,7 @@ __global__ void k_stiffness_assemble(NodeArgs A)
 
 __global__ void k_er_finish(NodeArgs A)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;
@@ -268,7 +270,7 @@ __global__ void k_er_finish(NodeArgs A)
 // right-hand side of the projection: (1/dt) sum_e A_e grad N_a . <U>_e
 __global__ void k_proj_rhs(NodeArgs A)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;
@@ -291,7 +293,7 @@ __global__ void k_proj_rhs(NodeArgs A)
 // <P> += phi, then d<P>/dx_j = driving gradient + recovered gradient of <P>
 __global__ void k_proj_update(NodeArgs A)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;
@@ -300,7 +302,7 @@ __global__ void k_proj_update(NodeArgs A)
 
 __global__ void k_proj_grad(NodeArgs A)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block((int)blockIdx.x, (int)gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= A.nn) return;
     const CaseDev& C = A.cases[A.node_case[s]];
     if (C.mode != 2) return;

@@ -193,7 +193,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     __shared__ int s_mel[4 * 64], s_mfirst[4 * 64];  // shared elements each wavefront merges, first positions
     __shared__ int s_nmerge[4];
     __shared__ int s_slot;                           // record slots taken by the workgroup
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD-aware order: the chip hands workgroups to its eight XCDs in turn
+    // (hardware block b on XCD b mod 8), so logical block lb gives each XCD a
+    // contiguous range of particle tiles, whose elements then meet in its L2
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int64_t gid = (int64_t)lb * blockDim.x + threadIdx.x;
     // block sizes are multiples of 64 and TILE of the block size, so a
     // wavefront lies inside one tile: the tile, the case and its constants
     // are the same for all lanes and are taken from the first lane (scalar
@@ -204,7 +208,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     // a rebinning pass skips the cases that keep the bins of their step: the
     // whole workgroup leaves (one case per workgroup), with no records
     if (A.rebin_only && !C.rebin) {
-        if (threadIdx.x == 0) A.wgcnt[blockIdx.x] = 0;
+        if (threadIdx.x == 0) A.wgcnt[lb] = 0;
         return;
     }
     const int64_t i = gid - C.poff;
@@ -439,8 +443,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     const int nrec = __popcll(rm), ridx = __popcll(rm & before);
     const int64_t ltile = gid / TILE - C.poff / TILE;     // the case's tile of this workgroup
     const int wg_slots = SC_RT * (int)blockDim.x / TILE;
-    const int wg_first = (int)((blockIdx.x * (int64_t)blockDim.x) % TILE) / (int)blockDim.x * wg_slots;
-    const long long kbase = (long long)blockIdx.x * 512;
+    const int wg_first = (int)((lb * (int64_t)blockDim.x) % TILE) / (int)blockDim.x * wg_slots;
+    const long long kbase = (long long)lb * 512;
     int base = 0;
     if (lane == 0 && nrec > 0) base = atomicAdd(&s_slot, nrec);
     base = __shfl(base, 0);
@@ -716,7 +720,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) A.wgcnt[blockIdx.x] = s_slot < wg_slots ? s_slot : wg_slots;
+    if (threadIdx.x == 0) A.wgcnt[lb] = s_slot < wg_slots ? s_slot : wg_slots;
     }
     // ---- counters, one atomic per wavefront
     {

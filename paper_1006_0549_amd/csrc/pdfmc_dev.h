@@ -30,6 +30,17 @@ enum Field {
 // the mean pressure, i.e. the velocity correction of the next step (R-27)
 constexpr int FE_GPX = 22, FE_GPY = 23;
 
+// The logical block of hardware block b of a grid of nb blocks. The chip
+// hands workgroups to its eight XCDs in turn (block b to XCD b mod 8), each
+// with an L2 of its own; this bijection gives XCD x the contiguous logical
+// blocks [x q + min(x, r), ...), q = nb / 8, r = nb mod 8, so that blocks
+// working on neighbouring data share an L2.
+__device__ inline int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 enum Counter {
     C_WALK_FALLBACK = 0, C_REFLECT, C_PERIODIC, C_OMEGA_FLIP, C_EMPTY_NODE, C_NAN,
     C_WALK_STEPS, C_CG_ER, C_CG_P, C_CG_FAIL, C_K_FLOOR, C_EPS_FLOOR, C_SCATTER_OVERFLOW
