@@ -21,9 +21,12 @@
 //          -> two post-smoothing steps, the second of which gives z_{k+1} on
 //          level 0 and accumulates r.z and sum z.
 // A converged column keeps its x and r (p = 0, alpha = 0); a system is done
-// when all its columns are. Scalars are accumulated with FP64 atomics into
-// rotating per-iteration slots (slot k mod 4, one per column); a slot is
-// cleared two phases after its last reader. The first lanes of each workgroup
+// when all its columns are. Scalars go into rotating per-iteration slots
+// (slot k mod 4, one per column): each row-parallel workgroup stores its
+// share, and k_mg_reduce adds a system's shares in block order into the slot;
+// the one workgroup of a system in the tail and the completion adds its sum
+// onto the cleared word. So every scalar is summed in a fixed order. A slot
+// is cleared two phases after its last reader. The first lanes of each workgroup
 // gather the slot words in one round trip and share them through LDS. Level
 // sizes are fixed per system, so a fixed number of iterations can be replayed
 // from a graph; systems that have converged leave every later phase at once,

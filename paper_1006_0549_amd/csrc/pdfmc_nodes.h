@@ -100,8 +100,7 @@ struct GalJob {
 // One linear system on the rows of one case; every pointer is offset to the
 // case's first row (local indices). Preconditioned CG whose iterations are
 // split into phases; scalars are accumulated per iteration in rotating slots.
-constexpr int MG_SLOT = 32;        // doubles per accumulator slot: 256 B, so that the atomic adds of
-                                   // many workgroups to different columns meet on different lines
+constexpr int MG_SLOT = 32;        // doubles per accumulator slot: one 256-byte line per slot and column
 constexpr int MG_NSLOT = 5;        // 4 iteration slots + 1 set-up slot
 constexpr int MG_PART = 16;        // doubles per row block's partial sums (nv M <= 10)
 struct MgJob {
