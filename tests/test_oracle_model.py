@@ -15,6 +15,8 @@ moments are known in closed form:
     cell variance is multiplied by (1 - dt/t_m)^2 each step.
 The estimator is checked by partition of unity, conservation of the weighted
 sums and a brute-force evaluation of the P1 shape functions by linear solves.
+A run of the full model on a small channel guards the reading of the
+projection (R-27), under which the channel stays bounded.
 """
 import math
 
@@ -469,3 +471,33 @@ def test_reaction_rejections(oracle_mod):
     a = _reaction_case(oracle_mod, mesh, parts, 1, 0, (5.0, 0, 0, 0), 0.01, 3)
     b = _reaction_case(oracle_mod, mesh, parts, 1, 0, (0.0, 0, 0, 0), 0.01, 3)
     assert np.array_equal(a[-1]["psi"], b[-1]["psi"])
+
+
+def test_full_model_channel_stays_bounded(oracle_mod):
+    """Regression for the reading of the projection (R-27, Sec. II closing
+    paragraph): the full model (elliptic relaxation and projection) on a small
+    channel, 20 particles per element, 250 steps. With the non-incremental
+    projection (<P> = phi, particles corrected by -dt grad <P> at the next
+    step) velocities and stresses stay at their initial scale. The incremental
+    form (<P> += phi through the next predictor) fed the sampling noise of <U>
+    into <P> with no damping: on this channel it reached max|U| ~ 50 and node
+    <v'^2> ~ 400 by step 180, and its relaxation solve stopped converging at
+    step 289."""
+    mesh = W.channel(n_half=10, nx=24, seed_key=(1, 1, 0))
+    params = W.default_params(mode=2, dt=5e-4, nu=1.0 / 1080.0, n_scalars=0, dpdx=(-1.0, 0.0), stream=1)
+    parts = W.init_particles(mesh, 20, 0, W.rng_for(1, 1, 1), u_std=1.0)
+    n = len(parts["x"])
+    o = oracle_mod.Oracle()
+    cs = o.add_case(mesh, params)
+    o.upload(cs, parts)
+    o.init()
+    for _ in range(5):
+        o.step(50)
+        r = o.download(cs, n)
+        st = o.stats(cs)
+        umax = float(np.abs(np.stack([r["u"], r["v"], r["w"]])).max())
+        assert np.all(np.isfinite(st)) and umax < 8.0, umax
+        assert st[:, 5:8].max() < 6.0, st[:, 5:8].max()
+        assert np.abs(o.pressure(cs)).max() < 100.0
+    cnt = o.counters(cs)
+    assert cnt["nan"] == 0 and cnt["cg_fail"] == 0
