@@ -591,10 +591,12 @@ __global__ void k_mg_dinv(const AmgDev* __restrict__ hs, const int4* __restrict_
 }
 
 // Inverse of the (slightly shifted) coarsest matrix by Gauss-Jordan
-// elimination in LDS, one workgroup per hierarchy.
-__global__ void __launch_bounds__(1024) k_mg_coarse(const AmgDev* __restrict__ hs)
+// elimination in LDS, one workgroup per hierarchy: hierarchies first,
+// first + stride, ... (the relaxation hierarchies every solve, the constant
+// projection hierarchies once).
+__global__ void __launch_bounds__(1024) k_mg_coarse(const AmgDev* __restrict__ hs, int first, int stride)
 {
-    const AmgDev& H = hs[blockIdx.x];
+    const AmgDev& H = hs[first + stride * (int)blockIdx.x];
     const EllDev& Ac = H.A[H.nlev - 1];
     const int nc = Ac.n;
     __shared__ double a[AMG_MAXC * AMG_MAXC];

@@ -293,7 +293,7 @@ struct pdfmc_ctx {
     struct TabRange { int64_t off = 0; int n_er = 0, n_all = 0; };
     TabRange tab0;                  // level-0 rows of every system
     TabRange tabl[AMG_MAXL];        // level-l rows of the systems with more than l large levels
-    int n_tab_dinv = 0;
+    int n_tab_dinv = 0, n_tab_dinv_er = 0;     // entries; those of the relaxation hierarchies first
     int maxbig_er = 0, maxbig_all = 0;
     // solver options: unrolled iterations (adaptive when mg_auto), small-level threshold
     int mg_iters = 32, mg_auto = 1, tail_rows = 64;
@@ -793,10 +793,16 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
     TRY(h2d(c, c->d_mg_tab, tab));
     std::vector<int4>& td = c->h_tab_dinv;
     td.clear();
-    for (int hi = 0; hi < 2 * c->n_amg; ++hi) {
-        const AmgDev& D = c->h_amgdev[hi];
-        for (int l = 0; l < D.nlev; ++l)
-            for (int r0 = 0; r0 < D.n[l]; r0 += 256) td.push_back(make_int4(hi, l, r0, 0));
+    // the relaxation hierarchies (even index: refreshed every solve), then
+    // the projection hierarchies (odd: their matrices are constant, refreshed
+    // once when the workspace is bound)
+    for (int h = 0; h < 2; ++h) {
+        for (int hi = h; hi < 2 * c->n_amg; hi += 2) {
+            const AmgDev& D = c->h_amgdev[hi];
+            for (int l = 0; l < D.nlev; ++l)
+                for (int r0 = 0; r0 < D.n[l]; r0 += 256) td.push_back(make_int4(hi, l, r0, 0));
+        }
+        if (h == 0) c->n_tab_dinv_er = (int)td.size();
     }
     if ((int64_t)td.size() > c->MGTD) return fail(c, PDFMC_E_STATE, "solver tables exceed their reservation");
     c->n_tab_dinv = (int)td.size();
@@ -862,8 +868,10 @@ pdfmc_status enqueue_mg(pdfmc_ctx* c, bool project)
     const int32_t* S = c->d_mg_state;
     const unsigned g0 = cnt(c->tab0);
     hipStream_t st = c->stream;
-    hipLaunchKernelGGL(k_mg_dinv, dim3(c->n_tab_dinv), dim3(256), 0, st, H, (const int4*)c->d_mg_tab_dinv);
-    hipLaunchKernelGGL(k_mg_coarse, dim3(2 * c->n_amg), dim3(1024), 0, st, H);
+    // the relaxation matrices change every step; the projection hierarchies
+    // were prepared when the workspace was bound
+    hipLaunchKernelGGL(k_mg_dinv, dim3(c->n_tab_dinv_er), dim3(256), 0, st, H, (const int4*)c->d_mg_tab_dinv);
+    hipLaunchKernelGGL(k_mg_coarse, dim3(c->n_amg), dim3(1024), 0, st, H, 0, 2);
     // every phase whose workgroups each hold a share of a system's sums is
     // followed by k_mg_reduce, which adds the shares in block order
     auto reduce = [&](int k, int word0, int M, int setup, int big_only) {
@@ -1575,6 +1583,14 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                                  c->gal_lpe_p[l]));
             LAUNCHCHK(c);
         }
+        // the projection hierarchies' inverse diagonals and coarsest inverses,
+        // once: their matrices are constant
+        if (c->n_tab_dinv > c->n_tab_dinv_er)
+            hipLaunchKernelGGL(k_mg_dinv, dim3(c->n_tab_dinv - c->n_tab_dinv_er), dim3(256), 0, c->stream,
+                               (const AmgDev*)c->d_amg, (const int4*)c->d_mg_tab_dinv + c->n_tab_dinv_er);
+        if (c->n_amg > 0)
+            hipLaunchKernelGGL(k_mg_coarse, dim3(c->n_amg), dim3(1024), 0, c->stream, (const AmgDev*)c->d_amg, 1, 2);
+        LAUNCHCHK(c);
     }
     // the scatter's per-element lists and overflow sums start empty (the
     // element pass clears what it consumes)

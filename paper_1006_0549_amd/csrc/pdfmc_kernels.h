@@ -28,7 +28,7 @@ __global__ void k_proj_grad(NodeArgs A);
 __global__ void k_fields_freeze(const CaseDev* cases, const int32_t* node_case, const double* Ffrz, double* F, int nn);
 template <typename R> __global__ void k_fields_elem(const double* F, const double* gphi, const int4* tri_s, R* Fel, int ne);
 __global__ void k_mg_dinv(const AmgDev* hs, const int4* tab);
-__global__ void k_mg_coarse(const AmgDev* hs);
+__global__ void k_mg_coarse(const AmgDev* hs, int first, int stride);
 __global__ void k_mg_setup1(const MgJob* jobs, const int4* tab, const int32_t* st);
 __global__ void k_mg_setup2(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st);
 __global__ void k_mg_pa(const MgJob* jobs, const AmgDev* hs, const int4* tab, const int32_t* st, int k);
