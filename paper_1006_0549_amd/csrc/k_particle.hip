@@ -163,6 +163,60 @@ __device__ inline int wave_sum_int(int v)
     return v;
 }
 
+// The value of lane (lane xor m) for the constant masks of a 64-lane bitonic
+// sort, without a trip through LDS where the lane pattern allows: masks 1 and
+// 2 by a quad permutation, 4 by reversing each quad and then each half-row
+// (i -> 7 - (i xor 3) = i xor 4 within eight lanes), 8 by reversing each
+// half-row and then each row (likewise within sixteen), 16 by the swizzle's
+// bit-mask mode (xor 16 within 32 lanes), 32 by a permute through LDS.
+__device__ inline unsigned lane_xor(unsigned v, int m)
+{
+    const int x = (int)v;
+    switch (m) {
+    case 1: return (unsigned)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);
+    case 2: return (unsigned)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);
+    case 4: return (unsigned)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, false), 0x141, 0xF,
+                                                      0xF, false);
+    case 8: return (unsigned)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false), 0x140, 0xF,
+                                                      0xF, false);
+    case 16: return (unsigned)__builtin_amdgcn_ds_swizzle(x, 0x401F);
+    default: return (unsigned)__shfl_xor(x, m);
+    }
+}
+
+// Lane moves of an FP64 value by a DPP control (row mask: the rows written;
+// the others read 0).
+template <int CTRL, int ROWS>
+__device__ inline double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Inclusive sum of v over the lanes [st, lane] of the wavefront (st: the
+// first lane of this lane's segment), every lane active: shifts by 1, 2, 4
+// and 8 within each row of sixteen lanes, then the last lane of row 0 and of
+// row 2 added to the rows after them, then lane 31 to rows 2 and 3, each step
+// only where the segment reaches the lane it takes from.
+__device__ inline double seg_scan(double v, int lane, int st)
+{
+    double y;
+    y = dpp_f64<0x111, 0xF>(v);
+    v = (lane & 15) >= 1 && lane - 1 >= st ? v + y : v;
+    y = dpp_f64<0x112, 0xF>(v);
+    v = (lane & 15) >= 2 && lane - 2 >= st ? v + y : v;
+    y = dpp_f64<0x114, 0xF>(v);
+    v = (lane & 15) >= 4 && lane - 4 >= st ? v + y : v;
+    y = dpp_f64<0x118, 0xF>(v);
+    v = (lane & 15) >= 8 && lane - 8 >= st ? v + y : v;
+    y = dpp_f64<0x142, 0xA>(v);                  // rows 1 and 3 take lanes 15 and 47
+    v = ((lane >> 4) & 1) && st <= (lane & ~15) - 1 ? v + y : v;
+    y = dpp_f64<0x143, 0xC>(v);                  // rows 2 and 3 take lane 31
+    v = lane >= 32 && st <= 31 ? v + y : v;
+    return v;
+}
+
 // ---------------------------------------------------------------- scatter helpers
 
 // per-lane record in LDS: lambda_0..2, w | U_1..3, omega | psi_0..3 | 1, 0
@@ -387,7 +441,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     for (int kk = 2; kk <= 64; kk <<= 1) {
 #pragma unroll
         for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            const unsigned o = (unsigned)__shfl_xor((int)sk, jj);
+            const unsigned o = lane_xor(sk, jj);
             const bool keep_min = ((lane & jj) == 0) == ((lane & kk) == 0);
             sk = keep_min ? min(o, sk) : max(o, sk);
         }
@@ -617,12 +671,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         const unsigned ckn = (unsigned)__shfl_down((int)ck, 1);
         const bool chead = lane == 0 || ckp != ck;
         const bool ctail = lane == 63 || ckn != ck;
-        int st = chead ? lane : 0;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int o = __shfl_up(st, d);
-            if (lane >= d && o > st) st = o;
-        }
+        // the run's first position: the last run head at or before this one
+        const int st = 63 - __clzll(__ballot(chead) & upto);
         const R* rq = wave_rec + src * NREC;
         const double w = pv ? (double)rq[3] : 0.0;
         double x[2 + MAXS];
@@ -631,15 +681,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
         for (int a = 0; a < MAXS; ++a) x[2 + a] = a < ns ? w * (double)rq[8 + a] : 0.0;
 #pragma unroll
-        for (int j2 = 0; j2 < 2 + MAXS; ++j2) {
-            if (j2 < nc) {
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const double y = __shfl_up(x[j2], d);
-                    if (lane - d >= st) x[j2] += y;
-                }
-            }
-        }
+        for (int j2 = 0; j2 < 2 + MAXS; ++j2)
+            if (j2 < nc) x[j2] = seg_scan(x[j2], lane, st);
         if (pv && ctail) {
             const int off = 3 * nq + sbin * nc;
             if (rkind == 1) {
