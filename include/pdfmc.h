@@ -277,8 +277,12 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t bl
  * synchronisation). Multigrid levels with more than tail_rows unknowns (default
  * 64) are processed by the row-parallel phases, smaller ones by one
  * workgroup per system. Results do not depend on either option beyond FP64
- * summation order. Errors: PDFMC_E_INVALID for iterations outside 0..100000
- * or tail_rows < 0. */
+ * summation order. Every scalar of the CG is summed in a fixed order (the
+ * row-parallel workgroups' shares, then the system's shares in block order),
+ * so with fixed settings the solves repeat bit for bit, and a case's solution
+ * does not depend on the other cases of the context as long as it completes
+ * within the row-parallel iterations. Errors: PDFMC_E_INVALID for iterations
+ * outside 0..100000 or tail_rows < 0. */
 pdfmc_status pdfmc_set_solver(pdfmc_ctx* ctx, int32_t iterations, int32_t tail_rows);
 /* Current unrolled iteration count and number of row-parallel levels
  * (either pointer may be NULL). */
@@ -294,6 +298,8 @@ pdfmc_status pdfmc_solver_info(pdfmc_ctx* ctx, int32_t* iterations, int32_t* lar
  * relaxation instead. The factor is used only when every mode-2 case has one
  * (a case whose factor has a supernode or reach above 2048 unknowns has
  * none). Results do not depend on the choice beyond the solver tolerance.
+ * The sweeps apply the updates of an unknown from the supernodes below it in
+ * a fixed (supernode) order, so a projection repeats bit for bit.
  * Errors: PDFMC_E_INVALID for another method. */
 typedef enum { PDFMC_PROJ_DIRECT = 0, PDFMC_PROJ_PCG = 1 } pdfmc_projection_method;
 pdfmc_status pdfmc_set_projection_solver(pdfmc_ctx* ctx, int32_t method);
