@@ -394,6 +394,63 @@ def test_reflection_cap_falls_back(oracle_mod):
     assert e == best
 
 
+def test_reflection_at_walls_of_any_orientation(oracle_mod):
+    """R-14 on the polygonal walls of an annulus, whose edges face every
+    direction: for each boundary edge, a point just beyond it (barycentric
+    -0.1 against the edge) comes back into the same element at its mirror
+    image in the edge's line, the one other point as far from both ends of
+    the edge as it is, and the velocity becomes 2 u_wall - u with that
+    edge's own wall velocity (each inner edge moves along itself)."""
+    mesh = W.annulus(n_r=4, n_theta=24, seed_key=(98, 0, 0))
+    o = oracle_mod.Oracle()
+    cs = o.add_case(mesh, W.default_params(mode=0, n_scalars=0, dpdx=(0.0, 0.0)))
+    va, vb = mesh.tri[:, [1, 2, 0]], mesh.tri[:, [2, 0, 1]]
+    edges = np.argwhere(mesh.edge_tag >= 0)
+    assert len(edges) == 48
+    u = (0.3, -0.7, 0.2)
+    for e, k in edges:
+        a, b = mesh.xy[va[e, k]], mesh.xy[vb[e, k]]
+        mid, cen = 0.5 * (a + b), mesh.xy[mesh.tri[e]].mean(0)
+        t = 1.3 * mid - 0.3 * cen
+        e2, x, y, u2 = o.walk(cs, int(e), float(t[0]), float(t[1]), u)
+        p = np.array([x, y])
+        assert e2 == e
+        assert np.linalg.norm(p - t) > 0.1 * np.linalg.norm(mid - cen)
+        for q in (a, b):
+            assert abs(np.linalg.norm(p - q) - np.linalg.norm(t - q)) < 1e-13
+        assert o.bary(cs, int(e), x, y).min() > 0.05
+        uw = np.array(mesh.bcs[mesh.edge_tag[e, k]]["u_wall"])
+        np.testing.assert_allclose(u2, 2.0 * uw - np.array(u), rtol=0, atol=1e-15)
+    cnt = o.counters(cs)
+    assert cnt["reflect"] == len(edges) and cnt["walk_fallback"] == 0
+
+
+def test_annulus_run_keeps_every_particle_inside(oracle_mod):
+    """Frozen fields on the annulus (rotating inner wall), velocities of a
+    tenth of the element size per step: after 30 steps every particle lies in
+    the element it is assigned to, the walls have reflected particles on
+    both circles, and nothing fell back or went non-finite."""
+    mesh = W.annulus(n_r=4, n_theta=24, seed_key=(98, 0, 0))
+    params = W.default_params(mode=0, dt=2e-3, nu=1e-3, n_scalars=0, dpdx=(0.0, 0.0))
+    parts = W.init_particles(mesh, 20, 0, W.rng_for(98, 0, 1), u_std=3.0)
+    F = W.frozen_fields(mesh, C0=2.1, omega=1.0, k=2.0, dpdx=(0.0, 0.0))
+    o = oracle_mod.Oracle()
+    cs = o.add_case(mesh, params)
+    o.upload(cs, parts)
+    o.fields_upload(cs, F)
+    o.init()
+    o.step(30)
+    n = len(parts["x"])
+    r = o.download(cs, n)
+    lam = np.array([o.bary(cs, int(e), x, y) for e, x, y in zip(r["elem"], r["x"], r["y"])])
+    assert lam.min() > -1e-12
+    rad = np.hypot(r["x"], r["y"])
+    assert rad.max() <= 1.0 + 1e-12 and rad.min() >= 0.5 * math.cos(math.pi / 24) - 1e-12
+    cnt = o.counters(cs)
+    assert cnt["reflect"] > 50 and cnt["walk_fallback"] == 0 and cnt["nan"] == 0
+    assert np.isfinite(r["u"]).all()
+
+
 # ------------------------------------------------------------ regression record
 
 def test_oracle_reproduces_its_regression_record(oracle_mod):

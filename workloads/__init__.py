@@ -243,6 +243,52 @@ def cavity(n_half: int = 112, first: float = 1e-3, lid: float = 1.0, seed_key=(3
     return Mesh(f"cavity{tri.shape[0]}", xy, tri, tag, bcs)
 
 
+def annulus(n_r: int = 8, n_theta: int = 50, r0: float = 0.5, r1: float = 1.0, spin: float = 1.0,
+            jitter: float = 0.2, seed_key=(6, 0, 0)) -> Mesh:
+    """Ring r0 <= r <= r1 between two circular walls drawn as polygons: n_theta
+    nodes on each circle at the angles 2 pi j / n_theta, n_r radial intervals,
+    interior nodes jittered by +-jitter of the local spacing in r and theta;
+    each quadrilateral cell split along one diagonal, alternating. The outer
+    wall is at rest. Every edge of the inner wall is a wall of its own moving
+    at spin * r0 along the edge (the circle's tangent at the edge's mid-angle,
+    counter-clockwise): a rotating inner cylinder. Boundaries: 0 the outer
+    wall, 1..n_theta the inner wall's edges."""
+    rng = rng_for(*seed_key)
+    dr, dth = (r1 - r0) / n_r, 2.0 * math.pi / n_theta
+    r = r0 + dr * np.arange(n_r + 1)[:, None] + np.zeros((1, n_theta))
+    th = dth * np.arange(n_theta)[None, :] + np.zeros((n_r + 1, 1))
+    r[1:-1] += rng.uniform(-jitter, jitter, size=(n_r - 1, n_theta)) * dr
+    th[1:-1] += rng.uniform(-jitter, jitter, size=(n_r - 1, n_theta)) * dth
+    xy = np.stack([(r * np.cos(th)).reshape(-1), (r * np.sin(th)).reshape(-1)], axis=1)
+    tri = []
+    for i in range(n_r):
+        for j in range(n_theta):
+            a, b = i * n_theta + j, i * n_theta + (j + 1) % n_theta
+            c, d = b + n_theta, a + n_theta
+            tri += [(a, b, c), (a, c, d)] if (i + j) % 2 == 0 else [(a, b, d), (b, c, d)]
+    tri = _orient_ccw(xy, np.array(tri, np.int32))
+    if not (element_areas(Mesh("", xy, tri, None, [])) > 0).all():
+        raise ValueError("annulus: degenerate triangle")
+
+    def classify(pa, pb):
+        ra, rb = math.hypot(*pa), math.hypot(*pb)
+        if abs(ra - r1) < 1e-12 and abs(rb - r1) < 1e-12:
+            return 0
+        if abs(ra - r0) < 1e-12 and abs(rb - r0) < 1e-12:
+            return 1
+        return -1
+
+    tag = _tag_edges(xy, tri, classify)
+    bcs = [dict(type=BC_WALL, u_wall=(0.0, 0.0, 0.0))]
+    va, vb = tri[:, [1, 2, 0]], tri[:, [2, 0, 1]]
+    for e, k in np.argwhere(tag == 1):
+        m = 0.5 * (xy[va[e, k]] + xy[vb[e, k]])
+        t = np.array([-m[1], m[0]]) / math.hypot(*m)
+        tag[e, k] = len(bcs)
+        bcs.append(dict(type=BC_WALL, u_wall=(spin * r0 * t[0], spin * r0 * t[1], 0.0)))
+    return Mesh(f"annulus{tri.shape[0]}", xy, tri, tag, bcs)
+
+
 # ----------------------------------------------------------------- particles
 
 def element_areas(mesh: Mesh) -> np.ndarray:
