@@ -252,9 +252,11 @@ pdfmc_status pdfmc_cell_means(pdfmc_ctx* ctx, int32_t case_id, double* mean, int
  * periodic crossings, omega sign flips, empty nodes, non-finite particles,
  * walk steps, ER CG iterations, projection CG iterations, CG failures,
  * k floor hits, eps floor hits, scatter overflows (a workgroup's element sums
- * that found no record slot or record list entry and were added with FP64
- * atomics instead: while this counter is 0, every statistic is summed in a
- * fixed order and a step repeats bit for bit). The five relaxation components of a case
+ * that found no record slot, belong to an element with more than 256
+ * records in the pass or found the pass's overflow list full, and were added
+ * with FP64 atomics instead: while this
+ * counter is 0, every statistic is summed in a fixed order and a step repeats
+ * bit for bit). The five relaxation components of a case
  * are solved as one system with five right-hand sides: its iterations count
  * once per component (the iterations until every component converged). */
 pdfmc_status pdfmc_counters(pdfmc_ctx* ctx, int32_t case_id, int64_t* out);

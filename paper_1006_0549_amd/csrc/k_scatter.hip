@@ -4,8 +4,10 @@
 // bits every time it runs on the same input.
 //
 //   k_scatter_register  one thread per record slot: lists each record written
-//                  this step under its element (an element with more than
-//                  SC_K records takes the rest as overflow sums, counted)
+//                  this step under its element (SC_K entries per element; up
+//                  to SC_XK more go to one overflow list for the pass; beyond
+//                  that, or with that list full, into FP64 overflow sums,
+//                  counted as scatter overflow)
 //   k_elem_reduce  one wavefront per element: the element's records (listed
 //                  in any order) are sorted by key and summed in that order,
 //                  plus the overflow sums when the element had any. Out: the
@@ -21,6 +23,14 @@
 #include "pdfmc_nodes.h"
 
 namespace pdfmc {
+
+// a wavefront's LDS writes made visible to all of its lanes
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ void k_scatter_register(NodeArgs A, int ntiles, int block, const int32_t* tile_case, const int32_t* pool_cnt,
                                    int pool_cap, unsigned long long* counters, int cells_on)
@@ -51,13 +61,24 @@ __global__ void k_scatter_register(NodeArgs A, int ntiles, int block, const int3
     const int el = (int)__double_as_longlong(rp[1]);
     if (t >= nreg) c = A.elem_case[el];
     const int slot = atomicAdd(A.ecnt + el, 1);
+    // the key travels with the handle, so the element pass ranks its records
+    // without reading their headers
+    const int64_t entry = (int64_t)((unsigned long long)key << 32 | (uint32_t)handle);
     if (slot < SC_K) {
-        // the key travels with the handle, so the element pass ranks its
-        // records without reading their headers
-        A.eslot[(int64_t)el * SC_K + slot] = (int64_t)((unsigned long long)key << 32 | (uint32_t)handle);
+        A.eslot[(int64_t)el * SC_K + slot] = entry;
         return;
     }
-    // list full: the record's values go to the element's overflow sums
+    if (slot < SC_K + SC_XK) {
+        // beyond the element's list: the pass's overflow list, which the
+        // element pass searches for the element's further records
+        const int q = atomicAdd(A.ovl_n, 1);
+        if (q < A.ovl_cap) {
+            A.ovl[q] = entry;
+            A.ovl_el[q] = el;
+            return;
+        }
+    }
+    // both lists full: the record's values go to the element's overflow sums
     const CaseDev& C = A.cases[c];
     const int ns = C.ns, nq = 12 + 2 * ns, nc = 2 + ns;
     const bool cells = cells_on && ns > 0;
@@ -74,6 +95,9 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__ cmean, int cells_on, int rebin_only)
 {
     __shared__ double s_cell[4][8 * (2 + MAXS)];
+    __shared__ int64_t s_xent[4][SC_XK];              // an element's records from the overflow list
+    __shared__ int s_rank_h[4][SC_K + SC_XK];         // its records' handles in key order
+    __shared__ int s_nx[4];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t e = (int64_t)blockIdx.x * 4 + wid;
     if (e >= A.ne) return;            // whole wavefronts leave together
@@ -86,43 +110,106 @@ __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__
     // the list entries are read together with the count (entries past the
     // count are stale and unused); lane j < n: record j as listed, and its key
     const int64_t ent = A.eslot[e * SC_K + lane];
-    const int n = min(A.ecnt[e], SC_K);
-    const double* rp = nullptr;
-    long long key = 0x7fffffffffffffffll;
-    if (lane < n) {
-        const int h = (int)(uint32_t)ent;
-        rp = h >= 0 ? A.srec + C.rec_off + (int64_t)h * C.rec_stride
-                    : A.srec + A.pool_off + (int64_t)(-1 - h) * A.pool_stride;
-        key = (long long)((unsigned long long)ent >> 32);
-    }
-    // rank of the record among the element's records (keys are distinct)
-    int rank = 0;
-    for (int i = 0; i < n; ++i) rank += __shfl(key, i) < key ? 1 : 0;
+    const int cnt = A.ecnt[e];
+    auto rec_of = [&](int h) -> const double* {
+        return h >= 0 ? A.srec + C.rec_off + (int64_t)h * C.rec_stride
+                      : A.srec + A.pool_off + (int64_t)(-1 - h) * A.pool_stride;
+    };
     // the bin of each lane's cell values (-1: a vertex sum); a record's cell
     // values are valid for the bins in its mask only
     const int b0 = cells && lane >= 3 * nq && lane < nv ? (lane - 3 * nq) / nc : -1;
     const int b1 = cells && lane + 64 >= 3 * nq && lane + 64 < nv ? (lane + 64 - 3 * nq) / nc : -1;
     double acc0 = 0.0, acc1 = 0.0;
-    // four records at a time: their loads first, then the sums in rank order
-    for (int r0 = 0; r0 < n; r0 += 4) {
-        long long mk[4];
-        double x0[4], x1[4];
+    if (cnt <= SC_K) {
+        const int n = cnt;
+        const double* rp = nullptr;
+        long long key = 0x7fffffffffffffffll;
+        if (lane < n) {
+            rp = rec_of((int)(uint32_t)ent);
+            key = (long long)((unsigned long long)ent >> 32);
+        }
+        // rank of the record among the element's records (keys are distinct)
+        int rank = 0;
+        for (int i = 0; i < n; ++i) rank += __shfl(key, i) < key ? 1 : 0;
+        // four records at a time: their loads first, then the sums in rank order
+        for (int r0 = 0; r0 < n; r0 += 4) {
+            long long mk[4];
+            double x0[4], x1[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            mk[u] = 0; x0[u] = 0.0; x1[u] = 0.0;
-            if (r0 + u < n) {
-                const int src = __ffsll((long long)__ballot(lane < n && rank == r0 + u)) - 1;
-                const double* q = (const double*)__shfl((long long)rp, src);
-                mk[u] = __double_as_longlong(q[2]);
-                if (lane < nv) x0[u] = q[SC_HDR + lane];
-                if (lane + 64 < nv) x1[u] = q[SC_HDR + 64 + lane];
+            for (int u = 0; u < 4; ++u) {
+                mk[u] = 0; x0[u] = 0.0; x1[u] = 0.0;
+                if (r0 + u < n) {
+                    const int src = __ffsll((long long)__ballot(lane < n && rank == r0 + u)) - 1;
+                    const double* q = (const double*)__shfl((long long)rp, src);
+                    mk[u] = __double_as_longlong(q[2]);
+                    if (lane < nv) x0[u] = q[SC_HDR + lane];
+                    if (lane + 64 < nv) x1[u] = q[SC_HDR + 64 + lane];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (r0 + u < n) {
+                    if (lane < nv && (b0 < 0 || ((mk[u] >> b0) & 1))) acc0 += x0[u];
+                    if (lane + 64 < nv && (b1 < 0 || ((mk[u] >> b1) & 1))) acc1 += x1[u];
+                }
             }
         }
+    } else {
+        // more records than the list holds: the element's further records (up
+        // to SC_XK) are in the pass's overflow list. They are gathered into
+        // LDS, each record is ranked by key among all of the element's, and
+        // the sums are taken in that order, as for a listed element.
+        int64_t* xs = s_xent[wid];
+        int* hs = s_rank_h[wid];
+        if (lane == 0) s_nx[wid] = 0;
+        wave_lds_sync();
+        const int nov = min(*A.ovl_n, A.ovl_cap);
+        for (int i = lane; i < nov; i += 64)
+            if (A.ovl_el[i] == (int32_t)e) {
+                const int q = atomicAdd(&s_nx[wid], 1);
+                if (q < SC_XK) xs[q] = A.ovl[i];
+            }
+        wave_lds_sync();
+        const int n = SC_K + min(s_nx[wid], SC_XK);
+        constexpr int MR = (SC_K + SC_XK) / 64;
+        long long kj[MR];
+        int hj[MR], rk[MR];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (r0 + u < n) {
-                if (lane < nv && (b0 < 0 || ((mk[u] >> b0) & 1))) acc0 += x0[u];
-                if (lane + 64 < nv && (b1 < 0 || ((mk[u] >> b1) & 1))) acc1 += x1[u];
+        for (int m = 0; m < MR; ++m) {
+            const int j = lane + 64 * m;
+            const int64_t en = m == 0 ? ent : (j < n ? xs[j - SC_K] : 0);
+            kj[m] = j < n ? (long long)((unsigned long long)en >> 32) : 0x7fffffffffffffffll;
+            hj[m] = (int)(uint32_t)en;
+            rk[m] = 0;
+        }
+        for (int i = 0; i < n; ++i) {
+            const long long ki = i < SC_K ? __shfl(kj[0], i) : (long long)((unsigned long long)xs[i - SC_K] >> 32);
+#pragma unroll
+            for (int m = 0; m < MR; ++m) rk[m] += ki < kj[m] ? 1 : 0;
+        }
+#pragma unroll
+        for (int m = 0; m < MR; ++m)
+            if (lane + 64 * m < n) hs[rk[m]] = hj[m];
+        wave_lds_sync();
+        for (int r0 = 0; r0 < n; r0 += 4) {
+            long long mk[4];
+            double x0[4], x1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                mk[u] = 0; x0[u] = 0.0; x1[u] = 0.0;
+                if (r0 + u < n) {
+                    const double* q = rec_of(hs[r0 + u]);
+                    mk[u] = __double_as_longlong(q[2]);
+                    if (lane < nv) x0[u] = q[SC_HDR + lane];
+                    if (lane + 64 < nv) x1[u] = q[SC_HDR + 64 + lane];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (r0 + u < n) {
+                    if (lane < nv && (b0 < 0 || ((mk[u] >> b0) & 1))) acc0 += x0[u];
+                    if (lane + 64 < nv && (b1 < 0 || ((mk[u] >> b1) & 1))) acc1 += x1[u];
+                }
             }
         }
     }
@@ -143,9 +230,7 @@ __global__ void __launch_bounds__(256) k_elem_reduce(NodeArgs A, R* __restrict__
     const int v0 = lane - 3 * nq, v1 = lane + 64 - 3 * nq;
     if (v0 >= 0 && v0 < 8 * nc) s_cell[wid][v0] = acc0;
     if (v1 >= 0 && v1 < 8 * nc) s_cell[wid][v1] = acc1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
     if (lane < 8) A.ccnt[e * 8 + lane] = (int32_t)s_cell[wid][lane * nc];
     // lane (b, a): mean of scalar a in bin b; bins with fewer than n_min
     // particles share one residual cell, pooled in bin order

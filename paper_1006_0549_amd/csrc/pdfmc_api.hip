@@ -269,6 +269,9 @@ struct pdfmc_ctx {
     int pool_cap = 0;
     int32_t *d_pool_cnt = nullptr, *d_ecnt = nullptr, *d_eof = nullptr, *d_wgcnt = nullptr;
     int64_t* d_eslot = nullptr;
+    int64_t* d_ovl = nullptr;       // the element lists' overflow list
+    int32_t* d_ovl_el = nullptr;
+    int32_t ovl_cap = 0;
     double *d_eo = nullptr, *d_etot = nullptr;
     char* d_Fel = nullptr;          // element-major fields in the particle precision
     double* d_Ffrz = nullptr;       // uploaded fields, for the slots a case keeps frozen
@@ -430,9 +433,12 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_nsum, (size_t)c->NN * NQ);
     k.take(c->d_stats, (size_t)c->NN * NST);
     k.take(c->d_srec, c->SREC);
-    k.take(c->d_pool_cnt, 1);
+    k.take(c->d_pool_cnt, 2);       // record pool count, overflow-list count
     k.take(c->d_ecnt, c->NE);
     k.take(c->d_eslot, (size_t)c->NE * SC_K);
+    c->ovl_cap = (int32_t)std::max<int64_t>(65536, c->NE);
+    k.take(c->d_ovl, (size_t)c->ovl_cap);
+    k.take(c->d_ovl_el, (size_t)c->ovl_cap);
     k.take(c->d_eof, c->NE);
     k.take(c->d_eo, (size_t)c->NE * SC_VMAX);
     k.take(c->d_wgcnt, 4 * (size_t)c->ntiles);
@@ -596,6 +602,7 @@ NodeArgs node_args(pdfmc_ctx* c)
     A.nsum = c->d_nsum; A.stats = c->d_stats; A.F = c->d_F; A.csum = nullptr; A.ccnt = c->d_ccnt;
     A.srec = c->d_srec; A.pool_off = c->pool_off; A.pool_stride = SC_HDR + SC_VMAX;
     A.ecnt = c->d_ecnt; A.eslot = c->d_eslot; A.eof = c->d_eof; A.eo = c->d_eo; A.wgcnt = c->d_wgcnt; A.etot = c->d_etot;
+    A.ovl = c->d_ovl; A.ovl_el = c->d_ovl_el; A.ovl_n = c->d_pool_cnt + 1; A.ovl_cap = c->ovl_cap;
     A.kf = c->d_kf; A.ef = c->d_ef; A.L2 = c->d_L2; A.er_r = c->d_er_r; A.er_dval = c->d_er_dval; A.er_b = c->d_er_b;
     A.er_x = c->d_er_x; A.er_val = c->d_er_val; A.pk_val = c->d_pk_val; A.pb = c->d_pb; A.phi = c->d_phi; A.P = c->d_P; A.gphi = c->d_gphi;
     A.counters = c->d_counters;
@@ -685,11 +692,12 @@ pdfmc_status enqueue_particles(pdfmc_ctx* c, int advance, int do_bins, int scatt
     return PDFMC_OK;
 }
 
-// Before a particle-kernel launch: the record pool starts empty (the element
-// pass leaves the per-element lists and overflow sums cleared).
+// Before a particle-kernel launch: the record pool and the element lists'
+// overflow list start empty (the element pass leaves the per-element lists
+// and overflow sums cleared).
 pdfmc_status enqueue_accum_clear(pdfmc_ctx* c)
 {
-    return enqueue_fill_i(c, c->d_pool_cnt, 1);
+    return enqueue_fill_i(c, c->d_pool_cnt, 2);
 }
 
 void drop_graphs(pdfmc_ctx* c);

@@ -52,6 +52,12 @@ struct NodeArgs {
     double* eo;                      // [ne][SC_VMAX] overflow sums
     const int32_t* wgcnt;            // [workgroups] regular record slots used by each workgroup
     double* etot;                    // [ne][3][NQ] vertex sums of each element
+    // an element's records beyond its SC_K list entries (up to SC_XK more):
+    // appended to one list for the pass, which the element pass searches
+    int64_t* ovl;                    // [ovl_cap] key << 32 | handle, as in eslot
+    int32_t* ovl_el;                 // [ovl_cap] their elements
+    int32_t* ovl_n;                  // entries appended in this pass (cleared before each particle kernel)
+    int32_t ovl_cap, pad3;
 };
 
 constexpr int AMG_MAXL = 8;        // multigrid levels

@@ -10,7 +10,12 @@ C ABI:
     and a case with no particles at all beside an ordinary case: three
     frozen-field steps give the oracle's state bit for bit in every case, the
     same counters, and for the empty case all-zero statistics (every node
-    empty keeps the zero moments it started with).
+    empty keeps the zero moments it started with);
+  - elements with records in more workgroups than their 64 list entries
+    (particles spread one per workgroup): the further records go through the
+    pass's overflow list and are summed in key order like the others, so
+    nothing falls back to atomics, two runs agree bit for bit, and the FP64
+    sums match the oracle's.
 """
 import numpy as np
 import pytest
@@ -127,3 +132,72 @@ def test_one_particle_and_empty_cases_in_a_batch(P, oracle_mod):
             assert gc_[k] == rc_[k], (len(e["x"]), k, gc_[k], rc_[k])
     empty = sim.stats(cases[2][0])
     assert not empty.any()
+
+
+def _spread_case(seed=73):
+    """The small square (450 elements) with 100 particles of each of
+    elements 0, 1 and 2 spread one per workgroup: workgroup w starts with the
+    w-th particle of each of the three, then 253 of the other elements'
+    particles in element order. Each of the three elements then has a record
+    in each of 100 workgroups, more than its 64 list entries."""
+    mesh = W.unit_square(16, 0.2, periodic_x=True, periodic_y=False, seed_key=(73, 0, 0))
+    rng = np.random.default_rng(seed)
+    base = W.init_particles(mesh, 60, 1, rng, u_std=0.3, psi_disks=[(0.5, 0.5, 0.25, 1.0)])
+    dense = W.init_particles(mesh, 100, 1, rng, u_std=0.3, psi_disks=[(0.5, 0.5, 0.25, 1.0)])
+    heads = [np.nonzero(dense["elem"] == el)[0] for el in range(3)]
+    rest = np.nonzero(base["elem"] >= 3)[0]
+    order = []
+    for w in range(100):
+        order += [("d", heads[el][w]) for el in range(3)]
+        order += [("b", r) for r in rest[253 * w:253 * (w + 1)]]
+    order += [("b", r) for r in rest[253 * 100:]]
+    parts = {}
+    for key in base:
+        col = [dense[key][..., i] if src == "d" else base[key][..., i] for src, i in order]
+        parts[key] = np.stack(col, axis=-1) if base[key].ndim == 2 else np.array(col, dtype=base[key].dtype)
+    parts["id"] = np.arange(len(order), dtype=np.uint32)
+    F = W.frozen_fields(mesh, C0=2.1, omega=1.3, k=0.02)
+    params = W.default_params(mode=0, dt=2e-3, nu=2e-3, n_scalars=1, n_bins=8, src=[])
+    return mesh, params, parts, F
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_elements_with_more_records_than_their_list(P, oracle_mod, precision):
+    """Elements whose particles lie in more workgroups than the 64 list
+    entries of an element: their further records go through the pass's
+    overflow list and are still summed in key order, so no sum falls back to
+    atomics (scatter_overflow stays 0), two runs give the same bits, and the
+    FP64 node sums and statistics match the oracle to the bar of a listed
+    element."""
+    mesh, params, parts, F = _spread_case()
+    n = len(parts["x"])
+    _flush(f"[spread] {precision}: {n} particles, elements 0-2 spread one particle per workgroup, 2 frozen steps")
+
+    def run():
+        sim = P.Sim(precision, "cuda:0")
+        cs = sim.add_case(mesh, params, n)
+        sim.bind()
+        sim.fields_upload(cs, F)
+        sim.upload(cs, parts)
+        sim.init()
+        sim.step(2)
+        return sim, cs
+
+    s1, c1 = run()
+    s2, c2 = run()
+    assert s1.counters(c1)["scatter_overflow"] == 0
+    assert np.array_equal(s1.node_sums(c1), s2.node_sums(c2))
+    assert np.array_equal(s1.stats(c1), s2.stats(c2))
+    if precision == "fp64":
+        o = oracle_mod.Oracle()
+        oc = o.add_case(mesh, params)
+        o.fields_upload(oc, F)
+        o.upload(oc, parts)
+        o.init(); o.step(2)
+        _assert_state_equal(s1.download(c1, n), o.download(oc, n))
+        gs, rs = s1.node_sums(c1), o.node_sums(oc)
+        tol = 1e-13 * np.abs(rs).max(0) + 1e-300
+        assert np.all(np.abs(gs - rs) <= np.maximum(tol, 1e-13 * np.abs(rs))), np.max(np.abs(gs - rs))
+        rows = _stat_rows(s1, c1)
+        d = np.abs(s1.stats(c1) - o.stats(oc))[rows] / _scale(o.stats(oc), 1)[rows]
+        assert d.max() <= 1e-12, d.max()
