@@ -226,3 +226,32 @@ def test_batch32_sort_is_a_permutation_at_full_size(P):
         assert same.mean() >= 1.0 - 1e-5, (ci, same.mean())
         for k in ("x", "y", "u", "v", "w", "omega"):
             assert np.allclose(A[k][same], B[k][same], rtol=1e-9, atol=1e-12), (ci, k)
+
+
+def test_batch32_full_size_runs_twice_bitwise(P):
+    """The benchmark's launch configuration (FP32, the 32-case batch, graph
+    replay, block 256, sort every 5 steps, tail rows 256) run twice from the
+    same upload for eight steps, a sort included: the node sums, statistics
+    and fields of every case are the same bits, and no element sum fell back
+    to atomics."""
+    b = W.config_batched()
+    cases = b["cases"]
+    _flush(f"[fullsize] batch32 run twice: {len(cases)} cases, FP32, graph replay, 8 steps each")
+    out = []
+    for run in range(2):
+        sim = P.Sim("fp32", "cuda:0")
+        ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in cases]
+        sim.bind()
+        sim.set_options(sort_interval=5, block_size=256, use_graph=True)
+        sim.set_solver(iterations=0, tail_rows=256)
+        for cs, c in zip(ids, cases):
+            sim.upload(cs, c["particles"])
+        sim.init()
+        sim.step(8)
+        out.append([(sim.node_sums(cs), sim.stats(cs), sim.fields(cs), sim.counters(cs)) for cs in ids])
+        _flush(f"[fullsize] batch32 run twice: run {run} done")
+        del sim
+    for ci, (a, b_) in enumerate(zip(*out)):
+        assert a[3]["scatter_overflow"] == 0 and a[3]["nan"] == 0, (ci, a[3])
+        for k in range(3):
+            assert np.array_equal(a[k], b_[k]), (ci, k)
