@@ -61,7 +61,6 @@ constexpr int SC_HDR = 3;
 constexpr int SC_RT = 40;       // regular record slots per particle tile
 constexpr int SC_SQ = 6;        // sums of shared elements a wavefront stages in LDS for the merge
 constexpr int SC_K = 64;        // record handles listed per element per step (one per lane of the element pass)
-constexpr int SC_XK = 192;      // further records per element, through the step's overflow list
 constexpr int SC_VMAX = 3 * NQ + 8 * (2 + MAXS);   // values of a record
 __device__ __host__ inline int sc_nvals(int ns, bool cells) { return 3 * (12 + 2 * ns) + (cells ? 8 * (2 + ns) : 0); }
 

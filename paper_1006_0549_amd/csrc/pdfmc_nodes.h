@@ -4,6 +4,10 @@
 
 namespace pdfmc {
 
+// records of an element beyond its SC_K list entries that the element pass
+// still sums in key order, through one overflow list per pass
+constexpr int SC_XK = 192;
+
 struct NodeArgs {
     int32_t nn, ne;                  // global statistics nodes and elements
     int32_t first_stats;             // 1: no previous node statistics exist yet
