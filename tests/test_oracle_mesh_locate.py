@@ -57,6 +57,34 @@ def test_euler_formula_and_area(oracle_mod):
     assert abs(info["vol"].sum() - 1.0) < 1e-13
 
 
+
+def test_annulus_mesh(oracle_mod):
+    """The ring between two polygonal circles: Euler's formula for a domain
+    with one hole (N_e = 2 N_n - N_b: no -2), the area of the ring between
+    two regular n-gons, n (r1^2 - r0^2) sin(2 pi / n) / 2, 2n boundary edges
+    whose ends lie on one circle, and each inner edge's wall velocity along
+    the edge at spin * r0."""
+    n, r0, r1 = 30, 0.4, 1.2
+    mesh = W.annulus(n_r=5, n_theta=n, r0=r0, r1=r1, spin=2.0, seed_key=(95, 0, 0))
+    o, cs = _case(oracle_mod, mesh)
+    edges = np.argwhere(mesh.edge_tag >= 0)
+    assert len(edges) == 2 * n
+    bnodes = set()
+    for e, k in edges:
+        a, b = mesh.xy[mesh.tri[e, (k + 1) % 3]], mesh.xy[mesh.tri[e, (k + 2) % 3]]
+        bnodes.update((int(mesh.tri[e, (k + 1) % 3]), int(mesh.tri[e, (k + 2) % 3])))
+        ra, rb = np.hypot(*a), np.hypot(*b)
+        assert abs(ra - rb) < 1e-12 and min(abs(ra - r0), abs(ra - r1)) < 1e-12
+        uw = np.array(mesh.bcs[mesh.edge_tag[e, k]]["u_wall"][:2])
+        if abs(ra - r0) < 1e-12:
+            t = (b - a) / np.linalg.norm(b - a)
+            assert abs(abs(uw @ t) - 2.0 * r0) < 1e-12 and abs(uw @ np.array([-t[1], t[0]])) < 1e-12
+        else:
+            assert not uw.any()
+    assert mesh.n_elems == 2 * mesh.n_nodes - len(bnodes)
+    area = 0.5 * n * (r1 ** 2 - r0 ** 2) * np.sin(2 * np.pi / n)
+    assert abs(o.mesh_info(cs)["vol"].sum() - area) < 1e-13 * area
+
 def test_periodic_merge(square):
     mesh, o, cs = square
     info = o.mesh_info(cs)
