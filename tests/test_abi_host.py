@@ -202,3 +202,28 @@ def test_init_fields_and_stage_rejections(pkg):
         s.step(-1)
     with pytest.raises(pkg.PdfmcError, match="STATE"):
         s.step(1, stages=s.STAGE_ADVANCE)
+
+
+def test_size_limits_rejected_on_the_host(pkg):
+    """Both size limits of the scatter's sort keys are checked on the host,
+    before any array beyond the sizes is read or any device memory is used:
+    a case of 2^23 elements (the wavefront sort packs the element above nine
+    bits of bin and lane into 32 bits) at add_case, and more than 2^29
+    particle slots in one context (record keys, workgroup * 512 + position,
+    stay below 2^32) at workspace_bind, which returns before it touches the
+    workspace address (a placeholder here)."""
+    import ctypes as C
+    import types
+    s = _sim(pkg)
+    mesh = W.unit_square(6, 0.0, periodic_x=True)
+    huge = types.SimpleNamespace(xy=mesh.xy, tri=mesh.tri, edge_tag=mesh.edge_tag, bcs=mesh.bcs,
+                                 n_nodes=mesh.n_nodes, n_elems=1 << 23)
+    with pytest.raises(pkg.PdfmcError, match=r"INVALID.*2\^23"):
+        s.add_case(huge, W.default_params(), 10)
+    s.add_case(mesh, W.default_params(), (1 << 29) + 1)
+    with pytest.raises(pkg.PdfmcError, match=r"INVALID.*2\^29"):
+        s._check(s._L.pdfmc_workspace_bind(s._h, C.c_void_p(256), C.c_uint64(1 << 62)), "workspace_bind")
+    t = _sim(pkg)
+    t.add_case(mesh, W.default_params(), 1 << 29)
+    with pytest.raises(pkg.PdfmcError, match="NOMEM"):
+        t._check(t._L.pdfmc_workspace_bind(t._h, C.c_void_p(256), C.c_uint64(1 << 20)), "workspace_bind")
