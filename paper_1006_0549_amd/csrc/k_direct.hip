@@ -119,15 +119,19 @@ __global__ void __launch_bounds__(DSB) k_ds_backward(const DsNode* __restrict__ 
     __shared__ double xr[CAP], ts[CAP], part[DSB];
     for (int r = threadIdx.x; r < m; r += DSB) xr[r] = x[vi[s + r]];
     __syncthreads();
-    // t_j = y_j - sum_r L21[r][j] x_r: for a supernode of at most DSB / 2
-    // unknowns the rows r are split over G groups of lanes whose partial
-    // sums are added through LDS
+    // t_j = y_j - sum_r L21[r][j] x_r: for a supernode of at most half the
+    // lanes of the split, the rows r are split over G groups of lanes whose
+    // partial sums are added through LDS. The split is the supernode's own:
+    // 256 lanes for one that the narrow sweep takes (s + m <= 128), all DSB
+    // for the others, which always run wide. So its bits do not depend on
+    // the variant that the other supernodes of its height need.
     const int sp = (s + 63) & ~63;
-    const int G = sp > 0 && sp <= DSB / 2 ? DSB / sp : 1;
+    const int gl = s + m <= 128 ? 256 : DSB;
+    const int G = sp > 0 && sp <= gl / 2 ? gl / sp : 1;
     if (G > 1) {
         const int g = threadIdx.x / sp, j = threadIdx.x - g * sp;
         double a = 0.0;
-        if (j < s)
+        if (j < s && g < G)
             for (int r = g; r < m; r += G) a += L21[(int64_t)r * s + j] * xr[r];
         part[threadIdx.x] = a;
         __syncthreads();

@@ -255,3 +255,37 @@ def test_batch32_full_size_runs_twice_bitwise(P):
         assert a[3]["scatter_overflow"] == 0 and a[3]["nan"] == 0, (ci, a[3])
         for k in range(3):
             assert np.array_equal(a[k], b_[k]), (ci, k)
+
+
+def test_batch32_full_size_batched_equals_sequential(P):
+    """Each of the 32 cases stepped alone gives the bits it gets inside the
+    batch (FP32, graph replay, sort every 5 steps, three steps): its sums,
+    statistics and fields depend on its own particles and systems only. The
+    row-parallel PCG iterations are fixed at 40 in both runs, so a system
+    that needs the one-workgroup completion takes it in both."""
+    b = W.config_batched()
+    cases = b["cases"]
+    _flush(f"[fullsize] batch32 batched vs sequential: {len(cases)} cases, FP32, 3 steps")
+
+    def run(sub):
+        sim = P.Sim("fp32", "cuda:0")
+        ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in sub]
+        sim.bind()
+        sim.set_options(sort_interval=5, block_size=256, use_graph=True)
+        sim.set_solver(iterations=40, tail_rows=256)
+        for cs, c in zip(ids, sub):
+            sim.upload(cs, c["particles"])
+        sim.init()
+        sim.step(3)
+        out = [(sim.node_sums(cs), sim.stats(cs), sim.fields(cs), sim.counters(cs)["scatter_overflow"]) for cs in ids]
+        del sim
+        return out
+
+    together = run(cases)
+    _flush("[fullsize] batch32 batched vs sequential: batch done")
+    for ci, c in enumerate(cases):
+        (alone,) = run([c])
+        assert alone[3] == 0 and together[ci][3] == 0, ci
+        for k in range(3):
+            assert np.array_equal(alone[k], together[ci][k]), (ci, k)
+    _flush("[fullsize] batch32 batched vs sequential: all cases equal")
