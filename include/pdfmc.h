@@ -283,7 +283,8 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t bl
  * row-parallel workgroups' shares, then the system's shares in block order),
  * so with fixed settings the solves repeat bit for bit, and a case's solution
  * does not depend on the other cases of the context as long as it completes
- * within the row-parallel iterations. Errors: PDFMC_E_INVALID for iterations
+ * within the row-parallel iterations (its coarse operators are formed with
+ * lanes per entry chosen from its own hierarchy). Errors: PDFMC_E_INVALID for iterations
  * outside 0..100000 or tail_rows < 0. */
 pdfmc_status pdfmc_set_solver(pdfmc_ctx* ctx, int32_t iterations, int32_t tail_rows);
 /* Current unrolled iteration count and number of row-parallel levels
@@ -301,7 +302,9 @@ pdfmc_status pdfmc_solver_info(pdfmc_ctx* ctx, int32_t* iterations, int32_t* lar
  * (a case whose factor has a supernode or reach above 2048 unknowns has
  * none). Results do not depend on the choice beyond the solver tolerance.
  * The sweeps apply the updates of an unknown from the supernodes below it in
- * a fixed (supernode) order, so a projection repeats bit for bit.
+ * a fixed (supernode) order and split each supernode's sums by its own size,
+ * so a projection repeats bit for bit and a case's projection does not
+ * depend on the other cases of the context.
  * Errors: PDFMC_E_INVALID for another method. */
 typedef enum { PDFMC_PROJ_DIRECT = 0, PDFMC_PROJ_PCG = 1 } pdfmc_projection_method;
 pdfmc_status pdfmc_set_projection_solver(pdfmc_ctx* ctx, int32_t method);
