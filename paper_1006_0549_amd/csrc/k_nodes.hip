@@ -351,12 +351,11 @@ template __global__ void k_fields_elem<float>(const double*, const double*, cons
 
 // ---------------------------------------------------------------- multigrid
 
-// LPE lanes per coarse entry (more on the coarser levels, whose entries
-// gather longer contribution lists); the group's partial sums meet by shuffles
+// LPE lanes per coarse entry (more where the entries gather longer
+// contribution lists); the group's partial sums meet by shuffles
 template <int LPE>
-__global__ void k_galerkin(const GalJob* __restrict__ jobs)
+__device__ inline void galerkin_body(const GalJob& J)
 {
-    const GalJob J = jobs[blockIdx.y];
     const int sub = threadIdx.x % LPE;
     const int g0 = (blockIdx.x * blockDim.x + threadIdx.x) / LPE, gs = gridDim.x * blockDim.x / LPE;
     for (int k = g0; k < J.nnz; k += gs) {
@@ -366,8 +365,15 @@ __global__ void k_galerkin(const GalJob* __restrict__ jobs)
         if (sub == 0) J.dst[J.gdst[k]] = s;
     }
 }
-template __global__ void k_galerkin<1>(const GalJob*);
-template __global__ void k_galerkin<4>(const GalJob*);
-template __global__ void k_galerkin<16>(const GalJob*);
+
+// one job (hierarchy) per blockIdx.y, each with its own lanes per entry, so
+// that a coarse value's summation order does not depend on the other jobs
+__global__ void k_galerkin(const GalJob* __restrict__ jobs)
+{
+    const GalJob J = jobs[blockIdx.y];
+    if (J.lpe >= 16) galerkin_body<16>(J);
+    else if (J.lpe >= 4) galerkin_body<4>(J);
+    else galerkin_body<1>(J);
+}
 
 }  // namespace pdfmc

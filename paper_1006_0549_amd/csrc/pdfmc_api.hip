@@ -331,12 +331,12 @@ struct pdfmc_ctx {
     double* d_amg_d = nullptr;
     AmgDev* d_amg = nullptr;
     GalJob* d_gal = nullptr;           // [AMG_MAXL][n_amg]: relaxation, then projection at [AMG_MAXL*n_amg + ...]
-    // Galerkin jobs of each level, grouped by lanes per coarse entry (1, 4,
-    // 16 lanes; class from the hierarchy's own contribution lists, so that a
-    // case's coarse values do not depend on the other cases of the batch)
-    int n_gal[AMG_MAXL][3] = {};
-    int n_gal_p[AMG_MAXL][3] = {};
-    int64_t gal_max[AMG_MAXL][3] = {}, gal_max_p[AMG_MAXL][3] = {};
+    // Galerkin jobs of each level; each job's lanes per coarse entry come
+    // from its own hierarchy, so a case's coarse values do not depend on the
+    // other cases of the batch
+    int n_gal[AMG_MAXL] = {};
+    int n_gal_p[AMG_MAXL] = {};
+    int64_t gal_max[AMG_MAXL] = {}, gal_max_p[AMG_MAXL] = {};   // largest nnz * lanes per entry
     // projection by the Cholesky factors: supernodes, their unknown indices
     // and values, the factored cases, supernodes ordered by height
     DsNode* d_ds_nodes = nullptr;
@@ -989,28 +989,14 @@ void mg_adapt(pdfmc_ctx* c)
     }
 }
 
-// Coarse operators of one level for n hierarchies: lpe lanes per coarse entry
-pdfmc_status enqueue_galerkin(pdfmc_ctx* c, const GalJob* jobs, int n, int64_t max_nnz, int lpe)
+// Coarse operators of one level for n hierarchies (max_lanes: the largest
+// nnz * lanes per entry of the jobs)
+pdfmc_status enqueue_galerkin(pdfmc_ctx* c, const GalJob* jobs, int n, int64_t max_lanes)
 {
     if (n == 0) return PDFMC_OK;
-    const dim3 g(std::min<int64_t>(nblk(max_nnz * lpe, 256), 1024), n);
-    if (lpe >= 16) hipLaunchKernelGGL(k_galerkin<16>, g, dim3(256), 0, c->stream, jobs);
-    else if (lpe >= 4) hipLaunchKernelGGL(k_galerkin<4>, g, dim3(256), 0, c->stream, jobs);
-    else hipLaunchKernelGGL(k_galerkin<1>, g, dim3(256), 0, c->stream, jobs);
+    const dim3 g(std::min<int64_t>(nblk(max_lanes, 256), 1024), n);
+    hipLaunchKernelGGL(k_galerkin, g, dim3(256), 0, c->stream, jobs);
     LAUNCHCHK(c);
-    return PDFMC_OK;
-}
-
-// All of a level's Galerkin jobs: one launch per class of lanes per coarse
-// entry (the jobs are stored in class order)
-pdfmc_status enqueue_galerkin_level(pdfmc_ctx* c, const GalJob* jobs, const int (&n)[3], const int64_t (&max_nnz)[3])
-{
-    static const int lpe[3] = {1, 4, 16};
-    int off = 0;
-    for (int q = 0; q < 3; ++q) {
-        TRY(enqueue_galerkin(c, jobs + off, n[q], max_nnz[q], lpe[q]));
-        off += n[q];
-    }
     return PDFMC_OK;
 }
 
@@ -1043,7 +1029,7 @@ pdfmc_status enqueue_fields(pdfmc_ctx* c, bool project)
         hipLaunchKernelGGL(k_er_assemble, g, b, 0, c->stream, A);
         if (project) hipLaunchKernelGGL(k_proj_rhs, g, b, 0, c->stream, A);
         for (int l = 0; l < AMG_MAXL; ++l)
-            TRY(enqueue_galerkin_level(c, c->d_gal + (size_t)l * c->n_amg, c->n_gal[l], c->gal_max[l]));
+            TRY(enqueue_galerkin(c, c->d_gal + (size_t)l * c->n_amg, c->n_gal[l], c->gal_max[l]));
         // relaxation and projection systems of every case together
         TRY(enqueue_solve(c, project));
         hipLaunchKernelGGL(k_er_finish, g, b, 0, c->stream, A);
@@ -1427,11 +1413,9 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
     // multigrid hierarchies: flat arrays, descriptors, Galerkin jobs
     std::vector<AmgDev> amgdev(2 * (size_t)std::max(c->n_amg, 1));
     std::vector<GalJob> gal(2 * (size_t)AMG_MAXL * std::max(c->n_amg, 1));
-    std::vector<GalJob> gcls[2][AMG_MAXL][3];   // (relaxation, projection) x level x class
-    for (int l = 0; l < AMG_MAXL; ++l)
-        for (int q = 0; q < 3; ++q) {
-            c->n_gal[l][q] = 0; c->n_gal_p[l][q] = 0; c->gal_max[l][q] = 0; c->gal_max_p[l][q] = 0;
-        }
+    for (int l = 0; l < AMG_MAXL; ++l) {
+        c->n_gal[l] = 0; c->n_gal_p[l] = 0; c->gal_max[l] = 0; c->gal_max_p[l] = 0;
+    }
     if (c->n_amg > 0) {
         std::vector<int32_t> ai;
         std::vector<double> ad;
@@ -1489,22 +1473,17 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                     G.dst = c->d_amg_d + o.Aval[l + 1];
                     // lanes per coarse entry from the mean contribution-list length
                     const double terms = G.nnz > 0 ? (double)E.gidx[l].size() / G.nnz : 0.0;
-                    const int q = terms >= 24.0 ? 2 : (terms >= 4.0 ? 1 : 0);
-                    gcls[h][l][q].push_back(G);
-                    int64_t& mx = h == 0 ? c->gal_max[l][q] : c->gal_max_p[l][q];
-                    mx = std::max<int64_t>(mx, G.nnz);
+                    G.lpe = terms >= 24.0 ? 16 : (terms >= 4.0 ? 4 : 1);
+                    if (h == 0) {
+                        gal[(size_t)l * c->n_amg + c->n_gal[l]++] = G;
+                        c->gal_max[l] = std::max<int64_t>(c->gal_max[l], (int64_t)G.nnz * G.lpe);
+                    } else {
+                        gal[(size_t)(AMG_MAXL + l) * c->n_amg + c->n_gal_p[l]++] = G;
+                        c->gal_max_p[l] = std::max<int64_t>(c->gal_max_p[l], (int64_t)G.nnz * G.lpe);
+                    }
                 }
             }
         }
-        // each level's jobs in class order
-        for (int h = 0; h < 2; ++h)
-            for (int l = 0; l < AMG_MAXL; ++l) {
-                size_t off = (size_t)(h * AMG_MAXL + l) * c->n_amg;
-                for (int q = 0; q < 3; ++q) {
-                    for (const GalJob& G : gcls[h][l][q]) gal[off++] = G;
-                    (h == 0 ? c->n_gal[l][q] : c->n_gal_p[l][q]) = (int)gcls[h][l][q].size();
-                }
-            }
         TRY(h2d(c, c->d_amg, amgdev));
         TRY(h2d(c, c->d_gal, gal));
     }
@@ -1604,7 +1583,7 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         hipLaunchKernelGGL(k_stiffness_assemble, dim3(nblk(NN, 256)), dim3(256), 0, c->stream, node_args(c));
         LAUNCHCHK(c);
         for (int l = 0; l < AMG_MAXL; ++l) {
-            TRY(enqueue_galerkin_level(c, c->d_gal + (size_t)(AMG_MAXL + l) * c->n_amg, c->n_gal_p[l], c->gal_max_p[l]));
+            TRY(enqueue_galerkin(c, c->d_gal + (size_t)(AMG_MAXL + l) * c->n_amg, c->n_gal_p[l], c->gal_max_p[l]));
             LAUNCHCHK(c);
         }
         // the projection hierarchies' inverse diagonals and coarsest inverses,

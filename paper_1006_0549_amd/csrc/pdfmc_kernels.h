@@ -43,7 +43,7 @@ __global__ void k_mg_post2(const MgJob* jobs, const AmgDev* hs, const int4* tab,
 __global__ void k_mg_finish(const MgJob* jobs, const AmgDev* hs, int k0);
 __global__ void k_mg_reduce(const MgJob* jobs, const AmgDev* hs, const int32_t* st, int k, int word0, int M, int setup,
                             int big_only);
-template <int LPE> __global__ void k_galerkin(const GalJob* jobs);
+__global__ void k_galerkin(const GalJob* jobs);
 __global__ void k_ds_prep(const DsCase* cs, const double* b, double* x);
 template <int DSB, int CAP>
 __global__ void k_ds_forward(const DsNode* nodes, const int32_t* list, const int32_t* idx, const double* val, double* x,

@@ -99,6 +99,7 @@ struct AmgDev {
 // dst[gdst[k]] = sum_j gcoef[j] src[gidx[j]], j in [gptr[k], gptr[k+1])
 struct GalJob {
     int32_t nnz;
+    int32_t lpe;                   // lanes per coarse entry: 1, 4 or 16 (from this hierarchy's lists)
     const int32_t* gptr;
     const int32_t* gidx;
     const double* gcoef;
