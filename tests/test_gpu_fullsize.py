@@ -257,18 +257,19 @@ def test_batch32_full_size_runs_twice_bitwise(P):
             assert np.array_equal(a[k], b_[k]), (ci, k)
 
 
-def test_batch32_full_size_batched_equals_sequential(P):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch32_full_size_batched_equals_sequential(P, precision):
     """Each of the 32 cases stepped alone gives the bits it gets inside the
-    batch (FP32, graph replay, sort every 5 steps, three steps): its sums,
+    batch (graph replay, sort every 5 steps, three steps): its sums,
     statistics and fields depend on its own particles and systems only. The
     row-parallel PCG iterations are fixed at 40 in both runs, so a system
     that needs the one-workgroup completion takes it in both."""
     b = W.config_batched()
     cases = b["cases"]
-    _flush(f"[fullsize] batch32 batched vs sequential: {len(cases)} cases, FP32, 3 steps")
+    _flush(f"[fullsize] batch32 batched vs sequential: {len(cases)} cases, {precision}, 3 steps")
 
     def run(sub):
-        sim = P.Sim("fp32", "cuda:0")
+        sim = P.Sim(precision, "cuda:0")
         ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in sub]
         sim.bind()
         sim.set_options(sort_interval=5, block_size=256, use_graph=True)
