@@ -1473,7 +1473,7 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
                     G.dst = c->d_amg_d + o.Aval[l + 1];
                     // lanes per coarse entry from the mean contribution-list length
                     const double terms = G.nnz > 0 ? (double)E.gidx[l].size() / G.nnz : 0.0;
-                    G.lpe = terms >= 24.0 ? 16 : (terms >= 4.0 ? 4 : 1);
+                    G.lpe = terms >= 5.0 ? 16 : (terms >= 2.0 ? 4 : 1);
                     if (h == 0) {
                         gal[(size_t)l * c->n_amg + c->n_gal[l]++] = G;
                         c->gal_max[l] = std::max<int64_t>(c->gal_max[l], (int64_t)G.nnz * G.lpe);
