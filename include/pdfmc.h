@@ -275,8 +275,8 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t bl
  * over all systems of all cases (a system that has converged skips the rest
  * at once), then completes any system that needs more in one workgroup per
  * system. iterations = 0 (the default) adapts the count to what the previous
- * steps needed (read back asynchronously every 8 steps, no host
- * synchronisation). Multigrid levels with more than tail_rows unknowns (default
+ * steps needed (read back asynchronously every 8 steps and applied two steps
+ * later, so the count changes at the same steps in every run). Multigrid levels with more than tail_rows unknowns (default
  * 64) are processed by the row-parallel phases, smaller ones by one
  * workgroup per system. Results do not depend on either option beyond FP64
  * summation order. Every scalar of the CG is summed in a fixed order (the

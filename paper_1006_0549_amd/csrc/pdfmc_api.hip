@@ -303,6 +303,7 @@ struct pdfmc_ctx {
     unsigned int* h_need = nullptr;   // pinned: iterations the last observed solve needed
     hipEvent_t need_ev = nullptr;
     int need_tick = 0;                 // steps since the last readback of the needed iterations
+    int need_wait = 0;                 // steps since that readback was enqueued
     bool need_pending = false;
     int need_low = 0;
     std::vector<AmgDev> h_amgdev;   // host copies of what the solver tables point at
@@ -942,8 +943,11 @@ pdfmc_status enqueue_solve(pdfmc_ctx* c, bool project)
 }
 
 // After a step: fetch the iteration count the solves needed (asynchronously);
-// before a step: adapt the number of unrolled iterations to what was needed.
+// before a step: adapt the number of unrolled iterations to what was needed,
+// NEED_LAG steps after the readback was enqueued, so that the count changes
+// at the same steps in every run.
 constexpr int NEED_EVERY = 8;
+constexpr int NEED_LAG = 2;
 
 pdfmc_status mg_after_step(pdfmc_ctx* c)
 {
@@ -960,13 +964,17 @@ pdfmc_status mg_after_step(pdfmc_ctx* c)
     HIPCHK(c, hipEventRecord(c->need_ev, c->stream));
     TRY(enqueue_fill_i(c, (int32_t*)c->d_mg_need, 1));
     c->need_pending = true;
+    c->need_wait = 0;
     return PDFMC_OK;
 }
 
 void mg_adapt(pdfmc_ctx* c)
 {
     if (!c->mg_auto || !c->need_pending) return;
-    if (hipEventQuery(c->need_ev) != hipSuccess) return;
+    // a fixed number of steps after the readback (by then the copy has long
+    // completed: the wait only bounds how far the host runs ahead)
+    if (++c->need_wait < NEED_LAG) return;
+    if (hipEventSynchronize(c->need_ev) != hipSuccess) return;
     c->need_pending = false;
     const int need = (int)*c->h_need;     // the largest of the last NEED_EVERY steps
     // the one-workgroup completion is many times slower per iteration than

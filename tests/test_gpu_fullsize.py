@@ -230,14 +230,15 @@ def test_batch32_sort_is_a_permutation_at_full_size(P):
 
 def test_batch32_full_size_runs_twice_bitwise(P):
     """The benchmark's launch configuration (FP32, the 32-case batch, graph
-    replay, block 256, sort every 5 steps, tail rows 256) run twice from the
-    same upload for eight steps, a sort included: the node sums, statistics
-    and fields of every case are the same bits, and no element sum fell back
-    to atomics."""
+    replay, block 256, sort every 5 steps, tail rows 256, adaptive PCG
+    iterations) run twice from the same upload for 40 steps, sorts and
+    changes of the unrolled iteration count included: the node sums,
+    statistics and fields of every case are the same bits, and no element sum
+    fell back to atomics."""
     b = W.config_batched()
     cases = b["cases"]
-    _flush(f"[fullsize] batch32 run twice: {len(cases)} cases, FP32, graph replay, 8 steps each")
-    out = []
+    _flush(f"[fullsize] batch32 run twice: {len(cases)} cases, FP32, graph replay, 40 steps each")
+    out, iters = [], []
     for run in range(2):
         sim = P.Sim("fp32", "cuda:0")
         ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in cases]
@@ -247,10 +248,13 @@ def test_batch32_full_size_runs_twice_bitwise(P):
         for cs, c in zip(ids, cases):
             sim.upload(cs, c["particles"])
         sim.init()
-        sim.step(8)
+        it0 = sim.solver_info()[0]
+        sim.step(40)
+        iters.append((it0, sim.solver_info()[0]))
         out.append([(sim.node_sums(cs), sim.stats(cs), sim.fields(cs), sim.counters(cs)) for cs in ids])
-        _flush(f"[fullsize] batch32 run twice: run {run} done")
+        _flush(f"[fullsize] batch32 run twice: run {run} done, unrolled iterations {iters[-1]}")
         del sim
+    assert iters[0] == iters[1] and iters[0][0] != iters[0][1], iters
     for ci, (a, b_) in enumerate(zip(*out)):
         assert a[3]["scatter_overflow"] == 0 and a[3]["nan"] == 0, (ci, a[3])
         for k in range(3):
