@@ -276,15 +276,17 @@ pdfmc_status pdfmc_set_options(pdfmc_ctx* ctx, int32_t sort_interval, int32_t bl
  * at once), then completes any system that needs more in one workgroup per
  * system. iterations = 0 (the default) adapts the count to what the previous
  * steps needed (read back asynchronously every 8 steps and applied two steps
- * later, so the count changes at the same steps in every run). Multigrid levels with more than tail_rows unknowns (default
+ * later, so the count changes at the same steps in every run): each system
+ * hands over to the one-workgroup completion at an iteration set from its
+ * own solves, and the phases are unrolled for the system that needs the
+ * most. Multigrid levels with more than tail_rows unknowns (default
  * 64) are processed by the row-parallel phases, smaller ones by one
  * workgroup per system. Results do not depend on either option beyond FP64
  * summation order. Every scalar of the CG is summed in a fixed order (the
  * row-parallel workgroups' shares, then the system's shares in block order),
- * so with fixed settings the solves repeat bit for bit, and a case's solution
- * does not depend on the other cases of the context as long as it completes
- * within the row-parallel iterations (its coarse operators are formed with
- * lanes per entry chosen from its own hierarchy). Errors: PDFMC_E_INVALID for iterations
+ * so the solves repeat bit for bit, and a case's solution does not depend on
+ * the other cases of the context (its hand-over iteration and the lanes per
+ * entry of its coarse operators come from its own systems). Errors: PDFMC_E_INVALID for iterations
  * outside 0..100000 or tail_rows < 0. */
 pdfmc_status pdfmc_set_solver(pdfmc_ctx* ctx, int32_t iterations, int32_t tail_rows);
 /* Current unrolled iteration count and number of row-parallel levels

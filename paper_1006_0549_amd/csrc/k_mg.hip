@@ -503,7 +503,8 @@ __device__ void finish_body(const MgJob& J, const AmgDev& H, int k0)
     __syncthreads();
     bool done = st[0] != 0;
     int it = done ? st[1] : 0;
-    for (int k = min(k0, J.maxit); !done; ++k) {
+    // from the first iteration the phases did not run for this system
+    for (int k = min(min(k0, J.ksw), J.maxit); !done; ++k) {
         const Scal sa = pa_scalars<NV, true>(J, k, v);
         if (sa.all) { done = true; it = k; break; }
         if (k >= J.maxit) { it = k; break; }
@@ -663,7 +664,7 @@ __global__ void __launch_bounds__(MGB) k_mg_pa(const MgJob* __restrict__ jobs, c
 {
     const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
-    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    if (st[2 * e.x] != 0 || k >= J.ksw) return;
 #define PA(NV) pa_kernel_body<NV>(J, hs[e.z], e.y, k)
     MG_DISPATCH(J, PA);
 #undef PA
@@ -675,7 +676,7 @@ __global__ void __launch_bounds__(MGB) k_mg_pb(const MgJob* __restrict__ jobs, c
 {
     const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
-    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    if (st[2 * e.x] != 0 || k >= J.ksw) return;
 #define PB(NV) pb_kernel_body<NV>(J, hs[e.z], e.y, k, first != 0)
     MG_DISPATCH(J, PB);
 #undef PB
@@ -688,7 +689,7 @@ __global__ void __launch_bounds__(MGB) k_mg_res(const MgJob* __restrict__ jobs, 
 {
     const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
-    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    if (st[2 * e.x] != 0 || k >= J.ksw) return;
     const AmgDev& H = hs[e.z];
 #define RES(NV)                                                  \
     {                                                            \
@@ -707,7 +708,7 @@ __global__ void __launch_bounds__(MGB) k_mg_restrict(const MgJob* __restrict__ j
 {
     const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
-    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    if (st[2 * e.x] != 0 || k >= J.ksw) return;
     const AmgDev& H = hs[e.z];
 #define RST(NV)                                                  \
     {                                                            \
@@ -724,7 +725,7 @@ __global__ void __launch_bounds__(MGB) k_mg_pre(const MgJob* __restrict__ jobs, 
 {
     const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
-    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    if (st[2 * e.x] != 0 || k >= J.ksw) return;
     const AmgDev& H = hs[e.z];
 #define PRE(NV)                                                  \
     {                                                            \
@@ -739,7 +740,7 @@ __global__ void __launch_bounds__(MGT) k_mg_tail(const MgJob* __restrict__ jobs,
                                                  const int32_t* __restrict__ st, int k)
 {
     const MgJob& J = jobs[blockIdx.x];
-    if (st[2 * blockIdx.x] != 0 || J.n <= 0 || k >= J.maxit) return;
+    if (st[2 * blockIdx.x] != 0 || J.n <= 0 || k >= J.ksw) return;
     // the pair loops use a multiple of NV lanes; the others only join the
     // barriers and reductions
 #define TAIL(NV) tail_body<NV>(J, hs[J.hier], k, (MGT / NV) * NV)
@@ -753,7 +754,7 @@ __global__ void __launch_bounds__(MGB) k_mg_prolong(const MgJob* __restrict__ jo
 {
     const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
-    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    if (st[2 * e.x] != 0 || k >= J.ksw) return;
     const AmgDev& H = hs[e.z];
 #define PRL(NV)                                                  \
     {                                                            \
@@ -770,7 +771,7 @@ __global__ void __launch_bounds__(MGB) k_mg_post1(const MgJob* __restrict__ jobs
 {
     const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
-    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    if (st[2 * e.x] != 0 || k >= J.ksw) return;
     const AmgDev& H = hs[e.z];
 #define PS1(NV)                                                  \
     {                                                            \
@@ -787,7 +788,7 @@ __global__ void __launch_bounds__(MGB) k_mg_post2(const MgJob* __restrict__ jobs
 {
     const int4 e = tab[xcd_block((int)blockIdx.x, (int)gridDim.x)];
     const MgJob& J = jobs[e.x];
-    if (st[2 * e.x] != 0 || k >= J.maxit) return;
+    if (st[2 * e.x] != 0 || k >= J.ksw) return;
     const AmgDev& H = hs[e.z];
 #define PS2(NV)                                                  \
     {                                                            \
@@ -814,7 +815,7 @@ __global__ void __launch_bounds__(256) k_mg_reduce(const MgJob* __restrict__ job
 {
     const MgJob& J = jobs[blockIdx.x];
     if (J.n <= 0) return;
-    if (!setup && (st[2 * blockIdx.x] != 0 || k >= J.maxit)) return;
+    if (!setup && (st[2 * blockIdx.x] != 0 || k >= J.ksw)) return;
     if (big_only && hs[J.hier].nbig < 1) return;
     __shared__ double sh[MG_PART * 16];
     const int nw = J.nv * M, nb = J.nblk0;

@@ -300,12 +300,14 @@ struct pdfmc_ctx {
     int maxbig_er = 0, maxbig_all = 0;
     // solver options: unrolled iterations (adaptive when mg_auto), small-level threshold
     int mg_iters = 32, mg_auto = 1, tail_rows = 64;
-    unsigned int* h_need = nullptr;   // pinned: iterations the last observed solve needed
+    unsigned int* h_need = nullptr;   // pinned, per system: iterations its solves needed in the last window
+    size_t h_need_n = 0;
+    std::vector<int32_t> ksw;         // per system: the iteration at which the phases hand it over
+    std::vector<int32_t> ksw_low;     // per system: consecutive windows that needed far fewer
     hipEvent_t need_ev = nullptr;
     int need_tick = 0;                 // steps since the last readback of the needed iterations
     int need_wait = 0;                 // steps since that readback was enqueued
     bool need_pending = false;
-    int need_low = 0;
     std::vector<AmgDev> h_amgdev;   // host copies of what the solver tables point at
     std::vector<MgJob> h_jobs;
     std::vector<int4> h_tab;
@@ -457,7 +459,7 @@ void carve(pdfmc_ctx* c, Carver& k)
     k.take(c->d_mg_vec, c->MGV);
     k.take(c->d_mg_acc, (size_t)(NER + 1) * c->cases.size() * MG_NSLOT * MG_SLOT);
     k.take(c->d_mg_state, (size_t)(NER + 1) * c->cases.size() * 2);
-    k.take(c->d_mg_need, 1);
+    k.take(c->d_mg_need, (NER + 1) * c->cases.size());   // per system
     k.take(c->d_mg_dinv, c->MGD);
     k.take(c->d_mg_ainv, 2 * (size_t)std::max(c->n_amg, 1) * AMG_MAXC * AMG_MAXC);
     k.take(c->d_mg_tab, c->MGT);
@@ -753,7 +755,6 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
             voff += nv * mg_vec_len(cs.amg[h]);
             J.iters = c->d_counters + (int64_t)ci * NCNT + (proj ? C_CG_P : C_CG_ER);
             J.fails = c->d_counters + (int64_t)ci * NCNT + C_CG_FAIL;
-            J.need = c->d_mg_need;
             (proj ? jp : jer).push_back(J);
         }
     }
@@ -765,11 +766,19 @@ pdfmc_status build_mg_jobs(pdfmc_ctx* c)
         jer[j].acc = c->d_mg_acc + aoff;
         aoff += (int64_t)jer[j].nv * MG_NSLOT * MG_SLOT;
         jer[j].state = c->d_mg_state + 2 * j;
+        jer[j].need = c->d_mg_need + j;
         jer[j].nblk0 = (int32_t)mg_blocks_nv(jer[j].n, jer[j].nv);
         jer[j].part = c->d_mg_part + poff * MG_PART;
         poff += jer[j].nblk0;
     }
     if (poff > c->MGP) return fail(c, PDFMC_E_STATE, "solver partial sums exceed their reservation");
+    // the hand-over iteration of each system: kept across rebuilds of the
+    // tables (same systems in the same order), else the unrolled count
+    if (c->ksw.size() != jer.size()) {
+        c->ksw.assign(jer.size(), c->mg_iters);
+        c->ksw_low.assign(jer.size(), 0);
+    }
+    for (size_t j = 0; j < jer.size(); ++j) jer[j].ksw = std::min(c->ksw[j], jer[j].maxit);
     c->h_jobs = jer;
     TRY(h2d(c, c->d_mg_jobs, c->h_jobs));
     const int nj = (int)jer.size();
@@ -960,41 +969,52 @@ pdfmc_status mg_after_step(pdfmc_ctx* c)
     c->need_tick = 0;
     // the counter holds the largest count of the steps since the last
     // readback (the solves only raise it); it restarts after the copy
-    HIPCHK(c, hipMemcpyAsync(c->h_need, c->d_mg_need, sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream));
+    const size_t nj = c->h_jobs.size();
+    HIPCHK(c, hipMemcpyAsync(c->h_need, c->d_mg_need, nj * sizeof(unsigned int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipEventRecord(c->need_ev, c->stream));
-    TRY(enqueue_fill_i(c, (int32_t*)c->d_mg_need, 1));
+    TRY(enqueue_fill_i(c, (int32_t*)c->d_mg_need, (int64_t)nj));
     c->need_pending = true;
     c->need_wait = 0;
     return PDFMC_OK;
 }
 
-void mg_adapt(pdfmc_ctx* c)
+pdfmc_status mg_adapt(pdfmc_ctx* c)
 {
-    if (!c->mg_auto || !c->need_pending) return;
+    if (!c->mg_auto || !c->need_pending) return PDFMC_OK;
     // a fixed number of steps after the readback (by then the copy has long
     // completed: the wait only bounds how far the host runs ahead)
-    if (++c->need_wait < NEED_LAG) return;
-    if (hipEventSynchronize(c->need_ev) != hipSuccess) return;
+    if (++c->need_wait < NEED_LAG) return PDFMC_OK;
+    if (hipEventSynchronize(c->need_ev) != hipSuccess) return PDFMC_OK;
     c->need_pending = false;
-    const int need = (int)*c->h_need;     // the largest of the last NEED_EVERY steps
-    // the one-workgroup completion is many times slower per iteration than
-    // the phases, so keep a margin above what the window needed
-    const int margin = std::max(2, need / 8);
-    int want = c->mg_iters;
-    if (need + 1 > c->mg_iters) {
-        want = need + margin;
-        c->need_low = 0;
-    } else if (need + 2 * margin < c->mg_iters) {
-        // two low readings in a row (two windows) before unrolling fewer
-        if (++c->need_low >= 2) { want = need + margin; c->need_low = 0; }
-    } else {
-        c->need_low = 0;
+    // per system, from its own solves only: the one-workgroup completion is
+    // many times slower per iteration than the phases, so keep a margin above
+    // what the window needed; lower the hand-over only after two low windows
+    bool changed = false;
+    int most = 1;
+    for (size_t j = 0; j < c->h_jobs.size(); ++j) {
+        const int need = (int)c->h_need[j];
+        const int margin = std::max(2, need / 8);
+        int want = c->ksw[j];
+        if (need + 1 > c->ksw[j]) {
+            want = need + margin;
+            c->ksw_low[j] = 0;
+        } else if (need + 2 * margin < c->ksw[j]) {
+            if (++c->ksw_low[j] >= 2) { want = need + margin; c->ksw_low[j] = 0; }
+        } else {
+            c->ksw_low[j] = 0;
+        }
+        want = std::max(1, std::min(want, 400));
+        if (want != c->ksw[j]) { c->ksw[j] = want; changed = true; }
+        c->h_jobs[j].ksw = std::min(want, c->h_jobs[j].maxit);
+        most = std::max(most, c->h_jobs[j].ksw);
     }
-    want = std::max(1, std::min(want, 400));
-    if (want != c->mg_iters) {
-        c->mg_iters = want;
+    if (changed) TRY(h2d(c, c->d_mg_jobs, c->h_jobs));
+    // the phases are unrolled for the system that needs the most
+    if (most != c->mg_iters) {
+        c->mg_iters = most;
         drop_graphs(c);
     }
+    return PDFMC_OK;
 }
 
 // Coarse operators of one level for n hierarchies (max_lanes: the largest
@@ -1495,10 +1515,19 @@ pdfmc_status pdfmc_workspace_bind(pdfmc_ctx* c, void* dev, uint64_t bytes)
         TRY(h2d(c, c->d_amg, amgdev));
         TRY(h2d(c, c->d_gal, gal));
     }
-    if (!c->h_need) {
-        HIPCHK(c, hipHostMalloc((void**)&c->h_need, sizeof(unsigned int), hipHostMallocDefault));
-        *c->h_need = 0;
+    {
+        const size_t nn = (NER + 1) * c->cases.size();
+        if (c->h_need && c->h_need_n < nn) {
+            (void)hipHostFree(c->h_need);
+            c->h_need = nullptr;
+        }
+        if (!c->h_need) {
+            HIPCHK(c, hipHostMalloc((void**)&c->h_need, nn * sizeof(unsigned int), hipHostMallocDefault));
+            c->h_need_n = nn;
+        }
+        for (size_t j = 0; j < nn; ++j) c->h_need[j] = 0;
     }
+    c->ksw.clear();
     if (!c->need_ev) HIPCHK(c, hipEventCreateWithFlags(&c->need_ev, hipEventDisableTiming));
     c->need_pending = false;
     // projection factors: supernodes with global unknown indices, listed by height
@@ -1886,7 +1915,7 @@ pdfmc_status pdfmc_step(pdfmc_ctx* c, int32_t n_steps, uint32_t stage_mask)
     }
     TRY(ensure_side_stream(c));
     for (int s = 0; s < n_steps; ++s) {
-        mg_adapt(c);
+        TRY(mg_adapt(c));
         // the periodic sort comes at the end of the step after which it is
         // due, so that it overlaps the fields phase
         const bool sort_after = c->sort_interval > 0 && c->ntiles > 0 && c->steps_since_sort + 1 >= c->sort_interval;
@@ -2014,6 +2043,15 @@ pdfmc_status pdfmc_set_solver(pdfmc_ctx* c, int32_t iterations, int32_t tail_row
     const bool retable = tail_rows != c->tail_rows;
     c->mg_auto = iterations == 0 ? 1 : 0;
     if (iterations > 0 && iterations != c->mg_iters) { c->mg_iters = iterations; drop_graphs(c); }
+    if (iterations > 0) {
+        // a fixed count: every system runs it in the phases
+        c->ksw.assign(c->ksw.size(), iterations);
+        c->ksw_low.assign(c->ksw_low.size(), 0);
+        if (c->bound && !c->h_jobs.empty()) {
+            for (auto& J : c->h_jobs) J.ksw = std::min(iterations, J.maxit);
+            TRY(h2d(c, c->d_mg_jobs, c->h_jobs));
+        }
+    }
     c->tail_rows = tail_rows;
     if (retable && c->bound) {
         HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -135,9 +135,12 @@ struct MgJob {
     int32_t* state;                // [0] converged, [1] iteration count
     unsigned long long* iters;
     unsigned long long* fails;
-    unsigned int* need;            // largest iteration count since the host last read it (all systems)
+    unsigned int* need;            // largest iteration count of this system since the host last read it
     double* part;                  // [nblk0][MG_PART] the row-parallel workgroups' sums of a phase
     int32_t nblk0;                 // row blocks of level 0
+    int32_t ksw;                   // the row-parallel phases run iterations k < ksw (<= maxit); the
+                                   // one-workgroup completion takes over at k = ksw. Set from this
+                                   // system's own history, so its bits do not depend on the batch.
 };
 
 // One supernode of a case's projection factor (nested-dissection Cholesky of

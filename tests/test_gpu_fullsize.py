@@ -261,27 +261,31 @@ def test_batch32_full_size_runs_twice_bitwise(P):
             assert np.array_equal(a[k], b_[k]), (ci, k)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_batch32_full_size_batched_equals_sequential(P, precision):
+@pytest.mark.parametrize("precision,iterations,steps", [("fp32", 40, 3), ("fp64", 40, 3), ("fp32", 0, 24)],
+                         ids=["fp32-fixed", "fp64-fixed", "fp32-adaptive"])
+def test_batch32_full_size_batched_equals_sequential(P, precision, iterations, steps):
     """Each of the 32 cases stepped alone gives the bits it gets inside the
-    batch (graph replay, sort every 5 steps, three steps): its sums,
-    statistics and fields depend on its own particles and systems only. The
-    row-parallel PCG iterations are fixed at 40 in both runs, so a system
-    that needs the one-workgroup completion takes it in both."""
+    batch (graph replay, sort every 5 steps): its sums, statistics and fields
+    depend on its own particles and systems only. With a fixed count of
+    row-parallel PCG iterations, and with the adaptive count over 24 steps
+    (two readbacks): each system hands over to the one-workgroup completion
+    at an iteration set from its own solves, so it takes the completion at
+    the same iteration in both runs."""
     b = W.config_batched()
     cases = b["cases"]
-    _flush(f"[fullsize] batch32 batched vs sequential: {len(cases)} cases, {precision}, 3 steps")
+    _flush(f"[fullsize] batch32 batched vs sequential: {len(cases)} cases, {precision}, iterations {iterations}, "
+           f"{steps} steps")
 
     def run(sub):
         sim = P.Sim(precision, "cuda:0")
         ids = [sim.add_case(c["mesh"], c["params"], len(c["particles"]["x"])) for c in sub]
         sim.bind()
         sim.set_options(sort_interval=5, block_size=256, use_graph=True)
-        sim.set_solver(iterations=40, tail_rows=256)
+        sim.set_solver(iterations=iterations, tail_rows=256)
         for cs, c in zip(ids, sub):
             sim.upload(cs, c["particles"])
         sim.init()
-        sim.step(3)
+        sim.step(steps)
         out = [(sim.node_sums(cs), sim.stats(cs), sim.fields(cs), sim.counters(cs)["scatter_overflow"]) for cs in ids]
         del sim
         return out
