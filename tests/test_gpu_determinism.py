@@ -12,9 +12,10 @@ scatter-overflow counter stays at 0:
   - after a sort the particles are in (element, id) order, and a sorted run
     follows the oracle as closely as an unsorted one.
 The Eulerian solves of the full model (mode 2) sum in fixed orders too: the
-multigrid PCG adds its workgroups' shares of each dot product in block order,
-and the forward sweep over the projection's Cholesky factor applies the
-updates of an unknown in supernode order. So the full model is checked the
+multigrid PCG adds its workgroups' shares of each dot product in block order
+(and hands each system over to the one-workgroup completion at an iteration
+set from its own solves), and the forward sweep over the projection's
+Cholesky factor applies the updates of an unknown in supernode order. So the full model is checked the
 same way, with the projection on the factor and on the multigrid PCG.
 """
 import numpy as np
@@ -180,9 +181,9 @@ def _full_context(P, precision, cases, steps, projection):
     ids = [sim.add_case(m, p, len(parts["x"])) for m, p, parts in cases]
     sim.bind()
     sim.set_options(sort_interval=3, use_graph=True)
-    # a fixed unrolled PCG length, well above what the systems need: every
-    # solve completes in the row-parallel phases in every context (the
-    # one-workgroup completion sums in another order)
+    # a fixed unrolled PCG length, well above what the systems need (the
+    # adaptive count, with each system's own hand-over to the one-workgroup
+    # completion, is covered by the full-size batch tests)
     sim.set_solver(iterations=40, tail_rows=64)
     sim.set_projection_solver(projection)
     for cs, (m, p, parts) in zip(ids, cases):
